@@ -1,0 +1,184 @@
+"""CPU oracle for group-closeness maximisation -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library: the C part
+(``oracle.c``) is compiled by gcc on its own, and the pure-Python part
+(``small.py``, ``mlp_ref.py``) uses numpy only.
+
+Contents
+  * ``oracle.c`` / this module: tier A plain greedy (full BFS per candidate),
+    tier B CPU Greedy++ (pruned BFS, lazy skip, BFScut), single gains,
+    group distances and farness.
+  * ``small.py``: tier C -- Floyd-Warshall, brute force over k-subsets, the
+    matrix form of the greedy of Chen et al., the bit-vector identity of the
+    paper's theorem, all for tiny graphs.
+  * ``mlp_ref.py``: float64 reference of the candidate-ordering MLP with the
+    same bfloat16 rounding points as the GPU kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OR_OK = 0
+OR_EINVAL = -1
+OR_EDISCONNECTED = -3
+OR_EINVARIANT = -100
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        I64, I32 = ctypes.c_int64, ctypes.c_int32
+        lib.or_bfs.restype = I64
+        lib.or_bfs.argtypes = [I64, i32p, i32p, I32, i32p, i32p]
+        lib.or_group_dist.restype = ctypes.c_int
+        lib.or_group_dist.argtypes = [I64, i32p, i32p, i32p, I32, i32p]
+        lib.or_farness.restype = I64
+        lib.or_farness.argtypes = [I64, i32p, i32p, i32p, I32]
+        lib.or_farness_all.restype = ctypes.c_int
+        lib.or_farness_all.argtypes = [I64, i32p, i32p, i64p]
+        lib.or_gain.restype = I64
+        lib.or_gain.argtypes = [I64, i32p, i32p, i32p, I32]
+        lib.or_gains.restype = ctypes.c_int
+        lib.or_gains.argtypes = [I64, i32p, i32p, i32p, i32p, I64, i64p]
+        lib.or_greedy.restype = ctypes.c_int
+        lib.or_greedy.argtypes = [I64, i32p, i32p, I32, i32p, i64p, ctypes.c_void_p]
+        lib.or_greedypp.restype = ctypes.c_int
+        lib.or_greedypp.argtypes = [I64, i32p, i32p, I32, I32, i32p, i64p, i64p, i64p]
+        lib.or_pruned_stats.restype = ctypes.c_int
+        lib.or_pruned_stats.argtypes = [I64, i32p, i32p, i32p, i32p, I64, i64p, i64p, i64p]
+        lib.or_num_threads.restype = ctypes.c_int
+        lib.or_num_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _csr(g):
+    return (int(g.n), np.ascontiguousarray(g.row_ptr, dtype=np.int32),
+            np.ascontiguousarray(g.col_idx, dtype=np.int32))
+
+
+def _check(rc):
+    if rc == OR_EDISCONNECTED:
+        raise OracleError("graph is disconnected")
+    if rc == OR_EINVARIANT:
+        raise OracleError("greedy invariant violated")
+    if rc != OR_OK:
+        raise OracleError("oracle error %d" % rc)
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
+
+
+def bfs(g, src: int) -> np.ndarray:
+    """d(src, w) for all w (-1 if unreachable)."""
+    n, rp, ci = _csr(g)
+    d = np.empty(n, dtype=np.int32)
+    q = np.empty(n, dtype=np.int32)
+    _load().or_bfs(n, rp, ci, int(src), d, q)
+    return d
+
+
+def group_dist(g, S) -> np.ndarray:
+    """d(w, S) = min_{s in S} d(w, s)."""
+    n, rp, ci = _csr(g)
+    S = np.ascontiguousarray(S, dtype=np.int32)
+    dS = np.empty(n, dtype=np.int32)
+    _check(_load().or_group_dist(n, rp, ci, S, int(S.shape[0]), dS))
+    return dS
+
+
+def farness(g, S) -> int:
+    """Integer group farness F(S) = sum_w d(S, w)."""
+    n, rp, ci = _csr(g)
+    S = np.ascontiguousarray(S, dtype=np.int32)
+    F = int(_load().or_farness(n, rp, ci, S, int(S.shape[0])))
+    if F < 0:
+        raise OracleError("bad group or disconnected graph")
+    return F
+
+
+def farness_all(g) -> np.ndarray:
+    """F({v}) for every node v."""
+    n, rp, ci = _csr(g)
+    F = np.empty(n, dtype=np.int64)
+    _check(_load().or_farness_all(n, rp, ci, F))
+    return F
+
+
+def gain(g, dS, v: int) -> int:
+    """g(v,S) = F(S) - F(S u {v}) by a full BFS from v."""
+    n, rp, ci = _csr(g)
+    return int(_load().or_gain(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), int(v)))
+
+
+def gains(g, dS, cand) -> np.ndarray:
+    n, rp, ci = _csr(g)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    out = np.empty(cand.shape[0], dtype=np.int64)
+    _check(_load().or_gains(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), cand,
+                            int(cand.shape[0]), out))
+    return out
+
+
+def greedy(g, k: int, with_gains: bool = False):
+    """Tier A plain greedy.  Returns (group, F) or (group, F, gains[(k-1), n])."""
+    n, rp, ci = _csr(g)
+    group = np.empty(k, dtype=np.int32)
+    F = np.empty(k, dtype=np.int64)
+    G = np.empty((max(k - 1, 1), n), dtype=np.int64) if with_gains else None
+    ptr = G.ctypes.data_as(ctypes.c_void_p) if with_gains else None
+    _check(_load().or_greedy(n, rp, ci, int(k), group, F, ptr))
+    if with_gains:
+        return group, F, G[: k - 1]
+    return group, F
+
+
+def greedypp(g, k: int, block: int = 64):
+    """Tier B CPU Greedy++.  Returns (group, F, evals per round, edges per round)."""
+    n, rp, ci = _csr(g)
+    group = np.empty(k, dtype=np.int32)
+    F = np.empty(k, dtype=np.int64)
+    ev = np.zeros(k, dtype=np.int64)
+    ed = np.zeros(k, dtype=np.int64)
+    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), group, F, ev, ed))
+    return group, F, ev, ed
+
+
+def pruned_stats(g, dS, cand):
+    """Per-candidate (gain, |V(v)|, sum_{w in V(v)} deg w) by pruned BFS."""
+    n, rp, ci = _csr(g)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    c = int(cand.shape[0])
+    gg = np.empty(c, dtype=np.int64)
+    vv = np.empty(c, dtype=np.int64)
+    ee = np.empty(c, dtype=np.int64)
+    _check(_load().or_pruned_stats(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), cand, c,
+                                   gg, vv, ee))
+    return gg, vv, ee

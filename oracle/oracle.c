@@ -1,0 +1,479 @@
+/*
+ * CPU oracle for group-closeness maximisation (Bergamini, Gonser, Meyerhenke,
+ * "Scaling up Group Closeness Maximization").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; it shares no code, header or table with the GPU path.
+ * Only the tests, the smoke check and the benchmark's CPU baseline use it.
+ *
+ * Everything is integer.  F(S) denotes the integer group farness
+ * sum_{w in V} d(S,w); it is n times the paper's f(S) = 1/c(S) with
+ * c(S) = n / sum_{v notin S} d(S,v) (Section 2), and it is the objective of
+ * the ILP form in Section 5.  The marginal gain of v is
+ * g(v,S) = F(S) - F(S u {v}) >= 0, i.e. minus n times the paper's
+ * Delta(v,S) of Section 4.2.
+ *
+ * Tier A  (or_greedy): the plain greedy of Section 3.2, computed from the
+ *   definition: every round recomputes F(S u {v}) for every v not in S with a
+ *   full BFS from v (Section 2: SSSP is BFS on unweighted graphs), then picks
+ *   the minimum.  Ties go to the smallest node id.
+ * Tier B  (or_greedypp): Greedy++ of Section 4, i.e. the memory-efficient
+ *   greedy (Algorithm "mem-greedy") with the pruned SSSP of Section 4.1 and
+ *   the supermodularity skip of Section 4.2; the first node comes from
+ *   top-k closeness with BFScut (Section 3.1, Algorithm "topk"), k = 1.
+ *   It is a second, independent route used where tier A is too slow, and the
+ *   tests show it equal to tier A.
+ *
+ * Readings of the paper taken here (all also listed in the design notes):
+ *   - ties between equal gains go to the smallest node id;
+ *   - the skip test of Section 4.2 compares (stale gain, -id) lexicographically
+ *     with the best (gain, -id) found so far in the round, so the result equals
+ *     tier A for any candidate order;
+ *   - the candidate scan order of the while-loop is ascending node id.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_EDISCONNECTED -3
+#define OR_EINVAL -1
+#define OR_EINVARIANT -100
+
+/* ------------------------------------------------------------------ BFS --- */
+
+/*
+ * Plain FIFO breadth-first search from `src` (Section 2: on unweighted graphs
+ * the shortest-path distance d(src, w) is the BFS level of w).
+ * dist[w] = d(src,w), or -1 when w is unreachable.  Returns #reached.
+ */
+int64_t or_bfs(int64_t n, const int32_t *rp, const int32_t *ci, int32_t src, int32_t *dist,
+               int32_t *queue) {
+    for (int64_t w = 0; w < n; ++w) dist[w] = -1;
+    int64_t head = 0, tail = 0;
+    dist[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        int32_t x = queue[head++];
+        for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
+            int32_t y = ci[e];
+            if (dist[y] < 0) {
+                dist[y] = dist[x] + 1;
+                queue[tail++] = y;
+            }
+        }
+    }
+    return tail;
+}
+
+/* d(w,S) = min_{s in S} d(w,s)  (Section 2), one BFS per member of S. */
+int or_group_dist(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *S, int32_t ns,
+                  int32_t *dS) {
+    if (ns < 1) return OR_EINVAL;
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int rc = OR_OK;
+    for (int32_t i = 0; i < ns && rc == OR_OK; ++i) {
+        if (S[i] < 0 || S[i] >= n) { rc = OR_EINVAL; break; }
+        if (or_bfs(n, rp, ci, S[i], d, q) != n) { rc = OR_EDISCONNECTED; break; }
+        for (int64_t w = 0; w < n; ++w)
+            if (i == 0 || d[w] < dS[w]) dS[w] = d[w];
+    }
+    free(d); free(q);
+    return rc;
+}
+
+/* F(S) = sum_w d(S,w); returns -1 on error. */
+int64_t or_farness(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *S, int32_t ns) {
+    int32_t *dS = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t F = -1;
+    if (or_group_dist(n, rp, ci, S, ns, dS) == OR_OK) {
+        F = 0;
+        for (int64_t w = 0; w < n; ++w) F += dS[w];
+    }
+    free(dS);
+    return F;
+}
+
+/* F({v}) for every v: n full BFS (the numerator-free farness behind c(v), Section 2). */
+int or_farness_all(int64_t n, const int32_t *rp, const int32_t *ci, int64_t *F) {
+    int rc = OR_OK;
+#pragma omp parallel
+    {
+        int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t v = 0; v < n; ++v) {
+            int64_t r = or_bfs(n, rp, ci, (int32_t)v, d, q);
+            int64_t s = 0;
+            for (int64_t w = 0; w < n; ++w) s += d[w];
+            F[v] = s;
+            if (r != n) {
+#pragma omp atomic write
+                rc = OR_EDISCONNECTED;
+            }
+        }
+        free(d); free(q);
+    }
+    return rc;
+}
+
+/*
+ * g(v,S) = F(S) - F(S u {v}) = sum_w (d_S[w] - min(d_S[w], d(v,w)))
+ * with a full BFS from v (the sum that Algorithm "mem-greedy" forms after its
+ * SSSP from u, written as a difference).
+ */
+int64_t or_gain(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *dS, int32_t v) {
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    or_bfs(n, rp, ci, v, d, q);
+    int64_t g = 0;
+    for (int64_t w = 0; w < n; ++w) {
+        int32_t m = d[w] < dS[w] ? d[w] : dS[w];
+        g += (int64_t)(dS[w] - m);
+    }
+    free(d); free(q);
+    return g;
+}
+
+/* gains for a list of candidates (parallel over candidates), full BFS each */
+int or_gains(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *dS, const int32_t *cand,
+             int64_t count, int64_t *gain) {
+#pragma omp parallel
+    {
+        int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < count; ++i) {
+            or_bfs(n, rp, ci, cand[i], d, q);
+            int64_t g = 0;
+            for (int64_t w = 0; w < n; ++w) {
+                int32_t m = d[w] < dS[w] ? d[w] : dS[w];
+                g += (int64_t)(dS[w] - m);
+            }
+            gain[i] = g;
+        }
+        free(d); free(q);
+    }
+    return OR_OK;
+}
+
+/* --------------------------------------------------------------- tier A --- */
+
+/*
+ * Plain greedy (Section 3.2, with the memory-efficient d_S vector of Section 4
+ * but no pruning and no skipping):
+ *   s_1 = argmin_v F({v});
+ *   s_{i+1} = argmin_{v notin S_i} F(S_i u {v});  ties -> smallest id.
+ * Outputs group[0..k-1] in pick order and Fout[i] = F(S_{i+1}).
+ * gains, when not NULL, receives (k-1) rows of n entries: row r holds
+ * g(v, S_{r+1}) for v notin S_{r+1} and -1 for members.
+ * The loop asserts the invariants that follow from the definitions and from
+ * the supermodularity lemma of Section 3.2; a violation returns OR_EINVARIANT.
+ */
+int or_greedy(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t *group,
+              int64_t *Fout, int64_t *gains) {
+    if (k < 1 || k > n) return OR_EINVAL;
+    int64_t *Fv = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *dS = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *dsnew = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t *inS = (uint8_t *)calloc((size_t)n, 1);
+    int rc = or_farness_all(n, rp, ci, Fv);
+    if (rc != OR_OK) goto done;
+    {
+        int32_t s = 0;
+        for (int64_t v = 1; v < n; ++v)
+            if (Fv[v] < Fv[s]) s = (int32_t)v;
+        group[0] = s;
+        inS[s] = 1;
+        or_bfs(n, rp, ci, s, dS, q);
+        int64_t F = Fv[s];
+        Fout[0] = F;
+        for (int64_t v = 0; v < n; ++v) prev[v] = INT64_MAX;
+        for (int32_t i = 1; i < k; ++i) {
+            int bad = 0;
+#pragma omp parallel
+            {
+                int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+                int32_t *qq = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+#pragma omp for schedule(dynamic, 4)
+                for (int64_t v = 0; v < n; ++v) {
+                    if (inS[v]) { Fv[v] = INT64_MAX; continue; }
+                    or_bfs(n, rp, ci, (int32_t)v, d, qq);
+                    int64_t t = 0;
+                    for (int64_t w = 0; w < n; ++w) t += (d[w] < dS[w] ? d[w] : dS[w]);
+                    Fv[v] = t;
+                }
+                free(d); free(qq);
+            }
+            int32_t best = -1;
+            for (int64_t v = 0; v < n; ++v) {
+                if (inS[v]) continue;
+                int64_t g = F - Fv[v];
+                /* gains never increase between rounds (supermodularity lemma) */
+                if (g > prev[v]) bad = 1;
+                /* v itself moves from d_S[v] >= 1 to 0 */
+                if (g < dS[v] || dS[v] < 1) bad = 1;
+                prev[v] = g;
+                if (best < 0 || Fv[v] < Fv[best]) best = (int32_t)v;
+            }
+            if (gains) {
+                int64_t *row = gains + (int64_t)(i - 1) * n;
+                for (int64_t v = 0; v < n; ++v) row[v] = inS[v] ? -1 : F - Fv[v];
+            }
+            /* add the pick; d_S <- min(d_S, d(s,.)) (the update of Algorithm "mem-greedy") */
+            or_bfs(n, rp, ci, best, dsnew, q);
+            int64_t sum = 0;
+            for (int64_t w = 0; w < n; ++w) {
+                int32_t m = dsnew[w] < dS[w] ? dsnew[w] : dS[w];
+                if (m > dS[w]) bad = 1; /* d_S never increases */
+                dS[w] = m;
+                sum += m;
+            }
+            if (sum != Fv[best]) bad = 1;            /* F(S) == sum_w d_S[w] */
+            if (!(Fv[best] < F)) bad = 1;            /* strictly decreasing while |S| < n */
+            F = Fv[best];
+            group[i] = best;
+            inS[best] = 1;
+            Fout[i] = F;
+            if (bad) { rc = OR_EINVARIANT; goto done; }
+        }
+    }
+done:
+    free(Fv); free(prev); free(dS); free(dsnew); free(q); free(inS);
+    return rc;
+}
+
+/* --------------------------------------------------------------- tier B --- */
+
+/*
+ * Pruned BFS from u (Section 4.1): a node w reached at level l is counted and
+ * expanded only if l < d_S[w]; otherwise its whole BFS subtree cannot improve
+ * on S and is not entered.  Returns g(u,S) = sum over the counted w of
+ * (d_S[w] - l).  `mark` holds per-thread visit stamps.
+ * *edges receives sum of deg(w) over counted w (the adjacency entries this
+ * search scans), *visited the number of counted nodes.
+ */
+static int64_t pruned_gain(const int32_t *rp, const int32_t *ci, const int32_t *dS, int32_t u,
+                           int32_t *lvl, int32_t *mark, int32_t stamp, int32_t *q, int64_t *edges,
+                           int64_t *visited) {
+    int64_t g = 0, e_cnt = 0, v_cnt = 0;
+    if (!(0 < dS[u])) { *edges = 0; *visited = 0; return 0; } /* u in S */
+    int64_t head = 0, tail = 0;
+    mark[u] = stamp; lvl[u] = 0; q[tail++] = u;
+    while (head < tail) {
+        int32_t x = q[head++];
+        g += dS[x] - lvl[x];
+        v_cnt += 1;
+        e_cnt += rp[x + 1] - rp[x];
+        for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
+            int32_t y = ci[e];
+            if (mark[y] == stamp) continue;
+            mark[y] = stamp;
+            int32_t l = lvl[x] + 1;
+            if (l < dS[y]) { lvl[y] = l; q[tail++] = y; }
+        }
+    }
+    *edges = e_cnt; *visited = v_cnt;
+    return g;
+}
+
+/* Full BFS from v with the BFScut lower bound of Section 3.1; returns F({v})
+ * or -1 when the bound proves (F({v}), v) cannot beat (bestF, bestId). */
+static int64_t bfscut(int64_t n, const int32_t *rp, const int32_t *ci, int32_t v, int64_t bestF,
+                      int32_t bestId, int32_t *lvl, int32_t *mark, int32_t stamp, int32_t *q) {
+    (void)lvl;
+    int64_t lo = 0, hi = 1, sum = 0;
+    mark[v] = stamp; q[0] = v;
+    for (int64_t d = 0; lo < hi; ++d) {
+        /* every node at distance <= d is in q[0..hi); the others are at >= d+1 */
+        int64_t lb = sum + (d + 1) * (n - hi);
+        if (bestId >= 0 && (lb > bestF || (lb == bestF && v > bestId))) return -1;
+        int64_t tail = hi;
+        for (int64_t i = lo; i < hi; ++i) {
+            int32_t x = q[i];
+            for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
+                int32_t y = ci[e];
+                if (mark[y] == stamp) continue;
+                mark[y] = stamp;
+                q[tail++] = y;
+            }
+        }
+        sum += (d + 1) * (tail - hi);
+        lo = hi; hi = tail;
+    }
+    if (hi != n) return -2;
+    return sum;
+}
+
+/*
+ * Greedy++ (Section 4): first node by top-k closeness (k = 1) visiting nodes
+ * by decreasing degree (ties: ascending id) with BFScut; then rounds of the
+ * lazy scan.  In each round candidates are taken in ascending id order;
+ * a candidate u is skipped when its gain from an earlier round (an upper
+ * bound by supermodularity) satisfies
+ *     ub[u] < best_gain  or  (ub[u] == best_gain and u > best_id).
+ * Non-skipped candidates are evaluated with pruned BFS in blocks of `block`
+ * (parallel inside a block); the best is updated between blocks, so the
+ * evaluation counts do not depend on thread timing.  In the first round
+ * after s_1 no bound exists and every candidate is evaluated.
+ * evals[i] (i = 1..k-1) receives the number of evaluations in round i;
+ * edges (nullable) receives, per round, the summed adjacency entries scanned.
+ */
+int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t block,
+                int32_t *group, int64_t *Fout, int64_t *evals, int64_t *edges) {
+    if (k < 1 || k > n || block < 1) return OR_EINVAL;
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = omp_get_max_threads();
+#endif
+    int32_t **lvl = (int32_t **)malloc(sizeof(void *) * (size_t)nthr);
+    int32_t **mark = (int32_t **)malloc(sizeof(void *) * (size_t)nthr);
+    int32_t **qs = (int32_t **)malloc(sizeof(void *) * (size_t)nthr);
+    int32_t *stamps = (int32_t *)calloc((size_t)nthr, sizeof(int32_t));
+    for (int t = 0; t < nthr; ++t) {
+        lvl[t] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        mark[t] = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        qs[t] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    }
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *dS = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *dnew = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *ub = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *batch = (int32_t *)malloc(sizeof(int32_t) * (size_t)block);
+    int64_t *bg = (int64_t *)malloc(sizeof(int64_t) * (size_t)block);
+    int64_t *be = (int64_t *)malloc(sizeof(int64_t) * (size_t)block);
+    int rc = OR_OK;
+
+    /* first node: decreasing degree, BFScut (sequential) */
+    for (int64_t v = 0; v < n; ++v) order[v] = (int32_t)v;
+    {
+        /* counting sort by degree, descending, stable in id */
+        int32_t maxd = 0;
+        for (int64_t v = 0; v < n; ++v) if (rp[v + 1] - rp[v] > maxd) maxd = rp[v + 1] - rp[v];
+        int64_t *cnt = (int64_t *)calloc((size_t)maxd + 2, sizeof(int64_t));
+        for (int64_t v = 0; v < n; ++v) cnt[maxd - (rp[v + 1] - rp[v]) + 1]++;
+        for (int32_t d = 0; d <= maxd; ++d) cnt[d + 1] += cnt[d];
+        for (int64_t v = 0; v < n; ++v) order[cnt[maxd - (rp[v + 1] - rp[v])]++] = (int32_t)v;
+        free(cnt);
+    }
+    int64_t bestF = -1;
+    int32_t bestId = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t v = order[i];
+        int32_t st = ++stamps[0];
+        int64_t F = bfscut(n, rp, ci, v, bestF, bestId, lvl[0], mark[0], st, qs[0]);
+        if (F == -2) { rc = OR_EDISCONNECTED; goto done; }
+        if (F < 0) continue;
+        if (bestId < 0 || F < bestF || (F == bestF && v < bestId)) { bestF = F; bestId = v; }
+    }
+    group[0] = bestId;
+    Fout[0] = bestF;
+    or_bfs(n, rp, ci, bestId, dS, qs[0]);
+    for (int64_t v = 0; v < n; ++v) ub[v] = INT64_MAX;
+    if (evals) evals[0] = 0;
+    if (edges) edges[0] = 0;
+    int64_t F = bestF;
+    for (int32_t r = 1; r < k; ++r) {
+        int64_t bgain = -1;
+        int32_t bid = -1;
+        int64_t pos = 0, nev = 0, ned = 0;
+        for (;;) {
+            int32_t nb = 0;
+            while (pos < n && nb < block) {
+                int32_t u = (int32_t)pos++;
+                if (dS[u] == 0) continue; /* u in S */
+                if (bid >= 0 && (ub[u] < bgain || (ub[u] == bgain && u > bid))) continue;
+                batch[nb++] = u;
+            }
+            if (nb == 0) break;
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int32_t j = 0; j < nb; ++j) {
+                int t = 0;
+#ifdef _OPENMP
+                t = omp_get_thread_num();
+#endif
+                int64_t vis;
+                int32_t st = ++stamps[t];
+                bg[j] = pruned_gain(rp, ci, dS, batch[j], lvl[t], mark[t], st, qs[t], &be[j], &vis);
+            }
+            for (int32_t j = 0; j < nb; ++j) {
+                int32_t u = batch[j];
+                ub[u] = bg[j];
+                ned += be[j];
+                if (bid < 0 || bg[j] > bgain || (bg[j] == bgain && u < bid)) { bgain = bg[j]; bid = u; }
+            }
+            nev += nb;
+        }
+        if (evals) evals[r] = nev;
+        if (edges) edges[r] = ned;
+        /* pick and update d_S by a pruned BFS from the pick (Section 4.1: only
+         * nodes with d(s,w) < d_S[w] change) */
+        group[r] = bid;
+        {
+            int32_t st = ++stamps[0];
+            int32_t *q = qs[0], *mk = mark[0], *lv = lvl[0];
+            int64_t head = 0, tail = 0;
+            mk[bid] = st; lv[bid] = 0; q[tail++] = bid;
+            while (head < tail) {
+                int32_t x = q[head++];
+                dnew[x] = lv[x];
+                for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
+                    int32_t y = ci[e];
+                    if (mk[y] == st) continue;
+                    mk[y] = st;
+                    if (lv[x] + 1 < dS[y]) { lv[y] = lv[x] + 1; q[tail++] = y; }
+                }
+            }
+            for (int64_t i = 0; i < tail; ++i) dS[q[i]] = dnew[q[i]];
+        }
+        F -= bgain;
+        Fout[r] = F;
+    }
+done:
+    for (int t = 0; t < nthr; ++t) { free(lvl[t]); free(mark[t]); free(qs[t]); }
+    free(lvl); free(mark); free(qs); free(stamps);
+    free(order); free(dS); free(dnew); free(ub); free(batch); free(bg); free(be);
+    return rc;
+}
+
+/*
+ * Pruned-BFS statistics for a candidate list under a given d_S: per candidate
+ * the gain, the number of counted nodes |V(v)| and the adjacency entries
+ * scanned sum_{w in V(v)} deg(w).  Used to count algorithmic work.
+ */
+int or_pruned_stats(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *dS,
+                    const int32_t *cand, int64_t count, int64_t *gain, int64_t *visited,
+                    int64_t *edges) {
+#pragma omp parallel
+    {
+        int32_t *lv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *mk = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t st = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < count; ++i) {
+            int64_t e, v;
+            gain[i] = pruned_gain(rp, ci, dS, cand[i], lv, mk, ++st, q, &e, &v);
+            if (visited) visited[i] = v;
+            if (edges) edges[i] = e;
+        }
+        free(lv); free(mk); free(q);
+    }
+    return OR_OK;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,282 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here uses the GPU library.  Each test pins a part of the oracle to
+something other than the oracle itself:
+  * the printed K5 example of Section 3.2 (tests/golden/k5_example.json);
+  * closed forms of F({v}) and of greedy sequences on paths, cycles, stars,
+    complete and complete bipartite graphs, from the definitions of Section 2;
+  * Floyd-Warshall distances, brute force over all k-subsets and the matrix
+    form of the greedy of Chen et al. (Section 3.2) on tiny graphs;
+  * the bit-vector identity of the theorem of Section 4.3;
+  * the supermodularity lemma of Section 3.2, exhaustively on tiny graphs;
+  * tier B (pruned, lazy Greedy++) against tier A (plain greedy).
+"""
+import itertools
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import small
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ------------------------------------------------------------ printed values
+
+def test_k5_printed_example():
+    with open(os.path.join(HERE, "golden", "k5_example.json")) as f:
+        gold = json.load(f)
+    g = graphgen.complete(5)
+    n = g.n
+    vals = {}
+    for row in gold["closeness"]:
+        S = row["S"]
+        F = oracle.farness(g, S)
+        c = Fraction(n, F)  # c(S) = n / sum_{v notin S} d(S,v); members contribute 0
+        assert c == Fraction(row["c_num"], row["c_den"]), S
+        vals[tuple(S)] = c
+    d1 = vals[(0, 1, 3)] - vals[(0, 1)]
+    d2 = vals[(0, 1, 2, 3)] - vals[(0, 1, 2)]
+    assert d1 == Fraction(*gold["differences"]["c(S+v)-c(S)"])
+    assert d2 == Fraction(*gold["differences"]["c(T+v)-c(T)"])
+    assert d1 < d2  # closeness is not submodular
+    # farness is supermodular on the same sets (Section 3.2 lemma)
+    fS = oracle.farness(g, [0, 1, 3]) - oracle.farness(g, [0, 1])
+    fT = oracle.farness(g, [0, 1, 2, 3]) - oracle.farness(g, [0, 1, 2])
+    assert fS <= fT
+
+
+# --------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 10, 31])
+def test_path_single_farness(n):
+    g = graphgen.path(n)
+    F = oracle.farness_all(g)
+    exp = np.array([v * (v + 1) // 2 + (n - 1 - v) * (n - v) // 2 for v in range(n)])
+    assert np.array_equal(F, exp)
+    grp, Fs = oracle.greedy(g, 1)
+    assert int(grp[0]) == (n - 1) // 2
+    assert int(Fs[0]) == n * n // 4
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 8, 11])
+def test_cycle_single_farness(n):
+    g = graphgen.cycle(n)
+    F = oracle.farness_all(g)
+    assert np.all(F == n * n // 4)
+    grp, _ = oracle.greedy(g, 1)
+    assert int(grp[0]) == 0
+
+
+@pytest.mark.parametrize("n", [3, 5, 9])
+def test_star(n):
+    g = graphgen.star(n)
+    F = oracle.farness_all(g)
+    assert int(F[0]) == n - 1
+    assert np.all(F[1:] == 2 * n - 3)
+    for k in range(1, n + 1):
+        grp, Fs = oracle.greedy(g, k)
+        assert grp.tolist() == list(range(k))
+        assert Fs.tolist() == [n - i for i in range(1, k + 1)]
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_complete(n):
+    g = graphgen.complete(n)
+    for k in range(1, n + 1):
+        grp, Fs = oracle.greedy(g, k)
+        assert grp.tolist() == list(range(k))
+        assert Fs.tolist() == [n - i for i in range(1, k + 1)]
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 3), (3, 5), (4, 4)])
+def test_complete_bipartite(a, b):
+    g = graphgen.complete_bipartite(a, b)
+    F = oracle.farness_all(g)
+    assert np.all(F[:a] == b + 2 * (a - 1))
+    assert np.all(F[a:] == a + 2 * (b - 1))
+
+
+def _h(L):
+    """Farness of L path nodes strictly between two group members."""
+    return (L + 1) * (L + 1) // 4
+
+
+def _path_F(n, S):
+    S = sorted(S)
+    F = S[0] * (S[0] + 1) // 2  # end segment before the first member
+    L = n - 1 - S[-1]
+    F += L * (L + 1) // 2
+    for a, b in zip(S, S[1:]):
+        F += _h(b - a - 1)
+    return F
+
+
+def _cycle_F(n, S):
+    S = sorted(S)
+    F = 0
+    for a, b in zip(S, S[1:] + [S[0] + n]):
+        F += _h(b - a - 1)
+    return F
+
+
+def _segment_greedy(n, k, Ffun):
+    S = []
+    out = []
+    for _ in range(k):
+        best = None
+        for v in range(n):
+            if v in S:
+                continue
+            f = Ffun(n, S + [v])
+            if best is None or f < best[0]:
+                best = (f, v)
+        S.append(best[1])
+        out.append(best[0])
+    return S, out
+
+
+@pytest.mark.parametrize("n,k", [(9, 4), (20, 6), (33, 7)])
+def test_path_greedy_segment_model(n, k):
+    g = graphgen.path(n)
+    grp, Fs = oracle.greedy(g, k)
+    S, F = _segment_greedy(n, k, _path_F)
+    assert grp.tolist() == S
+    assert Fs.tolist() == F
+
+
+@pytest.mark.parametrize("n,k", [(10, 4), (17, 5), (24, 6)])
+def test_cycle_greedy_segment_model(n, k):
+    g = graphgen.cycle(n)
+    grp, Fs = oracle.greedy(g, k)
+    S, F = _segment_greedy(n, k, _cycle_F)
+    assert grp.tolist() == S
+    assert Fs.tolist() == F
+    # two members at 0 and v: F = h(v-1) + h(n-v-1)
+    for v in range(1, n):
+        assert oracle.farness(g, [0, v]) == _h(v - 1) + _h(n - v - 1)
+
+
+# ------------------------------------------------ brute force on tiny graphs
+
+TINY = [(n, p, s) for n, p, s in [(5, 0.3, 1), (6, 0.4, 2), (7, 0.2, 3), (8, 0.3, 4), (9, 0.25, 5),
+                                   (10, 0.2, 6), (11, 0.3, 7), (12, 0.15, 8), (12, 0.4, 9)]]
+
+
+@pytest.mark.parametrize("n,p,seed", TINY)
+def test_bfs_and_farness_vs_floyd_warshall(n, p, seed):
+    g = graphgen.gnp_connected(n, p, seed)
+    D = small.floyd_warshall(g)
+    for v in range(n):
+        assert np.array_equal(oracle.bfs(g, v), D[v])
+    rng = np.random.default_rng(seed)
+    for _ in range(20):
+        k = int(rng.integers(1, n + 1))
+        S = rng.choice(n, size=k, replace=False).tolist()
+        assert oracle.farness(g, S) == small.farness(D, S)
+        assert np.array_equal(oracle.group_dist(g, S), D[S].min(axis=0))
+
+
+@pytest.mark.parametrize("n,p,seed", TINY)
+def test_greedy_vs_matrix_form_and_optimum(n, p, seed):
+    g = graphgen.gnp_connected(n, p, seed)
+    D = small.floyd_warshall(g)
+    for k in range(1, n + 1):
+        grp, Fs = oracle.greedy(g, k)
+        S, F = small.greedy_matrix(D, k)
+        assert grp.tolist() == S
+        assert Fs.tolist() == F
+        if k <= 5:
+            opt, _ = small.brute_force_opt(D, k)
+            assert opt <= int(Fs[-1])
+            if k == 1:
+                assert opt == int(Fs[0])
+
+
+@pytest.mark.parametrize("n,p,seed", TINY)
+def test_gains_theorem_identity(n, p, seed):
+    g = graphgen.gnp_connected(n, p, seed)
+    D = small.floyd_warshall(g)
+    bits = small.bit_vectors(g, n)
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(6):
+        k = int(rng.integers(1, n))
+        S = rng.choice(n, size=k, replace=False).tolist()
+        dS = oracle.group_dist(g, S)
+        for u in range(n):
+            gu = oracle.gain(g, dS, u)
+            assert gu == small.gain_def(D, S, u)
+            assert gu == small.theorem_gain(bits, S, u)
+            gp, _, _ = oracle.pruned_stats(g, dS, [u])
+            assert int(gp[0]) == gu
+
+
+@pytest.mark.parametrize("n,p,seed", [(6, 0.3, 11), (7, 0.35, 12), (7, 0.2, 13)])
+def test_supermodularity_exhaustive(n, p, seed):
+    """g(v,S) >= g(v,T) for all S subset T, v notin T (Section 3.2 lemma)."""
+    g = graphgen.gnp_connected(n, p, seed)
+    subsets = [list(c) for r in range(1, n) for c in itertools.combinations(range(n), r)]
+    gain = {}
+    for S in subsets:
+        dS = oracle.group_dist(g, S)
+        gs = oracle.gains(g, dS, np.arange(n, dtype=np.int32))
+        for v in range(n):
+            gain[(tuple(S), v)] = int(gs[v])
+    for T in subsets:
+        Tset = set(T)
+        for r in range(1, len(T) + 1):
+            for S in itertools.combinations(T, r):
+                for v in range(n):
+                    if v in Tset:
+                        continue
+                    assert gain[(tuple(S), v)] >= gain[(tuple(T), v)]
+
+
+@pytest.mark.parametrize("n,p,seed", TINY[:5])
+def test_tier_a_gain_rows(n, p, seed):
+    g = graphgen.gnp_connected(n, p, seed)
+    D = small.floyd_warshall(g)
+    k = min(n, 5)
+    grp, Fs, G = oracle.greedy(g, k, with_gains=True)
+    for r in range(k - 1):
+        S = grp[: r + 1].tolist()
+        for v in range(n):
+            if v in S:
+                assert G[r, v] == -1
+            else:
+                assert G[r, v] == small.gain_def(D, S, v)
+
+
+# -------------------------------------------------------- tier B vs tier A
+
+TIERB = [lambda: graphgen.ba(400, 3, 21), lambda: graphgen.ba(300, 1, 22),
+         lambda: graphgen.grid(12, 15, 23), lambda: graphgen.path(40), lambda: graphgen.cycle(33),
+         lambda: graphgen.gnp_connected(60, 0.05, 24), lambda: graphgen.star(30),
+         lambda: graphgen.complete_bipartite(4, 9)]
+
+
+@pytest.mark.parametrize("mk", TIERB)
+@pytest.mark.parametrize("block", [1, 7, 64])
+def test_tier_b_equals_tier_a(mk, block):
+    g = mk()
+    k = min(g.n, 12)
+    grp_a, F_a = oracle.greedy(g, k)
+    grp_b, F_b, ev, ed = oracle.greedypp(g, k, block=block)
+    assert grp_b.tolist() == grp_a.tolist()
+    assert F_b.tolist() == F_a.tolist()
+    if k > 1:
+        assert ev[1] == g.n - 1          # no bounds in the first round after s_1
+        assert np.all(ev[2:] <= g.n - np.arange(2, k))
+
+
+def test_tier_b_equals_tier_a_ba2000():
+    g = graphgen.workload("ba2000")
+    grp_a, F_a = oracle.greedy(g, 10)
+    grp_b, F_b, _, _ = oracle.greedypp(g, 10)
+    assert grp_a.tolist() == grp_b.tolist()
+    assert F_a.tolist() == F_b.tolist()
