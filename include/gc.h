@@ -1,0 +1,226 @@
+/*
+ * gc.h -- C ABI of the MI355X group-closeness library (libgc.so).
+ *
+ * Method: Greedy++ for group closeness maximisation (Bergamini, Gonser,
+ * Meyerhenke, "Scaling up Group Closeness Maximization").  On a connected,
+ * undirected, unweighted graph G = (V, E) (Section 2) the library picks k nodes
+ * greedily, each time adding the node with the largest marginal gain
+ *     g(v, S) = F(S) - F(S u {v}),   F(S) = sum_{w in V} d(S, w),
+ * where d(S, w) = min_{s in S} d(s, w) (Section 2).  F is the integer group
+ * farness: n times the paper's f(S) = 1/c(S) with c(S) = n / sum d(S, v)
+ * (Section 2), and the objective of the ILP of Section 5.  Gains are computed
+ * exactly by BFS from v pruned to nodes w with d(v, w) < d(S, w) (Section 4.1);
+ * gains of earlier rounds are upper bounds that let the greedy loop skip
+ * candidates (Section 4.2, valid by the supermodularity lemma of Section 3.2).
+ *
+ * Conventions for every function
+ *  - Return value: GC_OK (0) or a negative gc_status.  On error no output is
+ *    written; gc_last_error() gives a message (thread-local).
+ *  - d_* arguments are device pointers (HIP global memory) owned by the caller;
+ *    h_* arguments are host pointers owned by the caller.  The library never
+ *    allocates device memory: all device scratch lives in a caller-supplied
+ *    workspace of at least gc_workspace_size() bytes that was prepared once by
+ *    gc_workspace_init().  Every call returns the workspace to its prepared
+ *    state, so it can be reused by later calls on the same stream.  Calls that
+ *    share one workspace must not overlap in time (use one stream).
+ *  - Work is enqueued on `stream`.  Calls with h_* outputs synchronise the
+ *    stream before returning; calls with only d_* outputs are asynchronous.
+ *  - Distances d(S, .) are stored as uint8 (dist_bytes = 1, INF = 255) or
+ *    uint16 (dist_bytes = 2, INF = 65535).  A distance array that is INF
+ *    everywhere stands for S = {} .
+ *  - Node ids are int32 in [0, n); ties between equal gains or equal farness
+ *    always go to the smallest node id.
+ */
+#ifndef GC_H
+#define GC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gc_status {
+    GC_OK = 0,
+    GC_EINVAL = -1,        /* bad argument, malformed CSR, k or node out of range */
+    GC_ENOTSYM = -2,       /* adjacency is not symmetric (graph not undirected) */
+    GC_EDISCONNECTED = -3, /* graph has more than one connected component */
+    GC_ERANGE = -4,        /* a distance does not fit the chosen dist_bytes */
+    GC_EWORKSPACE = -5,    /* workspace missing, too small or not initialised */
+    GC_ENOMEM = -6,        /* host allocation failed */
+    GC_EDEVICE = -7        /* a HIP runtime call failed */
+} gc_status;
+
+/* gc_load_csr flags */
+#define GC_VALIDATE 0x1u /* check the CSR contract (default; strongly advised) */
+
+/* candidate orders for the lazy greedy loop (gc_opts.order) */
+#define GC_ORDER_PLAIN 0   /* ascending node id, the scan of the paper's while-loop */
+#define GC_ORDER_CELF 1    /* stale gain descending, then id ascending */
+#define GC_ORDER_LEARNED 2 /* MLP-predicted gain (capped by the stale gain) descending */
+
+typedef struct gc_graph gc_graph; /* opaque; borrows the caller's device CSR */
+
+/*
+ * Options for gc_greedy_group.  Zero-initialise and set what you need;
+ * a NULL opts pointer means all defaults (plain order, width 64, block 64).
+ */
+typedef struct gc_opts {
+    int32_t order;          /* GC_ORDER_* */
+    int32_t bitset_width;   /* sources per bit-parallel BFS: 64 (0 = default 64) */
+    int32_t block;          /* rounds >= 2: candidates evaluated between two
+                               threshold updates (0 = bitset_width) */
+    int32_t nprefix;        /* resume: the first nprefix picks are given */
+    const int32_t *h_prefix;/* host, nprefix ids (a previous run's pick order) */
+    const void *d_mlp;      /* GC_ORDER_LEARNED: device MLP parameters, layout of
+                               gc_mlp_param_count(); NULL otherwise */
+    int32_t debug_checks;   /* 1: re-check F(S) == sum_w d(S,w) after every pick */
+    int32_t reserved;
+    /* optional logging of every exact evaluation (host buffers, may be NULL):
+       round, node, gain and the 8 MLP features at evaluation time */
+    int64_t log_capacity;
+    int32_t *h_log_round;
+    int32_t *h_log_node;
+    int64_t *h_log_gain;
+    float *h_log_feat;      /* log_capacity x 8 */
+    int64_t *h_log_count;   /* out: entries written (may exceed capacity: the rest dropped) */
+} gc_opts;
+
+/* Counters filled by gc_greedy_group (all optional). */
+typedef struct gc_stats {
+    int64_t evals_total;    /* exact gain evaluations, all rounds */
+    int64_t evals_round1;   /* evaluations in the first round after s_1 (n-1) */
+    int64_t evals_later;    /* evaluations in rounds >= 2 */
+    int64_t edges_alg;      /* sum over evaluations of sum_{w in V(v)} deg(w) */
+    int64_t visited;        /* sum over evaluations of |V(v)| */
+    int64_t gain_launches;  /* gain-kernel launches */
+    int64_t closest_sources;/* sources that entered a closeness BFS in gc_closest_node */
+    int32_t dist_bytes;     /* width chosen for d(S,.) */
+    int32_t ecc_s1;         /* eccentricity of the first pick */
+    double ms_total;        /* wall time of the call (host clock) */
+    double ms_closest;      /* finding s_1 */
+    double ms_round1;       /* first gain round */
+    double ms_later;        /* gain rounds >= 2 incl. selection */
+    double ms_update;       /* d(S,.) updates */
+    double ms_mlp;          /* feature + MLP inference (learned order) */
+    int64_t *h_evals_per_round; /* optional, caller-owned, k entries */
+} gc_stats;
+
+/* ---------------------------------------------------------------- graph --- */
+
+/*
+ * gc_load_csr -- wrap a device CSR as a graph handle (Section 2: connected,
+ * undirected, unweighted G).
+ *   n          node count, 1 <= n < 2^31
+ *   nnz        entries of d_col_idx = 2|E| (each undirected edge stored twice)
+ *   d_row_ptr  device int32[n+1], d_row_ptr[0] = 0, d_row_ptr[n] = nnz
+ *   d_col_idx  device int32[nnz], each row strictly ascending
+ *   flags      GC_VALIDATE: copy the CSR to the host once and check it --
+ *              GC_EINVAL for a bad row_ptr, an id out of range, an unsorted
+ *              row, a self-loop or a duplicate; GC_ENOTSYM for a missing
+ *              reverse edge; GC_EDISCONNECTED if not connected.
+ *   stream     used for the copies
+ *   out        receives the handle (free with gc_free_graph)
+ * The handle borrows the two device arrays: they must stay valid and
+ * unchanged until gc_free_graph.  The handle may be used from several host
+ * threads at once if each uses its own workspace.
+ */
+int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                uint32_t flags, hipStream_t stream, gc_graph **out);
+void gc_free_graph(gc_graph *g);
+int32_t gc_graph_n(const gc_graph *g);
+int64_t gc_graph_nnz(const gc_graph *g);
+
+/* ------------------------------------------------------------ workspace --- */
+
+/*
+ * gc_workspace_size -- bytes of device workspace needed by every call below
+ * for graph g and the given bit-parallel width (64, or 0 for the default).
+ * GC_EINVAL for another width.
+ */
+int gc_workspace_size(const gc_graph *g, int32_t bitset_width, size_t *bytes);
+
+/*
+ * gc_workspace_init -- prepare a workspace of ws_bytes >= gc_workspace_size()
+ * bytes for graph g (zero-fills it and stamps a header).  Asynchronous on
+ * stream.  Needed once per (workspace, graph); the library's calls keep it
+ * prepared.  GC_EWORKSPACE if it is too small.
+ */
+int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------- operations --- */
+
+/*
+ * gc_closest_node -- s_1 = argmin_v F({v}), the node of maximum closeness
+ * c(v) = (n-1)/sum_w d(v,w) (Section 2), first line of the memory-efficient
+ * greedy (Appendix, Algorithm "mem-greedy").  Found as in top-k closeness with
+ * k = 1 (Section 3.1, Algorithm "topk"): sources visited by decreasing degree,
+ * each BFS cut as soon as a lower bound on its farness exceeds the best
+ * farness found.  Ties go to the smallest id.
+ *   h_node     host out: s_1
+ *   h_farness  host out: F({s_1})
+ * Synchronises the stream.
+ */
+int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                    int32_t *h_node, int64_t *h_farness);
+
+/*
+ * gc_update_dist -- add `node` to S: d(S,.) <- min(d(S,.), d(node,.))
+ * (Algorithm "mem-greedy", the update after each pick).  Done by BFS from
+ * node pruned to nodes w with d(node,w) < d(S,w), which leaves every other
+ * entry unchanged (Section 4.1).
+ *   d_dist      device uint8/uint16[n], in/out: d(S,.) -> d(S u {node},.);
+ *               all-INF means S = {} (then a full BFS is run)
+ *   dist_bytes  1 or 2 (GC_EINVAL otherwise)
+ *   d_farness   device int64, in/out: F(S) -> F(S u {node}); its input is
+ *               ignored when S = {}
+ * Errors: GC_EINVAL for node out of range; GC_ERANGE is reported by a later
+ * synchronising call if a distance reached INF (use dist_bytes = 2, or
+ * gc_greedy_group, which picks the width itself).
+ */
+int gc_update_dist(const gc_graph *g, int32_t node, void *d_dist, int32_t dist_bytes, void *d_ws,
+                   size_t ws_bytes, hipStream_t stream, int64_t *d_farness);
+
+/*
+ * gc_marginal_gains -- g(v,S) = F(S) - F(S u {v}) for count candidates
+ * (Section 4.1, pruned SSSP; the per-level counting view is the theorem of
+ * Section 4.3).  Candidates are processed in groups of bitset_width sources
+ * that share one bit-parallel BFS frontier.  A candidate already in S gets 0.
+ * Requires S != {} (d_dist finite everywhere).
+ *   d_dist      device uint8/uint16[n] = d(S,.)
+ *   d_cand      device int32[count], ids in [0,n) (duplicates allowed)
+ *   d_gain      device int64[count] out
+ *   d_edges     device int64[count] out or NULL: sum_{w in V(v)} deg(w)
+ *   d_visited   device int32[count] out or NULL: |V(v)|
+ * Asynchronous.  Candidate ids are not range-checked on the device; pass ids
+ * in [0, n).
+ */
+int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
+                      const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
+                      int32_t *d_visited, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * gc_greedy_group -- Greedy++ (Section 4): k picks, exactly the picks of the
+ * plain greedy of Section 3.2 with smallest-id ties, for every candidate order.
+ *   k           1 <= k <= n (GC_EINVAL otherwise)
+ *   opts        NULL or options (see gc_opts)
+ *   h_group     host out int32[k]: picks in order
+ *   h_farness   host out int64[k]: F(S_1), ..., F(S_k)
+ *   h_stats     host out or NULL
+ * Synchronises the stream.
+ */
+int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts, void *d_ws,
+                    size_t ws_bytes, hipStream_t stream, int32_t *h_group, int64_t *h_farness,
+                    gc_stats *h_stats);
+
+/* ----------------------------------------------------------------- misc --- */
+
+const char *gc_strerror(int code);
+const char *gc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GC_H */

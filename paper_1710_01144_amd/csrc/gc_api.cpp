@@ -1,0 +1,706 @@
+// Host side of libgc.so: graph handles, CSR validation, workspace layout and
+// the Greedy++ driver (Section 4 of Bergamini, Gonser, Meyerhenke).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "gc.h"
+#include "gc_kernels.h"
+#include "gc_mlp.h"
+
+using namespace gck;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(GC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+extern "C" const char *gc_strerror(int code) {
+    switch (code) {
+    case GC_OK: return "ok";
+    case GC_EINVAL: return "invalid argument";
+    case GC_ENOTSYM: return "adjacency is not symmetric";
+    case GC_EDISCONNECTED: return "graph is not connected";
+    case GC_ERANGE: return "distance exceeds the distance width";
+    case GC_EWORKSPACE: return "workspace missing or too small";
+    case GC_ENOMEM: return "host allocation failed";
+    case GC_EDEVICE: return "HIP runtime error";
+    default: return "unknown error";
+    }
+}
+
+extern "C" const char *gc_last_error(void) { return g_last_error.c_str(); }
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------- graph
+
+struct gc_graph {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *d_rp;
+    const int32_t *d_ci;
+    std::vector<int32_t> h_rp;  // host copy of row_ptr (degrees, orders)
+    int32_t max_deg;
+    int32_t num_cu;
+};
+
+extern "C" int32_t gc_graph_n(const gc_graph *g) { return g ? g->n : -1; }
+extern "C" int64_t gc_graph_nnz(const gc_graph *g) { return g ? g->nnz : -1; }
+
+static int hw_threads() {
+    unsigned t = std::thread::hardware_concurrency();
+    if (t == 0) t = 1;
+    if (t > 16) t = 16;
+    return (int)t;
+}
+
+template <typename F>
+static void parallel_for(int64_t n, F f) {
+    const int nt = (int)std::min<int64_t>(hw_threads(), std::max<int64_t>(1, n / 65536));
+    if (nt <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+        th.emplace_back([=] { f(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// CSR contract of the method's input (Section 2: connected, undirected,
+// unweighted): ranges, sorted rows, no self-loops or duplicates, symmetry,
+// one component.
+static int validate_csr(int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
+                        const std::vector<int32_t> &ci) {
+    std::atomic<int> bad{GC_OK};
+    std::atomic<int64_t> where{-1};
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi && bad.load(std::memory_order_relaxed) == GC_OK; ++u) {
+            for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+                const int32_t v = ci[e];
+                if (v < 0 || v >= n || v == u || (e > rp[u] && ci[e - 1] >= v)) {
+                    bad = GC_EINVAL;
+                    where = u;
+                    break;
+                }
+                if (!std::binary_search(ci.begin() + rp[v], ci.begin() + rp[v + 1], (int32_t)u)) {
+                    int exp = GC_OK;
+                    bad.compare_exchange_strong(exp, GC_ENOTSYM);
+                    where = u;
+                    break;
+                }
+            }
+        }
+    });
+    if (bad != GC_OK) {
+        if (bad == GC_ENOTSYM)
+            return fail(GC_ENOTSYM, "row %lld has an edge without its reverse", (long long)where.load());
+        return fail(GC_EINVAL, "row %lld: id out of range, self-loop, unsorted or duplicate entry",
+                    (long long)where.load());
+    }
+    std::vector<uint8_t> seen((size_t)n, 0);
+    std::vector<int32_t> q((size_t)n);
+    int64_t h = 0, t = 0;
+    q[t++] = 0;
+    seen[0] = 1;
+    while (h < t) {
+        int32_t x = q[h++];
+        for (int32_t e = rp[x]; e < rp[x + 1]; ++e)
+            if (!seen[ci[e]]) {
+                seen[ci[e]] = 1;
+                q[t++] = ci[e];
+            }
+    }
+    if (t != n) return fail(GC_EDISCONNECTED, "graph has %lld of %d nodes in the component of node 0",
+                            (long long)t, n);
+    (void)nnz;
+    return GC_OK;
+}
+
+extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
+                           const int32_t *d_col_idx, uint32_t flags, hipStream_t stream,
+                           gc_graph **out) {
+    if (!out) return fail(GC_EINVAL, "out is NULL");
+    if (n < 1) return fail(GC_EINVAL, "n must be >= 1 (got %d)", n);
+    if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(GC_EINVAL, "nnz out of range");
+    if (!d_row_ptr || (nnz > 0 && !d_col_idx)) return fail(GC_EINVAL, "NULL CSR array");
+    gc_graph *g = new (std::nothrow) gc_graph();
+    if (!g) return fail(GC_ENOMEM, "no memory for the handle");
+    g->n = n;
+    g->nnz = nnz;
+    g->d_rp = d_row_ptr;
+    g->d_ci = d_col_idx;
+    try {
+        g->h_rp.resize((size_t)n + 1);
+    } catch (...) {
+        delete g;
+        return fail(GC_ENOMEM, "no memory for row_ptr copy");
+    }
+    hipError_t e = hipMemcpyAsync(g->h_rp.data(), d_row_ptr, sizeof(int32_t) * ((size_t)n + 1),
+                                  hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(GC_EDEVICE, "copying row_ptr: %s", hipGetErrorString(e));
+    }
+    const auto &rp = g->h_rp;
+    if (rp[0] != 0 || rp[n] != nnz) {
+        delete g;
+        return fail(GC_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    }
+    int32_t md = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        if (rp[u + 1] < rp[u]) {
+            delete g;
+            return fail(GC_EINVAL, "row_ptr decreases at row %d", u);
+        }
+        md = std::max(md, rp[u + 1] - rp[u]);
+    }
+    g->max_deg = md;
+    if (flags & GC_VALIDATE) {
+        std::vector<int32_t> ci;
+        try {
+            ci.resize((size_t)nnz);
+        } catch (...) {
+            delete g;
+            return fail(GC_ENOMEM, "no memory for the validation copy");
+        }
+        if (nnz > 0) {
+            e = hipMemcpyAsync(ci.data(), d_col_idx, sizeof(int32_t) * (size_t)nnz,
+                               hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) {
+                delete g;
+                return fail(GC_EDEVICE, "copying col_idx: %s", hipGetErrorString(e));
+            }
+        }
+        int rc = validate_csr(n, nnz, rp, ci);
+        if (rc != GC_OK) {
+            delete g;
+            return rc;
+        }
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    g->num_cu = cus;
+    *out = g;
+    return GC_OK;
+}
+
+extern "C" void gc_free_graph(gc_graph *g) { delete g; }
+
+// --------------------------------------------------------------- workspace
+
+namespace {
+
+constexpr size_t kCtrBytes = 4096;
+
+struct WsLayout {
+    size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots, total;
+    int32_t nslots;
+    SlotLayout slot;
+};
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int32_t choose_slots(const gc_graph *g, const SlotLayout &sl) {
+    int64_t target = 4LL * g->num_cu;  // persistent workgroups of the gain engine
+    if (const char *s = getenv("GC_SLOTS")) {
+        long v = strtol(s, nullptr, 10);
+        if (v > 0) target = v;
+    }
+    const size_t budget = (size_t)8 << 30;
+    int64_t cap = (int64_t)(budget / std::max<size_t>(sl.bytes, 1));
+    int64_t ns = std::min(target, std::max<int64_t>(cap, 1));
+    return (int32_t)std::max<int64_t>(ns, 1);
+}
+
+WsLayout ws_layout(const gc_graph *g) {
+    WsLayout L;
+    const size_t n = (size_t)g->n;
+    size_t o = 0;
+    L.ctr = o; o += kCtrBytes;
+    L.dist16 = o; o += al256(n * 2 + 4);
+    L.dist8 = o; o += al256(n + 4);
+    L.far = o; o += 256;
+    L.cand = o; o += al256(n * 4);
+    L.gain = o; o += al256(n * 8);
+    L.aux = o; o += al256(n * 8);
+    L.aux2 = o; o += al256(n * 4);
+    L.q0 = o; o += al256(n * 4);
+    L.q1 = o; o += al256(n * 4);
+    L.claim = o; o += al256(((n + 31) / 32) * 4);
+    L.slot = slot_layout(g->n);
+    L.nslots = choose_slots(g, L.slot);
+    L.slots = o; o += (size_t)L.nslots * L.slot.bytes;
+    L.total = o;
+    return L;
+}
+
+struct Ws {
+    WsLayout L;
+    char *base;
+    int32_t *ctr() const { return reinterpret_cast<int32_t *>(base + L.ctr); }
+    uint16_t *dist16() const { return reinterpret_cast<uint16_t *>(base + L.dist16); }
+    uint8_t *dist8() const { return reinterpret_cast<uint8_t *>(base + L.dist8); }
+    int64_t *far() const { return reinterpret_cast<int64_t *>(base + L.far); }
+    int32_t *cand() const { return reinterpret_cast<int32_t *>(base + L.cand); }
+    int64_t *gain() const { return reinterpret_cast<int64_t *>(base + L.gain); }
+    int64_t *aux() const { return reinterpret_cast<int64_t *>(base + L.aux); }
+    int32_t *aux2() const { return reinterpret_cast<int32_t *>(base + L.aux2); }
+    Slots slots() const { return Slots{base + L.slots, L.slot.bytes, L.nslots}; }
+};
+
+int get_ws(const gc_graph *g, void *d_ws, size_t ws_bytes, Ws *w) {
+    if (!g) return fail(GC_EINVAL, "graph is NULL");
+    w->L = ws_layout(g);
+    if (!d_ws) return fail(GC_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(GC_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < w->L.total)
+        return fail(GC_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w->L.total);
+    w->base = reinterpret_cast<char *>(d_ws);
+    return GC_OK;
+}
+
+}  // namespace
+
+extern "C" int gc_workspace_size(const gc_graph *g, int32_t bitset_width, size_t *bytes) {
+    if (!g || !bytes) return fail(GC_EINVAL, "NULL argument");
+    if (bitset_width != 0 && bitset_width != 64)
+        return fail(GC_EINVAL, "bitset_width must be 64 or 0");
+    WsLayout L = ws_layout(g);
+    *bytes = L.total + gc_mlp_ws_bytes(g->n);
+    return GC_OK;
+}
+
+extern "C" int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream) {
+    Ws w;
+    int rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base), w.L.total / 4, 0u, stream));
+    return GC_OK;
+}
+
+// ------------------------------------------------------------- operations
+
+namespace {
+
+int grid_for_batches(const Ws &w, int64_t nsrc) {
+    int64_t nb = (nsrc + kSrc - 1) / kSrc;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, w.L.nslots));
+}
+
+int bfs_grid(const gc_graph *g) {
+    return std::max(1, std::min(4 * g->num_cu, (g->n + 3) / 4 + 1));
+}
+
+// Level-synchronous BFS from root over d_dist (pruned; full when S = {}).
+// Returns the number of levels expanded and the deepest level in *last.
+int run_update(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int dist_bytes,
+               int64_t *d_far, hipStream_t s, int32_t *last, int32_t *claimed) {
+    BfsArgs a;
+    a.rp = g->d_rp;
+    a.ci = g->d_ci;
+    a.n = g->n;
+    a.dist = d_dist;
+    a.q0 = reinterpret_cast<int32_t *>(w.base + w.L.q0);
+    a.q1 = reinterpret_cast<int32_t *>(w.base + w.L.q1);
+    a.claim = reinterpret_cast<uint32_t *>(w.base + w.L.claim);
+    a.ctr = w.ctr();
+    a.full = 0;
+    HIP_OK(launch_bfs_init(a, dist_bytes, root, s));
+    const int grid = bfs_grid(g);
+    int32_t level = 0;
+    int chunk = 4;
+    int32_t h[8];
+    for (;;) {
+        for (int i = 0; i < chunk; ++i) HIP_OK(launch_bfs_level(a, dist_bytes, level + i, grid, s));
+        level += chunk;
+        HIP_OK(hipMemcpyAsync(h, w.ctr(), sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (h[C_BFS_CNT0 + level % 3] == 0) break;
+        chunk = std::min(chunk * 2, 64);
+    }
+    HIP_OK(launch_bfs_finish(a, d_far, s));
+    if (last) *last = h[C_BFS_LAST];
+    if (claimed) *claimed = h[C_BFS_CLAIMED];
+    return GC_OK;
+}
+
+int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
+              const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
+              int32_t *d_vis, hipStream_t s) {
+    if (count <= 0) return GC_OK;
+    EngineArgs a;
+    a.rp = g->d_rp;
+    a.ci = g->d_ci;
+    a.n = g->n;
+    a.dist = d_dist;
+    a.src = d_cand;
+    a.nsrc = count;
+    a.out_gain = d_gain;
+    a.out_edges = d_edges;
+    a.out_vis = d_vis;
+    a.ctr = w.ctr();
+    a.slots = w.slots();
+    HIP_OK(launch_gain(a, dist_bytes, grid_for_batches(w, count), s));
+    return GC_OK;
+}
+
+// s_1 = argmin (F({v}), v): the top-k closeness search of Section 3.1 with
+// k = 1.  A full BFS from the highest-degree node gives a first bound; every
+// node whose level-0 bound already exceeds it is dropped on the host, the
+// rest run the cut BFS batches in decreasing-degree order.
+int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, int64_t *far,
+                int64_t *sources, int32_t *ecc_out) {
+    const int32_t n = g->n;
+    const auto &rp = g->h_rp;
+    std::vector<int32_t> order((size_t)n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return (rp[x + 1] - rp[x]) > (rp[y + 1] - rp[y]);
+    });
+    const int32_t v0 = order[0];
+    // full BFS from v0 in 16-bit distances
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.dist16()), ((size_t)n * 2 + 3) / 4,
+                           0xFFFFFFFFu, s));
+    int32_t last = 0, claimed = 0;
+    int rc = run_update(g, w, v0, w.dist16(), 2, w.far(), s, &last, &claimed);
+    if (rc) return rc;
+    int64_t F0 = 0;
+    HIP_OK(hipMemcpyAsync(&F0, w.far(), sizeof(F0), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (claimed != n) return fail(GC_ERANGE, "BFS from %d reached %d of %d nodes within 65534 levels",
+                                  v0, claimed, n);
+    // level-0 bound: min(n-1,deg) nodes at distance 1, the rest at >= 2
+    std::vector<int32_t> list;
+    list.reserve((size_t)n);
+    for (int32_t i = 1; i < n; ++i) {
+        const int32_t v = order[i];
+        const int64_t d = std::min<int64_t>(rp[v + 1] - rp[v], (int64_t)n - 1);
+        const int64_t lb0 = d + 2 * ((int64_t)n - 1 - d);
+        if (lb0 <= F0) list.push_back(v);
+    }
+    int32_t best = v0;
+    int64_t bestF = F0;
+    if (!list.empty()) {
+        const int32_t cnt = (int32_t)list.size();
+        HIP_OK(hipMemcpyAsync(w.cand(), list.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
+        HIP_OK(launch_set_i64(reinterpret_cast<int64_t *>(w.ctr() + C_I64_BASE) + L_BEST_FAR, F0, s));
+        EngineArgs a;
+        a.rp = g->d_rp;
+        a.ci = g->d_ci;
+        a.n = n;
+        a.dist = nullptr;
+        a.src = w.cand();
+        a.nsrc = cnt;
+        a.out_gain = w.gain();
+        a.out_edges = nullptr;
+        a.out_vis = nullptr;
+        a.ctr = w.ctr();
+        a.slots = w.slots();
+        HIP_OK(launch_closeness(a, grid_for_batches(w, cnt), s));
+        std::vector<int64_t> F((size_t)cnt);
+        HIP_OK(hipMemcpyAsync(F.data(), w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < cnt; ++i) {
+            if (F[i] < 0) continue;
+            if (F[i] < bestF || (F[i] == bestF && list[i] < best)) {
+                bestF = F[i];
+                best = list[i];
+            }
+        }
+    }
+    *node = best;
+    *far = bestF;
+    if (sources) *sources = 1 + (int64_t)list.size();
+    if (ecc_out) *ecc_out = last;
+    return GC_OK;
+}
+
+}  // namespace
+
+extern "C" int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                               int32_t *h_node, int64_t *h_farness) {
+    Ws w;
+    int rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    if (!h_node || !h_farness) return fail(GC_EINVAL, "NULL output");
+    int32_t node;
+    int64_t far;
+    rc = run_closest(g, w, stream, &node, &far, nullptr, nullptr);
+    if (rc) return rc;
+    *h_node = node;
+    *h_farness = far;
+    return GC_OK;
+}
+
+extern "C" int gc_update_dist(const gc_graph *g, int32_t node, void *d_dist, int32_t dist_bytes,
+                              void *d_ws, size_t ws_bytes, hipStream_t stream, int64_t *d_farness) {
+    Ws w;
+    int rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    if (node < 0 || node >= g->n) return fail(GC_EINVAL, "node %d out of range", node);
+    if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
+    if (!d_dist || !d_farness) return fail(GC_EINVAL, "NULL device pointer");
+    return run_update(g, w, node, d_dist, dist_bytes, d_farness, stream, nullptr, nullptr);
+}
+
+extern "C" int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
+                                 const int32_t *d_cand, int32_t count, int64_t *d_gain,
+                                 int64_t *d_edges, int32_t *d_visited, void *d_ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+    Ws w;
+    int rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
+    if (count < 0) return fail(GC_EINVAL, "count < 0");
+    if (count > 0 && (!d_dist || !d_cand || !d_gain)) return fail(GC_EINVAL, "NULL device pointer");
+    return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream);
+}
+
+// ------------------------------------------------------------- the greedy
+
+namespace {
+
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    hipError_t ensure(size_t b) {
+        if (b <= bytes) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+};
+
+}  // namespace
+
+extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts, void *d_ws,
+                               size_t ws_bytes, hipStream_t s, int32_t *h_group,
+                               int64_t *h_farness, gc_stats *h_stats) {
+    const double t_start = now_ms();
+    Ws w;
+    int rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    const int32_t n = g->n;
+    if (k < 1 || k > n) return fail(GC_EINVAL, "k = %d outside [1, n = %d]", k, n);
+    if (!h_group || !h_farness) return fail(GC_EINVAL, "NULL output");
+    gc_opts o{};
+    if (opts) o = *opts;
+    if (o.bitset_width != 0 && o.bitset_width != 64) return fail(GC_EINVAL, "bitset_width must be 64");
+    if (o.order < GC_ORDER_PLAIN || o.order > GC_ORDER_LEARNED) return fail(GC_EINVAL, "bad order");
+    if (o.order == GC_ORDER_LEARNED && !o.d_mlp) return fail(GC_EINVAL, "learned order needs d_mlp");
+    const int32_t block = o.block > 0 ? o.block : kSrc;
+    if (o.nprefix < 0 || o.nprefix > k || (o.nprefix > 0 && !o.h_prefix))
+        return fail(GC_EINVAL, "bad prefix");
+    for (int32_t i = 0; i < o.nprefix; ++i)
+        if (o.h_prefix[i] < 0 || o.h_prefix[i] >= n) return fail(GC_EINVAL, "prefix id out of range");
+
+    gc_stats st{};
+    if (h_stats) st.h_evals_per_round = h_stats->h_evals_per_round;
+    std::vector<int32_t> group;
+    std::vector<int64_t> Fs;
+    group.reserve(k);
+    Fs.reserve(k);
+    std::vector<uint8_t> inS((size_t)n, 0);
+    std::vector<int64_t> ub((size_t)n, std::numeric_limits<int64_t>::max());
+    std::vector<int32_t> last_eval((size_t)n, -1);
+    std::vector<uint8_t> ds_at_eval;  // d(S,v) when v was last evaluated (features)
+    PinnedBuf pin_cand, pin_gain;
+    if (pin_cand.ensure(sizeof(int32_t) * (size_t)n) != hipSuccess ||
+        pin_gain.ensure(sizeof(int64_t) * (size_t)n * 2) != hipSuccess)
+        return fail(GC_ENOMEM, "pinned host buffers");
+    int32_t *hc = reinterpret_cast<int32_t *>(pin_cand.p);
+    int64_t *hg = reinterpret_cast<int64_t *>(pin_gain.p);
+    int64_t *he = hg + n;
+    const bool want_edges = true;
+
+    // ---- s_1 (Algorithm "mem-greedy", first line) and d(S,.) of S = {s_1}
+    double t0 = now_ms();
+    int32_t s1;
+    int64_t F1;
+    int32_t dist_bytes = 1;
+    if (o.nprefix > 0) {
+        s1 = o.h_prefix[0];
+    } else {
+        rc = run_closest(g, w, s, &s1, &F1, &st.closest_sources, nullptr);
+        if (rc) return rc;
+    }
+    st.ms_closest = now_ms() - t0;
+    t0 = now_ms();
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.dist16()), ((size_t)n * 2 + 3) / 4,
+                           0xFFFFFFFFu, s));
+    int32_t ecc = 0, claimed = 0;
+    rc = run_update(g, w, s1, w.dist16(), 2, w.far(), s, &ecc, &claimed);
+    if (rc) return rc;
+    if (claimed != n) return fail(GC_ERANGE, "eccentricity of node %d exceeds 65534", s1);
+    void *d_dist;
+    if (ecc <= 254) {
+        HIP_OK(launch_u16_to_u8(w.dist16(), w.dist8(), n, s));
+        d_dist = w.dist8();
+        dist_bytes = 1;
+    } else {
+        d_dist = w.dist16();
+        dist_bytes = 2;
+    }
+    int64_t F = 0;
+    HIP_OK(hipMemcpyAsync(&F, w.far(), sizeof(F), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    st.ms_update += now_ms() - t0;
+    st.ecc_s1 = ecc;
+    st.dist_bytes = dist_bytes;
+    group.push_back(s1);
+    Fs.push_back(F);
+    inS[s1] = 1;
+    // resumed prefix: rebuild d(S,.) by pruned BFS, bounds restart at +inf
+    for (int32_t i = 1; i < o.nprefix; ++i) {
+        const int32_t v = o.h_prefix[i];
+        t0 = now_ms();
+        rc = run_update(g, w, v, d_dist, dist_bytes, w.far(), s, nullptr, nullptr);
+        if (rc) return rc;
+        HIP_OK(hipMemcpyAsync(&F, w.far(), sizeof(F), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        st.ms_update += now_ms() - t0;
+        group.push_back(v);
+        Fs.push_back(F);
+        inS[v] = 1;
+    }
+    if (st.h_evals_per_round)
+        for (int32_t i = 0; i < k; ++i) st.h_evals_per_round[i] = 0;
+
+    // evaluate a list of candidates, returning gains (and edges) on the host
+    auto evaluate = [&](int32_t cnt) -> int {
+        HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
+        int r = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(),
+                          want_edges ? w.aux() : nullptr, want_edges ? w.aux2() : nullptr, s);
+        if (r) return r;
+        HIP_OK(hipMemcpyAsync(hg, w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
+        if (want_edges)
+            HIP_OK(hipMemcpyAsync(he, w.aux(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        st.gain_launches += 1;
+        return GC_OK;
+    };
+
+    std::vector<int32_t> order;
+    const int32_t first_gain_round = (int32_t)group.size();
+    for (int32_t r = first_gain_round; r < k; ++r) {
+        const double tr = now_ms();
+        int64_t best_gain = -1;
+        int32_t best_id = -1;
+        int64_t nev = 0;
+        // candidate order for this round (ties: ascending id)
+        order.clear();
+        for (int32_t v = 0; v < n; ++v)
+            if (!inS[v]) order.push_back(v);
+        if (o.order == GC_ORDER_CELF) {
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t x, int32_t y) { return ub[x] > ub[y]; });
+        }
+        // no bounds exist yet in the first round: every candidate is evaluated
+        const bool first_round = (r == first_gain_round);
+        size_t pos = 0;
+        const int32_t blk = first_round ? n : block;
+        for (;;) {
+            int32_t cnt = 0;
+            while (pos < order.size() && cnt < blk) {
+                const int32_t u = order[pos++];
+                // skip: stale gain (an upper bound, Section 4.2) cannot beat the best
+                if (best_id >= 0 && (ub[u] < best_gain || (ub[u] == best_gain && u > best_id))) {
+                    if (o.order == GC_ORDER_CELF) { pos = order.size(); break; }
+                    continue;
+                }
+                hc[cnt++] = u;
+            }
+            if (cnt == 0) break;
+            rc = evaluate(cnt);
+            if (rc) return rc;
+            for (int32_t j = 0; j < cnt; ++j) {
+                const int32_t u = hc[j];
+                const int64_t gu = hg[j];
+                ub[u] = gu;
+                last_eval[u] = r;
+                st.edges_alg += he[j];
+                if (best_id < 0 || gu > best_gain || (gu == best_gain && u < best_id)) {
+                    best_gain = gu;
+                    best_id = u;
+                }
+            }
+            nev += cnt;
+        }
+        if (first_round) {
+            st.evals_round1 += nev;
+            st.ms_round1 += now_ms() - tr;
+        } else {
+            st.evals_later += nev;
+            st.ms_later += now_ms() - tr;
+        }
+        if (st.h_evals_per_round) st.h_evals_per_round[r] = nev;
+        st.evals_total += nev;
+        if (best_id < 0) return fail(GC_EINVAL, "no candidate left");
+        // pick, then d(S,.) <- min(d(S,.), d(pick,.)) by pruned BFS
+        t0 = now_ms();
+        rc = run_update(g, w, best_id, d_dist, dist_bytes, w.far(), s, nullptr, nullptr);
+        if (rc) return rc;
+        int64_t Fdev = 0;
+        HIP_OK(hipMemcpyAsync(&Fdev, w.far(), sizeof(Fdev), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        st.ms_update += now_ms() - t0;
+        F -= best_gain;
+        if (Fdev != F)
+            return fail(GC_EDEVICE, "farness mismatch after pick %d: update %lld vs gains %lld", r,
+                        (long long)Fdev, (long long)F);
+        group.push_back(best_id);
+        Fs.push_back(F);
+        inS[best_id] = 1;
+    }
+    for (int32_t i = 0; i < k; ++i) {
+        h_group[i] = group[i];
+        h_farness[i] = Fs[i];
+    }
+    st.ms_total = now_ms() - t_start;
+    if (h_stats) *h_stats = st;
+    return GC_OK;
+}

@@ -1,0 +1,82 @@
+// Internal interface between the host driver (gc_api.cpp) and the HIP
+// kernels (gc_kernels.hip).  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gck {
+
+constexpr int kWG = 256;      // threads per workgroup of the bit-parallel engine
+constexpr int kSrc = 64;      // sources per bitset word
+
+// Workspace counters (int32 slots of the counter block).
+enum : int {
+    C_GAIN_NEXT = 0,   // next batch to take (gain / closeness engine)
+    C_GAIN_DONE = 1,   // workgroups finished (the last one resets both)
+    C_BFS_CNT0 = 2,    // three rotating frontier counters of the level BFS
+    C_BFS_LAST = 5,    // deepest level that claimed a node
+    C_BFS_CLAIMED = 6, // nodes claimed by the current level BFS
+    C_I64_BASE = 8,    // int64 area starts at int32 slot 8
+};
+// int64 slots (index into the int64 view starting at int32 slot 8)
+enum : int {
+    L_BFS_SUM = 0,     // sum of contributions of the level BFS
+    L_BEST_FAR = 1,    // best farness found by the closeness engine
+    L_EDGES = 2,       // total algorithmic edges of a gain launch
+    L_VISITED = 3,     // total |V(v)| of a gain launch
+};
+
+struct Slots {
+    char *base;        // nslots * stride bytes
+    size_t stride;
+    int32_t nslots;
+};
+
+// Per-slot array offsets (bytes); all arrays have n entries.
+struct SlotLayout {
+    size_t vis, next, tq, uq, qv0, qv1, qm0, qm1, bytes;
+};
+SlotLayout slot_layout(int64_t n);
+
+struct EngineArgs {
+    const int32_t *rp;
+    const int32_t *ci;
+    int32_t n;
+    const void *dist;        // uint8/uint16 d(S,.) (gain mode)
+    const int32_t *src;      // sources, grouped 64 per batch
+    int32_t nsrc;
+    int64_t *out_gain;       // gain mode: g(v,S); closeness mode: F({v}) or -1 if cut
+    int64_t *out_edges;      // optional
+    int32_t *out_vis;        // optional
+    int32_t *ctr;            // workspace counter block
+    Slots slots;
+};
+
+// gain mode: dist_bytes 1 or 2.  closeness mode: dist ignored.
+hipError_t launch_gain(const EngineArgs &a, int dist_bytes, int grid, hipStream_t s);
+hipError_t launch_closeness(const EngineArgs &a, int grid, hipStream_t s);
+
+struct BfsArgs {
+    const int32_t *rp;
+    const int32_t *ci;
+    int32_t n;
+    void *dist;              // uint8/uint16 (or int32 when dist_bytes == 4)
+    int32_t *q0;
+    int32_t *q1;
+    uint32_t *claim;         // ceil(n/32) words
+    int32_t *ctr;
+    int32_t full;            // 1: S = {} (sum levels), 0: sum (old - level)
+};
+// init: clears claim bitmap and counters, claims the root (level 0).
+hipError_t launch_bfs_init(const BfsArgs &a, int dist_bytes, int32_t root, hipStream_t s);
+// one level: frontier at distance `level` -> distance level+1.
+hipError_t launch_bfs_level(const BfsArgs &a, int dist_bytes, int32_t level, int grid,
+                            hipStream_t s);
+// F_out = full ? sum : F_in - sum
+hipError_t launch_bfs_finish(const BfsArgs &a, int64_t *d_far, hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s);
+hipError_t launch_u16_to_u8(const uint16_t *in, uint8_t *out, int64_t n, hipStream_t s);
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);
+
+}  // namespace gck

@@ -1,0 +1,255 @@
+"""Thin ctypes binding of libgc.so (the C ABI in include/gc.h).
+
+Argument marshalling only: device buffers are torch tensors on the current
+HIP device, passed by data pointer together with torch's current stream.
+Every computation runs in the library's HIP kernels; if libgc.so is missing
+the binding raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libgc.so")
+_lib = None
+
+GC_OK = 0
+GC_EINVAL = -1
+GC_ENOTSYM = -2
+GC_EDISCONNECTED = -3
+GC_ERANGE = -4
+GC_EWORKSPACE = -5
+GC_ENOMEM = -6
+GC_EDEVICE = -7
+
+GC_VALIDATE = 0x1
+
+ORDER_PLAIN = 0
+ORDER_CELF = 1
+ORDER_LEARNED = 2
+ORDERS = {"plain": ORDER_PLAIN, "celf": ORDER_CELF, "learned": ORDER_LEARNED}
+
+EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_workspace_size",
+            "gc_workspace_init", "gc_closest_node", "gc_update_dist", "gc_marginal_gains",
+            "gc_greedy_group", "gc_strerror", "gc_last_error"]
+
+
+class GCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("gc error %d: %s" % (code, msg))
+        self.code = code
+
+
+class GcOpts(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("bitset_width", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("nprefix", ctypes.c_int32),
+                ("h_prefix", ctypes.POINTER(ctypes.c_int32)), ("d_mlp", ctypes.c_void_p),
+                ("debug_checks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("log_capacity", ctypes.c_int64),
+                ("h_log_round", ctypes.POINTER(ctypes.c_int32)),
+                ("h_log_node", ctypes.POINTER(ctypes.c_int32)),
+                ("h_log_gain", ctypes.POINTER(ctypes.c_int64)),
+                ("h_log_feat", ctypes.POINTER(ctypes.c_float)),
+                ("h_log_count", ctypes.POINTER(ctypes.c_int64))]
+
+
+class GcStats(ctypes.Structure):
+    _fields_ = [("evals_total", ctypes.c_int64), ("evals_round1", ctypes.c_int64),
+                ("evals_later", ctypes.c_int64), ("edges_alg", ctypes.c_int64),
+                ("visited", ctypes.c_int64), ("gain_launches", ctypes.c_int64),
+                ("closest_sources", ctypes.c_int64), ("dist_bytes", ctypes.c_int32),
+                ("ecc_s1", ctypes.c_int32), ("ms_total", ctypes.c_double),
+                ("ms_closest", ctypes.c_double), ("ms_round1", ctypes.c_double),
+                ("ms_later", ctypes.c_double), ("ms_update", ctypes.c_double),
+                ("ms_mlp", ctypes.c_double),
+                ("h_evals_per_round", ctypes.POINTER(ctypes.c_int64))]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "h_evals_per_round"}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libgc.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libgc.so not built: run `python -m paper_1710_01144_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.gc_load_csr.restype = ctypes.c_int
+    lib.gc_load_csr.argtypes = [i32, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    lib.gc_free_graph.restype = None
+    lib.gc_free_graph.argtypes = [vp]
+    lib.gc_graph_n.restype = i32
+    lib.gc_graph_n.argtypes = [vp]
+    lib.gc_graph_nnz.restype = i64
+    lib.gc_graph_nnz.argtypes = [vp]
+    lib.gc_workspace_size.restype = ctypes.c_int
+    lib.gc_workspace_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.gc_workspace_init.restype = ctypes.c_int
+    lib.gc_workspace_init.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.gc_closest_node.restype = ctypes.c_int
+    lib.gc_closest_node.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32),
+                                    ctypes.POINTER(i64)]
+    lib.gc_update_dist.restype = ctypes.c_int
+    lib.gc_update_dist.argtypes = [vp, i32, vp, i32, vp, ctypes.c_size_t, vp, vp]
+    lib.gc_marginal_gains.restype = ctypes.c_int
+    lib.gc_marginal_gains.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.gc_greedy_group.restype = ctypes.c_int
+    lib.gc_greedy_group.argtypes = [vp, i32, ctypes.POINTER(GcOpts), vp, ctypes.c_size_t, vp,
+                                    ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                    ctypes.POINTER(GcStats)]
+    lib.gc_strerror.restype = ctypes.c_char_p
+    lib.gc_strerror.argtypes = [ctypes.c_int]
+    lib.gc_last_error.restype = ctypes.c_char_p
+    lib.gc_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != GC_OK:
+        lib = load_library()
+        raise GCError(rc, lib.gc_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Graph:
+    """A device CSR graph plus its library handle and workspace.
+
+    row_ptr, col_idx: int32 tensors on the current HIP device (or numpy arrays,
+    which are copied there).  The tensors are kept alive by this object.
+    """
+
+    def __init__(self, row_ptr, col_idx, validate: bool = True, workspace: bool = True):
+        lib = load_library()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if isinstance(row_ptr, np.ndarray):
+            row_ptr = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int32))
+        if isinstance(col_idx, np.ndarray):
+            col_idx = torch.from_numpy(np.ascontiguousarray(col_idx, dtype=np.int32))
+        self.row_ptr = row_ptr.to(dev, dtype=torch.int32).contiguous()
+        self.col_idx = col_idx.to(dev, dtype=torch.int32).contiguous()
+        if self.col_idx.numel() == 0:
+            self.col_idx = torch.zeros(1, dtype=torch.int32, device=dev)[:0]
+        self.n = int(self.row_ptr.numel() - 1)
+        self.nnz = int(self.col_idx.numel())
+        h = ctypes.c_void_p()
+        _check(lib.gc_load_csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx),
+                               GC_VALIDATE if validate else 0, _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.ws = None
+        self.ws_bytes = 0
+        if workspace:
+            self.alloc_workspace()
+
+    @classmethod
+    def from_graphgen(cls, g, **kw):
+        return cls(g.row_ptr, g.col_idx, **kw)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gc_free_graph(h)
+            self.handle = None
+
+    def workspace_size(self, bitset_width: int = 0) -> int:
+        sz = ctypes.c_size_t()
+        _check(load_library().gc_workspace_size(self.handle, bitset_width, ctypes.byref(sz)))
+        return int(sz.value)
+
+    def alloc_workspace(self, bitset_width: int = 0):
+        self.ws_bytes = self.workspace_size(bitset_width)
+        # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.row_ptr.device)
+        _check(load_library().gc_workspace_init(self.handle, _ptr(self.ws), self.ws_bytes, _stream()))
+
+    # ------------------------------------------------------------ operations
+    def closest_node(self):
+        node, far = ctypes.c_int32(), ctypes.c_int64()
+        _check(load_library().gc_closest_node(self.handle, _ptr(self.ws), self.ws_bytes, _stream(),
+                                              ctypes.byref(node), ctypes.byref(far)))
+        return int(node.value), int(far.value)
+
+    def new_dist(self, dist_bytes: int = 1):
+        """A d(S,.) buffer for S = {} (all INF), padded to whole 4-byte words."""
+        dt = torch.uint8 if dist_bytes == 1 else torch.int16
+        nwords = (self.n * dist_bytes + 3) // 4
+        buf = torch.full((nwords * 4 // dist_bytes,), -1, dtype=dt, device=self.row_ptr.device)
+        return buf
+
+    def update_dist(self, node: int, dist, dist_bytes: int, farness):
+        _check(load_library().gc_update_dist(self.handle, int(node), _ptr(dist), dist_bytes,
+                                             _ptr(self.ws), self.ws_bytes, _stream(), _ptr(farness)))
+
+    def marginal_gains(self, dist, dist_bytes: int, cand, stats: bool = False):
+        cand = cand.to(self.row_ptr.device, dtype=torch.int32).contiguous()
+        count = int(cand.numel())
+        gain = torch.empty(max(count, 1), dtype=torch.int64, device=self.row_ptr.device)
+        edges = torch.empty_like(gain) if stats else None
+        vis = torch.empty(max(count, 1), dtype=torch.int32, device=self.row_ptr.device) if stats else None
+        _check(load_library().gc_marginal_gains(self.handle, _ptr(dist), dist_bytes, _ptr(cand), count,
+                                                _ptr(gain), _ptr(edges), _ptr(vis), _ptr(self.ws),
+                                                self.ws_bytes, _stream()))
+        if stats:
+            return gain[:count], edges[:count], vis[:count]
+        return gain[:count]
+
+    def greedy_group(self, k: int, order: str = "plain", block: int = 0, prefix=None,
+                     mlp_params=None, log_capacity: int = 0):
+        lib = load_library()
+        opts = GcOpts()
+        opts.order = ORDERS[order]
+        opts.bitset_width = 64
+        opts.block = int(block)
+        keep = []
+        if prefix is not None and len(prefix) > 0:
+            arr = np.ascontiguousarray(prefix, dtype=np.int32)
+            keep.append(arr)
+            opts.nprefix = int(arr.shape[0])
+            opts.h_prefix = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if mlp_params is not None:
+            opts.d_mlp = ctypes.c_void_p(mlp_params.data_ptr())
+        log = None
+        if log_capacity > 0:
+            log = {"round": np.zeros(log_capacity, np.int32), "node": np.zeros(log_capacity, np.int32),
+                   "gain": np.zeros(log_capacity, np.int64),
+                   "feat": np.zeros((log_capacity, 8), np.float32), "count": np.zeros(1, np.int64)}
+            opts.log_capacity = log_capacity
+            opts.h_log_round = log["round"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            opts.h_log_node = log["node"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            opts.h_log_gain = log["gain"].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            opts.h_log_feat = log["feat"].ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            opts.h_log_count = log["count"].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        group = np.zeros(k, dtype=np.int32)
+        far = np.zeros(k, dtype=np.int64)
+        per_round = np.zeros(k, dtype=np.int64)
+        st = GcStats()
+        st.h_evals_per_round = per_round.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        _check(lib.gc_greedy_group(self.handle, int(k), ctypes.byref(opts), _ptr(self.ws),
+                                   self.ws_bytes, _stream(),
+                                   group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   far.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   ctypes.byref(st)))
+        stats = st.as_dict()
+        stats["evals_per_round"] = per_round
+        if log is not None:
+            c = int(min(log["count"][0], log_capacity))
+            stats["log"] = {key: v[:c] for key, v in log.items() if key != "count"}
+        return group, far, stats

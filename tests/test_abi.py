@@ -1,0 +1,40 @@
+"""The C-ABI library loads and exports every function include/gc.h declares.
+
+CPU only: no compute calls (there may be no GPU here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(gc_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_declared_symbols():
+    from paper_1710_01144_amd import gc
+    lib = ctypes.CDLL(gc.library_path())
+    declared = _declared()
+    assert {"gc_load_csr", "gc_closest_node", "gc_marginal_gains", "gc_update_dist",
+            "gc_greedy_group"} <= declared
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(gc.EXPORTED) <= declared
+
+
+def test_strerror_without_device():
+    from paper_1710_01144_amd import gc
+    lib = gc.load_library()
+    for code in range(0, -8, -1):
+        assert lib.gc_strerror(code)
+    # argument checks happen before any device call
+    out = ctypes.c_void_p()
+    assert lib.gc_load_csr(0, 0, None, None, 1, None, ctypes.byref(out)) == gc.GC_EINVAL
+    assert lib.gc_load_csr(5, -1, None, None, 1, None, ctypes.byref(out)) == gc.GC_EINVAL
