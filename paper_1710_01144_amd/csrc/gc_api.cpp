@@ -73,6 +73,11 @@ struct gc_graph {
     std::vector<int32_t> h_rp;  // host copy of row_ptr (degrees, orders)
     int32_t max_deg;
     int32_t num_cu;
+    // tuning read once at load time so the workspace layout never changes
+    int64_t slots_target;   // GC_SLOTS
+    int64_t vis_budget;     // GC_VIS_BUDGET_MB (bytes)
+    int64_t log_entries;    // GC_LOG_ENTRIES
+    bool wg_engine;         // GC_ENGINE=wg
 };
 
 extern "C" int32_t gc_graph_n(const gc_graph *g) { return g ? g->n : -1; }
@@ -218,6 +223,23 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
     g->num_cu = cus;
+    g->wg_engine = false;
+    if (const char *e = getenv("GC_ENGINE")) g->wg_engine = strcmp(e, "wg") == 0;
+    g->slots_target = (g->wg_engine ? 4LL : 1LL) * cus;
+    if (const char *e = getenv("GC_SLOTS")) {
+        long long v = strtoll(e, nullptr, 10);
+        if (v > 0) g->slots_target = v;
+    }
+    g->vis_budget = (int64_t)4 << 30;
+    if (const char *e = getenv("GC_VIS_BUDGET_MB")) {
+        long long v = strtoll(e, nullptr, 10);
+        if (v > 0) g->vis_budget = (int64_t)v << 20;
+    }
+    g->log_entries = (int64_t)8 << 20;
+    if (const char *e = getenv("GC_LOG_ENTRIES")) {
+        long long v = strtoll(e, nullptr, 10);
+        if (v > 0) g->log_entries = v;
+    }
     *out = g;
     return GC_OK;
 }
@@ -231,19 +253,27 @@ namespace {
 constexpr size_t kCtrBytes = 4096;
 
 struct WsLayout {
-    size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots, total;
+    size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
+    size_t wvis, ly, lb, lm, lo, lvl, total;
     int32_t nslots;
     SlotLayout slot;
+    int64_t kmax;       // batches per launch of the device-wide gain engine
+    size_t vis_stride;  // words per batch
+    int64_t cap;        // frontier log entries
 };
+
+constexpr int32_t kMaxLevels = 65536;  // 16-bit distances: at most 65534 levels
+constexpr int kFlagSlot = 16;          // int32 counter slot of the overflow flag
+constexpr int kMaxdSlot = 17;          // int32 counter slot for max d(S,.)
+
+
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int32_t choose_slots(const gc_graph *g, const SlotLayout &sl) {
-    int64_t target = 4LL * g->num_cu;  // persistent workgroups of the gain engine
-    if (const char *s = getenv("GC_SLOTS")) {
-        long v = strtol(s, nullptr, 10);
-        if (v > 0) target = v;
-    }
+    // persistent workgroups of the per-batch engine (closeness search; gains
+    // only with GC_ENGINE=wg)
+    const int64_t target = g->slots_target;
     const size_t budget = (size_t)8 << 30;
     int64_t cap = (int64_t)(budget / std::max<size_t>(sl.bytes, 1));
     int64_t ns = std::min(target, std::max<int64_t>(cap, 1));
@@ -268,6 +298,24 @@ WsLayout ws_layout(const gc_graph *g) {
     L.slot = slot_layout(g->n);
     L.nslots = choose_slots(g, L.slot);
     L.slots = o; o += (size_t)L.nslots * L.slot.bytes;
+    // device-wide engine: per-batch visited words and the frontier log
+    L.vis_stride = (n + 31) & ~(size_t)31;
+    const int64_t nb_all = ((int64_t)n + 63) / 64;
+    const size_t vis_budget = (size_t)g->vis_budget;
+    int64_t kmax = (int64_t)(vis_budget / (L.vis_stride * 8));
+    kmax = std::max<int64_t>(1, std::min<int64_t>(kmax, nb_all));
+    L.kmax = kmax;
+    int64_t cap = g->log_entries;
+    cap = std::min<int64_t>(cap, 64LL * kmax * (int64_t)n + 128);
+    cap = std::max<int64_t>(cap, (int64_t)n + 128);
+    cap = std::min<int64_t>(cap, ((int64_t)1 << 24) - 128);
+    L.cap = cap;
+    L.wvis = o; o += al256((size_t)kmax * L.vis_stride * 8);
+    L.ly = o; o += al256((size_t)cap * 4);
+    L.lb = o; o += al256((size_t)cap * 4);
+    L.lm = o; o += al256((size_t)cap * 8);
+    L.lo = o; o += al256((size_t)cap * 8);
+    L.lvl = o; o += al256((size_t)(kMaxLevels + 2) * sizeof(WideLevel));
     L.total = o;
     return L;
 }
@@ -284,6 +332,21 @@ struct Ws {
     int64_t *aux() const { return reinterpret_cast<int64_t *>(base + L.aux); }
     int32_t *aux2() const { return reinterpret_cast<int32_t *>(base + L.aux2); }
     Slots slots() const { return Slots{base + L.slots, L.slot.bytes, L.nslots}; }
+    int32_t *flags() const { return ctr() + kFlagSlot; }
+    int32_t *maxd() const { return ctr() + kMaxdSlot; }
+    WideArgs wide() const {
+        WideArgs a{};
+        a.vis = reinterpret_cast<uint64_t *>(base + L.wvis);
+        a.vis_stride = L.vis_stride;
+        a.ly = reinterpret_cast<int32_t *>(base + L.ly);
+        a.lb = reinterpret_cast<int32_t *>(base + L.lb);
+        a.lm = reinterpret_cast<uint64_t *>(base + L.lm);
+        a.lo = reinterpret_cast<int64_t *>(base + L.lo);
+        a.cap = L.cap;
+        a.lvl = reinterpret_cast<WideLevel *>(base + L.lvl);
+        a.flags = flags();
+        return a;
+    }
 };
 
 int get_ws(const gc_graph *g, void *d_ws, size_t ws_bytes, Ws *w) {
@@ -330,9 +393,13 @@ int bfs_grid(const gc_graph *g) {
 }
 
 // Level-synchronous BFS from root over d_dist (pruned; full when S = {}).
-// Returns the number of levels expanded and the deepest level in *last.
+// nlev >= 0: launch exactly nlev levels without synchronising (a pruned BFS
+// needs at most max d(S,.) - 1); nlev < 0: launch chunks of levels until the
+// frontier is empty (synchronises), reporting the deepest level in *last and
+// the nodes reached in *claimed.
 int run_update(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int dist_bytes,
-               int64_t *d_far, hipStream_t s, int32_t *last, int32_t *claimed) {
+               int64_t *d_far, hipStream_t s, int32_t *last, int32_t *claimed,
+               int32_t nlev = -1) {
     BfsArgs a;
     a.rp = g->d_rp;
     a.ci = g->d_ci;
@@ -345,6 +412,11 @@ int run_update(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int d
     a.full = 0;
     HIP_OK(launch_bfs_init(a, dist_bytes, root, s));
     const int grid = bfs_grid(g);
+    if (nlev >= 0) {
+        for (int32_t L = 0; L < nlev; ++L) HIP_OK(launch_bfs_level(a, dist_bytes, L, grid, s));
+        HIP_OK(launch_bfs_finish(a, d_far, s));
+        return GC_OK;
+    }
     int32_t level = 0;
     int chunk = 4;
     int32_t h[8];
@@ -362,10 +434,9 @@ int run_update(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int d
     return GC_OK;
 }
 
-int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
-              const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
-              int32_t *d_vis, hipStream_t s) {
-    if (count <= 0) return GC_OK;
+int run_gains_wg(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
+                 const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
+                 int32_t *d_vis, hipStream_t s) {
     EngineArgs a;
     a.rp = g->d_rp;
     a.ci = g->d_ci;
@@ -379,6 +450,74 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     a.ctr = w.ctr();
     a.slots = w.slots();
     HIP_OK(launch_gain(a, dist_bytes, grid_for_batches(w, count), s));
+    return GC_OK;
+}
+
+int wide_grid(const gc_graph *g) { return 4 * g->num_cu; }
+
+// Marginal gains of count candidates with the device-wide engine.
+// nlev = number of BFS levels to expand (max d(S,.) - 1 suffices; < 0: measure
+// it).  Synchronises the stream once to check for log overflow; an overflowed
+// launch is re-run with fewer batches per launch.
+int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
+              const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
+              int32_t *d_vis, hipStream_t s, int32_t nlev) {
+    if (count <= 0) return GC_OK;
+    if (g->wg_engine)
+        return run_gains_wg(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_vis, s);
+    if (nlev < 0) {
+        int32_t maxd = 0;
+        HIP_OK(launch_max_dist(d_dist, dist_bytes, g->n, w.maxd(), s));
+        HIP_OK(hipMemcpyAsync(&maxd, w.maxd(), sizeof(maxd), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        nlev = std::max(maxd - 1, 0);
+    }
+    nlev = std::min(nlev, kMaxLevels - 1);
+    const int grid = wide_grid(g);
+    int64_t kb = w.L.kmax;  // batches per launch
+    int32_t spb = 64;       // sources per batch
+    int64_t done = 0;
+    while (done < count) {
+        // launch chunks of kb batches, then check the overflow flag once
+        const int64_t per = kb * spb;
+        int32_t tag = 0;
+        int64_t off = done;
+        while (off < count) {
+            WideArgs a = w.wide();
+            a.rp = g->d_rp;
+            a.ci = g->d_ci;
+            a.n = g->n;
+            a.dist = d_dist;
+            a.src = d_cand + off;
+            a.nsrc = std::min<int64_t>(per, count - off);
+            a.spb = spb;
+            a.gain = d_gain + off;
+            a.edges = d_edges ? d_edges + off : nullptr;
+            a.visited = d_vis ? d_vis + off : nullptr;
+            a.tag = ++tag;
+            HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
+            HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
+            HIP_OK(launch_wide_end(a, nlev, grid, s));
+            off += a.nsrc;
+        }
+        int32_t flag = 0;
+        HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (flag == 0) return GC_OK;
+        // chunk `flag` overflowed the frontier log: it and the chunks after it
+        // are redone with fewer batches (then fewer sources per batch) per
+        // launch, after clearing the visited words.  One source per launch
+        // claims each node at most once, so it always fits (cap >= n).
+        done += (int64_t)(flag - 1) * per;
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.wvis),
+                               (size_t)w.L.kmax * w.L.vis_stride * 2, 0u, s));
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
+        if (kb > 1) kb = std::max<int64_t>(1, kb / 2);
+        else if (spb > 1) spb = std::max(1, spb / 2);
+        else
+            return fail(GC_EWORKSPACE, "frontier log of %lld entries too small for one source",
+                        (long long)w.L.cap);
+    }
     return GC_OK;
 }
 
@@ -491,7 +630,7 @@ extern "C" int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t 
     if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
     if (count < 0) return fail(GC_EINVAL, "count < 0");
     if (count > 0 && (!d_dist || !d_cand || !d_gain)) return fail(GC_EINVAL, "NULL device pointer");
-    return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream);
+    return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream, -1);
 }
 
 // ------------------------------------------------------------- the greedy
@@ -591,6 +730,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     st.ms_update += now_ms() - t0;
     st.ecc_s1 = ecc;
     st.dist_bytes = dist_bytes;
+    const int32_t ecc_bound = ecc;  // max d(S,.) never grows as S grows
     group.push_back(s1);
     Fs.push_back(F);
     inS[s1] = 1;
@@ -598,7 +738,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     for (int32_t i = 1; i < o.nprefix; ++i) {
         const int32_t v = o.h_prefix[i];
         t0 = now_ms();
-        rc = run_update(g, w, v, d_dist, dist_bytes, w.far(), s, nullptr, nullptr);
+        rc = run_update(g, w, v, d_dist, dist_bytes, w.far(), s, nullptr, nullptr,
+                        std::max(ecc_bound - 1, 0));
         if (rc) return rc;
         HIP_OK(hipMemcpyAsync(&F, w.far(), sizeof(F), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
@@ -614,7 +755,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     auto evaluate = [&](int32_t cnt) -> int {
         HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
         int r = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(),
-                          want_edges ? w.aux() : nullptr, want_edges ? w.aux2() : nullptr, s);
+                          want_edges ? w.aux() : nullptr, want_edges ? w.aux2() : nullptr, s,
+                          std::max(ecc_bound - 1, 0));
         if (r) return r;
         HIP_OK(hipMemcpyAsync(hg, w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
         if (want_edges)
@@ -682,16 +824,20 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         if (best_id < 0) return fail(GC_EINVAL, "no candidate left");
         // pick, then d(S,.) <- min(d(S,.), d(pick,.)) by pruned BFS
         t0 = now_ms();
-        rc = run_update(g, w, best_id, d_dist, dist_bytes, w.far(), s, nullptr, nullptr);
+        rc = run_update(g, w, best_id, d_dist, dist_bytes, w.far(), s, nullptr, nullptr,
+                        std::max(ecc_bound - 1, 0));
         if (rc) return rc;
-        int64_t Fdev = 0;
-        HIP_OK(hipMemcpyAsync(&Fdev, w.far(), sizeof(Fdev), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        st.ms_update += now_ms() - t0;
         F -= best_gain;
-        if (Fdev != F)
-            return fail(GC_EDEVICE, "farness mismatch after pick %d: update %lld vs gains %lld", r,
-                        (long long)Fdev, (long long)F);
+        if (o.debug_checks || r == k - 1) {
+            // the update BFS tracks F(S) on its own: it must agree with the gains
+            int64_t Fdev = 0;
+            HIP_OK(hipMemcpyAsync(&Fdev, w.far(), sizeof(Fdev), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            if (Fdev != F)
+                return fail(GC_EDEVICE, "farness mismatch after pick %d: update %lld vs gains %lld",
+                            r, (long long)Fdev, (long long)F);
+        }
+        st.ms_update += now_ms() - t0;
         group.push_back(best_id);
         Fs.push_back(F);
         inS[best_id] = 1;

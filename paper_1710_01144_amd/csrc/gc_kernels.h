@@ -75,6 +75,41 @@ hipError_t launch_bfs_level(const BfsArgs &a, int dist_bytes, int32_t level, int
 // F_out = full ? sum : F_in - sum
 hipError_t launch_bfs_finish(const BfsArgs &a, int64_t *d_far, hipStream_t s);
 
+// ------------------------------------------------ device-wide gain engine
+struct WideLevel {
+    int64_t start;                 // first log index of this level's entries
+    unsigned long long packed;     // (entry count << 40) | adjacency entries to expand
+};
+
+struct WideArgs {
+    const int32_t *rp;
+    const int32_t *ci;
+    int32_t n;
+    const void *dist;              // uint8/uint16 d(S,.)
+    const int32_t *src;            // candidates of this launch, spb per batch
+    int64_t nsrc;
+    int32_t spb;                   // sources per batch (bits used per word), 1..64
+    int64_t *gain;                 // out [nsrc]
+    int64_t *edges;                // out [nsrc] or null
+    int32_t *visited;              // out [nsrc] or null
+    uint64_t *vis;                 // batch b: vis[b*vis_stride .. +n), zero between launches
+    size_t vis_stride;
+    int32_t *ly;                   // frontier log: node
+    int32_t *lb;                   //               batch
+    uint64_t *lm;                  //               source bits
+    int64_t *lo;                   //               first adjacency position (per level)
+    int64_t cap;                   // log capacity (entries)
+    WideLevel *lvl;                // per-level records, nlev + 2 of them
+    int32_t *flags;                // [0]: nonzero after an overflow (value = tag)
+    int32_t tag;
+};
+hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s);
+hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,
+                              hipStream_t s);
+hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_t s);
+// *out = max_i dist[i] (device int32), for the level bound of pruned BFS
+hipError_t launch_max_dist(const void *dist, int dist_bytes, int64_t n, int32_t *out, hipStream_t s);
+
 hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s);
 hipError_t launch_u16_to_u8(const uint16_t *in, uint8_t *out, int64_t n, hipStream_t s);
 hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);

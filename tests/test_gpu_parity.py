@@ -116,3 +116,54 @@ def test_greedy_rmat16(gclib):
     assert st["edges_alg"] == int(ed_b.sum())
     # F(S) against the definition
     assert int(F[-1]) == oracle.farness(g, grp)
+
+
+ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_ENGINE": "wg"}]
+
+
+@pytest.mark.parametrize("env", ENGINE_ENVS, ids=["default", "chunked", "log-overflow", "wg-engine"])
+def test_engine_configurations(gclib, device, monkeypatch, env):
+    """Launch chunking, frontier-log overflow retries and the per-workgroup
+    engine all give the oracle's gains and greedy picks."""
+    for key, v in env.items():
+        monkeypatch.setenv(key, v)
+    g = graphgen.rmat(12, 16, 7)
+    G = _graph(gclib, g)
+    grp_ref, F_ref, gains_ref = oracle.greedy(g, 4, with_gains=True)
+    dist = G.new_dist(1)
+    far = torch.zeros(1, dtype=torch.int64, device=device)
+    S = []
+    for i, s in enumerate(grp_ref[:3]):
+        _note("engine %s update %d" % (env, i))
+        G.update_dist(int(s), dist, 1, far)
+        S.append(int(s))
+        _note("engine %s gains round %d" % (env, i + 1))
+        cand = torch.arange(g.n, dtype=torch.int32)
+        gain = G.marginal_gains(dist, 1, cand).cpu().numpy()
+        exp = gains_ref[i].copy()
+        exp[np.array(S)] = 0
+        assert np.array_equal(gain, exp)
+    _note("engine %s greedy" % env)
+    grp, F, st = G.greedy_group(4)
+    assert grp.tolist() == grp_ref.tolist() and F.tolist() == F_ref.tolist()
+
+
+def test_marginal_gains_u16_and_duplicates(gclib, device):
+    """16-bit distances (eccentricity > 254), duplicate and member candidates."""
+    g = graphgen.path(600)
+    G = _graph(gclib, g)
+    dist = G.new_dist(2)
+    far = torch.zeros(1, dtype=torch.int64, device=device)
+    S = [17, 444]
+    for s in S:
+        G.update_dist(s, dist, 2, far)
+    torch.cuda.synchronize()
+    assert np.array_equal(dist[: g.n].cpu().numpy().astype(np.int64) & 0xFFFF,
+                          oracle.group_dist(g, S))
+    assert int(far.item()) == oracle.farness(g, S)
+    rng = np.random.default_rng(3)
+    cand = np.concatenate([rng.integers(0, g.n, 150), [17, 17, 444, 5, 5, 5]]).astype(np.int32)
+    _note("gains u16 path600")
+    gain = G.marginal_gains(dist, 2, torch.from_numpy(cand)).cpu().numpy()
+    dS = oracle.group_dist(g, S)
+    assert np.array_equal(gain, oracle.gains(g, dS, cand))
