@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--order", default="plain", choices=["plain", "celf", "learned"])
+    ap.add_argument("--block", type=int, default=64,
+                    help="rounds >= 2: candidates evaluated between threshold updates")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time the other orders and block sizes (reported, not the value)")
     ap.add_argument("--roofline-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -86,12 +90,12 @@ def main():
 
     # ---- timed job
     for _ in range(args.warmup):
-        G.greedy_group(k, order=args.order)
+        G.greedy_group(k, order=args.order, block=args.block)
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        grp, F, st = G.greedy_group(k, order=args.order)
+        grp, F, st = G.greedy_group(k, order=args.order, block=args.block)
         stats.append(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -103,6 +107,22 @@ def main():
     if args.verbose:
         log("stats " + json.dumps({kk: (float(v) if not isinstance(v, np.ndarray) else v.tolist())
                                    for kk, v in stats[-1].items()}))
+
+    variants = {}
+    if args.compare:
+        for order in ("plain", "celf"):
+            for blk in (64, 256):
+                G.greedy_group(k, order=order, block=blk)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                reps = 3
+                for _ in range(reps):
+                    gv, Fv, sv = G.greedy_group(k, order=order, block=blk)
+                torch.cuda.synchronize()
+                ms = 1000 * (time.perf_counter() - t1) / reps
+                assert gv.tolist() == grp.tolist() and Fv.tolist() == F.tolist()
+                variants["%s_b%d" % (order, blk)] = {"ms": round(ms, 3), "evals_later": int(sv["evals_later"])}
+        log("variants " + json.dumps(variants))
 
     # ---- roofline of the dominant kernel: first gain round, all candidates
     s1 = int(grp[0])
@@ -166,10 +186,12 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": "%s, k=%d, %s lazy order" % (desc, k, args.order),
-                   "n": g.n, "nnz": g.nnz, "k": k, "order": args.order, "bitset_width": 64,
+                   "n": g.n, "nnz": g.nnz, "k": k, "order": args.order, "block": args.block,
+                   "bitset_width": 64,
                    "dist_bytes": int(stats[-1]["dist_bytes"])},
         "group_wall_ms": round(ms_per_step, 4),
         "evals": {"round1": int(stats[-1]["evals_round1"]), "later": int(stats[-1]["evals_later"])},
+        "variants": variants or None,
         "breakdown_ms": {kk: round(float(stats[-1][kk]), 3) for kk in
                          ("ms_closest", "ms_round1", "ms_later", "ms_update", "ms_mlp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

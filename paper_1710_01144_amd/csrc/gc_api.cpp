@@ -71,6 +71,7 @@ struct gc_graph {
     const int32_t *d_rp;
     const int32_t *d_ci;
     std::vector<int32_t> h_rp;  // host copy of row_ptr (degrees, orders)
+    std::vector<int32_t> by_degree;  // nodes by decreasing degree, ties ascending id
     int32_t max_deg;
     int32_t num_cu;
     // tuning read once at load time so the workspace layout never changes
@@ -223,6 +224,16 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
     g->num_cu = cus;
+    try {
+        g->by_degree.resize((size_t)n);
+    } catch (...) {
+        delete g;
+        return fail(GC_ENOMEM, "no memory for the degree order");
+    }
+    std::iota(g->by_degree.begin(), g->by_degree.end(), 0);
+    std::stable_sort(g->by_degree.begin(), g->by_degree.end(), [&](int32_t x, int32_t y) {
+        return (rp[x + 1] - rp[x]) > (rp[y + 1] - rp[y]);
+    });
     g->wg_engine = false;
     if (const char *e = getenv("GC_ENGINE")) g->wg_engine = strcmp(e, "wg") == 0;
     g->slots_target = (g->wg_engine ? 4LL : 1LL) * cus;
@@ -254,7 +265,7 @@ constexpr size_t kCtrBytes = 4096;
 
 struct WsLayout {
     size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
-    size_t wvis, ly, lb, lm, lo, lvl, total;
+    size_t wvis, ly, lr, lb, lm, lo, lvl, total;
     int32_t nslots;
     SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
@@ -265,6 +276,7 @@ struct WsLayout {
 constexpr int32_t kMaxLevels = 65536;  // 16-bit distances: at most 65534 levels
 constexpr int kFlagSlot = 16;          // int32 counter slot of the overflow flag
 constexpr int kMaxdSlot = 17;          // int32 counter slot for max d(S,.)
+constexpr int kDoneSlot = 18;          // int32 workgroup counter of the final gain kernel
 
 
 
@@ -312,6 +324,7 @@ WsLayout ws_layout(const gc_graph *g) {
     L.cap = cap;
     L.wvis = o; o += al256((size_t)kmax * L.vis_stride * 8);
     L.ly = o; o += al256((size_t)cap * 4);
+    L.lr = o; o += al256((size_t)cap * 4);
     L.lb = o; o += al256((size_t)cap * 4);
     L.lm = o; o += al256((size_t)cap * 8);
     L.lo = o; o += al256((size_t)cap * 8);
@@ -339,12 +352,15 @@ struct Ws {
         a.vis = reinterpret_cast<uint64_t *>(base + L.wvis);
         a.vis_stride = L.vis_stride;
         a.ly = reinterpret_cast<int32_t *>(base + L.ly);
+        a.lr = reinterpret_cast<int32_t *>(base + L.lr);
         a.lb = reinterpret_cast<int32_t *>(base + L.lb);
         a.lm = reinterpret_cast<uint64_t *>(base + L.lm);
         a.lo = reinterpret_cast<int64_t *>(base + L.lo);
         a.cap = L.cap;
         a.lvl = reinterpret_cast<WideLevel *>(base + L.lvl);
         a.flags = flags();
+        a.done = ctr() + kDoneSlot;
+        a.min_edges = 1024;
         return a;
     }
 };
@@ -457,14 +473,34 @@ int wide_grid(const gc_graph *g) { return 4 * g->num_cu; }
 
 // Marginal gains of count candidates with the device-wide engine.
 // nlev = number of BFS levels to expand (max d(S,.) - 1 suffices; < 0: measure
-// it).  Synchronises the stream once to check for log overflow; an overflowed
-// launch is re-run with fewer batches per launch.
+// it).  d_cand may be device memory or host-mapped pinned memory.  With
+// host-mapped hm_gain/hm_edges/hm_flag (device pointers of pinned buffers) the
+// final kernel writes the results there and no copy call is needed; h_gain/
+// h_edges are their host views (or plain host buffers filled by copies).
+// Synchronises the stream once to check for log overflow; an overflowed
+// launch is redone with fewer batches (then fewer sources) per launch.
+struct HostIO {
+    int64_t *hm_gain = nullptr;   // device pointer of a pinned buffer
+    int64_t *hm_edges = nullptr;
+    int32_t *hm_flag = nullptr;
+    volatile int32_t *h_flag = nullptr;  // host view of hm_flag
+};
+
 int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
               const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
-              int32_t *d_vis, hipStream_t s, int32_t nlev) {
+              int32_t *d_vis, hipStream_t s, int32_t nlev, int64_t *h_gain = nullptr,
+              int64_t *h_edges = nullptr, const HostIO *io = nullptr) {
     if (count <= 0) return GC_OK;
-    if (g->wg_engine)
-        return run_gains_wg(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_vis, s);
+    if (g->wg_engine) {
+        int rc = run_gains_wg(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_vis, s);
+        if (rc) return rc;
+        if (h_gain)
+            HIP_OK(hipMemcpyAsync(h_gain, d_gain, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
+        if (h_edges && d_edges)
+            HIP_OK(hipMemcpyAsync(h_edges, d_edges, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
+        if (h_gain || h_edges) HIP_OK(hipStreamSynchronize(s));
+        return GC_OK;
+    }
     if (nlev < 0) {
         int32_t maxd = 0;
         HIP_OK(launch_max_dist(d_dist, dist_bytes, g->n, w.maxd(), s));
@@ -473,6 +509,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         nlev = std::max(maxd - 1, 0);
     }
     nlev = std::min(nlev, kMaxLevels - 1);
+    const bool mapped = io && io->hm_flag;
     const int grid = wide_grid(g);
     int64_t kb = w.L.kmax;  // batches per launch
     int32_t spb = 64;       // sources per batch
@@ -495,22 +532,40 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             a.edges = d_edges ? d_edges + off : nullptr;
             a.visited = d_vis ? d_vis + off : nullptr;
             a.tag = ++tag;
+            if (mapped) {
+                a.h_gain = io->hm_gain ? io->hm_gain + off : nullptr;
+                a.h_edges = io->hm_edges ? io->hm_edges + off : nullptr;
+                a.h_flag = io->hm_flag;
+            }
             HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
             HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
             HIP_OK(launch_wide_end(a, nlev, grid, s));
             off += a.nsrc;
         }
         int32_t flag = 0;
-        HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
+        if (mapped) {
+            HIP_OK(hipStreamSynchronize(s));
+            flag = *io->h_flag;
+        } else {
+            HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
+            // results go out with the same synchronisation (discarded on overflow)
+            if (h_gain)
+                HIP_OK(hipMemcpyAsync(h_gain, d_gain, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
+            if (h_edges && d_edges)
+                HIP_OK(hipMemcpyAsync(h_edges, d_edges, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+        }
         if (flag == 0) return GC_OK;
         // chunk `flag` overflowed the frontier log: it and the chunks after it
         // are redone with fewer batches (then fewer sources per batch) per
-        // launch, after clearing the visited words.  One source per launch
-        // claims each node at most once, so it always fits (cap >= n).
+        // launch, after clearing the visited words and level records.  One
+        // source per launch claims each node at most once, so it always fits
+        // (cap >= n).
         done += (int64_t)(flag - 1) * per;
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.wvis),
                                (size_t)w.L.kmax * w.L.vis_stride * 2, 0u, s));
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
+                               (size_t)(nlev + 2) * sizeof(WideLevel) / 4, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
         if (kb > 1) kb = std::max<int64_t>(1, kb / 2);
         else if (spb > 1) spb = std::max(1, spb / 2);
@@ -521,20 +576,42 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     return GC_OK;
 }
 
+// d(S,.) <- min(d(S,.), d(root,.)) and F(S) -= g(root, S) with the
+// edge-balanced engine (S != {}); asynchronous.  nlev = max d(S,.) - 1.
+int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int dist_bytes,
+                    int64_t *d_far, hipStream_t s, int32_t nlev) {
+    nlev = std::min(std::max(nlev, 0), kMaxLevels - 1);
+    WideArgs a = w.wide();
+    a.rp = g->d_rp;
+    a.ci = g->d_ci;
+    a.n = g->n;
+    a.dist = d_dist;
+    a.src = nullptr;
+    a.root = root;
+    a.nsrc = 1;
+    a.spb = 1;
+    a.gain = w.far() + 1;
+    a.tag = 1;
+    a.write = true;
+    a.far = d_far;
+    const int grid = wide_grid(g);
+    HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
+    HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
+    HIP_OK(launch_wide_end(a, nlev, grid, s));
+    return GC_OK;
+}
+
 // s_1 = argmin (F({v}), v): the top-k closeness search of Section 3.1 with
 // k = 1.  A full BFS from the highest-degree node gives a first bound; every
 // node whose level-0 bound already exceeds it is dropped on the host, the
 // rest run the cut BFS batches in decreasing-degree order.
 int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, int64_t *far,
-                int64_t *sources, int32_t *ecc_out) {
+                int64_t *sources, int32_t *ecc_out, int32_t *v0_out = nullptr) {
     const int32_t n = g->n;
     const auto &rp = g->h_rp;
-    std::vector<int32_t> order((size_t)n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-        return (rp[x + 1] - rp[x]) > (rp[y + 1] - rp[y]);
-    });
+    const auto &order = g->by_degree;
     const int32_t v0 = order[0];
+    if (v0_out) *v0_out = v0;
     // full BFS from v0 in 16-bit distances
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.dist16()), ((size_t)n * 2 + 3) / 4,
                            0xFFFFFFFFu, s));
@@ -687,13 +764,28 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     std::vector<int64_t> ub((size_t)n, std::numeric_limits<int64_t>::max());
     std::vector<int32_t> last_eval((size_t)n, -1);
     std::vector<uint8_t> ds_at_eval;  // d(S,v) when v was last evaluated (features)
-    PinnedBuf pin_cand, pin_gain;
+    // pinned host buffers the kernels read and write directly (no copy calls)
+    PinnedBuf pin_cand, pin_gain, pin_flag;
     if (pin_cand.ensure(sizeof(int32_t) * (size_t)n) != hipSuccess ||
-        pin_gain.ensure(sizeof(int64_t) * (size_t)n * 2) != hipSuccess)
+        pin_gain.ensure(sizeof(int64_t) * (size_t)n * 2) != hipSuccess ||
+        pin_flag.ensure(256) != hipSuccess)
         return fail(GC_ENOMEM, "pinned host buffers");
     int32_t *hc = reinterpret_cast<int32_t *>(pin_cand.p);
     int64_t *hg = reinterpret_cast<int64_t *>(pin_gain.p);
     int64_t *he = hg + n;
+    int32_t *hflag = reinterpret_cast<int32_t *>(pin_flag.p);
+    *hflag = 0;
+    int32_t *dc = nullptr;
+    int64_t *dg = nullptr;
+    int32_t *dflag = nullptr;
+    HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dc), hc, 0));
+    HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dg), hg, 0));
+    HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dflag), hflag, 0));
+    HostIO io;
+    io.hm_gain = dg;
+    io.hm_edges = dg + n;
+    io.hm_flag = dflag;
+    io.h_flag = hflag;
     const bool want_edges = true;
 
     // ---- s_1 (Algorithm "mem-greedy", first line) and d(S,.) of S = {s_1}
@@ -701,19 +793,26 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     int32_t s1;
     int64_t F1;
     int32_t dist_bytes = 1;
+    int32_t v0 = -1, ecc_v0 = 0;
     if (o.nprefix > 0) {
         s1 = o.h_prefix[0];
     } else {
-        rc = run_closest(g, w, s, &s1, &F1, &st.closest_sources, nullptr);
+        rc = run_closest(g, w, s, &s1, &F1, &st.closest_sources, &ecc_v0, &v0);
         if (rc) return rc;
     }
     st.ms_closest = now_ms() - t0;
     t0 = now_ms();
-    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.dist16()), ((size_t)n * 2 + 3) / 4,
-                           0xFFFFFFFFu, s));
     int32_t ecc = 0, claimed = 0;
-    rc = run_update(g, w, s1, w.dist16(), 2, w.far(), s, &ecc, &claimed);
-    if (rc) return rc;
+    if (s1 == v0) {
+        // the closeness search already left d(v0,.) and F({v0}) in the workspace
+        ecc = ecc_v0;
+        claimed = n;
+    } else {
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.dist16()), ((size_t)n * 2 + 3) / 4,
+                               0xFFFFFFFFu, s));
+        rc = run_update(g, w, s1, w.dist16(), 2, w.far(), s, &ecc, &claimed);
+        if (rc) return rc;
+    }
     if (claimed != n) return fail(GC_ERANGE, "eccentricity of node %d exceeds 65534", s1);
     void *d_dist;
     if (ecc <= 254) {
@@ -738,8 +837,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     for (int32_t i = 1; i < o.nprefix; ++i) {
         const int32_t v = o.h_prefix[i];
         t0 = now_ms();
-        rc = run_update(g, w, v, d_dist, dist_bytes, w.far(), s, nullptr, nullptr,
-                        std::max(ecc_bound - 1, 0));
+        rc = run_update_wide(g, w, v, d_dist, dist_bytes, w.far(), s, ecc_bound - 1);
         if (rc) return rc;
         HIP_OK(hipMemcpyAsync(&F, w.far(), sizeof(F), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
@@ -753,48 +851,71 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
 
     // evaluate a list of candidates, returning gains (and edges) on the host
     auto evaluate = [&](int32_t cnt) -> int {
-        HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
-        int r = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(),
-                          want_edges ? w.aux() : nullptr, want_edges ? w.aux2() : nullptr, s,
-                          std::max(ecc_bound - 1, 0));
+        int r;
+        if (g->wg_engine) {
+            HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
+            r = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(),
+                          want_edges ? w.aux() : nullptr, nullptr, s,
+                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr);
+        } else {
+            r = run_gains(g, w, d_dist, dist_bytes, dc, cnt, w.gain(),
+                          want_edges ? w.aux() : nullptr, nullptr, s,
+                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr, &io);
+        }
         if (r) return r;
-        HIP_OK(hipMemcpyAsync(hg, w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
-        if (want_edges)
-            HIP_OK(hipMemcpyAsync(he, w.aux(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
         st.gain_launches += 1;
         return GC_OK;
     };
 
-    std::vector<int32_t> order;
+    // Lazy selection (Section 4.2).  A candidate u is skipped while its gain
+    // from an earlier round -- an upper bound by supermodularity -- cannot beat
+    // the best (gain, -id) found so far in this round; the round ends when no
+    // candidate is left that could.  With the key (ub, -id) compared
+    // lexicographically the pick is the plain greedy's pick (smallest id among
+    // equal gains) for every candidate order.
+    //   plain: ascending id scan; CELF: a lazy max-heap on (ub, -id).
+    struct HeapEntry {
+        int64_t ub;
+        int32_t id;
+        uint32_t ver;
+    };
+    auto heap_less = [](const HeapEntry &x, const HeapEntry &y) {
+        return x.ub < y.ub || (x.ub == y.ub && x.id > y.id);
+    };
+    std::vector<HeapEntry> heap;
+    std::vector<uint32_t> ver;
     const int32_t first_gain_round = (int32_t)group.size();
     for (int32_t r = first_gain_round; r < k; ++r) {
         const double tr = now_ms();
         int64_t best_gain = -1;
         int32_t best_id = -1;
         int64_t nev = 0;
-        // candidate order for this round (ties: ascending id)
-        order.clear();
-        for (int32_t v = 0; v < n; ++v)
-            if (!inS[v]) order.push_back(v);
-        if (o.order == GC_ORDER_CELF) {
-            std::stable_sort(order.begin(), order.end(),
-                             [&](int32_t x, int32_t y) { return ub[x] > ub[y]; });
-        }
-        // no bounds exist yet in the first round: every candidate is evaluated
+        auto can_beat = [&](int32_t u) {
+            return best_id < 0 || ub[u] > best_gain || (ub[u] == best_gain && u < best_id);
+        };
+        // no bounds exist yet in the first round: every candidate is evaluated at once
         const bool first_round = (r == first_gain_round);
-        size_t pos = 0;
+        const bool use_heap = !first_round && o.order == GC_ORDER_CELF;
         const int32_t blk = first_round ? n : block;
+        int32_t pos = 0;
         for (;;) {
             int32_t cnt = 0;
-            while (pos < order.size() && cnt < blk) {
-                const int32_t u = order[pos++];
-                // skip: stale gain (an upper bound, Section 4.2) cannot beat the best
-                if (best_id >= 0 && (ub[u] < best_gain || (ub[u] == best_gain && u > best_id))) {
-                    if (o.order == GC_ORDER_CELF) { pos = order.size(); break; }
-                    continue;
+            if (use_heap) {
+                while (cnt < blk && !heap.empty()) {
+                    const HeapEntry top = heap.front();
+                    if (inS[top.id] || top.ver != ver[top.id]) {
+                        std::pop_heap(heap.begin(), heap.end(), heap_less);
+                        heap.pop_back();
+                        continue;
+                    }
+                    if (!can_beat(top.id)) break;  // nothing below the top can either
+                    std::pop_heap(heap.begin(), heap.end(), heap_less);
+                    heap.pop_back();
+                    hc[cnt++] = top.id;
                 }
-                hc[cnt++] = u;
+            } else {
+                for (; pos < n && cnt < blk; ++pos)
+                    if (!inS[pos] && can_beat(pos)) hc[cnt++] = pos;
             }
             if (cnt == 0) break;
             rc = evaluate(cnt);
@@ -809,8 +930,20 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     best_gain = gu;
                     best_id = u;
                 }
+                if (use_heap) {
+                    ++ver[u];
+                    heap.push_back(HeapEntry{gu, u, ver[u]});
+                    std::push_heap(heap.begin(), heap.end(), heap_less);
+                }
             }
             nev += cnt;
+        }
+        if (first_round && o.order == GC_ORDER_CELF) {
+            ver.assign((size_t)n, 0u);
+            heap.clear();
+            for (int32_t v = 0; v < n; ++v)
+                if (!inS[v] && v != best_id) heap.push_back(HeapEntry{ub[v], v, 0u});
+            std::make_heap(heap.begin(), heap.end(), heap_less);
         }
         if (first_round) {
             st.evals_round1 += nev;
@@ -824,8 +957,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         if (best_id < 0) return fail(GC_EINVAL, "no candidate left");
         // pick, then d(S,.) <- min(d(S,.), d(pick,.)) by pruned BFS
         t0 = now_ms();
-        rc = run_update(g, w, best_id, d_dist, dist_bytes, w.far(), s, nullptr, nullptr,
-                        std::max(ecc_bound - 1, 0));
+        rc = run_update_wide(g, w, best_id, d_dist, dist_bytes, w.far(), s, ecc_bound - 1);
         if (rc) return rc;
         F -= best_gain;
         if (o.debug_checks || r == k - 1) {

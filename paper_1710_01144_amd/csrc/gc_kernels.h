@@ -95,6 +95,7 @@ struct WideArgs {
     uint64_t *vis;                 // batch b: vis[b*vis_stride .. +n), zero between launches
     size_t vis_stride;
     int32_t *ly;                   // frontier log: node
+    int32_t *lr;                   //               row start of the node
     int32_t *lb;                   //               batch
     uint64_t *lm;                  //               source bits
     int64_t *lo;                   //               first adjacency position (per level)
@@ -102,6 +103,18 @@ struct WideArgs {
     WideLevel *lvl;                // per-level records, nlev + 2 of them
     int32_t *flags;                // [0]: nonzero after an overflow (value = tag)
     int32_t tag;
+    int32_t min_edges;             // adjacency entries per workgroup before a level
+                                   // uses more workgroups (small levels stay compact)
+    int32_t *done;                 // workgroup counter of the final kernel (zero between launches)
+    // optional host-mapped destinations written by the final kernel
+    int64_t *h_gain;
+    int64_t *h_edges;
+    int32_t *h_flag;
+    // d(S,.) update mode: one source (the pick), distances written in place,
+    // *far -= its gain at the end
+    bool write;
+    int64_t *far;
+    int32_t root;                  // source when src is null (nsrc = 1)
 };
 hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s);
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,

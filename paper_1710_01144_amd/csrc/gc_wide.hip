@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kWin = 256;   // entries staged per window
 constexpr int kUnroll = 4;  // edges per thread per step (independent loads in flight)
+constexpr int kLdsSrc = 1024;  // launches with at most this many sources sum gains in LDS
 constexpr uint64_t kM40 = (1ull << 40) - 1;
 
 __device__ __forceinline__ int lane_id() {
@@ -53,7 +54,8 @@ __device__ __forceinline__ void set_flag(int32_t *flag, int32_t v) {
 // Append entries of lanes with p to the frontier of the next level.  Called
 // by every lane of a fully active wave.
 __device__ __forceinline__ void push_entries(const WideArgs &a, WideLevel *nl, int64_t nbase, bool p,
-                                             int32_t y, int32_t b, uint64_t bits, int32_t deg) {
+                                             int32_t y, int32_t rs, int32_t b, uint64_t bits,
+                                             int32_t deg) {
     const uint64_t bal = __ballot(p);
     if (bal == 0) return;
     const int lane = lane_id();
@@ -80,39 +82,30 @@ __device__ __forceinline__ void push_entries(const WideArgs &a, WideLevel *nl, i
         return;
     }
     a.ly[pos] = y;
+    a.lr[pos] = rs;
     a.lb[pos] = b;
     a.lm[pos] = bits;
     a.lo[pos] = (int64_t)(old & kM40) + (incl - dp);
 }
 
-__global__ void k_wide_zero(WideArgs a, int32_t nlev) {
-    const int64_t tot = (int64_t)a.nsrc > (int64_t)nlev + 2 ? (int64_t)a.nsrc : (int64_t)nlev + 2;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (i < a.nsrc) {
-            a.gain[i] = 0;
-            if (a.edges) a.edges[i] = 0;
-            if (a.visited) a.visited[i] = 0;
-        }
-        if (i < nlev + 2) {
-            a.lvl[i].start = 0;
-            a.lvl[i].packed = 0ull;
-        }
-    }
-}
-
 // Level 0: every source claims its own node (weight d(S,v) - 0).
-template <typename DistT>
+// WRITE: the d(S,.) update after a pick -- a claimed node also stores its
+// new distance (in place: a later test against it fails, and the visited bit
+// settles concurrent claims), and the single source's gain is F(S) - F(S+s).
+template <typename DistT, bool WRITE>
 __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
     if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    const DistT *dist = reinterpret_cast<const DistT *>(a.dist);
+    DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     bool p = false;
-    int32_t v = 0, b = 0, deg = 0;
+    int32_t v = 0, b = 0, deg = 0, rs = 0;
     uint64_t nw = 0;
     if (t < a.nsrc) {
-        v = a.src[t];
+        v = a.src ? a.src[t] : a.root;
         b = (int32_t)(t / a.spb);
+        a.gain[t] = 0;
+        if (a.edges) a.edges[t] = 0;
+        if (a.visited) a.visited[t] = 0;
         const uint32_t d = dist[v];
         if (d > 0u) {
             const uint64_t bit = 1ull << (t - (int64_t)b * a.spb);
@@ -120,7 +113,9 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
             const uint64_t old = atomicOr(w, (unsigned long long)bit);
             nw = bit & ~old;
             if (nw) {
-                deg = a.rp[v + 1] - a.rp[v];
+                if (WRITE) dist[v] = 0;
+                rs = a.rp[v];
+                deg = a.rp[v + 1] - rs;
                 a.gain[t] = (int64_t)d;
                 if (a.edges) a.edges[t] = deg;
                 if (a.visited) a.visited[t] = 1;
@@ -128,16 +123,94 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
             }
         }
     }
-    push_entries(a, &a.lvl[0], 0, p, v, b, nw, deg);
+    push_entries(a, &a.lvl[0], 0, p, v, rs, b, nw, deg);
 }
 
-template <typename DistT>
+// Work-group-wide append: thread t holds up to kUnroll new entries (p[r]);
+// one 64-bit atomic reserves the slots and adjacency ranges of all of them.
+__device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int64_t nbase,
+                                           const bool *p, const int32_t *y, const int32_t *rs,
+                                           const int32_t *bb, const uint64_t *nw, const int32_t *deg,
+                                           int64_t *s_wc, int64_t *s_wd, uint64_t *s_old) {
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    int64_t c = 0, dsum = 0;
+#pragma unroll
+    for (int r = 0; r < kUnroll; ++r)
+        if (p[r]) {
+            c += 1;
+            dsum += deg[r];
+        }
+    int64_t ic = c, id = dsum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t tc = __shfl_up(ic, o);
+        const int64_t td = __shfl_up(id, o);
+        if (lane >= o) {
+            ic += tc;
+            id += td;
+        }
+    }
+    if (lane == 63) {
+        s_wc[w] = ic;
+        s_wd[w] = id;
+    }
+    __syncthreads();
+    int64_t pc = 0, pd = 0, tc = 0, td = 0;
+#pragma unroll
+    for (int k = 0; k < kWG / 64; ++k) {
+        if (k < w) {
+            pc += s_wc[k];
+            pd += s_wd[k];
+        }
+        tc += s_wc[k];
+        td += s_wd[k];
+    }
+    if (threadIdx.x == 0) {
+        uint64_t old = 0;
+        if (tc > 0) {
+            old = atomicAdd(&nl->packed, ((unsigned long long)tc << 40) + (unsigned long long)td);
+            if ((old & kM40) + (uint64_t)td >= (1ull << 39) || (old >> 40) + (uint64_t)tc >= (1ull << 24))
+                set_flag(a.flags, a.tag);
+        }
+        *s_old = old;
+    }
+    __syncthreads();
+    if (tc == 0) return;
+    const uint64_t old = *s_old;
+    int64_t idx = (int64_t)(old >> 40) + pc + (ic - c);
+    int64_t off = (int64_t)(old & kM40) + pd + (id - dsum);
+#pragma unroll
+    for (int r = 0; r < kUnroll; ++r) {
+        if (!p[r]) continue;
+        const int64_t pos = nbase + idx;
+        if (pos < a.cap) {
+            a.ly[pos] = y[r];
+            a.lr[pos] = rs[r];
+            a.lb[pos] = bb[r];
+            a.lm[pos] = nw[r];
+            a.lo[pos] = off;
+        } else {
+            set_flag(a.flags, a.tag);
+        }
+        idx += 1;
+        off += deg[r];
+    }
+}
+
+template <typename DistT, bool WRITE>
 __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     __shared__ int64_t s_off[kWin + 1];
     __shared__ int32_t s_rs[kWin];
     __shared__ int32_t s_b[kWin];
     __shared__ uint64_t s_m[kWin];
     __shared__ int64_t s_first;
+    __shared__ int64_t s_wc[kWG / 64], s_wd[kWG / 64];
+    __shared__ uint64_t s_old;
+    // per-source sums when the launch is small enough (flushed once at the end)
+    __shared__ unsigned long long s_g[kLdsSrc];
+    __shared__ unsigned long long s_e[kLdsSrc];
+    __shared__ unsigned int s_v[kLdsSrc];
 
     if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const WideLevel me = a.lvl[L];
@@ -148,19 +221,33 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) a.lvl[L + 1].start = nbase;
     if (E == 0) return;
-    const int64_t G = gridDim.x;
+    // small levels use few workgroups: each takes at least min_edges entries
+    int64_t G = (E + a.min_edges - 1) / a.min_edges;
+    if (G > (int64_t)gridDim.x) G = gridDim.x;
+    if ((int64_t)blockIdx.x >= G) return;
     const int64_t eb = E * (int64_t)blockIdx.x / G;
     const int64_t ee = E * ((int64_t)blockIdx.x + 1) / G;
     if (eb >= ee) return;
 
-    const DistT *dist = reinterpret_cast<const DistT *>(a.dist);
+    DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
     const int32_t *__restrict__ rp = a.rp;
     const int32_t *__restrict__ ci = a.ci;
     const uint32_t nl = (uint32_t)L + 1u;
     WideLevel *next = &a.lvl[L + 1];
+    const bool lds_acc = a.nsrc <= kLdsSrc;
+    if (lds_acc) {
+        for (int q = tid; q < a.nsrc; q += kWG) {
+            s_g[q] = 0;
+            s_e[q] = 0;
+            s_v[q] = 0;
+        }
+    }
 
-    // largest entry index i with off[i] <= eb (64-ary search by wave 0)
-    if (tid < 64) {
+    // largest entry index i with off[i] <= eb (64-ary search by wave 0);
+    // the first workgroup starts at entry 0
+    if (blockIdx.x == 0) {
+        if (tid == 0) s_first = 0;
+    } else if (tid < 64) {
         int64_t lo = 0, hi = N - 1;
         while (lo < hi) {
             const int64_t p = lo + ((hi - lo) * tid) / 63;
@@ -183,7 +270,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
         if (tid < cnt) {
             const int64_t q = start + i + tid;
             s_off[tid] = a.lo[q];
-            s_rs[tid] = rp[a.ly[q]];
+            s_rs[tid] = a.lr[q];
             s_b[tid] = a.lb[q];
             s_m[tid] = a.lm[q];
         }
@@ -192,9 +279,10 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
         const int64_t wlo = eb > s_off[0] ? eb : s_off[0];
         const int64_t whi = ee < s_off[cnt] ? ee : s_off[cnt];
         for (int64_t e0 = wlo; e0 < whi; e0 += (int64_t)kWG * kUnroll) {
-            int32_t y[kUnroll];
-            int32_t own[kUnroll];
+            int32_t y[kUnroll], own[kUnroll], bb[kUnroll], deg[kUnroll], rs[kUnroll];
             uint32_t d[kUnroll];
+            bool p[kUnroll];
+            uint64_t nw[kUnroll];
 #pragma unroll
             for (int r = 0; r < kUnroll; ++r) {
                 const int64_t e = e0 + tid + (int64_t)r * kWG;
@@ -214,52 +302,97 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
             for (int r = 0; r < kUnroll; ++r) d[r] = own[r] >= 0 ? (uint32_t)dist[y[r]] : 0u;
 #pragma unroll
             for (int r = 0; r < kUnroll; ++r) {
-                bool p = false;
-                uint64_t nw = 0;
-                int32_t bb = 0, deg = 0;
+                p[r] = false;
+                nw[r] = 0;
+                bb[r] = 0;
+                deg[r] = 0;
+                rs[r] = 0;
                 if (own[r] >= 0 && nl < d[r]) {
-                    bb = s_b[own[r]];
-                    uint64_t *vw = a.vis + (size_t)bb * a.vis_stride + y[r];
+                    bb[r] = s_b[own[r]];
+                    uint64_t *vw = a.vis + (size_t)bb[r] * a.vis_stride + y[r];
+                    // issue the row-pointer loads together with the visited word
+                    rs[r] = rp[y[r]];
+                    const int32_t re = rp[y[r] + 1];
                     const uint64_t m = s_m[own[r]] & ~(*vw);
                     if (m) {
                         const uint64_t old = atomicOr(reinterpret_cast<unsigned long long *>(vw),
                                                       (unsigned long long)m);
-                        nw = m & ~old;
-                        if (nw) {
-                            const int64_t c = (int64_t)(d[r] - nl);
-                            deg = rp[y[r] + 1] - rp[y[r]];
-                            const int64_t gb = (int64_t)bb * a.spb;
-                            for (uint64_t mm = nw; mm; mm &= mm - 1) {
-                                const int j = __ffsll((unsigned long long)mm) - 1;
-                                atomicAdd(reinterpret_cast<unsigned long long *>(a.gain + gb + j),
-                                          (unsigned long long)c);
-                                if (a.edges)
-                                    atomicAdd(reinterpret_cast<unsigned long long *>(a.edges + gb + j),
-                                              (unsigned long long)deg);
-                                if (a.visited) atomicAdd(a.visited + gb + j, 1);
+                        nw[r] = m & ~old;
+                        if (nw[r]) {
+                            if (WRITE) dist[y[r]] = (DistT)nl;
+                            const unsigned long long c = d[r] - nl;
+                            deg[r] = re - rs[r];
+                            const int64_t gb = (int64_t)bb[r] * a.spb;
+                            for (uint64_t mm = nw[r]; mm; mm &= mm - 1) {
+                                const int64_t j = gb + (__ffsll((unsigned long long)mm) - 1);
+                                if (lds_acc) {
+                                    atomicAdd(&s_g[j], c);
+                                    if (a.edges) atomicAdd(&s_e[j], (unsigned long long)deg[r]);
+                                    if (a.visited) atomicAdd(&s_v[j], 1u);
+                                } else {
+                                    atomicAdd(reinterpret_cast<unsigned long long *>(a.gain + j), c);
+                                    if (a.edges)
+                                        atomicAdd(reinterpret_cast<unsigned long long *>(a.edges + j),
+                                                  (unsigned long long)deg[r]);
+                                    if (a.visited) atomicAdd(a.visited + j, 1);
+                                }
                             }
-                            p = true;
+                            p[r] = true;
                         }
                     }
                 }
-                push_entries(a, next, nbase, p, y[r], bb, nw, deg);
             }
+            push_block(a, next, nbase, p, y, rs, bb, nw, deg, s_wc, s_wd, &s_old);
         }
         __syncthreads();
         if (whi >= ee || i + cnt >= N) break;
         i += cnt;
     }
+    if (lds_acc) {
+        __syncthreads();
+        for (int q = tid; q < a.nsrc; q += kWG) {
+            if (s_g[q]) atomicAdd(reinterpret_cast<unsigned long long *>(a.gain + q), s_g[q]);
+            if (a.edges && s_e[q]) atomicAdd(reinterpret_cast<unsigned long long *>(a.edges + q), s_e[q]);
+            if (a.visited && s_v[q]) atomicAdd(a.visited + q, (int)s_v[q]);
+        }
+    }
 }
 
-// Return every touched word of vis to zero (entries of all levels).
-__global__ void k_wide_clear(WideArgs a, int32_t nlev) {
-    if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+// End of a launch: return every touched visited word to zero, copy the
+// results to the host-mapped buffers if given, and (last workgroup) zero the
+// level records so the next launch starts clean.  After an overflow nothing is
+// cleared here; the host clears and retries.
+__global__ void k_wide_end(WideArgs a, int32_t nlev) {
+    const int32_t flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (flag) {
+        if (a.h_flag && blockIdx.x == 0 && threadIdx.x == 0) *a.h_flag = flag;
+        return;
+    }
     const WideLevel last = a.lvl[nlev];
     int64_t tot = last.start + (int64_t)(last.packed >> 40);
     if (tot > a.cap) tot = a.cap;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot;
-         i += (int64_t)gridDim.x * blockDim.x)
-        a.vis[(size_t)a.lb[i] * a.vis_stride + a.ly[i]] = 0;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = t0; i < tot; i += nt) a.vis[(size_t)a.lb[i] * a.vis_stride + a.ly[i]] = 0;
+    if (a.h_gain)
+        for (int64_t i = t0; i < a.nsrc; i += nt) a.h_gain[i] = a.gain[i];
+    if (a.h_edges && a.edges)
+        for (int64_t i = t0; i < a.nsrc; i += nt) a.h_edges[i] = a.edges[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int d = atomicAdd(a.done, 1);
+        if (d == (int)gridDim.x - 1) {
+            // every workgroup has read the level records: reset them
+            for (int32_t l = 0; l <= nlev + 1; ++l) {
+                a.lvl[l].start = 0;
+                a.lvl[l].packed = 0ull;
+            }
+            atomicExch(a.done, 0);
+            if (a.h_flag) *a.h_flag = 0;
+            if (a.far) *a.far -= a.gain[0];  // update: F(S + s) = F(S) - g(s, S)
+        }
+    }
 }
 
 template <typename DistT>
@@ -285,32 +418,38 @@ __global__ void k_set_i32(int32_t *p, int32_t v) {
 }  // namespace
 
 hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s) {
-    const int64_t tot = a.nsrc > nlev + 2 ? a.nsrc : nlev + 2;
-    int g = (int)((tot + 255) / 256);
-    if (g > 2048) g = 2048;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_wide_zero, dim3(g), dim3(256), 0, s, a, nlev);
+    (void)nlev;
     const int groots = (int)((a.nsrc + 255) / 256);
-    if (dist_bytes == 1)
-        hipLaunchKernelGGL((k_wide_roots<uint8_t>), dim3(groots), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_wide_roots<uint16_t>), dim3(groots), dim3(256), 0, s, a);
+    if (dist_bytes == 1) {
+        if (a.write) hipLaunchKernelGGL((k_wide_roots<uint8_t, true>), dim3(groots), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_wide_roots<uint8_t, false>), dim3(groots), dim3(256), 0, s, a);
+    } else {
+        if (a.write) hipLaunchKernelGGL((k_wide_roots<uint16_t, true>), dim3(groots), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_wide_roots<uint16_t, false>), dim3(groots), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,
                               hipStream_t s) {
     for (int32_t L = l0; L < l1; ++L) {
-        if (dist_bytes == 1)
-            hipLaunchKernelGGL((k_wide_level<uint8_t>), dim3(grid), dim3(kWG), 0, s, a, L);
-        else
-            hipLaunchKernelGGL((k_wide_level<uint16_t>), dim3(grid), dim3(kWG), 0, s, a, L);
+        if (dist_bytes == 1) {
+            if (a.write) hipLaunchKernelGGL((k_wide_level<uint8_t, true>), dim3(grid), dim3(kWG), 0, s, a, L);
+            else hipLaunchKernelGGL((k_wide_level<uint8_t, false>), dim3(grid), dim3(kWG), 0, s, a, L);
+        } else {
+            if (a.write) hipLaunchKernelGGL((k_wide_level<uint16_t, true>), dim3(grid), dim3(kWG), 0, s, a, L);
+            else hipLaunchKernelGGL((k_wide_level<uint16_t, false>), dim3(grid), dim3(kWG), 0, s, a, L);
+        }
     }
     return hipGetLastError();
 }
 
 hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_wide_clear, dim3(grid), dim3(256), 0, s, a, nlev);
+    // enough workgroups for the visited-word clean-up of a launch of this size
+    int64_t g = (a.nsrc + 63) / 64 * 4;
+    if (g > grid) g = grid;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_wide_end, dim3((int)g), dim3(256), 0, s, a, nlev);
     return hipGetLastError();
 }
 

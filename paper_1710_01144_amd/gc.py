@@ -212,12 +212,13 @@ class Graph:
         return gain[:count]
 
     def greedy_group(self, k: int, order: str = "plain", block: int = 0, prefix=None,
-                     mlp_params=None, log_capacity: int = 0):
+                     mlp_params=None, log_capacity: int = 0, debug: bool = False):
         lib = load_library()
         opts = GcOpts()
         opts.order = ORDERS[order]
         opts.bitset_width = 64
         opts.block = int(block)
+        opts.debug_checks = 1 if debug else 0
         keep = []
         if prefix is not None and len(prefix) > 0:
             arr = np.ascontiguousarray(prefix, dtype=np.int32)

@@ -103,12 +103,13 @@ def test_greedy_ba2000_k10(gclib):
         assert st["evals_round1"] == g.n - 1
 
 
-def test_greedy_rmat16(gclib):
+@pytest.mark.parametrize("block", [64, 256])
+def test_greedy_rmat16(gclib, block):
     g = graphgen.workload("rmat16")
     G = _graph(gclib, g)
-    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 50, block=64)
-    _note("greedy rmat16 k=50 plain")
-    grp, F, st = G.greedy_group(50, order="plain")
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 50, block=block)
+    _note("greedy rmat16 k=50 plain block %d" % block)
+    grp, F, st = G.greedy_group(50, order="plain", block=block, debug=True)
     assert grp.tolist() == grp_b.tolist()
     assert F.tolist() == F_b.tolist()
     # same scan order and block: the same evaluations as the CPU Greedy++
@@ -116,6 +117,9 @@ def test_greedy_rmat16(gclib):
     assert st["edges_alg"] == int(ed_b.sum())
     # F(S) against the definition
     assert int(F[-1]) == oracle.farness(g, grp)
+    _note("greedy rmat16 k=50 celf block %d" % block)
+    grp_c, F_c, st_c = G.greedy_group(50, order="celf", block=block)
+    assert grp_c.tolist() == grp_b.tolist() and F_c.tolist() == F_b.tolist()
 
 
 ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_ENGINE": "wg"}]
