@@ -74,8 +74,8 @@ typedef struct gc_opts {
                                threshold updates (0 = bitset_width) */
     int32_t nprefix;        /* resume: the first nprefix picks are given */
     const int32_t *h_prefix;/* host, nprefix ids (a previous run's pick order) */
-    const void *d_mlp;      /* GC_ORDER_LEARNED: device MLP parameters, layout of
-                               gc_mlp_param_count(); NULL otherwise */
+    const void *d_mlp;      /* GC_ORDER_LEARNED: device inference block made by
+                               gc_mlp_pack(); NULL otherwise */
     int32_t debug_checks;   /* 1: re-check F(S) == sum_w d(S,w) after every pick */
     int32_t reserved;
     /* optional logging of every exact evaluation (host buffers, may be NULL):
@@ -214,6 +214,63 @@ int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
 int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts, void *d_ws,
                     size_t ws_bytes, hipStream_t stream, int32_t *h_group, int64_t *h_farness,
                     gc_stats *h_stats);
+
+/* --------------------------------------------- candidate-ordering MLP --- */
+/*
+ * Not part of the paper's method: a small network that predicts marginal
+ * gains so that GC_ORDER_LEARNED evaluates likely winners first.  Exact
+ * pruned BFS still decides every pick, so the group and farness do not depend
+ * on the network.  8 features -> 64 -> 64 -> 1 with ReLU; weights bfloat16,
+ * biases and accumulation float32; target log2(1 + gain).
+ *
+ * Master parameters: float32[GC_MLP_PARAMS] in the order W1 (64x8, row j =
+ * hidden unit j), b1 (64), W2 (64x64, row j = unit j), b2 (64), W3 (64), b3.
+ * Inference block: gc_mlp_block_bytes() bytes made by gc_mlp_pack (bf16
+ * weights rounded to nearest-even, float32 biases).
+ * Rounding points: x = bf16(feature); h1 = bf16(relu(W1 x + b1));
+ * h2 = bf16(relu(W2 h1 + b2)); out = W3 h2 + b3 (float32).
+ */
+#define GC_MLP_INPUTS 8
+#define GC_MLP_HIDDEN 64
+#define GC_MLP_PARAMS 4801
+
+size_t gc_mlp_block_bytes(void);
+/* master float32 -> inference block; asynchronous */
+int gc_mlp_pack(const float *d_master, void *d_block, hipStream_t stream);
+/*
+ * gc_mlp_forward -- out[s] for count samples; d_x float32 [count x 8].
+ * d_h1, d_h2: optional float32 [count x 64] activations (as bf16 values),
+ * needed by gc_mlp_backward.  Asynchronous.
+ */
+int gc_mlp_forward(const void *d_block, const float *d_x, int32_t count, float *d_out, float *d_h1,
+                   float *d_h2, hipStream_t stream);
+/* floats of scratch gc_mlp_backward needs for count samples */
+size_t gc_mlp_scratch_floats(int32_t count);
+/*
+ * gc_mlp_backward -- gradient of the mean squared error
+ * (1/count) sum_s (out_s - y_s)^2 with respect to the master parameters,
+ * d_grad float32[GC_MLP_PARAMS] in the master layout.  Uses the activations
+ * of gc_mlp_forward; products of bf16 values, float32 sums in sample order.
+ */
+int gc_mlp_backward(const void *d_block, const float *d_x, const float *d_h1, const float *d_h2,
+                    const float *d_out, const float *d_y, int32_t count, float *d_grad,
+                    float *d_scratch, hipStream_t stream);
+/* one Adam step (Kingma and Ba) on the master vector; step counts from 1 */
+int gc_mlp_adam(float *d_master, float *d_m, float *d_v, const float *d_grad, int32_t step,
+                float lr, float beta1, float beta2, float eps, hipStream_t stream);
+/*
+ * gc_node_features -- the 8 features of the learned order for count nodes
+ * (d_cand, or nodes 0..count-1 when NULL), float32 [count x 8]:
+ *   log2(1+deg v), d(S,v)/ecc1, log2(1+ub[v]), log2(1+sum_{u in N(v)} deg u),
+ *   log2(1+round-last_eval[v]) (round if never), d_at_eval[v]-d(S,v) (0 if
+ *   never), round/k, log2(1+d(S,v)).
+ * d_ub int64[n] (stale gains), d_last_eval int32[n] (-1 = never),
+ * d_dist_at_eval uint16[n].  Asynchronous.
+ */
+int gc_node_features(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
+                     const int32_t *d_cand, int32_t count, const int64_t *d_ub,
+                     const int32_t *d_last_eval, const uint16_t *d_dist_at_eval, int32_t round,
+                     int32_t k, int32_t ecc1, float *d_feat, hipStream_t stream);
 
 /* ----------------------------------------------------------------- misc --- */
 

@@ -336,6 +336,7 @@ WsLayout ws_layout(const gc_graph *g) {
 struct Ws {
     WsLayout L;
     char *base;
+    size_t bytes;
     int32_t *ctr() const { return reinterpret_cast<int32_t *>(base + L.ctr); }
     uint16_t *dist16() const { return reinterpret_cast<uint16_t *>(base + L.dist16); }
     uint8_t *dist8() const { return reinterpret_cast<uint8_t *>(base + L.dist8); }
@@ -346,6 +347,27 @@ struct Ws {
     int32_t *aux2() const { return reinterpret_cast<int32_t *>(base + L.aux2); }
     Slots slots() const { return Slots{base + L.slots, L.slot.bytes, L.nslots}; }
     int32_t *flags() const { return ctr() + kFlagSlot; }
+    // learned-order region (after the main layout; see gc_mlp_ws_bytes)
+    struct Mlp {
+        float *feat;
+        float *score;
+        float *twohop;
+        int64_t *ub;
+        int32_t *last_eval;
+        uint16_t *dist_at_eval;
+    };
+    Mlp mlp(int64_t n) const {
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        char *p = base + L.total;
+        Mlp m;
+        m.feat = reinterpret_cast<float *>(p); p += al((size_t)n * 8 * 4);
+        m.score = reinterpret_cast<float *>(p); p += al((size_t)n * 4);
+        m.twohop = reinterpret_cast<float *>(p); p += al((size_t)n * 4);
+        m.ub = reinterpret_cast<int64_t *>(p); p += al((size_t)n * 8);
+        m.last_eval = reinterpret_cast<int32_t *>(p); p += al((size_t)n * 4);
+        m.dist_at_eval = reinterpret_cast<uint16_t *>(p);
+        return m;
+    }
     int32_t *maxd() const { return ctr() + kMaxdSlot; }
     WideArgs wide() const {
         WideArgs a{};
@@ -372,6 +394,7 @@ int get_ws(const gc_graph *g, void *d_ws, size_t ws_bytes, Ws *w) {
     if (((uintptr_t)d_ws & 255) != 0) return fail(GC_EWORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < w->L.total)
         return fail(GC_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w->L.total);
+    w->bytes = ws_bytes;
     w->base = reinterpret_cast<char *>(d_ws);
     return GC_OK;
 }
@@ -484,6 +507,11 @@ struct HostIO {
     int64_t *hm_edges = nullptr;
     int32_t *hm_flag = nullptr;
     volatile int32_t *h_flag = nullptr;  // host view of hm_flag
+    // device copies of the lazy-loop state (learned order features)
+    int64_t *ub = nullptr;
+    int32_t *last_eval = nullptr;
+    uint16_t *dist_at_eval = nullptr;
+    int32_t round = 0;
 };
 
 int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
@@ -532,10 +560,17 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             a.edges = d_edges ? d_edges + off : nullptr;
             a.visited = d_vis ? d_vis + off : nullptr;
             a.tag = ++tag;
+            a.dist_bytes = dist_bytes;
             if (mapped) {
                 a.h_gain = io->hm_gain ? io->hm_gain + off : nullptr;
                 a.h_edges = io->hm_edges ? io->hm_edges + off : nullptr;
                 a.h_flag = io->hm_flag;
+            }
+            if (io && io->ub) {
+                a.ub_out = io->ub;
+                a.le_out = io->last_eval;
+                a.dsat_out = io->dist_at_eval;
+                a.round = io->round;
             }
             HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
             HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
@@ -787,6 +822,27 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     io.hm_flag = dflag;
     io.h_flag = hflag;
     const bool want_edges = true;
+    const bool learned = o.order == GC_ORDER_LEARNED;
+    const bool logging = o.log_capacity > 0 && o.h_log_round && o.h_log_node && o.h_log_gain &&
+                         o.h_log_feat && o.h_log_count;
+    const bool need_state = learned || logging;
+    if (need_state && ws_bytes < w.L.total + gc_mlp_ws_bytes(n))
+        return fail(GC_EWORKSPACE, "learned order / logging needs the full gc_workspace_size()");
+    PinnedBuf pin_score, pin_feat;
+    float *hscore = nullptr, *dscore = nullptr, *hfeat = nullptr, *dfeat = nullptr;
+    if (need_state) {
+        if (pin_score.ensure(sizeof(float) * (size_t)n) != hipSuccess)
+            return fail(GC_ENOMEM, "pinned score buffer");
+        hscore = reinterpret_cast<float *>(pin_score.p);
+        HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dscore), hscore, 0));
+        if (logging) {
+            if (pin_feat.ensure(sizeof(float) * 8 * (size_t)n) != hipSuccess)
+                return fail(GC_ENOMEM, "pinned feature buffer");
+            hfeat = reinterpret_cast<float *>(pin_feat.p);
+            HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dfeat), hfeat, 0));
+            *o.h_log_count = 0;
+        }
+    }
 
     // ---- s_1 (Algorithm "mem-greedy", first line) and d(S,.) of S = {s_1}
     double t0 = now_ms();
@@ -874,6 +930,45 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     // lexicographically the pick is the plain greedy's pick (smallest id among
     // equal gains) for every candidate order.
     //   plain: ascending id scan; CELF: a lazy max-heap on (ub, -id).
+    const Ws::Mlp mw = w.mlp(n);
+    if (need_state) {
+        HIP_OK(launch_twohop(g->d_rp, g->d_ci, n, mw.twohop, s));
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(mw.ub), (size_t)n * 2, 0u, s));
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(mw.last_eval), (size_t)n, 0xFFFFFFFFu, s));
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(mw.dist_at_eval), ((size_t)n + 1) / 2, 0u, s));
+        io.ub = mw.ub;
+        io.last_eval = mw.last_eval;
+        io.dist_at_eval = mw.dist_at_eval;
+    }
+    // features of every node and (learned order) their scores, at a round start
+    auto score_round = [&](int32_t r) -> int {
+        const double tm = now_ms();
+        FeatArgs fa;
+        fa.rp = g->d_rp;
+        fa.ci = g->d_ci;
+        fa.dist = d_dist;
+        fa.cand = nullptr;
+        fa.count = n;
+        fa.ub = mw.ub;
+        fa.last_eval = mw.last_eval;
+        fa.dist_at_eval = mw.dist_at_eval;
+        fa.twohop = mw.twohop;
+        fa.round = r;
+        fa.k = k;
+        fa.ecc1 = ecc_bound;
+        fa.feat = logging ? dfeat : mw.feat;
+        HIP_OK(launch_features(fa, dist_bytes, s));
+        if (learned)
+            HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(o.d_mlp), fa.feat, n, nullptr,
+                                      nullptr, nullptr, mw.ub, dscore, s));
+        HIP_OK(hipStreamSynchronize(s));
+        st.ms_mlp += now_ms() - tm;
+        return GC_OK;
+    };
+    std::vector<int32_t> pool;
+    auto score_before = [&](int32_t x, int32_t y) {
+        return hscore[x] > hscore[y] || (hscore[x] == hscore[y] && x < y);
+    };
     struct HeapEntry {
         int64_t ub;
         int32_t id;
@@ -895,12 +990,53 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         };
         // no bounds exist yet in the first round: every candidate is evaluated at once
         const bool first_round = (r == first_gain_round);
-        const bool use_heap = !first_round && o.order == GC_ORDER_CELF;
+        const bool use_heap = !first_round && (o.order == GC_ORDER_CELF || learned);
         const int32_t blk = first_round ? n : block;
         int32_t pos = 0;
+        io.round = r;
+        if (need_state && !first_round) {
+            rc = score_round(r);
+            if (rc) return rc;
+        }
+        bool learned_first_block = learned && !first_round;
         for (;;) {
             int32_t cnt = 0;
-            if (use_heap) {
+            if (learned && !first_round) {
+                pool.clear();
+                if (learned_first_block) {
+                    // nothing evaluated yet: every live candidate can win;
+                    // take the best-scored block of them
+                    for (int32_t v = 0; v < n; ++v)
+                        if (!inS[v]) pool.push_back(v);
+                    const size_t take = std::min<size_t>((size_t)blk, pool.size());
+                    std::partial_sort(pool.begin(), pool.begin() + take, pool.end(), score_before);
+                    for (size_t j = 0; j < take; ++j) hc[cnt++] = pool[j];
+                    learned_first_block = false;
+                } else {
+                    // candidates whose bound can still win, best-scored first
+                    while (!heap.empty()) {
+                        const HeapEntry top = heap.front();
+                        if (inS[top.id] || top.ver != ver[top.id]) {
+                            std::pop_heap(heap.begin(), heap.end(), heap_less);
+                            heap.pop_back();
+                            continue;
+                        }
+                        if (!can_beat(top.id)) break;
+                        std::pop_heap(heap.begin(), heap.end(), heap_less);
+                        heap.pop_back();
+                        pool.push_back(top.id);
+                    }
+                    std::sort(pool.begin(), pool.end(), score_before);
+                    for (size_t j = 0; j < pool.size(); ++j) {
+                        if (cnt < blk) {
+                            hc[cnt++] = pool[j];
+                        } else {  // not taken now: back into the heap unchanged
+                            heap.push_back(HeapEntry{ub[pool[j]], pool[j], ver[pool[j]]});
+                            std::push_heap(heap.begin(), heap.end(), heap_less);
+                        }
+                    }
+                }
+            } else if (use_heap) {
                 while (cnt < blk && !heap.empty()) {
                     const HeapEntry top = heap.front();
                     if (inS[top.id] || top.ver != ver[top.id]) {
@@ -920,6 +1056,16 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             if (cnt == 0) break;
             rc = evaluate(cnt);
             if (rc) return rc;
+            if (logging && !first_round) {
+                for (int32_t j = 0; j < cnt; ++j) {
+                    const int64_t at = (*o.h_log_count)++;
+                    if (at >= o.log_capacity) continue;
+                    o.h_log_round[at] = r;
+                    o.h_log_node[at] = hc[j];
+                    o.h_log_gain[at] = hg[j];
+                    std::memcpy(o.h_log_feat + at * 8, hfeat + (size_t)hc[j] * 8, 8 * sizeof(float));
+                }
+            }
             for (int32_t j = 0; j < cnt; ++j) {
                 const int32_t u = hc[j];
                 const int64_t gu = hg[j];
@@ -938,7 +1084,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             }
             nev += cnt;
         }
-        if (first_round && o.order == GC_ORDER_CELF) {
+        if (first_round && (o.order == GC_ORDER_CELF || learned)) {
             ver.assign((size_t)n, 0u);
             heap.clear();
             for (int32_t v = 0; v < n; ++v)
@@ -980,5 +1126,77 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     }
     st.ms_total = now_ms() - t_start;
     if (h_stats) *h_stats = st;
+    return GC_OK;
+}
+
+// ------------------------------------------------ candidate-ordering MLP
+
+extern "C" size_t gc_mlp_block_bytes(void) { return sizeof(MlpBlock); }
+
+extern "C" int gc_mlp_pack(const float *d_master, void *d_block, hipStream_t stream) {
+    if (!d_master || !d_block) return fail(GC_EINVAL, "NULL device pointer");
+    HIP_OK(launch_mlp_pack(d_master, reinterpret_cast<MlpBlock *>(d_block), stream));
+    return GC_OK;
+}
+
+extern "C" int gc_mlp_forward(const void *d_block, const float *d_x, int32_t count, float *d_out,
+                              float *d_h1, float *d_h2, hipStream_t stream) {
+    if (count < 0) return fail(GC_EINVAL, "count < 0");
+    if (count > 0 && (!d_block || !d_x || !d_out)) return fail(GC_EINVAL, "NULL device pointer");
+    HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(d_block), d_x, count, d_out, d_h1,
+                              d_h2, nullptr, nullptr, stream));
+    return GC_OK;
+}
+
+extern "C" size_t gc_mlp_scratch_floats(int32_t count) {
+    if (count < 0) return 0;
+    return ((size_t)count + 63) / 64 * 64 + 2 * (size_t)count * GC_MLP_HIDDEN;
+}
+
+extern "C" int gc_mlp_backward(const void *d_block, const float *d_x, const float *d_h1,
+                               const float *d_h2, const float *d_out, const float *d_y,
+                               int32_t count, float *d_grad, float *d_scratch, hipStream_t stream) {
+    if (count < 1) return fail(GC_EINVAL, "count must be >= 1");
+    if (!d_block || !d_x || !d_h1 || !d_h2 || !d_out || !d_y || !d_grad || !d_scratch)
+        return fail(GC_EINVAL, "NULL device pointer");
+    HIP_OK(launch_mlp_backward(reinterpret_cast<const MlpBlock *>(d_block), d_x, d_h1, d_h2, d_out,
+                               d_y, count, d_grad, d_scratch, stream));
+    return GC_OK;
+}
+
+extern "C" int gc_mlp_adam(float *d_master, float *d_m, float *d_v, const float *d_grad,
+                           int32_t step, float lr, float beta1, float beta2, float eps,
+                           hipStream_t stream) {
+    if (!d_master || !d_m || !d_v || !d_grad) return fail(GC_EINVAL, "NULL device pointer");
+    if (step < 1) return fail(GC_EINVAL, "step counts from 1");
+    HIP_OK(launch_mlp_adam(d_master, d_m, d_v, d_grad, step, lr, beta1, beta2, eps, stream));
+    return GC_OK;
+}
+
+extern "C" int gc_node_features(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
+                                const int32_t *d_cand, int32_t count, const int64_t *d_ub,
+                                const int32_t *d_last_eval, const uint16_t *d_dist_at_eval,
+                                int32_t round, int32_t k, int32_t ecc1, float *d_feat,
+                                hipStream_t stream) {
+    if (!g) return fail(GC_EINVAL, "graph is NULL");
+    if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
+    if (count < 0) return fail(GC_EINVAL, "count < 0");
+    if (count > 0 && (!d_dist || !d_ub || !d_last_eval || !d_dist_at_eval || !d_feat))
+        return fail(GC_EINVAL, "NULL device pointer");
+    FeatArgs fa;
+    fa.rp = g->d_rp;
+    fa.ci = g->d_ci;
+    fa.dist = d_dist;
+    fa.cand = d_cand;
+    fa.count = count;
+    fa.ub = d_ub;
+    fa.last_eval = d_last_eval;
+    fa.dist_at_eval = d_dist_at_eval;
+    fa.twohop = nullptr;
+    fa.round = round;
+    fa.k = k;
+    fa.ecc1 = ecc1;
+    fa.feat = d_feat;
+    HIP_OK(launch_features(fa, dist_bytes, stream));
     return GC_OK;
 }

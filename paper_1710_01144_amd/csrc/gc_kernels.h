@@ -115,6 +115,12 @@ struct WideArgs {
     bool write;
     int64_t *far;
     int32_t root;                  // source when src is null (nsrc = 1)
+    // optional scatter of the results into per-node lazy-loop state
+    int64_t *ub_out;               // ub[src[i]] = gain[i]
+    int32_t *le_out;               // last_eval[src[i]] = round
+    uint16_t *dsat_out;            // dist_at_eval[src[i]] = d(S, src[i])
+    int32_t round;
+    int32_t dist_bytes;
 };
 hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s);
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,

@@ -378,6 +378,14 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
         for (int64_t i = t0; i < a.nsrc; i += nt) a.h_gain[i] = a.gain[i];
     if (a.h_edges && a.edges)
         for (int64_t i = t0; i < a.nsrc; i += nt) a.h_edges[i] = a.edges[i];
+    if (a.ub_out)
+        for (int64_t i = t0; i < a.nsrc; i += nt) {
+            const int32_t v = a.src[i];
+            a.ub_out[v] = a.gain[i];
+            a.le_out[v] = a.round;
+            a.dsat_out[v] = a.dist_bytes == 1 ? (uint16_t)reinterpret_cast<const uint8_t *>(a.dist)[v]
+                                              : reinterpret_cast<const uint16_t *>(a.dist)[v];
+        }
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();

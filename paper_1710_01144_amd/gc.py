@@ -35,7 +35,12 @@ ORDERS = {"plain": ORDER_PLAIN, "celf": ORDER_CELF, "learned": ORDER_LEARNED}
 
 EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_workspace_size",
             "gc_workspace_init", "gc_closest_node", "gc_update_dist", "gc_marginal_gains",
-            "gc_greedy_group", "gc_strerror", "gc_last_error"]
+            "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
+            "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
+            "gc_node_features"]
+MLP_PARAMS = 4801
+MLP_IN = 8
+MLP_HIDDEN = 64
 
 
 class GCError(RuntimeError):
@@ -108,6 +113,21 @@ def load_library():
     lib.gc_greedy_group.argtypes = [vp, i32, ctypes.POINTER(GcOpts), vp, ctypes.c_size_t, vp,
                                     ctypes.POINTER(i32), ctypes.POINTER(i64),
                                     ctypes.POINTER(GcStats)]
+    lib.gc_mlp_block_bytes.restype = ctypes.c_size_t
+    lib.gc_mlp_block_bytes.argtypes = []
+    lib.gc_mlp_pack.restype = ctypes.c_int
+    lib.gc_mlp_pack.argtypes = [vp, vp, vp]
+    lib.gc_mlp_forward.restype = ctypes.c_int
+    lib.gc_mlp_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.gc_mlp_scratch_floats.restype = ctypes.c_size_t
+    lib.gc_mlp_scratch_floats.argtypes = [i32]
+    lib.gc_mlp_backward.restype = ctypes.c_int
+    lib.gc_mlp_backward.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.gc_mlp_adam.restype = ctypes.c_int
+    lib.gc_mlp_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, vp]
+    lib.gc_node_features.restype = ctypes.c_int
+    lib.gc_node_features.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp]
     lib.gc_strerror.restype = ctypes.c_char_p
     lib.gc_strerror.argtypes = [ctypes.c_int]
     lib.gc_last_error.restype = ctypes.c_char_p
@@ -211,6 +231,17 @@ class Graph:
             return gain[:count], edges[:count], vis[:count]
         return gain[:count]
 
+    def node_features(self, dist, dist_bytes, ub, last_eval, dist_at_eval, round_, k, ecc1,
+                      cand=None):
+        dev = self.row_ptr.device
+        count = self.n if cand is None else int(cand.numel())
+        feat = torch.empty((max(count, 1), MLP_IN), dtype=torch.float32, device=dev)
+        _check(load_library().gc_node_features(self.handle, _ptr(dist), dist_bytes,
+                                               _ptr(cand), count, _ptr(ub), _ptr(last_eval),
+                                               _ptr(dist_at_eval), int(round_), int(k), int(ecc1),
+                                               _ptr(feat), _stream()))
+        return feat[:count]
+
     def greedy_group(self, k: int, order: str = "plain", block: int = 0, prefix=None,
                      mlp_params=None, log_capacity: int = 0, debug: bool = False):
         lib = load_library()
@@ -254,3 +285,82 @@ class Graph:
             c = int(min(log["count"][0], log_capacity))
             stats["log"] = {key: v[:c] for key, v in log.items() if key != "count"}
         return group, far, stats
+
+
+class Mlp:
+    """Device state of the candidate-ordering MLP: float32 master weights,
+    Adam moments and the packed bf16 inference block (all torch tensors)."""
+
+    def __init__(self, master, device=None):
+        lib = load_library()
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        m = torch.as_tensor(np.asarray(master, dtype=np.float32))
+        assert m.numel() == MLP_PARAMS
+        self.master = m.to(dev).contiguous()
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.block = torch.zeros(int(lib.gc_mlp_block_bytes()), dtype=torch.uint8, device=dev)
+        self.step = 0
+        self.pack()
+
+    def pack(self):
+        _check(load_library().gc_mlp_pack(_ptr(self.master), _ptr(self.block), _stream()))
+
+    def forward(self, x, activations: bool = False):
+        x = x.contiguous()
+        count = int(x.shape[0])
+        dev = self.master.device
+        out = torch.empty(max(count, 1), dtype=torch.float32, device=dev)
+        h1 = h2 = None
+        if activations:
+            h1 = torch.empty((max(count, 1), MLP_HIDDEN), dtype=torch.float32, device=dev)
+            h2 = torch.empty_like(h1)
+        _check(load_library().gc_mlp_forward(_ptr(self.block), _ptr(x), count, _ptr(out), _ptr(h1),
+                                             _ptr(h2), _stream()))
+        if activations:
+            return out[:count], h1[:count], h2[:count]
+        return out[:count]
+
+    def backward(self, x, h1, h2, out, y):
+        lib = load_library()
+        count = int(x.shape[0])
+        dev = self.master.device
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev)
+        scratch = torch.empty(int(lib.gc_mlp_scratch_floats(count)), dtype=torch.float32, device=dev)
+        _check(lib.gc_mlp_backward(_ptr(self.block), _ptr(x.contiguous()), _ptr(h1), _ptr(h2),
+                                   _ptr(out), _ptr(y.contiguous()), count, _ptr(grad), _ptr(scratch),
+                                   _stream()))
+        return grad
+
+    def adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(load_library().gc_mlp_adam(_ptr(self.master), _ptr(self.m), _ptr(self.v), _ptr(grad),
+                                          self.step, lr, beta1, beta2, eps, _stream()))
+        self.pack()
+
+    def train(self, X, Y, steps: int = 2000, batch: int = 1024, lr: float = 3e-3, seed: int = 0):
+        """Minibatch Adam on (X, Y) (numpy float32); batches are contiguous
+        slices of a host-side permutation redrawn every epoch."""
+        dev = self.master.device
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        N = X.shape[0]
+        batch = min(batch, N)
+        rng = np.random.default_rng(seed)
+        losses = []
+        s = 0
+        while s < steps:
+            perm = rng.permutation(N)
+            Xd = torch.from_numpy(X[perm]).to(dev)
+            Yd = torch.from_numpy(Y[perm]).to(dev)
+            for lo in range(0, N - batch + 1, batch):
+                if s >= steps:
+                    break
+                xb, yb = Xd[lo:lo + batch], Yd[lo:lo + batch]
+                out, h1, h2 = self.forward(xb, activations=True)
+                g = self.backward(xb, h1, h2, out, yb)
+                self.adam(g, lr=lr)
+                if s % 100 == 0 or s == steps - 1:
+                    losses.append(float(((out - yb) ** 2).mean().item()))
+                s += 1
+        return losses
