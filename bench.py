@@ -59,7 +59,35 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU baseline: repeat the oracle run until this much time is spent")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--calib-bytes", type=int, default=1 << 30,
+                    help="size of the plain device copy timed (and profiled) as the bandwidth "
+                         "and counter calibration")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ["paper_1710_01144_amd/csrc/gc_wide.hip", "paper_1710_01144_amd/csrc/gc_kernels.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per first-round launch from the committed rocprofv3 counter
+    summary, or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "k_wide_level_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def log(msg):
@@ -141,18 +169,39 @@ def main():
     V1 = int(v_c.to(torch.int64).sum().item())
     alg_bytes = 8 * V1 + (4 + dist_bytes) * E1
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # kernel time of the launch: HIP events recorded by the library on this
+    # stream right before its first and after its last gain kernel
+    gc.timing_enable(True)
     G.marginal_gains(dist, dist_bytes, cand)  # warm
-    ev0.record(stream)
+    times = []
     for _ in range(args.roofline_reps):
         G.marginal_gains(dist, dist_bytes, cand)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = ev0.elapsed_time(ev1) / args.roofline_reps
+        times.append(gc.timing_last_ms())
+    gc.timing_enable(False)
+    kern_ms = float(np.mean(times))
     achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
+    traffic = measured_traffic(args.workload)
     log("round-1 gain launch: %d candidates, E_alg %d, |V| %d, %.3f ms, %.1f GB/s algorithmic"
         % (cand.numel(), E1, V1, kern_ms, achieved))
+
+    # ---- a plain copy of known size: measured bandwidth and counter scale
+    copy_gbs = None
+    if args.calib_bytes > 0:
+        nb = args.calib_bytes // 4
+        src_t = torch.ones(nb, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(5):
+            dst_t.copy_(src_t)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms = c0.elapsed_time(c1) / 5
+        copy_gbs = 2 * nb * 4 / (copy_ms / 1000.0) / 1e9
+        log("copy calibration: %d bytes read + written in %.3f ms = %.1f GB/s" % (nb * 4, copy_ms, copy_gbs))
+        del src_t, dst_t
 
     # ---- CPU baseline: the oracle's Greedy++ (tier B) on the same job
     cpu = None
@@ -195,9 +244,10 @@ def main():
         "breakdown_ms": {kk: round(float(stats[-1][kk]), 3) for kk in
                          ("ms_closest", "ms_round1", "ms_later", "ms_update", "ms_mlp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "kernel": "k_engine gain mode (first gain round, %d candidates)" % cand.numel(),
-                     "kernel_ms": round(kern_ms, 4), "alg_bytes": alg_bytes},
+                     "kernel_ms": round(kern_ms, 4), "alg_bytes": alg_bytes,
+                     "copy_gbs_measured": round(copy_gbs, 1) if copy_gbs else None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

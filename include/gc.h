@@ -277,6 +277,15 @@ int gc_node_features(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
 const char *gc_strerror(int code);
 const char *gc_last_error(void);
 
+/*
+ * Kernel timing for measurement: with gc_timing_enable(1) every marginal-gain
+ * evaluation records two HIP events on its stream, immediately before its
+ * first and after its last kernel; gc_timing_last_ms() returns the elapsed
+ * time of the last one (-1 if none).  Per host thread.
+ */
+int gc_timing_enable(int on);
+double gc_timing_last_ms(void);
+
 #ifdef __cplusplus
 }
 #endif

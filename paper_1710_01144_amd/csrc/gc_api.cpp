@@ -58,6 +58,26 @@ extern "C" const char *gc_strerror(int code) {
 
 extern "C" const char *gc_last_error(void) { return g_last_error.c_str(); }
 
+// Optional HIP-event timing of the gain kernels (gc_timing_enable).
+static thread_local bool g_timing = false;
+static thread_local float g_timing_ms = -1.f;
+static thread_local hipEvent_t g_ev0 = nullptr, g_ev1 = nullptr;
+
+extern "C" int gc_timing_enable(int on) {
+    g_timing = on != 0;
+    if (g_timing && !g_ev0) {
+        if (hipEventCreate(&g_ev0) != hipSuccess || hipEventCreate(&g_ev1) != hipSuccess) {
+            g_timing = false;
+            g_last_error = "hipEventCreate failed";
+            return GC_EDEVICE;
+        }
+    }
+    g_timing_ms = -1.f;
+    return GC_OK;
+}
+
+extern "C" double gc_timing_last_ms(void) { return (double)g_timing_ms; }
+
 static double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -539,6 +559,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     nlev = std::min(nlev, kMaxLevels - 1);
     const bool mapped = io && io->hm_flag;
     const int grid = wide_grid(g);
+    if (g_timing) HIP_OK(hipEventRecord(g_ev0, s));
     int64_t kb = w.L.kmax;  // batches per launch
     int32_t spb = 64;       // sources per batch
     int64_t done = 0;
@@ -578,6 +599,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             off += a.nsrc;
         }
         int32_t flag = 0;
+        if (g_timing) HIP_OK(hipEventRecord(g_ev1, s));
         if (mapped) {
             HIP_OK(hipStreamSynchronize(s));
             flag = *io->h_flag;
@@ -590,7 +612,10 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                 HIP_OK(hipMemcpyAsync(h_edges, d_edges, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
             HIP_OK(hipStreamSynchronize(s));
         }
-        if (flag == 0) return GC_OK;
+        if (flag == 0) {
+            if (g_timing) HIP_OK(hipEventElapsedTime(&g_timing_ms, g_ev0, g_ev1));
+            return GC_OK;
+        }
         // chunk `flag` overflowed the frontier log: it and the chunks after it
         // are redone with fewer batches (then fewer sources per batch) per
         // launch, after clearing the visited words and level records.  One

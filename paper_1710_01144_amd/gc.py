@@ -37,7 +37,7 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_workspace_init", "gc_closest_node", "gc_update_dist", "gc_marginal_gains",
             "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
-            "gc_node_features"]
+            "gc_node_features", "gc_timing_enable", "gc_timing_last_ms"]
 MLP_PARAMS = 4801
 MLP_IN = 8
 MLP_HIDDEN = 64
@@ -128,12 +128,24 @@ def load_library():
                                 ctypes.c_float, vp]
     lib.gc_node_features.restype = ctypes.c_int
     lib.gc_node_features.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp]
+    lib.gc_timing_enable.restype = ctypes.c_int
+    lib.gc_timing_enable.argtypes = [ctypes.c_int]
+    lib.gc_timing_last_ms.restype = ctypes.c_double
+    lib.gc_timing_last_ms.argtypes = []
     lib.gc_strerror.restype = ctypes.c_char_p
     lib.gc_strerror.argtypes = [ctypes.c_int]
     lib.gc_last_error.restype = ctypes.c_char_p
     lib.gc_last_error.argtypes = []
     _lib = lib
     return lib
+
+
+def timing_enable(on: bool = True):
+    _check(load_library().gc_timing_enable(1 if on else 0))
+
+
+def timing_last_ms() -> float:
+    return float(load_library().gc_timing_last_ms())
 
 
 def _check(rc: int):
