@@ -99,6 +99,9 @@ struct gc_graph {
     int64_t vis_budget;     // GC_VIS_BUDGET_MB (bytes)
     int64_t log_entries;    // GC_LOG_ENTRIES
     bool wg_engine;         // GC_ENGINE=wg
+    int32_t level_wgs_per_cu;  // GC_LEVEL_WGS (workgroups per CU of a level kernel)
+    int32_t unroll;         // GC_UNROLL (4 or 8)
+    int32_t min_edges;      // GC_MIN_EDGES (adjacency entries per workgroup)
 };
 
 extern "C" int32_t gc_graph_n(const gc_graph *g) { return g ? g->n : -1; }
@@ -265,6 +268,21 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
     if (const char *e = getenv("GC_VIS_BUDGET_MB")) {
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->vis_budget = (int64_t)v << 20;
+    }
+    g->level_wgs_per_cu = 4;
+    if (const char *e = getenv("GC_LEVEL_WGS")) {
+        long v = strtol(e, nullptr, 10);
+        if (v >= 1 && v <= 64) g->level_wgs_per_cu = (int32_t)v;
+    }
+    g->unroll = 8;
+    if (const char *e = getenv("GC_UNROLL")) {
+        const long v = strtol(e, nullptr, 10);
+        g->unroll = v >= 16 ? 16 : (v >= 8 ? 8 : 4);
+    }
+    g->min_edges = 512;
+    if (const char *e = getenv("GC_MIN_EDGES")) {
+        long v = strtol(e, nullptr, 10);
+        if (v >= 16) g->min_edges = (int32_t)v;
     }
     g->log_entries = (int64_t)8 << 20;
     if (const char *e = getenv("GC_LOG_ENTRIES")) {
@@ -512,7 +530,7 @@ int run_gains_wg(const gc_graph *g, const Ws &w, const void *d_dist, int dist_by
     return GC_OK;
 }
 
-int wide_grid(const gc_graph *g) { return 4 * g->num_cu; }
+int wide_grid(const gc_graph *g) { return g->level_wgs_per_cu * g->num_cu; }
 
 // Marginal gains of count candidates with the device-wide engine.
 // nlev = number of BFS levels to expand (max d(S,.) - 1 suffices; < 0: measure
@@ -570,6 +588,8 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         int64_t off = done;
         while (off < count) {
             WideArgs a = w.wide();
+            a.unroll = g->unroll;
+            a.min_edges = g->min_edges;
             a.rp = g->d_rp;
             a.ci = g->d_ci;
             a.n = g->n;
@@ -642,6 +662,8 @@ int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, 
                     int64_t *d_far, hipStream_t s, int32_t nlev) {
     nlev = std::min(std::max(nlev, 0), kMaxLevels - 1);
     WideArgs a = w.wide();
+    a.unroll = g->unroll;
+    a.min_edges = g->min_edges;
     a.rp = g->d_rp;
     a.ci = g->d_ci;
     a.n = g->n;

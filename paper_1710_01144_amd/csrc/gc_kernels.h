@@ -121,6 +121,7 @@ struct WideArgs {
     uint16_t *dsat_out;            // dist_at_eval[src[i]] = d(S, src[i])
     int32_t round;
     int32_t dist_bytes;
+    int32_t unroll;                // 4 or 8 edges per thread per step (large launches)
 };
 hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s);
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,

@@ -30,7 +30,6 @@ namespace gck {
 namespace {
 
 constexpr int kWin = 256;   // entries staged per window
-constexpr int kUnroll = 4;  // edges per thread per step (independent loads in flight)
 constexpr int kLdsSrc = 1024;  // launches with at most this many sources sum gains in LDS
 constexpr uint64_t kM40 = (1ull << 40) - 1;
 
@@ -126,8 +125,9 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
     push_entries(a, &a.lvl[0], 0, p, v, rs, b, nw, deg);
 }
 
-// Work-group-wide append: thread t holds up to kUnroll new entries (p[r]);
+// Work-group-wide append: thread t holds up to U new entries (p[r]);
 // one 64-bit atomic reserves the slots and adjacency ranges of all of them.
+template <int U>
 __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int64_t nbase,
                                            const bool *p, const int32_t *y, const int32_t *rs,
                                            const int32_t *bb, const uint64_t *nw, const int32_t *deg,
@@ -136,7 +136,7 @@ __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int
     const int w = threadIdx.x >> 6;
     int64_t c = 0, dsum = 0;
 #pragma unroll
-    for (int r = 0; r < kUnroll; ++r)
+    for (int r = 0; r < U; ++r)
         if (p[r]) {
             c += 1;
             dsum += deg[r];
@@ -181,7 +181,7 @@ __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int
     int64_t idx = (int64_t)(old >> 40) + pc + (ic - c);
     int64_t off = (int64_t)(old & kM40) + pd + (id - dsum);
 #pragma unroll
-    for (int r = 0; r < kUnroll; ++r) {
+    for (int r = 0; r < U; ++r) {
         if (!p[r]) continue;
         const int64_t pos = nbase + idx;
         if (pos < a.cap) {
@@ -198,7 +198,10 @@ __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int
     }
 }
 
-template <typename DistT, bool WRITE>
+// LDS: per-source sums in LDS (launches of <= kLdsSrc sources); large
+// launches add straight to global memory and keep LDS small for occupancy.
+// U: edges per thread per step.
+template <typename DistT, bool WRITE, bool LDS, int U>
 __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     __shared__ int64_t s_off[kWin + 1];
     __shared__ int32_t s_rs[kWin];
@@ -208,9 +211,9 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     __shared__ int64_t s_wc[kWG / 64], s_wd[kWG / 64];
     __shared__ uint64_t s_old;
     // per-source sums when the launch is small enough (flushed once at the end)
-    __shared__ unsigned long long s_g[kLdsSrc];
-    __shared__ unsigned long long s_e[kLdsSrc];
-    __shared__ unsigned int s_v[kLdsSrc];
+    __shared__ unsigned long long s_g[LDS ? kLdsSrc : 1];
+    __shared__ unsigned long long s_e[LDS ? kLdsSrc : 1];
+    __shared__ unsigned int s_v[LDS ? kLdsSrc : 1];
 
     if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const WideLevel me = a.lvl[L];
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     const int32_t *__restrict__ ci = a.ci;
     const uint32_t nl = (uint32_t)L + 1u;
     WideLevel *next = &a.lvl[L + 1];
-    const bool lds_acc = a.nsrc <= kLdsSrc;
+    constexpr bool lds_acc = LDS;
     if (lds_acc) {
         for (int q = tid; q < a.nsrc; q += kWG) {
             s_g[q] = 0;
@@ -278,13 +281,13 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
         __syncthreads();
         const int64_t wlo = eb > s_off[0] ? eb : s_off[0];
         const int64_t whi = ee < s_off[cnt] ? ee : s_off[cnt];
-        for (int64_t e0 = wlo; e0 < whi; e0 += (int64_t)kWG * kUnroll) {
-            int32_t y[kUnroll], own[kUnroll], bb[kUnroll], deg[kUnroll], rs[kUnroll];
-            uint32_t d[kUnroll];
-            bool p[kUnroll];
-            uint64_t nw[kUnroll];
+        for (int64_t e0 = wlo; e0 < whi; e0 += (int64_t)kWG * U) {
+            int32_t y[U], own[U], bb[U], deg[U], rs[U];
+            uint32_t d[U];
+            bool p[U];
+            uint64_t nw[U];
 #pragma unroll
-            for (int r = 0; r < kUnroll; ++r) {
+            for (int r = 0; r < U; ++r) {
                 const int64_t e = e0 + tid + (int64_t)r * kWG;
                 own[r] = -1;
                 y[r] = 0;
@@ -299,9 +302,9 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kUnroll; ++r) d[r] = own[r] >= 0 ? (uint32_t)dist[y[r]] : 0u;
+            for (int r = 0; r < U; ++r) d[r] = own[r] >= 0 ? (uint32_t)dist[y[r]] : 0u;
 #pragma unroll
-            for (int r = 0; r < kUnroll; ++r) {
+            for (int r = 0; r < U; ++r) {
                 p[r] = false;
                 nw[r] = 0;
                 bb[r] = 0;
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                     }
                 }
             }
-            push_block(a, next, nbase, p, y, rs, bb, nw, deg, s_wc, s_wd, &s_old);
+            push_block<U>(a, next, nbase, p, y, rs, bb, nw, deg, s_wc, s_wd, &s_old);
         }
         __syncthreads();
         if (whi >= ee || i + cnt >= N) break;
@@ -438,15 +441,32 @@ hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hi
     return hipGetLastError();
 }
 
+template <typename DistT, bool WRITE>
+static void launch_level(const WideArgs &a, int32_t L, int grid, hipStream_t s) {
+    const bool lds = a.nsrc <= kLdsSrc;
+    if (lds) {
+        if (a.unroll >= 8)
+            hipLaunchKernelGGL((k_wide_level<DistT, WRITE, true, 8>), dim3(grid), dim3(kWG), 0, s, a, L);
+        else
+            hipLaunchKernelGGL((k_wide_level<DistT, WRITE, true, 4>), dim3(grid), dim3(kWG), 0, s, a, L);
+    } else if (a.unroll == 16) {
+        hipLaunchKernelGGL((k_wide_level<DistT, WRITE, false, 16>), dim3(grid), dim3(kWG), 0, s, a, L);
+    } else if (a.unroll == 8) {
+        hipLaunchKernelGGL((k_wide_level<DistT, WRITE, false, 8>), dim3(grid), dim3(kWG), 0, s, a, L);
+    } else {
+        hipLaunchKernelGGL((k_wide_level<DistT, WRITE, false, 4>), dim3(grid), dim3(kWG), 0, s, a, L);
+    }
+}
+
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,
                               hipStream_t s) {
     for (int32_t L = l0; L < l1; ++L) {
         if (dist_bytes == 1) {
-            if (a.write) hipLaunchKernelGGL((k_wide_level<uint8_t, true>), dim3(grid), dim3(kWG), 0, s, a, L);
-            else hipLaunchKernelGGL((k_wide_level<uint8_t, false>), dim3(grid), dim3(kWG), 0, s, a, L);
+            if (a.write) launch_level<uint8_t, true>(a, L, grid, s);
+            else launch_level<uint8_t, false>(a, L, grid, s);
         } else {
-            if (a.write) hipLaunchKernelGGL((k_wide_level<uint16_t, true>), dim3(grid), dim3(kWG), 0, s, a, L);
-            else hipLaunchKernelGGL((k_wide_level<uint16_t, false>), dim3(grid), dim3(kWG), 0, s, a, L);
+            if (a.write) launch_level<uint16_t, true>(a, L, grid, s);
+            else launch_level<uint16_t, false>(a, L, grid, s);
         }
     }
     return hipGetLastError();

@@ -171,3 +171,56 @@ def test_marginal_gains_u16_and_duplicates(gclib, device):
     gain = G.marginal_gains(dist, 2, torch.from_numpy(cand)).cpu().numpy()
     dS = oracle.group_dist(g, S)
     assert np.array_equal(gain, oracle.gains(g, dS, cand))
+
+
+def test_greedy_grid_u16(gclib):
+    """High-diameter perturbed grid (16-bit distances when ecc > 254)."""
+    g = graphgen.grid(900, 5, 9, shortcut_frac=0.0)
+    G = _graph(gclib, g)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 12, block=64)
+    for order in ("plain", "celf"):
+        _note("greedy grid900x5 k=12 %s" % order)
+        grp, F, st = G.greedy_group(12, order=order, debug=True)
+        assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+        if order == "plain":
+            assert st["evals_per_round"].tolist() == ev_b.tolist()
+    assert st["dist_bytes"] == 2
+
+
+@pytest.mark.parametrize("side", [64, 128])
+def test_greedy_grid_square(gclib, side):
+    g = graphgen.grid(side, side, 10 + side)
+    G = _graph(gclib, g)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 20, block=64)
+    _note("greedy grid%d k=20" % side)
+    grp, F, st = G.greedy_group(20, debug=True)
+    assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+    assert st["evals_per_round"].tolist() == ev_b.tolist()
+    assert st["edges_alg"] == int(ed_b.sum())
+
+
+def test_greedy_rmat20_k100_full_size(gclib):
+    """R-MAT scale 20, k = 100: the whole group, every F(S_i) and the
+    evaluation counts per round against the CPU Greedy++ at full size."""
+    g = graphgen.workload("rmat20")
+    G = _graph(gclib, g)
+    _note("greedy rmat20 k=100 (GPU)")
+    grp, F, st = G.greedy_group(100, order="plain")
+    _note("greedy rmat20 k=100 (CPU oracle, tier B)")
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 100, block=64)
+    assert grp.tolist() == grp_b.tolist()
+    assert F.tolist() == F_b.tolist()
+    assert st["evals_per_round"].tolist() == ev_b.tolist()
+    assert st["edges_alg"] == int(ed_b.sum())
+    # F(S_k) from the definition, one BFS per member
+    assert int(F[-1]) == oracle.farness(g, grp)
+    # sampled round-2 gains one by one by full BFS
+    dS = oracle.group_dist(g, grp[:1])
+    rng = np.random.default_rng(5)
+    cand = rng.choice(g.n, 40, replace=False).astype(np.int32)
+    dist = G.new_dist(st["dist_bytes"])
+    import torch
+    far = torch.zeros(1, dtype=torch.int64, device=G.row_ptr.device)
+    G.update_dist(int(grp[0]), dist, st["dist_bytes"], far)
+    got = G.marginal_gains(dist, st["dist_bytes"], torch.from_numpy(cand)).cpu().numpy()
+    assert np.array_equal(got, oracle.gains(g, dS, cand))
