@@ -33,7 +33,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + ["-c", path, "-o", obj]
     else:
-        cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
+        cmd = [HIPCC, "--offload-arch=" + ARCH] + COMMON + ["-c", path, "-o", obj]
     subprocess.check_call(cmd)
     return obj
 

@@ -303,7 +303,7 @@ constexpr size_t kCtrBytes = 4096;
 
 struct WsLayout {
     size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
-    size_t wvis, ly, lr, lb, lm, lo, lvl, total;
+    size_t wvis, ly, lr, lb, lm, lo, lvl, act, cutprev, farout, total;
     int32_t nslots;
     SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
@@ -367,6 +367,9 @@ WsLayout ws_layout(const gc_graph *g) {
     L.lm = o; o += al256((size_t)cap * 8);
     L.lo = o; o += al256((size_t)cap * 8);
     L.lvl = o; o += al256((size_t)(kMaxLevels + 2) * sizeof(WideLevel));
+    L.act = o; o += al256((size_t)kmax * 8);
+    L.cutprev = o; o += al256(n * 16);
+    L.farout = o; o += al256(n * 8);
     L.total = o;
     return L;
 }
@@ -683,10 +686,66 @@ int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, 
     return GC_OK;
 }
 
+// Full BFS from root into dist16 (uint16, INF = 65535 everywhere first) on the
+// edge-balanced engine in write-back mode: every node's distance is written,
+// *d_far = n*65535 - sum(65535 - d) = sum_w d(root,w) = F({root}), and
+// *ecc_out = max distance (65535 if some node is farther: GC_ERANGE).
+// Synchronises (the depth is not known in advance).
+int run_full_bfs(const gc_graph *g, const Ws &w, int32_t root, uint16_t *dist16, int64_t *d_far,
+                 hipStream_t s, int32_t *ecc_out) {
+    const int32_t n = g->n;
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(dist16), ((size_t)n * 2 + 3) / 4, 0xFFFFFFFFu, s));
+    HIP_OK(launch_set_i64(d_far, (int64_t)n * 65535, s));
+    WideArgs a = w.wide();
+    a.unroll = g->unroll;
+    a.min_edges = g->min_edges;
+    a.rp = g->d_rp;
+    a.ci = g->d_ci;
+    a.n = n;
+    a.dist = dist16;
+    a.src = nullptr;
+    a.root = root;
+    a.nsrc = 1;
+    a.spb = 1;
+    a.gain = w.far() + 1;
+    a.tag = 1;
+    a.write = true;
+    a.far = d_far;
+    a.dist_bytes = 2;
+    const int grid = wide_grid(g);
+    HIP_OK(launch_wide_begin(a, 2, 0, s));
+    int32_t L = 0;
+    for (;;) {
+        const int32_t step = L < 16 ? 4 : 16;
+        const int32_t L1 = std::min(L + step, kMaxLevels - 1);
+        HIP_OK(launch_wide_levels(a, 2, L, L1, grid, s));
+        L = L1;
+        WideLevel rec;
+        HIP_OK(hipMemcpyAsync(&rec, reinterpret_cast<WideLevel *>(w.base + w.L.lvl) + L, sizeof(rec),
+                              hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if ((rec.packed >> 40) == 0 || L >= kMaxLevels - 1) break;
+    }
+    HIP_OK(launch_wide_end(a, L, grid, s));
+    int32_t maxd = 0;
+    HIP_OK(launch_max_dist(dist16, 2, n, w.maxd(), s));
+    HIP_OK(hipMemcpyAsync(&maxd, w.maxd(), sizeof(maxd), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    *ecc_out = maxd;
+    return GC_OK;
+}
+
 // s_1 = argmin (F({v}), v): the top-k closeness search of Section 3.1 with
-// k = 1.  A full BFS from the highest-degree node gives a first bound; every
-// node whose level-0 bound already exceeds it is dropped on the host, the
-// rest run the cut BFS batches in decreasing-degree order.
+// k = 1.  A full BFS from the highest-degree node gives a first bound F0.
+// Every node's farness is at least its level-1 bound
+//   deg(v) + 2*min(rem, two(v) - deg(v)) + 3*(rem - min(...)),  rem = n-1-deg(v),
+// (nodes at distance 2 are at most the adjacency of v's neighbours minus one
+// back-edge each; two(v) = sum of neighbour degrees), so nodes whose bound
+// exceeds the best are dropped on the host.  The rest run, by decreasing
+// degree and 64 to a batch, as full multi-source BFS on the device-wide engine
+// (distances from an all-INF array), each source cut as soon as its BFScut
+// bound exceeds the best farness found so far; the bound is re-applied on the
+// host between chunks as the best improves.  Ties: smallest id.
 int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, int64_t *far,
                 int64_t *sources, int32_t *ecc_out, int32_t *v0_out = nullptr) {
     const int32_t n = g->n;
@@ -694,59 +753,129 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     const auto &order = g->by_degree;
     const int32_t v0 = order[0];
     if (v0_out) *v0_out = v0;
-    // full BFS from v0 in 16-bit distances
-    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.dist16()), ((size_t)n * 2 + 3) / 4,
-                           0xFFFFFFFFu, s));
-    int32_t last = 0, claimed = 0;
-    int rc = run_update(g, w, v0, w.dist16(), 2, w.far(), s, &last, &claimed);
+    // full BFS from v0 in 16-bit distances (kept in dist16 for reuse)
+    int32_t last = 0;
+    int rc = run_full_bfs(g, w, v0, w.dist16(), w.far(), s, &last);
     if (rc) return rc;
     int64_t F0 = 0;
     HIP_OK(hipMemcpyAsync(&F0, w.far(), sizeof(F0), hipMemcpyDeviceToHost, s));
+    HIP_OK(launch_twohop_i64(g->d_rp, g->d_ci, n, w.aux(), s));
+    std::vector<int64_t> two((size_t)n);
+    HIP_OK(hipMemcpyAsync(two.data(), w.aux(), sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    if (claimed != n) return fail(GC_ERANGE, "BFS from %d reached %d of %d nodes within 65534 levels",
-                                  v0, claimed, n);
-    // level-0 bound: min(n-1,deg) nodes at distance 1, the rest at >= 2
-    std::vector<int32_t> list;
-    list.reserve((size_t)n);
-    for (int32_t i = 1; i < n; ++i) {
-        const int32_t v = order[i];
-        const int64_t d = std::min<int64_t>(rp[v + 1] - rp[v], (int64_t)n - 1);
-        const int64_t lb0 = d + 2 * ((int64_t)n - 1 - d);
-        if (lb0 <= F0) list.push_back(v);
-    }
+    if (last >= 65535) return fail(GC_ERANGE, "a node is 65535 or more hops from node %d", v0);
     int32_t best = v0;
     int64_t bestF = F0;
-    if (!list.empty()) {
-        const int32_t cnt = (int32_t)list.size();
-        HIP_OK(hipMemcpyAsync(w.cand(), list.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
-        HIP_OK(launch_set_i64(reinterpret_cast<int64_t *>(w.ctr() + C_I64_BASE) + L_BEST_FAR, F0, s));
-        EngineArgs a;
+    auto lb1 = [&](int32_t v) -> int64_t {
+        const int64_t d = rp[v + 1] - rp[v];
+        const int64_t rem = (int64_t)n - 1 - d;
+        int64_t near = two[v] - d;
+        if (near > rem) near = rem;
+        if (near < 0) near = 0;
+        return d + 2 * near + 3 * (rem - near);
+    };
+    auto may_win = [&](int32_t v) {
+        const int64_t b = lb1(v);
+        return b < bestF || (b == bestF && v < best);
+    };
+    std::vector<int32_t> list;
+    for (int32_t i = 1; i < n; ++i)
+        if (may_win(order[i])) list.push_back(order[i]);
+    int64_t nsources = 1;
+    // INF distances for the full BFS: the second level-BFS queue is free here
+    uint16_t *inf16 = reinterpret_cast<uint16_t *>(w.base + w.L.q1);
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(inf16), ((size_t)n * 2 + 3) / 4, 0xFFFFFFFFu, s));
+    int64_t *dbest = reinterpret_cast<int64_t *>(w.ctr() + C_I64_BASE) + L_BEST_FAR;
+    // sources per launch: a full BFS logs at most one entry per (node, level)
+    // per batch, so keep batches * n * (a few levels) within the log
+    // one source per batch: a claim then always settles a node for good, so a
+    // batch logs at most n entries (with several sources per word a node can be
+    // logged once per claiming neighbour and source)
+    int64_t kb = std::max<int64_t>(1, std::min<int64_t>(w.L.kmax, w.L.cap / ((int64_t)n + 64)));
+    int32_t spb = 1;
+    std::vector<int64_t> fo;
+    std::vector<int32_t> chunk;
+    size_t pos = 0;
+    const int grid = wide_grid(g);
+    while (pos < list.size()) {
+        chunk.clear();
+        while (pos < list.size() && (int64_t)chunk.size() < kb * spb) {
+            const int32_t v = list[pos++];
+            if (may_win(v)) chunk.push_back(v);
+        }
+        if (chunk.empty()) break;
+        const int64_t cnt = (int64_t)chunk.size();
+        HIP_OK(hipMemcpyAsync(w.cand(), chunk.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
+        HIP_OK(launch_set_i64(dbest, bestF, s));
+        WideArgs a = w.wide();
+        a.unroll = g->unroll;
+        a.min_edges = g->min_edges;
         a.rp = g->d_rp;
         a.ci = g->d_ci;
         a.n = n;
-        a.dist = nullptr;
+        a.dist = inf16;
         a.src = w.cand();
         a.nsrc = cnt;
-        a.out_gain = w.gain();
-        a.out_edges = nullptr;
-        a.out_vis = nullptr;
-        a.ctr = w.ctr();
-        a.slots = w.slots();
-        HIP_OK(launch_closeness(a, grid_for_batches(w, cnt), s));
-        std::vector<int64_t> F((size_t)cnt);
-        HIP_OK(hipMemcpyAsync(F.data(), w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
+        a.spb = spb;
+        a.gain = w.gain();
+        a.edges = w.aux();
+        a.visited = w.aux2();
+        a.tag = 1;
+        a.dist_bytes = 2;
+        a.active = reinterpret_cast<unsigned long long *>(w.base + w.L.act);
+        a.prev = reinterpret_cast<int64_t *>(w.base + w.L.cutprev);
+        a.far_out = reinterpret_cast<int64_t *>(w.base + w.L.farout);
+        HIP_OK(launch_wide_begin(a, 2, 0, s));
+        int32_t L = 0;
+        bool overflow = false;
+        for (;;) {
+            const int32_t step = 4;
+            for (int32_t i = 0; i < step && L + i < kMaxLevels - 1; ++i) {
+                HIP_OK(launch_wide_levels(a, 2, L + i, L + i + 1, grid, s));
+                HIP_OK(launch_wide_cut(a, L + i, dbest, s));
+            }
+            L = std::min(L + step, kMaxLevels - 1);
+            WideLevel rec;
+            int32_t flag = 0;
+            HIP_OK(hipMemcpyAsync(&rec, reinterpret_cast<WideLevel *>(w.base + w.L.lvl) + L,
+                                  sizeof(rec), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            if (flag) {
+                overflow = true;
+                break;
+            }
+            if ((rec.packed >> 40) == 0 || L >= kMaxLevels - 1) break;
+        }
+        if (overflow) {
+            // too many frontier entries: clear and redo this chunk with fewer sources
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.wvis),
+                                   (size_t)w.L.kmax * w.L.vis_stride * 2, 0u, s));
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
+                                   (size_t)(kMaxLevels + 2) * sizeof(WideLevel) / 4, 0u, s));
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
+            if (kb > 1) kb /= 2;
+            else if (spb > 1) spb = std::max(1, spb / 2);
+            else return fail(GC_EWORKSPACE, "frontier log too small for one source");
+            pos -= chunk.size();
+            continue;
+        }
+        HIP_OK(launch_wide_end(a, L, grid, s));
+        fo.resize((size_t)cnt);
+        HIP_OK(hipMemcpyAsync(fo.data(), a.far_out, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        for (int32_t i = 0; i < cnt; ++i) {
-            if (F[i] < 0) continue;
-            if (F[i] < bestF || (F[i] == bestF && list[i] < best)) {
-                bestF = F[i];
-                best = list[i];
+        nsources += cnt;
+        for (int64_t i = 0; i < cnt; ++i) {
+            if (fo[i] < 0) continue;
+            if (fo[i] < bestF || (fo[i] == bestF && chunk[i] < best)) {
+                bestF = fo[i];
+                best = chunk[i];
             }
         }
     }
     *node = best;
     *far = bestF;
-    if (sources) *sources = 1 + (int64_t)list.size();
+    if (sources) *sources = nsources;
     if (ecc_out) *ecc_out = last;
     return GC_OK;
 }
@@ -911,10 +1040,9 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         ecc = ecc_v0;
         claimed = n;
     } else {
-        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.dist16()), ((size_t)n * 2 + 3) / 4,
-                               0xFFFFFFFFu, s));
-        rc = run_update(g, w, s1, w.dist16(), 2, w.far(), s, &ecc, &claimed);
+        rc = run_full_bfs(g, w, s1, w.dist16(), w.far(), s, &ecc);
         if (rc) return rc;
+        claimed = ecc < 65535 ? n : 0;
     }
     if (claimed != n) return fail(GC_ERANGE, "eccentricity of node %d exceeds 65534", s1);
     void *d_dist;

@@ -122,7 +122,17 @@ struct WideArgs {
     int32_t round;
     int32_t dist_bytes;
     int32_t unroll;                // 4 or 8 edges per thread per step (large launches)
+    // closeness search (first pick): per-batch masks of sources still expanding,
+    // per-source previous (reached, adjacency) totals, farness or -1 (cut)
+    unsigned long long *active;
+    int64_t *prev;                 // 2 x nsrc
+    int64_t *far_out;              // nsrc
 };
+// After level L: BFScut test for every live source of a closeness launch
+// (distances from an all-INF 16-bit array, so F = reached*65535 - gain).
+hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, hipStream_t s);
+hipError_t launch_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n, int64_t *out,
+                             hipStream_t s);
 hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s);
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,
                               hipStream_t s);

@@ -105,6 +105,16 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
         a.gain[t] = 0;
         if (a.edges) a.edges[t] = 0;
         if (a.visited) a.visited[t] = 0;
+        if (a.active) {
+            a.far_out[t] = -1;
+            a.prev[2 * t] = 1;                           // the root itself
+            a.prev[2 * t + 1] = a.rp[v + 1] - a.rp[v];   // its adjacency
+            const int64_t j = t - (int64_t)b * a.spb;
+            if (j == 0) {
+                const int64_t nb = a.nsrc - (int64_t)b * a.spb < a.spb ? a.nsrc - (int64_t)b * a.spb : a.spb;
+                a.active[b] = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+            }
+        }
         const uint32_t d = dist[v];
         if (d > 0u) {
             const uint64_t bit = 1ull << (t - (int64_t)b * a.spb);
@@ -275,7 +285,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
             s_off[tid] = a.lo[q];
             s_rs[tid] = a.lr[q];
             s_b[tid] = a.lb[q];
-            s_m[tid] = a.lm[q];
+            s_m[tid] = a.active ? (a.lm[q] & a.active[a.lb[q]]) : a.lm[q];
         }
         if (tid == 0) s_off[cnt] = (i + cnt < N) ? a.lo[start + i + cnt] : E;
         __syncthreads();
@@ -406,6 +416,60 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
     }
 }
 
+// BFScut test (Section 3.1) after level L of a closeness launch: every node at
+// distance <= L+1 from source v is known (r of them, distance sum `sum`); of
+// the rem = n - r others at most ef (adjacency entries of the distance-(L+1)
+// nodes, minus one back-edge each) are at distance L+2, the rest are farther.
+// A source whose bound exceeds the best farness known is dropped.
+__global__ void k_wide_cut(WideArgs a, int32_t L, int64_t *best) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= a.nsrc) return;
+    const int64_t b = t / a.spb;
+    const uint64_t bit = 1ull << (t - b * a.spb);
+    if (!(__hip_atomic_load(&a.active[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) return;
+    const int64_t r = a.visited[t];
+    const int64_t e = a.edges[t];
+    const int64_t dr = r - a.prev[2 * t];
+    const int64_t de = e - a.prev[2 * t + 1];
+    a.prev[2 * t] = r;
+    a.prev[2 * t + 1] = e;
+    const int64_t sum = r * 65535 - a.gain[t];
+    if (r == a.n) {
+        a.far_out[t] = sum;
+        atomicMin(reinterpret_cast<unsigned long long *>(best), (unsigned long long)sum);
+        atomicAnd(&a.active[b], ~bit);
+        return;
+    }
+    if (dr == 0) {  // frontier empty before reaching every node (disconnected)
+        atomicAnd(&a.active[b], ~bit);
+        return;
+    }
+    const int64_t rem = (int64_t)a.n - r;
+    const int64_t ef = de - dr;
+    const int64_t near = ef < rem ? ef : rem;
+    const int64_t lb = sum + (int64_t)(L + 2) * near + (int64_t)(L + 3) * (rem - near);
+    const int64_t bv = (int64_t)__hip_atomic_load(reinterpret_cast<unsigned long long *>(best),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lb > bv) atomicAnd(&a.active[b], ~bit);
+}
+
+// sum of neighbour degrees, one wave per row (hub rows spread over the lanes)
+__global__ __launch_bounds__(256) void k_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n,
+                                                     int64_t *out) {
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (row >= n) return;
+    const int32_t rs = rp[row], re = rp[row + 1];
+    int64_t acc = 0;
+    for (int32_t e = rs + lane; e < re; e += 64) {
+        const int32_t u = ci[e];
+        acc += rp[u + 1] - rp[u];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) out[row] = acc;
+}
+
 template <typename DistT>
 __global__ void k_max_dist(const DistT *dist, int64_t n, int32_t *out) {
     uint32_t m = 0;
@@ -478,6 +542,19 @@ hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_
     if (g > grid) g = grid;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_wide_end, dim3((int)g), dim3(256), 0, s, a, nlev);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, hipStream_t s) {
+    const int g = (int)((a.nsrc + 255) / 256);
+    hipLaunchKernelGGL(k_wide_cut, dim3(g < 1 ? 1 : g), dim3(256), 0, s, a, L, best);
+    return hipGetLastError();
+}
+
+hipError_t launch_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n, int64_t *out,
+                             hipStream_t s) {
+    const int64_t g = ((int64_t)n * 64 + 255) / 256;
+    hipLaunchKernelGGL(k_twohop_i64, dim3((int)(g < 1 ? 1 : g)), dim3(256), 0, s, rp, ci, n, out);
     return hipGetLastError();
 }
 
