@@ -264,7 +264,7 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->slots_target = v;
     }
-    g->vis_budget = (int64_t)4 << 30;
+    g->vis_budget = (int64_t)16 << 30;
     if (const char *e = getenv("GC_VIS_BUDGET_MB")) {
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->vis_budget = (int64_t)v << 20;
@@ -284,7 +284,8 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         long v = strtol(e, nullptr, 10);
         if (v >= 16) g->min_edges = (int32_t)v;
     }
-    g->log_entries = (int64_t)8 << 20;
+    // frontier log: 16 entries per node, between 8M and 256M entries (20 bytes each)
+    g->log_entries = std::min<int64_t>((int64_t)256 << 20, std::max<int64_t>((int64_t)8 << 20, 16LL * n));
     if (const char *e = getenv("GC_LOG_ENTRIES")) {
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->log_entries = v;
@@ -303,7 +304,7 @@ constexpr size_t kCtrBytes = 4096;
 
 struct WsLayout {
     size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
-    size_t wvis, ly, lr, lb, lm, lo, lvl, act, cutprev, farout, total;
+    size_t wvis, ly, lr, lb, lo, lvl, act, cutprev, farout, total;
     int32_t nslots;
     SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
@@ -323,6 +324,8 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 int32_t choose_slots(const gc_graph *g, const SlotLayout &sl) {
     // persistent workgroups of the per-batch engine (closeness search; gains
     // only with GC_ENGINE=wg)
+    // only the per-workgroup gain engine (GC_ENGINE=wg) uses these slots
+    if (!g->wg_engine) return 1;
     const int64_t target = g->slots_target;
     const size_t budget = (size_t)8 << 30;
     int64_t cap = (int64_t)(budget / std::max<size_t>(sl.bytes, 1));
@@ -348,23 +351,24 @@ WsLayout ws_layout(const gc_graph *g) {
     L.slot = slot_layout(g->n);
     L.nslots = choose_slots(g, L.slot);
     L.slots = o; o += (size_t)L.nslots * L.slot.bytes;
-    // device-wide engine: per-batch visited words and the frontier log
+    // device-wide engine: per-(batch, node) 32-byte records (visited word and
+    // three rotating frontier words) and the frontier log
     L.vis_stride = (n + 31) & ~(size_t)31;
     const int64_t nb_all = ((int64_t)n + 63) / 64;
     const size_t vis_budget = (size_t)g->vis_budget;
-    int64_t kmax = (int64_t)(vis_budget / (L.vis_stride * 8));
+    int64_t kmax = (int64_t)(vis_budget / (L.vis_stride * 32));
     kmax = std::max<int64_t>(1, std::min<int64_t>(kmax, nb_all));
     L.kmax = kmax;
     int64_t cap = g->log_entries;
     cap = std::min<int64_t>(cap, 64LL * kmax * (int64_t)n + 128);
     cap = std::max<int64_t>(cap, (int64_t)n + 128);
-    cap = std::min<int64_t>(cap, ((int64_t)1 << 24) - 128);
+    // (a level holds fewer than 2^27 entries and 2^35 adjacency entries: the
+    // append flags more as an overflow)
     L.cap = cap;
-    L.wvis = o; o += al256((size_t)kmax * L.vis_stride * 8);
+    L.wvis = o; o += al256((size_t)kmax * L.vis_stride * 32);
     L.ly = o; o += al256((size_t)cap * 4);
     L.lr = o; o += al256((size_t)cap * 4);
     L.lb = o; o += al256((size_t)cap * 4);
-    L.lm = o; o += al256((size_t)cap * 8);
     L.lo = o; o += al256((size_t)cap * 8);
     L.lvl = o; o += al256((size_t)(kMaxLevels + 2) * sizeof(WideLevel));
     L.act = o; o += al256((size_t)kmax * 8);
@@ -417,7 +421,6 @@ struct Ws {
         a.ly = reinterpret_cast<int32_t *>(base + L.ly);
         a.lr = reinterpret_cast<int32_t *>(base + L.lr);
         a.lb = reinterpret_cast<int32_t *>(base + L.lb);
-        a.lm = reinterpret_cast<uint64_t *>(base + L.lm);
         a.lo = reinterpret_cast<int64_t *>(base + L.lo);
         a.cap = L.cap;
         a.lvl = reinterpret_cast<WideLevel *>(base + L.lvl);
@@ -555,10 +558,16 @@ struct HostIO {
     int32_t round = 0;
 };
 
+struct LaunchShape {
+    int64_t kb = 0;   // batches per launch (0: as many as fit)
+    int32_t spb = 64; // sources per batch
+};
+
 int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
               const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
               int32_t *d_vis, hipStream_t s, int32_t nlev, int64_t *h_gain = nullptr,
-              int64_t *h_edges = nullptr, const HostIO *io = nullptr) {
+              int64_t *h_edges = nullptr, const HostIO *io = nullptr,
+              LaunchShape *shape = nullptr) {
     if (count <= 0) return GC_OK;
     if (g->wg_engine) {
         int rc = run_gains_wg(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_vis, s);
@@ -581,8 +590,10 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     const bool mapped = io && io->hm_flag;
     const int grid = wide_grid(g);
     if (g_timing) HIP_OK(hipEventRecord(g_ev0, s));
-    int64_t kb = w.L.kmax;  // batches per launch
-    int32_t spb = 64;       // sources per batch
+    // batches per launch and sources per batch; a caller-kept shape carries
+    // what an earlier overflow taught across calls
+    int64_t kb = (shape && shape->kb > 0) ? std::min<int64_t>(shape->kb, w.L.kmax) : w.L.kmax;
+    int32_t spb = shape ? shape->spb : 64;
     int64_t done = 0;
     while (done < count) {
         // launch chunks of kb batches, then check the overflow flag once
@@ -637,6 +648,10 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         }
         if (flag == 0) {
             if (g_timing) HIP_OK(hipEventElapsedTime(&g_timing_ms, g_ev0, g_ev1));
+            if (shape) {
+                shape->kb = kb;
+                shape->spb = spb;
+            }
             return GC_OK;
         }
         // chunk `flag` overflowed the frontier log: it and the chunks after it
@@ -646,7 +661,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         // (cap >= n).
         done += (int64_t)(flag - 1) * per;
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.wvis),
-                               (size_t)w.L.kmax * w.L.vis_stride * 2, 0u, s));
+                               (size_t)w.L.kmax * w.L.vis_stride * 8, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
                                (size_t)(nlev + 2) * sizeof(WideLevel) / 4, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
@@ -724,7 +739,7 @@ int run_full_bfs(const gc_graph *g, const Ws &w, int32_t root, uint16_t *dist16,
         HIP_OK(hipMemcpyAsync(&rec, reinterpret_cast<WideLevel *>(w.base + w.L.lvl) + L, sizeof(rec),
                               hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        if ((rec.packed >> 40) == 0 || L >= kMaxLevels - 1) break;
+        if ((rec.packed >> kCntShift) == 0 || L >= kMaxLevels - 1) break;
     }
     HIP_OK(launch_wide_end(a, L, grid, s));
     int32_t maxd = 0;
@@ -786,13 +801,11 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     uint16_t *inf16 = reinterpret_cast<uint16_t *>(w.base + w.L.q1);
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(inf16), ((size_t)n * 2 + 3) / 4, 0xFFFFFFFFu, s));
     int64_t *dbest = reinterpret_cast<int64_t *>(w.ctr() + C_I64_BASE) + L_BEST_FAR;
-    // sources per launch: a full BFS logs at most one entry per (node, level)
-    // per batch, so keep batches * n * (a few levels) within the log
-    // one source per batch: a claim then always settles a node for good, so a
-    // batch logs at most n entries (with several sources per word a node can be
-    // logged once per claiming neighbour and source)
-    int64_t kb = std::max<int64_t>(1, std::min<int64_t>(w.L.kmax, w.L.cap / ((int64_t)n + 64)));
-    int32_t spb = 1;
+    // a batch logs each node once per distinct distance from its sources; the
+    // hubs of one batch are close to each other, so plan for two per node and
+    // let an overflow halve the launch
+    int64_t kb = std::max<int64_t>(1, std::min<int64_t>(w.L.kmax, w.L.cap / (2 * (int64_t)n + 64)));
+    int32_t spb = 64;
     std::vector<int64_t> fo;
     std::vector<int32_t> chunk;
     size_t pos = 0;
@@ -845,12 +858,12 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
                 overflow = true;
                 break;
             }
-            if ((rec.packed >> 40) == 0 || L >= kMaxLevels - 1) break;
+            if ((rec.packed >> kCntShift) == 0 || L >= kMaxLevels - 1) break;
         }
         if (overflow) {
             // too many frontier entries: clear and redo this chunk with fewer sources
             HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.wvis),
-                                   (size_t)w.L.kmax * w.L.vis_stride * 2, 0u, s));
+                                   (size_t)w.L.kmax * w.L.vis_stride * 8, 0u, s));
             HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
                                    (size_t)(kMaxLevels + 2) * sizeof(WideLevel) / 4, 0u, s));
             HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
@@ -1033,6 +1046,11 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         if (rc) return rc;
     }
     st.ms_closest = now_ms() - t0;
+    if (getenv("GC_VERBOSE")) {
+        fprintf(stderr, "[gc] first pick %d after %.2f ms (%lld sources)\n", s1, st.ms_closest,
+                (long long)st.closest_sources);
+        fflush(stderr);
+    }
     t0 = now_ms();
     int32_t ecc = 0, claimed = 0;
     if (s1 == v0) {
@@ -1080,8 +1098,12 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     if (st.h_evals_per_round)
         for (int32_t i = 0; i < k; ++i) st.h_evals_per_round[i] = 0;
 
+    const bool verbose = getenv("GC_VERBOSE") != nullptr;
+    LaunchShape shape_r1, shape_later;
+    int32_t cur_round = 0, first_round_idx = (int32_t)group.size();
     // evaluate a list of candidates, returning gains (and edges) on the host
     auto evaluate = [&](int32_t cnt) -> int {
+        LaunchShape *shape = cur_round == first_round_idx ? &shape_r1 : &shape_later;
         int r;
         if (g->wg_engine) {
             HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
@@ -1091,7 +1113,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         } else {
             r = run_gains(g, w, d_dist, dist_bytes, dc, cnt, w.gain(),
                           want_edges ? w.aux() : nullptr, nullptr, s,
-                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr, &io);
+                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr, &io, shape);
         }
         if (r) return r;
         st.gain_launches += 1;
@@ -1169,6 +1191,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         const int32_t blk = first_round ? n : block;
         int32_t pos = 0;
         io.round = r;
+        cur_round = r;
         if (need_state && !first_round) {
             rc = score_round(r);
             if (rc) return rc;
@@ -1275,6 +1298,11 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         }
         if (st.h_evals_per_round) st.h_evals_per_round[r] = nev;
         st.evals_total += nev;
+        if (verbose) {
+            fprintf(stderr, "[gc] round %d: %lld evaluations, best %d gain %lld, %.2f ms since start\n", r,
+                    (long long)nev, best_id, (long long)best_gain, now_ms() - t_start);
+            fflush(stderr);
+        }
         if (best_id < 0) return fail(GC_EINVAL, "no candidate left");
         // pick, then d(S,.) <- min(d(S,.), d(pick,.)) by pruned BFS
         t0 = now_ms();

@@ -76,9 +76,12 @@ hipError_t launch_bfs_level(const BfsArgs &a, int dist_bytes, int32_t level, int
 hipError_t launch_bfs_finish(const BfsArgs &a, int64_t *d_far, hipStream_t s);
 
 // ------------------------------------------------ device-wide gain engine
+// a level record packs its entry count above bit kCntShift and the adjacency
+// entries its entries expand below it
+constexpr int kCntShift = 36;
 struct WideLevel {
     int64_t start;                 // first log index of this level's entries
-    unsigned long long packed;     // (entry count << 40) | adjacency entries to expand
+    unsigned long long packed;     // (entry count << kCntShift) | adjacency entries to expand
 };
 
 struct WideArgs {
@@ -92,12 +95,11 @@ struct WideArgs {
     int64_t *gain;                 // out [nsrc]
     int64_t *edges;                // out [nsrc] or null
     int32_t *visited;              // out [nsrc] or null
-    uint64_t *vis;                 // batch b: vis[b*vis_stride .. +n), zero between launches
+    uint64_t *vis;                 // batch b, node y: 4 words at (b*vis_stride + y)*4, zero between launches
     size_t vis_stride;
     int32_t *ly;                   // frontier log: node
     int32_t *lr;                   //               row start of the node
     int32_t *lb;                   //               batch
-    uint64_t *lm;                  //               source bits
     int64_t *lo;                   //               first adjacency position (per level)
     int64_t cap;                   // log capacity (entries)
     WideLevel *lvl;                // per-level records, nlev + 2 of them

@@ -1,37 +1,44 @@
 // Device-wide bit-parallel pruned BFS for marginal gains (gfx950).
 //
-// Candidates are grouped 64 to a batch; batch b owns a dense word array
-// vis_b[0..n) whose bit j marks nodes already reached by source j of the
-// batch.  All batches of a launch advance one BFS level per kernel, so a
-// level is one edge-balanced sweep over the whole device:
+// Candidates are grouped up to 64 to a batch (one bit per source).  Batch b
+// owns one 32-byte record per node y: the visited word vis (bit j = source j
+// has reached y) and three "frontier" words fr[0..2].  All batches of a launch
+// advance one BFS level per kernel, so a level is one edge-balanced sweep over
+// the whole device.  For a frontier entry (b, x) at distance L with source
+// bits F = fr[L % 3] of (b, x), every neighbour y is handled as follows:
 //
-//   frontier entry (b, x, F) at distance L, F = bits of the sources that
-//   reached x at distance L.  For each neighbour y of x:
-//     L+1 >= d(S,y)        -> pruned (Section 4.1): neither y nor anything
-//                             behind it can be closer to the source than to S;
-//                             nothing is written;
-//     otherwise claim nw = F & ~vis_b[y] with one atomicOr; every claimed
-//     source j gains d(S,y) - (L+1) (the summand of the gain sum in the proof
-//     of the Section 4.3 theorem) and (b, y, nw) joins the next frontier.
+//   L+1 >= d(S,y)  -> pruned (Section 4.1): neither y nor anything behind it is
+//                     closer to these sources than to S; nothing is written.
+//   otherwise      -> nw = F & ~vis; one atomicOr on vis returns exactly the
+//                     bits this claim adds, each source j in nw gains
+//                     d(S,y) - (L+1) (the summand of the gain sum in the proof
+//                     of the Section 4.3 theorem); then atomicOr(fr[(L+1)%3],
+//                     nw), and the claim that finds that word empty appends
+//                     (b, y) to the next frontier.
 //
-// Load balance: when entries are appended, one 64-bit atomic per wave
-// reserves both their slots and the range of adjacency positions they will
-// expand ((count << 40) | edges).  Edge offsets are therefore monotone in
-// the entry index, and the next level splits its total edge count evenly over
-// the workgroups (a hub's adjacency is spread over many of them); each
-// workgroup finds its first entry with a 64-ary search and walks windows of
-// 256 entries staged in LDS.
+// So settlement is exact per claim, and every (batch, node) enters a level's
+// frontier once, carrying the union of the bits that reached it: sources that
+// share territory share the expansion (the point of the bit-parallel form).
+// Level L+1 reads fr[(L+1)%3]; level L+2 writes fr[(L+3)%3] = fr[L%3], which
+// level L+1 clears first -- no word is read and written in the same kernel.
 //
-// No level count is needed from the host: a pruned BFS never goes deeper than
-// max_y d(S,y) - 1, so the host launches that many levels.
+// Load balance: one 64-bit atomic per workgroup step reserves both the slots
+// of new entries and the adjacency positions they will expand
+// ((count << kCntShift) | edges), so edge offsets are monotone in the entry index; the
+// next level splits its total evenly over the workgroups (a hub's adjacency is
+// spread over many of them), each finding its first entry with a 64-ary
+// search and walking windows of 256 entries staged in LDS.
+//
+// A pruned BFS never goes deeper than max_y d(S,y) - 1, so the host launches
+// that many levels without reading anything back.
 #include "gc_kernels.h"
 
 namespace gck {
 namespace {
 
-constexpr int kWin = 256;   // entries staged per window
+constexpr int kWin = 256;      // entries staged per window
 constexpr int kLdsSrc = 1024;  // launches with at most this many sources sum gains in LDS
-constexpr uint64_t kM40 = (1ull << 40) - 1;
+constexpr uint64_t kMEdges = (1ull << kCntShift) - 1;
 
 __device__ __forceinline__ int lane_id() {
     return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -46,19 +53,32 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ void set_flag(int32_t *flag, int32_t v) {
-    atomicCAS(flag, 0, v);
+__device__ __forceinline__ void set_flag(int32_t *flag, int32_t v) { atomicCAS(flag, 0, v); }
+
+// word k (0 = visited, 1..3 = frontier of level k-1 mod 3) of (batch b, node y)
+__device__ __forceinline__ unsigned long long *rec(const WideArgs &a, int64_t b, int64_t y, int k) {
+    return reinterpret_cast<unsigned long long *>(a.vis) + ((size_t)b * a.vis_stride + (size_t)y) * 4 + k;
 }
 
-// Append entries of lanes with p to the frontier of the next level.  Called
-// by every lane of a fully active wave.
-__device__ __forceinline__ void push_entries(const WideArgs &a, WideLevel *nl, int64_t nbase, bool p,
-                                             int32_t y, int32_t rs, int32_t b, uint64_t bits,
-                                             int32_t deg) {
+__device__ __forceinline__ void log_entry(const WideArgs &a, int64_t pos, int32_t y, int32_t rs,
+                                          int32_t b, int64_t off) {
+    if (pos < a.cap) {
+        a.ly[pos] = y;
+        a.lr[pos] = rs;
+        a.lb[pos] = b;
+        a.lo[pos] = off;
+    } else {
+        set_flag(a.flags, a.tag);
+    }
+}
+
+// Wave-level append (every lane of a fully active wave calls it).
+__device__ __forceinline__ void push_wave(const WideArgs &a, WideLevel *nl, int64_t nbase, bool p,
+                                          int32_t y, int32_t rs, int32_t b, int32_t deg) {
     const uint64_t bal = __ballot(p);
     if (bal == 0) return;
     const int lane = lane_id();
-    int dp = p ? deg : 0;
+    const int dp = p ? deg : 0;
     int incl = dp;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -68,80 +88,24 @@ __device__ __forceinline__ void push_entries(const WideArgs &a, WideLevel *nl, i
     const int total = __shfl(incl, 63);
     uint64_t old = 0;
     if (lane == 0) {
-        old = atomicAdd(&nl->packed, ((unsigned long long)__popcll(bal) << 40) + (unsigned long long)total);
-        if ((old & kM40) + (uint64_t)total >= (1ull << 39) || (old >> 40) + 64 >= (1ull << 24))
+        old = atomicAdd(&nl->packed, ((unsigned long long)__popcll(bal) << kCntShift) + (unsigned long long)total);
+        if ((old & kMEdges) + (uint64_t)total >= (1ull << (kCntShift - 1)) ||
+            (old >> kCntShift) + 64 >= (1ull << (63 - kCntShift)))
             set_flag(a.flags, a.tag);
     }
     old = shfl64(old, 0);
     if (!p) return;
-    const int64_t idx = (int64_t)(old >> 40) + bits_below(bal);
-    const int64_t pos = nbase + idx;
-    if (pos >= a.cap) {
-        set_flag(a.flags, a.tag);
-        return;
-    }
-    a.ly[pos] = y;
-    a.lr[pos] = rs;
-    a.lb[pos] = b;
-    a.lm[pos] = bits;
-    a.lo[pos] = (int64_t)(old & kM40) + (incl - dp);
+    log_entry(a, nbase + (int64_t)(old >> kCntShift) + bits_below(bal), y, rs, b,
+              (int64_t)(old & kMEdges) + (incl - dp));
 }
 
-// Level 0: every source claims its own node (weight d(S,v) - 0).
-// WRITE: the d(S,.) update after a pick -- a claimed node also stores its
-// new distance (in place: a later test against it fails, and the visited bit
-// settles concurrent claims), and the single source's gain is F(S) - F(S+s).
-template <typename DistT, bool WRITE>
-__global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
-    if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool p = false;
-    int32_t v = 0, b = 0, deg = 0, rs = 0;
-    uint64_t nw = 0;
-    if (t < a.nsrc) {
-        v = a.src ? a.src[t] : a.root;
-        b = (int32_t)(t / a.spb);
-        a.gain[t] = 0;
-        if (a.edges) a.edges[t] = 0;
-        if (a.visited) a.visited[t] = 0;
-        if (a.active) {
-            a.far_out[t] = -1;
-            a.prev[2 * t] = 1;                           // the root itself
-            a.prev[2 * t + 1] = a.rp[v + 1] - a.rp[v];   // its adjacency
-            const int64_t j = t - (int64_t)b * a.spb;
-            if (j == 0) {
-                const int64_t nb = a.nsrc - (int64_t)b * a.spb < a.spb ? a.nsrc - (int64_t)b * a.spb : a.spb;
-                a.active[b] = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
-            }
-        }
-        const uint32_t d = dist[v];
-        if (d > 0u) {
-            const uint64_t bit = 1ull << (t - (int64_t)b * a.spb);
-            unsigned long long *w = reinterpret_cast<unsigned long long *>(a.vis + (size_t)b * a.vis_stride + v);
-            const uint64_t old = atomicOr(w, (unsigned long long)bit);
-            nw = bit & ~old;
-            if (nw) {
-                if (WRITE) dist[v] = 0;
-                rs = a.rp[v];
-                deg = a.rp[v + 1] - rs;
-                a.gain[t] = (int64_t)d;
-                if (a.edges) a.edges[t] = deg;
-                if (a.visited) a.visited[t] = 1;
-                p = true;
-            }
-        }
-    }
-    push_entries(a, &a.lvl[0], 0, p, v, rs, b, nw, deg);
-}
-
-// Work-group-wide append: thread t holds up to U new entries (p[r]);
-// one 64-bit atomic reserves the slots and adjacency ranges of all of them.
+// Work-group append: thread t holds up to U new entries (p[r]); one 64-bit
+// atomic reserves the slots and adjacency ranges of all of them.
 template <int U>
 __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int64_t nbase,
                                            const bool *p, const int32_t *y, const int32_t *rs,
-                                           const int32_t *bb, const uint64_t *nw, const int32_t *deg,
-                                           int64_t *s_wc, int64_t *s_wd, uint64_t *s_old) {
+                                           const int32_t *bb, const int32_t *deg, int64_t *s_wc,
+                                           int64_t *s_wd, uint64_t *s_old) {
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     int64_t c = 0, dsum = 0;
@@ -179,8 +143,9 @@ __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int
     if (threadIdx.x == 0) {
         uint64_t old = 0;
         if (tc > 0) {
-            old = atomicAdd(&nl->packed, ((unsigned long long)tc << 40) + (unsigned long long)td);
-            if ((old & kM40) + (uint64_t)td >= (1ull << 39) || (old >> 40) + (uint64_t)tc >= (1ull << 24))
+            old = atomicAdd(&nl->packed, ((unsigned long long)tc << kCntShift) + (unsigned long long)td);
+            if ((old & kMEdges) + (uint64_t)td >= (1ull << (kCntShift - 1)) ||
+                (old >> kCntShift) + (uint64_t)tc >= (1ull << (63 - kCntShift)))
                 set_flag(a.flags, a.tag);
         }
         *s_old = old;
@@ -188,29 +153,66 @@ __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int
     __syncthreads();
     if (tc == 0) return;
     const uint64_t old = *s_old;
-    int64_t idx = (int64_t)(old >> 40) + pc + (ic - c);
-    int64_t off = (int64_t)(old & kM40) + pd + (id - dsum);
+    int64_t idx = (int64_t)(old >> kCntShift) + pc + (ic - c);
+    int64_t off = (int64_t)(old & kMEdges) + pd + (id - dsum);
 #pragma unroll
     for (int r = 0; r < U; ++r) {
         if (!p[r]) continue;
-        const int64_t pos = nbase + idx;
-        if (pos < a.cap) {
-            a.ly[pos] = y[r];
-            a.lr[pos] = rs[r];
-            a.lb[pos] = bb[r];
-            a.lm[pos] = nw[r];
-            a.lo[pos] = off;
-        } else {
-            set_flag(a.flags, a.tag);
-        }
+        log_entry(a, nbase + idx, y[r], rs[r], bb[r], off);
         idx += 1;
         off += deg[r];
     }
 }
 
-// LDS: per-source sums in LDS (launches of <= kLdsSrc sources); large
-// launches add straight to global memory and keep LDS small for occupancy.
-// U: edges per thread per step.
+// Level 0: every source claims its own node (weight d(S,v) - 0).
+// WRITE: the d(S,.) update after a pick -- a claimed node also stores its new
+// distance (in place: a later prune test against it fails, and the visited
+// bit settles concurrent claims); the single source's gain is F(S) - F(S+s).
+template <typename DistT, bool WRITE>
+__global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
+    if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool p = false;
+    int32_t v = 0, b = 0, deg = 0, rs = 0;
+    if (t < a.nsrc) {
+        v = a.src ? a.src[t] : a.root;
+        b = (int32_t)(t / a.spb);
+        const int64_t j = t - (int64_t)b * a.spb;
+        a.gain[t] = 0;
+        if (a.edges) a.edges[t] = 0;
+        if (a.visited) a.visited[t] = 0;
+        if (a.active) {
+            a.far_out[t] = -1;
+            a.prev[2 * t] = 1;                           // the root itself
+            a.prev[2 * t + 1] = a.rp[v + 1] - a.rp[v];   // its adjacency
+            if (j == 0) {
+                const int64_t left = a.nsrc - (int64_t)b * a.spb;
+                const int64_t nb = left < a.spb ? left : a.spb;
+                a.active[b] = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+            }
+        }
+        const uint32_t d = dist[v];
+        if (d > 0u) {
+            const uint64_t bit = 1ull << j;
+            const uint64_t old = atomicOr(rec(a, b, v, 0), (unsigned long long)bit);
+            if (bit & ~old) {
+                if (WRITE) dist[v] = 0;
+                rs = a.rp[v];
+                deg = a.rp[v + 1] - rs;
+                a.gain[t] = (int64_t)d;
+                if (a.edges) a.edges[t] = deg;
+                if (a.visited) a.visited[t] = 1;
+                p = atomicOr(rec(a, b, v, 1), (unsigned long long)bit) == 0ull;
+            }
+        }
+    }
+    push_wave(a, &a.lvl[0], 0, p, v, rs, b, deg);
+}
+
+// One BFS level.  LDS: per-source sums in LDS (launches of <= kLdsSrc
+// sources); large launches add straight to global memory and keep LDS small
+// for occupancy.  U: edges per thread per step.
 template <typename DistT, bool WRITE, bool LDS, int U>
 __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     __shared__ int64_t s_off[kWin + 1];
@@ -220,19 +222,28 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     __shared__ int64_t s_first;
     __shared__ int64_t s_wc[kWG / 64], s_wd[kWG / 64];
     __shared__ uint64_t s_old;
-    // per-source sums when the launch is small enough (flushed once at the end)
     __shared__ unsigned long long s_g[LDS ? kLdsSrc : 1];
     __shared__ unsigned long long s_e[LDS ? kLdsSrc : 1];
     __shared__ unsigned int s_v[LDS ? kLdsSrc : 1];
 
     if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const WideLevel me = a.lvl[L];
-    const int64_t N = (int64_t)(me.packed >> 40);
-    const int64_t E = (int64_t)(me.packed & kM40);
+    const int64_t N = (int64_t)(me.packed >> kCntShift);
+    const int64_t E = (int64_t)(me.packed & kMEdges);
     const int64_t start = me.start;
     const int64_t nbase = start + N;
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) a.lvl[L + 1].start = nbase;
+    const int fr_cur = 1 + L % 3, fr_next = 1 + (L + 1) % 3;
+    // clear the frontier words of level L-1 (read in the previous kernel; the
+    // next kernel writes this slot again)
+    if (L >= 1) {
+        const int fr_prev = 1 + (L + 2) % 3;
+        const int64_t pstart = a.lvl[L - 1].start;
+        for (int64_t q = pstart + blockIdx.x * (int64_t)kWG + tid; q < start && q < a.cap;
+             q += (int64_t)gridDim.x * kWG)
+            *rec(a, a.lb[q], a.ly[q], fr_prev) = 0ull;
+    }
     if (E == 0) return;
     // small levels use few workgroups: each takes at least min_edges entries
     int64_t G = (E + a.min_edges - 1) / a.min_edges;
@@ -282,10 +293,12 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
         const int cnt = (int)cnt64;
         if (tid < cnt) {
             const int64_t q = start + i + tid;
+            const int32_t b = a.lb[q];
             s_off[tid] = a.lo[q];
             s_rs[tid] = a.lr[q];
-            s_b[tid] = a.lb[q];
-            s_m[tid] = a.active ? (a.lm[q] & a.active[a.lb[q]]) : a.lm[q];
+            s_b[tid] = b;
+            const uint64_t f = *rec(a, b, a.ly[q], fr_cur);
+            s_m[tid] = a.active ? (f & a.active[b]) : f;
         }
         if (tid == 0) s_off[cnt] = (i + cnt < N) ? a.lo[start + i + cnt] : E;
         __syncthreads();
@@ -295,7 +308,6 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
             int32_t y[U], own[U], bb[U], deg[U], rs[U];
             uint32_t d[U];
             bool p[U];
-            uint64_t nw[U];
 #pragma unroll
             for (int r = 0; r < U; ++r) {
                 const int64_t e = e0 + tid + (int64_t)r * kWG;
@@ -307,8 +319,10 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                         const int mid = (lo + hi + 1) >> 1;
                         if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
                     }
-                    own[r] = lo;
-                    y[r] = ci[s_rs[lo] + (int32_t)(e - s_off[lo])];
+                    if (s_m[lo]) {
+                        own[r] = lo;
+                        y[r] = ci[s_rs[lo] + (int32_t)(e - s_off[lo])];
+                    }
                 }
             }
 #pragma unroll
@@ -316,27 +330,24 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
 #pragma unroll
             for (int r = 0; r < U; ++r) {
                 p[r] = false;
-                nw[r] = 0;
                 bb[r] = 0;
                 deg[r] = 0;
                 rs[r] = 0;
                 if (own[r] >= 0 && nl < d[r]) {
                     bb[r] = s_b[own[r]];
-                    uint64_t *vw = a.vis + (size_t)bb[r] * a.vis_stride + y[r];
-                    // issue the row-pointer loads together with the visited word
+                    unsigned long long *vw = rec(a, bb[r], y[r], 0);
+                    // row pointers are needed only for a claim: load them with the visited word
                     rs[r] = rp[y[r]];
                     const int32_t re = rp[y[r] + 1];
-                    const uint64_t m = s_m[own[r]] & ~(*vw);
+                    const uint64_t m = s_m[own[r]] & ~(uint64_t)(*vw);
                     if (m) {
-                        const uint64_t old = atomicOr(reinterpret_cast<unsigned long long *>(vw),
-                                                      (unsigned long long)m);
-                        nw[r] = m & ~old;
-                        if (nw[r]) {
+                        const uint64_t nw = m & ~(uint64_t)atomicOr(vw, (unsigned long long)m);
+                        if (nw) {
                             if (WRITE) dist[y[r]] = (DistT)nl;
                             const unsigned long long c = d[r] - nl;
                             deg[r] = re - rs[r];
                             const int64_t gb = (int64_t)bb[r] * a.spb;
-                            for (uint64_t mm = nw[r]; mm; mm &= mm - 1) {
+                            for (uint64_t mm = nw; mm; mm &= mm - 1) {
                                 const int64_t j = gb + (__ffsll((unsigned long long)mm) - 1);
                                 if (lds_acc) {
                                     atomicAdd(&s_g[j], c);
@@ -350,12 +361,13 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                                     if (a.visited) atomicAdd(a.visited + j, 1);
                                 }
                             }
-                            p[r] = true;
+                            // first claim of (batch, node) at this level: one frontier entry
+                            p[r] = atomicOr(rec(a, bb[r], y[r], fr_next), (unsigned long long)nw) == 0ull;
                         }
                     }
                 }
             }
-            push_block<U>(a, next, nbase, p, y, rs, bb, nw, deg, s_wc, s_wd, &s_old);
+            push_block<U>(a, next, nbase, p, y, rs, bb, deg, s_wc, s_wd, &s_old);
         }
         __syncthreads();
         if (whi >= ee || i + cnt >= N) break;
@@ -371,10 +383,11 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     }
 }
 
-// End of a launch: return every touched visited word to zero, copy the
-// results to the host-mapped buffers if given, and (last workgroup) zero the
-// level records so the next launch starts clean.  After an overflow nothing is
-// cleared here; the host clears and retries.
+// End of a launch: return every touched node record to zero, copy the results
+// to the host-mapped buffers if given, scatter them into the lazy-loop state if
+// asked, and (last workgroup) zero the level records so the next launch starts
+// clean.  After an overflow nothing is cleared here; the host clears and
+// retries.
 __global__ void k_wide_end(WideArgs a, int32_t nlev) {
     const int32_t flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (flag) {
@@ -382,11 +395,17 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
         return;
     }
     const WideLevel last = a.lvl[nlev];
-    int64_t tot = last.start + (int64_t)(last.packed >> 40);
+    int64_t tot = last.start + (int64_t)(last.packed >> kCntShift);
     if (tot > a.cap) tot = a.cap;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = t0; i < tot; i += nt) a.vis[(size_t)a.lb[i] * a.vis_stride + a.ly[i]] = 0;
+    for (int64_t i = t0; i < tot; i += nt) {
+        unsigned long long *r0 = rec(a, a.lb[i], a.ly[i], 0);
+        r0[0] = 0ull;
+        r0[1] = 0ull;
+        r0[2] = 0ull;
+        r0[3] = 0ull;
+    }
     if (a.h_gain)
         for (int64_t i = t0; i < a.nsrc; i += nt) a.h_gain[i] = a.gain[i];
     if (a.h_edges && a.edges)
@@ -537,7 +556,7 @@ hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int
 }
 
 hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_t s) {
-    // enough workgroups for the visited-word clean-up of a launch of this size
+    // enough workgroups for the record clean-up of a launch of this size
     int64_t g = (a.nsrc + 63) / 64 * 4;
     if (g > grid) g = grid;
     if (g < 1) g = 1;
