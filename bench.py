@@ -40,6 +40,10 @@ WORKLOADS = {
     "grid1024": ("1024x1024 grid, 5% edges dropped, 0.1%*n shortcuts, largest component", "grid1024"),
     "rmat24": ("R-MAT scale 24, edge factor 16, largest component", "rmat24"),
 }
+# Workloads whose GPU run is switched off: the first R-MAT scale 24 run ended in
+# a GPU memory fault inside the first-pick search, and its cause has not been
+# found; it stays off until it is.
+DISABLED = {"rmat24": "the first-pick search faulted the GPU on this graph (cause not yet found)"}
 
 
 def parse():
@@ -108,6 +112,10 @@ def main():
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.workload in DISABLED:
+        print("bench.py: workload %s is switched off: %s" % (args.workload, DISABLED[args.workload]),
+              file=sys.stderr)
+        sys.exit(2)
     desc, wl = WORKLOADS[args.workload]
     t0 = time.time()
     g = graphgen.workload(wl)
@@ -162,12 +170,22 @@ def main():
         dist = G.new_dist(2)
         G.update_dist(s1, dist, 2, far)
         dist_bytes = 2
-    cand = torch.tensor([v for v in range(g.n) if v != s1], dtype=torch.int32, device=dev)
+    cand = torch.from_numpy(np.delete(np.arange(g.n, dtype=np.int32), s1)).to(dev)
     gain, e_c, v_c = G.marginal_gains(dist, dist_bytes, cand, stats=True)
     torch.cuda.synchronize()
     E1 = int(e_c.sum().item())
     V1 = int(v_c.to(torch.int64).sum().item())
-    alg_bytes = 8 * V1 + (4 + dist_bytes) * E1
+    words = G.gain_words()
+    # bit-parallel top-down bytes per batch and level (64 sources per word):
+    # each expanded entry reads its row-pointer pair and frontier word (16 B)
+    # and 4 B of column index per adjacency entry; each adjacency entry reads
+    # the target's visited word and ORs its next-frontier word (16 B); each
+    # touched target writes next / visited / frontier words (24 B) and reads
+    # its d(S,.) byte(s)
+    X = words["entries"] - words["entries_last"]
+    Y = words["entries"] - words["entries_root"]
+    Ew = words["edges"]
+    alg_bytes = 16 * X + 20 * Ew + (24 + dist_bytes) * Y
     stream = torch.cuda.current_stream()
     # kernel time of the launch: HIP events recorded by the library on this
     # stream right before its first and after its last gain kernel
@@ -181,8 +199,10 @@ def main():
     kern_ms = float(np.mean(times))
     achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
     traffic = measured_traffic(args.workload)
-    log("round-1 gain launch: %d candidates, E_alg %d, |V| %d, %.3f ms, %.1f GB/s algorithmic"
-        % (cand.numel(), E1, V1, kern_ms, achieved))
+    log("round-1 gain launch: %d candidates, E_alg %d, |V| %d, word entries %d, word edges %d, "
+        "%.3f ms, %.1f GB/s algorithmic, GTEPS alg %.1f word %.1f"
+        % (cand.numel(), E1, V1, words["entries"], Ew, kern_ms, achieved,
+           E1 / kern_ms / 1e6, Ew / kern_ms / 1e6))
 
     # ---- a plain copy of known size: measured bandwidth and counter scale
     copy_gbs = None
@@ -245,8 +265,10 @@ def main():
                          ("ms_closest", "ms_round1", "ms_later", "ms_update", "ms_mlp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "kernel": "k_engine gain mode (first gain round, %d candidates)" % cand.numel(),
+                     "kernel": "k_wide_level (first gain round, %d candidates)" % cand.numel(),
                      "kernel_ms": round(kern_ms, 4), "alg_bytes": alg_bytes,
+                     "words": words, "gteps_alg": round(E1 / kern_ms / 1e6, 2),
+                     "gteps_word": round(Ew / kern_ms / 1e6, 2),
                      "copy_gbs_measured": round(copy_gbs, 1) if copy_gbs else None},
         "cpu_baseline": cpu,
     }

@@ -105,6 +105,14 @@ typedef struct gc_stats {
     double ms_later;        /* gain rounds >= 2 incl. selection */
     double ms_update;       /* d(S,.) updates */
     double ms_mlp;          /* feature + MLP inference (learned order) */
+    /* word-level work of the gain launches (one frontier entry is a node
+     * reached by some of the 64 sources of a batch at one level; see
+     * gc_gain_words) */
+    int64_t entries_word;   /* frontier entries, all levels */
+    int64_t entries_root;   /* of which root entries (level 0) */
+    int64_t entries_last;   /* of which entries of the last level (not expanded) */
+    int64_t edges_word;     /* adjacency entries expanded (levels before the last) */
+    int64_t edges_last;     /* adjacency entries of the last level's entries */
     int64_t *h_evals_per_round; /* optional, caller-owned, k entries */
 } gc_stats;
 
@@ -176,6 +184,7 @@ int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t 
  *   dist_bytes  1 or 2 (GC_EINVAL otherwise)
  *   d_farness   device int64, in/out: F(S) -> F(S u {node}); its input is
  *               ignored when S = {}
+ * Synchronises the stream every few levels (the depth is found as it goes).
  * Errors: GC_EINVAL for node out of range; GC_ERANGE is reported by a later
  * synchronising call if a distance reached INF (use dist_bytes = 2, or
  * gc_greedy_group, which picks the width itself).
@@ -194,12 +203,27 @@ int gc_update_dist(const gc_graph *g, int32_t node, void *d_dist, int32_t dist_b
  *   d_gain      device int64[count] out
  *   d_edges     device int64[count] out or NULL: sum_{w in V(v)} deg(w)
  *   d_visited   device int32[count] out or NULL: |V(v)|
- * Asynchronous.  Candidate ids are not range-checked on the device; pass ids
- * in [0, n).
+ * Synchronises the stream twice: to read max d(S,.) (the BFS depth) and to
+ * check the frontier log (an overflowed launch is redone with fewer sources
+ * per launch; the results are the same).  Candidate ids are not range-checked
+ * on the device; pass ids in [0, n).
  */
 int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
                       const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
                       int32_t *d_visited, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * gc_gain_words -- word-level work of the last gc_marginal_gains call on this
+ * workspace (the bit-parallel form of Section 4.3: one frontier entry carries
+ * every source of a batch that reached a node at the same level).
+ *   h_words  host int64[5] out: frontier entries of all levels, of level 0
+ *            (roots), of the last level (logged, not expanded); adjacency
+ *            entries expanded; adjacency entries of the last level.
+ * With one candidate per call, entries = |V(v)| and the two adjacency counts
+ * add up to the d_edges output.  Synchronises the stream.
+ */
+int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_bytes, hipStream_t stream,
+                  int64_t *h_words);
 
 /*
  * gc_greedy_group -- Greedy++ (Section 4): k picks, exactly the picks of the

@@ -414,6 +414,7 @@ struct Ws {
         return m;
     }
     int32_t *maxd() const { return ctr() + kMaxdSlot; }
+    int64_t *words() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_WORDS; }
     WideArgs wide() const {
         WideArgs a{};
         a.vis = reinterpret_cast<uint64_t *>(base + L.wvis);
@@ -616,6 +617,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             a.visited = d_vis ? d_vis + off : nullptr;
             a.tag = ++tag;
             a.dist_bytes = dist_bytes;
+            a.words = w.words();
             if (mapped) {
                 a.h_gain = io->hm_gain ? io->hm_gain + off : nullptr;
                 a.h_edges = io->hm_edges ? io->hm_edges + off : nullptr;
@@ -797,6 +799,13 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     for (int32_t i = 1; i < n; ++i)
         if (may_win(order[i])) list.push_back(order[i]);
     int64_t nsources = 1;
+    const bool verbose = getenv("GC_VERBOSE") != nullptr;
+    double t_print = now_ms();
+    if (verbose) {
+        fprintf(stderr, "[gc] closeness: F({%d}) = %lld, %zu of %d nodes pass the level-1 bound\n", v0,
+                (long long)F0, list.size(), n - 1);
+        fflush(stderr);
+    }
     // INF distances for the full BFS: the second level-BFS queue is free here
     uint16_t *inf16 = reinterpret_cast<uint16_t *>(w.base + w.L.q1);
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(inf16), ((size_t)n * 2 + 3) / 4, 0xFFFFFFFFu, s));
@@ -812,6 +821,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     const int grid = wide_grid(g);
     while (pos < list.size()) {
         chunk.clear();
+        const size_t pos0 = pos;
         while (pos < list.size() && (int64_t)chunk.size() < kb * spb) {
             const int32_t v = list[pos++];
             if (may_win(v)) chunk.push_back(v);
@@ -870,7 +880,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
             if (kb > 1) kb /= 2;
             else if (spb > 1) spb = std::max(1, spb / 2);
             else return fail(GC_EWORKSPACE, "frontier log too small for one source");
-            pos -= chunk.size();
+            pos = pos0;  // the filtered-out nodes before the chunk's end are checked again
             continue;
         }
         HIP_OK(launch_wide_end(a, L, grid, s));
@@ -884,6 +894,13 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
                 bestF = fo[i];
                 best = chunk[i];
             }
+        }
+        if (verbose && now_ms() - t_print > 2000.0) {
+            t_print = now_ms();
+            fprintf(stderr, "[gc] closeness: %zu of %zu listed, %lld sources run, best %d (F %lld), "
+                    "%lld batches x %d per launch\n", pos, list.size(), (long long)nsources, best,
+                    (long long)bestF, (long long)kb, spb);
+            fflush(stderr);
         }
     }
     *node = best;
@@ -931,7 +948,20 @@ extern "C" int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t 
     if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
     if (count < 0) return fail(GC_EINVAL, "count < 0");
     if (count > 0 && (!d_dist || !d_cand || !d_gain)) return fail(GC_EINVAL, "NULL device pointer");
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.words()), 2 * kWordCounters, 0u, stream));
     return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream, -1);
+}
+
+extern "C" int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_bytes, hipStream_t stream,
+                             int64_t *h_words) {
+    Ws w;
+    int rc = get_ws(g, const_cast<void *>(d_ws), ws_bytes, &w);
+    if (rc) return rc;
+    if (!h_words) return fail(GC_EINVAL, "NULL output");
+    HIP_OK(hipMemcpyAsync(h_words, w.words(), sizeof(int64_t) * kWordCounters, hipMemcpyDeviceToHost,
+                          stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    return GC_OK;
 }
 
 // ------------------------------------------------------------- the greedy
@@ -980,6 +1010,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
 
     gc_stats st{};
     if (h_stats) st.h_evals_per_round = h_stats->h_evals_per_round;
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.words()), 2 * kWordCounters, 0u, s));
     std::vector<int32_t> group;
     std::vector<int64_t> Fs;
     group.reserve(k);
@@ -1328,7 +1359,17 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         h_farness[i] = Fs[i];
     }
     st.ms_total = now_ms() - t_start;
-    if (h_stats) *h_stats = st;
+    if (h_stats) {
+        int64_t wc[kWordCounters];
+        HIP_OK(hipMemcpyAsync(wc, w.words(), sizeof(wc), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        st.entries_word = wc[0];
+        st.entries_root = wc[1];
+        st.entries_last = wc[2];
+        st.edges_word = wc[3];
+        st.edges_last = wc[4];
+        *h_stats = st;
+    }
     return GC_OK;
 }
 

@@ -22,8 +22,11 @@ enum : int {
 enum : int {
     L_BFS_SUM = 0,     // sum of contributions of the level BFS
     L_BEST_FAR = 1,    // best farness found by the closeness engine
-    L_EDGES = 2,       // total algorithmic edges of a gain launch
-    L_VISITED = 3,     // total |V(v)| of a gain launch
+    // word-level work of the device-wide engine, summed over gain launches:
+    // frontier entries (all levels, root level, last level) and adjacency
+    // entries of expanded levels / of the last level
+    L_WORDS = 64,
+    kWordCounters = 5,
 };
 
 struct Slots {
@@ -129,6 +132,7 @@ struct WideArgs {
     unsigned long long *active;
     int64_t *prev;                 // 2 x nsrc
     int64_t *far_out;              // nsrc
+    int64_t *words;                // optional: kWordCounters totals, added to at the end
 };
 // After level L: BFScut test for every live source of a closeness launch
 // (distances from an all-INF 16-bit array, so F = reached*65535 - gain).

@@ -423,7 +423,21 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
         __threadfence();
         const int d = atomicAdd(a.done, 1);
         if (d == (int)gridDim.x - 1) {
-            // every workgroup has read the level records: reset them
+            // every workgroup has read the level records: count, then reset them
+            if (a.words) {
+                int64_t nall = 0, eexp = 0;
+                for (int32_t l = 0; l <= nlev; ++l) {
+                    const uint64_t pk = a.lvl[l].packed;
+                    nall += (int64_t)(pk >> kCntShift);
+                    if (l < nlev) eexp += (int64_t)(pk & kMEdges);
+                }
+                const uint64_t pl = a.lvl[nlev].packed;
+                a.words[0] += nall;
+                a.words[1] += (int64_t)(a.lvl[0].packed >> kCntShift);
+                a.words[2] += (int64_t)(pl >> kCntShift);
+                a.words[3] += eexp;
+                a.words[4] += (int64_t)(pl & kMEdges);
+            }
             for (int32_t l = 0; l <= nlev + 1; ++l) {
                 a.lvl[l].start = 0;
                 a.lvl[l].packed = 0ull;

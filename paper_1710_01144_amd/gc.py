@@ -35,7 +35,7 @@ ORDERS = {"plain": ORDER_PLAIN, "celf": ORDER_CELF, "learned": ORDER_LEARNED}
 
 EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_workspace_size",
             "gc_workspace_init", "gc_closest_node", "gc_update_dist", "gc_marginal_gains",
-            "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
+            "gc_gain_words", "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
             "gc_node_features", "gc_timing_enable", "gc_timing_last_ms"]
 MLP_PARAMS = 4801
@@ -71,6 +71,9 @@ class GcStats(ctypes.Structure):
                 ("ms_closest", ctypes.c_double), ("ms_round1", ctypes.c_double),
                 ("ms_later", ctypes.c_double), ("ms_update", ctypes.c_double),
                 ("ms_mlp", ctypes.c_double),
+                ("entries_word", ctypes.c_int64), ("entries_root", ctypes.c_int64),
+                ("entries_last", ctypes.c_int64), ("edges_word", ctypes.c_int64),
+                ("edges_last", ctypes.c_int64),
                 ("h_evals_per_round", ctypes.POINTER(ctypes.c_int64))]
 
     def as_dict(self):
@@ -109,6 +112,8 @@ def load_library():
     lib.gc_update_dist.argtypes = [vp, i32, vp, i32, vp, ctypes.c_size_t, vp, vp]
     lib.gc_marginal_gains.restype = ctypes.c_int
     lib.gc_marginal_gains.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.gc_gain_words.restype = ctypes.c_int
+    lib.gc_gain_words.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i64)]
     lib.gc_greedy_group.restype = ctypes.c_int
     lib.gc_greedy_group.argtypes = [vp, i32, ctypes.POINTER(GcOpts), vp, ctypes.c_size_t, vp,
                                     ctypes.POINTER(i32), ctypes.POINTER(i64),
@@ -242,6 +247,13 @@ class Graph:
         if stats:
             return gain[:count], edges[:count], vis[:count]
         return gain[:count]
+
+    def gain_words(self) -> dict:
+        """Word-level work of the last marginal_gains call (see gc_gain_words)."""
+        out = (ctypes.c_int64 * 5)()
+        _check(load_library().gc_gain_words(self.handle, _ptr(self.ws), self.ws_bytes, _stream(), out))
+        return dict(zip(("entries", "entries_root", "entries_last", "edges", "edges_last"),
+                        (int(x) for x in out)))
 
     def node_features(self, dist, dist_bytes, ub, last_eval, dist_at_eval, round_, k, ecc1,
                       cand=None):

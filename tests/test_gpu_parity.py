@@ -91,6 +91,39 @@ def test_update_dist_and_gains_ba2000(gclib, device):
         assert np.array_equal(vis.cpu().numpy().astype(np.int64), vv)
 
 
+def test_word_counters_ba2000(gclib, device):
+    """The engine's word-level counters: with one candidate per call a frontier
+    entry is one visited node, so entries = |V(v)| and the adjacency counts add
+    up to the per-candidate edge count; with 64 sources per batch the entries
+    lie between the per-source totals / 64 and the totals."""
+    g = graphgen.workload("ba2000")
+    G = _graph(gclib, g)
+    s1 = int(oracle.greedy(g, 1)[0][0])
+    dist = G.new_dist(1)
+    far = torch.zeros(1, dtype=torch.int64, device=device)
+    G.update_dist(s1, dist, 1, far)
+    dS = oracle.group_dist(g, [s1])
+    rng = np.random.default_rng(4)
+    _note("word counters, single candidates")
+    for v in rng.choice(g.n, 12, replace=False).tolist() + [s1]:
+        gain, edges, vis = G.marginal_gains(dist, 1, torch.tensor([v], dtype=torch.int32), stats=True)
+        w = G.gain_words()
+        gg, vv, ee = oracle.pruned_stats(g, dS, np.array([v], dtype=np.int32))
+        assert int(vis.item()) == int(vv[0]) == w["entries"]
+        assert w["edges"] + w["edges_last"] == int(edges.item()) == int(ee[0])
+        assert w["entries_root"] == (0 if v == s1 else 1)
+    _note("word counters, one launch over all candidates")
+    cand = torch.arange(g.n, dtype=torch.int32)
+    gain, edges, vis = G.marginal_gains(dist, 1, cand, stats=True)
+    w = G.gain_words()
+    tv = int(vis.to(torch.int64).sum().item())
+    te = int(edges.sum().item())
+    assert w["entries_root"] == g.n - 1
+    assert tv >= w["entries"] >= -(-tv // 64)
+    assert te >= w["edges"] + w["edges_last"] >= -(-te // 64)
+    assert w["entries"] >= w["entries_root"] + w["entries_last"]
+
+
 def test_greedy_ba2000_k10(gclib):
     g = graphgen.workload("ba2000")
     grp_ref, F_ref = oracle.greedy(g, 10)
