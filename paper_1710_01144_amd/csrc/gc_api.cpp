@@ -968,6 +968,37 @@ extern "C" int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_byte
 
 namespace {
 
+// Max tree over node ids holding the stale gains (ub; -1 for members of S).
+// The plain scan's next candidate that can still beat the best is the leftmost
+// id >= pos whose ub reaches the best gain, found in O(log n) instead of a walk
+// over every remaining id.
+struct MaxTree {
+    int32_t leaves = 1;
+    std::vector<int64_t> t;
+    void build(const std::vector<int64_t> &ub, const std::vector<uint8_t> &inS) {
+        const int32_t n = (int32_t)ub.size();
+        leaves = 1;
+        while (leaves < n) leaves <<= 1;
+        t.assign((size_t)2 * leaves, -1);
+        for (int32_t i = 0; i < n; ++i) t[(size_t)leaves + i] = inS[i] ? -1 : ub[i];
+        for (int32_t i = leaves - 1; i >= 1; --i) t[i] = std::max(t[2 * i], t[2 * i + 1]);
+    }
+    void set(int32_t i, int64_t x) {
+        size_t j = (size_t)leaves + i;
+        t[j] = x;
+        for (j >>= 1; j >= 1; j >>= 1) t[j] = std::max(t[2 * j], t[2 * j + 1]);
+    }
+    // leftmost id >= lo with value >= x, or -1
+    int32_t first_at_least(int32_t lo, int64_t x) const { return first(1, 0, leaves, lo, x); }
+    int32_t first(size_t node, int32_t nl, int32_t nr, int32_t lo, int64_t x) const {
+        if (nr <= lo || t[node] < x) return -1;
+        if (nr - nl == 1) return nl;
+        const int32_t mid = nl + (nr - nl) / 2;
+        const int32_t r = first(2 * node, nl, mid, lo, x);
+        return r >= 0 ? r : first(2 * node + 1, mid, nr, lo, x);
+    }
+};
+
 struct PinnedBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -1207,6 +1238,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     };
     std::vector<HeapEntry> heap;
     std::vector<uint32_t> ver;
+    const bool plain_scan = o.order != GC_ORDER_CELF && !learned;
+    MaxTree tree;
     const int32_t first_gain_round = (int32_t)group.size();
     for (int32_t r = first_gain_round; r < k; ++r) {
         const double tr = now_ms();
@@ -1278,9 +1311,22 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     heap.pop_back();
                     hc[cnt++] = top.id;
                 }
-            } else {
+            } else if (first_round) {
                 for (; pos < n && cnt < blk; ++pos)
-                    if (!inS[pos] && can_beat(pos)) hc[cnt++] = pos;
+                    if (!inS[pos]) hc[cnt++] = pos;
+            } else {
+                // ascending ids that can still beat the best: the tree skips
+                // every id whose bound is below the best gain
+                const int64_t thr = best_id < 0 ? 0 : best_gain;
+                while (cnt < blk && pos < n) {
+                    const int32_t u = tree.first_at_least(pos, thr);
+                    if (u < 0) {
+                        pos = n;
+                        break;
+                    }
+                    pos = u + 1;
+                    if (can_beat(u)) hc[cnt++] = u;  // an equal bound with a larger id cannot
+                }
             }
             if (cnt == 0) break;
             rc = evaluate(cnt);
@@ -1299,6 +1345,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 const int32_t u = hc[j];
                 const int64_t gu = hg[j];
                 ub[u] = gu;
+                if (plain_scan && !first_round) tree.set(u, gu);
                 last_eval[u] = r;
                 st.edges_alg += he[j];
                 if (best_id < 0 || gu > best_gain || (gu == best_gain && u < best_id)) {
@@ -1313,6 +1360,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             }
             nev += cnt;
         }
+        if (first_round && plain_scan) tree.build(ub, inS);
         if (first_round && (o.order == GC_ORDER_CELF || learned)) {
             ver.assign((size_t)n, 0u);
             heap.clear();
@@ -1353,6 +1401,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         group.push_back(best_id);
         Fs.push_back(F);
         inS[best_id] = 1;
+        if (plain_scan && !tree.t.empty()) tree.set(best_id, -1);
     }
     for (int32_t i = 0; i < k; ++i) {
         h_group[i] = group[i];
