@@ -315,7 +315,6 @@ struct WsLayout {
 constexpr int32_t kMaxLevels = 65536;  // 16-bit distances: at most 65534 levels
 constexpr int kFlagSlot = 16;          // int32 counter slot of the overflow flag
 constexpr int kMaxdSlot = 17;          // int32 counter slot for max d(S,.)
-constexpr int kDoneSlot = 18;          // int32 workgroup counter of the final gain kernel
 
 
 
@@ -426,7 +425,6 @@ struct Ws {
         a.cap = L.cap;
         a.lvl = reinterpret_cast<WideLevel *>(base + L.lvl);
         a.flags = flags();
-        a.done = ctr() + kDoneSlot;
         a.min_edges = 1024;
         return a;
     }

@@ -110,7 +110,6 @@ struct WideArgs {
     int32_t tag;
     int32_t min_edges;             // adjacency entries per workgroup before a level
                                    // uses more workgroups (small levels stay compact)
-    int32_t *done;                 // workgroup counter of the final kernel (zero between launches)
     // optional host-mapped destinations written by the final kernel
     int64_t *h_gain;
     int64_t *h_edges;

@@ -215,10 +215,14 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
 // for occupancy.  U: edges per thread per step.
 template <typename DistT, bool WRITE, bool LDS, int U>
 __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
+    constexpr int kStep = kWG * U;  // adjacency entries per workgroup step
     __shared__ int64_t s_off[kWin + 1];
     __shared__ int32_t s_rs[kWin];
     __shared__ int32_t s_b[kWin];
     __shared__ uint64_t s_m[kWin];
+    __shared__ size_t s_rb[kWin];   // first record of the entry's batch
+    __shared__ int16_t s_idx[kStep];  // window entry of each adjacency entry of a step
+    __shared__ int32_t s_wmax[kWG / 64];
     __shared__ int64_t s_first;
     __shared__ int64_t s_wc[kWG / 64], s_wd[kWG / 64];
     __shared__ uint64_t s_old;
@@ -297,6 +301,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
             s_off[tid] = a.lo[q];
             s_rs[tid] = a.lr[q];
             s_b[tid] = b;
+            s_rb[tid] = (size_t)b * a.vis_stride;
             const uint64_t f = *rec(a, b, a.ly[q], fr_cur);
             s_m[tid] = a.active ? (f & a.active[b]) : f;
         }
@@ -304,7 +309,49 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
         __syncthreads();
         const int64_t wlo = eb > s_off[0] ? eb : s_off[0];
         const int64_t whi = ee < s_off[cnt] ? ee : s_off[cnt];
-        for (int64_t e0 = wlo; e0 < whi; e0 += (int64_t)kWG * U) {
+        // the window's first adjacency entry to expand lies in entry 0
+        int carry = 0;
+        for (int64_t e0 = wlo; e0 < whi; e0 += kStep) {
+            // Entry of every adjacency entry of the step: the entry holding
+            // the first one marks position 0, every entry starting inside the
+            // step marks its first position, and a max-scan fills the gaps.
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                const int q = tid + r * kWG;
+                s_idx[q] = q == 0 ? (int16_t)carry : (int16_t)-1;
+            }
+            __syncthreads();
+            if (tid < cnt) {
+                const int64_t p = s_off[tid] - e0;
+                if (p >= 0 && p < kStep) s_idx[p] = (int16_t)tid;
+            }
+            __syncthreads();
+            {
+                const int lane = lane_id();
+                int run = -1;
+                int16_t v[U];
+#pragma unroll
+                for (int r = 0; r < U; ++r) {
+                    const int x = s_idx[tid * U + r];
+                    run = x > run ? x : run;
+                    v[r] = (int16_t)run;
+                }
+                int inc = run;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(inc, o);
+                    if (lane >= o) inc = t > inc ? t : inc;
+                }
+                int pre = __shfl_up(inc, 1);
+                if (lane == 0) pre = -1;
+                if (lane == 63) s_wmax[tid >> 6] = inc;
+                __syncthreads();
+                for (int k = 0; k < (tid >> 6); ++k) pre = s_wmax[k] > pre ? s_wmax[k] : pre;
+#pragma unroll
+                for (int r = 0; r < U; ++r) s_idx[tid * U + r] = v[r] > pre ? v[r] : (int16_t)pre;
+            }
+            __syncthreads();
+            carry = s_idx[kStep - 1];
             int32_t y[U], own[U], bb[U], deg[U], rs[U];
             uint32_t d[U];
             bool p[U];
@@ -314,11 +361,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                 own[r] = -1;
                 y[r] = 0;
                 if (e < whi) {
-                    int lo = 0, hi = cnt - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
-                    }
+                    const int lo = s_idx[tid + r * kWG];
                     if (s_m[lo]) {
                         own[r] = lo;
                         y[r] = ci[s_rs[lo] + (int32_t)(e - s_off[lo])];
@@ -335,7 +378,8 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                 rs[r] = 0;
                 if (own[r] >= 0 && nl < d[r]) {
                     bb[r] = s_b[own[r]];
-                    unsigned long long *vw = rec(a, bb[r], y[r], 0);
+                    unsigned long long *vw =
+                        reinterpret_cast<unsigned long long *>(a.vis) + (s_rb[own[r]] + (size_t)y[r]) * 4;
                     // row pointers are needed only for a claim: load them with the visited word
                     rs[r] = rp[y[r]];
                     const int32_t re = rp[y[r] + 1];
@@ -362,7 +406,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                                 }
                             }
                             // first claim of (batch, node) at this level: one frontier entry
-                            p[r] = atomicOr(rec(a, bb[r], y[r], fr_next), (unsigned long long)nw) == 0ull;
+                            p[r] = atomicOr(vw + fr_next, (unsigned long long)nw) == 0ull;
                         }
                     }
                 }
@@ -384,10 +428,9 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
 }
 
 // End of a launch: return every touched node record to zero, copy the results
-// to the host-mapped buffers if given, scatter them into the lazy-loop state if
-// asked, and (last workgroup) zero the level records so the next launch starts
-// clean.  After an overflow nothing is cleared here; the host clears and
-// retries.
+// to the host-mapped buffers if given and scatter them into the lazy-loop
+// state if asked.  After an overflow nothing is cleared here; the host clears
+// and retries.
 __global__ void k_wide_end(WideArgs a, int32_t nlev) {
     const int32_t flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (flag) {
@@ -418,34 +461,35 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
             a.dsat_out[v] = a.dist_bytes == 1 ? (uint16_t)reinterpret_cast<const uint8_t *>(a.dist)[v]
                                               : reinterpret_cast<const uint16_t *>(a.dist)[v];
         }
-    __syncthreads();
+}
+
+// After k_wide_end (one workgroup): count the launch's word-level work, zero
+// the level records so the next launch starts clean, clear the host-visible
+// flag and (update mode) F(S + s) = F(S) - g(s, S).
+__global__ void k_wide_reset(WideArgs a, int32_t nlev) {
+    if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     if (threadIdx.x == 0) {
-        __threadfence();
-        const int d = atomicAdd(a.done, 1);
-        if (d == (int)gridDim.x - 1) {
-            // every workgroup has read the level records: count, then reset them
-            if (a.words) {
-                int64_t nall = 0, eexp = 0;
-                for (int32_t l = 0; l <= nlev; ++l) {
-                    const uint64_t pk = a.lvl[l].packed;
-                    nall += (int64_t)(pk >> kCntShift);
-                    if (l < nlev) eexp += (int64_t)(pk & kMEdges);
-                }
-                const uint64_t pl = a.lvl[nlev].packed;
-                a.words[0] += nall;
-                a.words[1] += (int64_t)(a.lvl[0].packed >> kCntShift);
-                a.words[2] += (int64_t)(pl >> kCntShift);
-                a.words[3] += eexp;
-                a.words[4] += (int64_t)(pl & kMEdges);
+        if (a.words) {
+            int64_t nall = 0, eexp = 0;
+            for (int32_t l = 0; l <= nlev; ++l) {
+                const uint64_t pk = a.lvl[l].packed;
+                nall += (int64_t)(pk >> kCntShift);
+                if (l < nlev) eexp += (int64_t)(pk & kMEdges);
             }
-            for (int32_t l = 0; l <= nlev + 1; ++l) {
-                a.lvl[l].start = 0;
-                a.lvl[l].packed = 0ull;
-            }
-            atomicExch(a.done, 0);
-            if (a.h_flag) *a.h_flag = 0;
-            if (a.far) *a.far -= a.gain[0];  // update: F(S + s) = F(S) - g(s, S)
+            const uint64_t pl = a.lvl[nlev].packed;
+            a.words[0] += nall;
+            a.words[1] += (int64_t)(a.lvl[0].packed >> kCntShift);
+            a.words[2] += (int64_t)(pl >> kCntShift);
+            a.words[3] += eexp;
+            a.words[4] += (int64_t)(pl & kMEdges);
         }
+        if (a.h_flag) *a.h_flag = 0;
+        if (a.far) *a.far -= a.gain[0];  // update: F(S + s) = F(S) - g(s, S)
+    }
+    __syncthreads();
+    for (int32_t l = threadIdx.x; l <= nlev + 1; l += blockDim.x) {
+        a.lvl[l].start = 0;
+        a.lvl[l].packed = 0ull;
     }
 }
 
@@ -570,11 +614,12 @@ hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int
 }
 
 hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_t s) {
-    // enough workgroups for the record clean-up of a launch of this size
-    int64_t g = (a.nsrc + 63) / 64 * 4;
-    if (g > grid) g = grid;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_wide_end, dim3((int)g), dim3(256), 0, s, a, nlev);
+    // the record clean-up is a scatter of 32-byte stores, one per frontier
+    // entry: it takes the whole grid even for a small batch (a hub's pruned
+    // BFS can touch most of the graph); the level records are reset after it
+    const int g = grid < 1 ? 1 : grid;
+    hipLaunchKernelGGL(k_wide_end, dim3(g), dim3(256), 0, s, a, nlev);
+    hipLaunchKernelGGL(k_wide_reset, dim3(1), dim3(256), 0, s, a, nlev);
     return hipGetLastError();
 }
 
