@@ -304,7 +304,7 @@ constexpr size_t kCtrBytes = 4096;
 
 struct WsLayout {
     size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
-    size_t wvis, ly, lr, lb, lo, lvl, act, cutprev, farout, total;
+    size_t wvis, ly, lr, lb, lo, lz, lvl, act, cutprev, farout, cisplit, rinfo, dist1, total;
     int32_t nslots;
     SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
@@ -369,10 +369,15 @@ WsLayout ws_layout(const gc_graph *g) {
     L.lr = o; o += al256((size_t)cap * 4);
     L.lb = o; o += al256((size_t)cap * 4);
     L.lo = o; o += al256((size_t)cap * 8);
+    L.lz = o; o += al256((size_t)cap * 8);
     L.lvl = o; o += al256((size_t)(kMaxLevels + 2) * sizeof(WideLevel));
     L.act = o; o += al256((size_t)kmax * 8);
     L.cutprev = o; o += al256(n * 16);
     L.farout = o; o += al256(n * 8);
+    // rows split by d(S,.) at the first gain round (see WideArgs::rinfo)
+    L.cisplit = o; o += al256((size_t)g->nnz * 4 + 4);
+    L.rinfo = o; o += al256(n * 16);
+    L.dist1 = o; o += al256(n * 2 + 4);
     L.total = o;
     return L;
 }
@@ -414,6 +419,7 @@ struct Ws {
     }
     int32_t *maxd() const { return ctr() + kMaxdSlot; }
     int64_t *words() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_WORDS; }
+    int64_t *zcnt() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_TOUCHED; }
     WideArgs wide() const {
         WideArgs a{};
         a.vis = reinterpret_cast<uint64_t *>(base + L.wvis);
@@ -422,6 +428,8 @@ struct Ws {
         a.lr = reinterpret_cast<int32_t *>(base + L.lr);
         a.lb = reinterpret_cast<int32_t *>(base + L.lb);
         a.lo = reinterpret_cast<int64_t *>(base + L.lo);
+        a.lz = reinterpret_cast<int64_t *>(base + L.lz);
+        a.zcnt = reinterpret_cast<unsigned long long *>(zcnt());
         a.cap = L.cap;
         a.lvl = reinterpret_cast<WideLevel *>(base + L.lvl);
         a.flags = flags();
@@ -537,6 +545,33 @@ int run_gains_wg(const gc_graph *g, const Ws &w, const void *d_dist, int dist_by
 
 int wide_grid(const gc_graph *g) { return g->level_wgs_per_cu * g->num_cu; }
 
+// Rows split by the distances a gain or update launch prunes against (see
+// WideArgs::rinfo); valid while d(S,.) stays at or below those distances.
+struct Split {
+    const int32_t *ci = nullptr;
+    const int4 *rinfo = nullptr;
+    const void *dist1 = nullptr;
+};
+
+int build_split(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes, hipStream_t s,
+                Split *out) {
+    int32_t *ci = reinterpret_cast<int32_t *>(w.base + w.L.cisplit);
+    int4 *ri = reinterpret_cast<int4 *>(w.base + w.L.rinfo);
+    void *d1 = w.base + w.L.dist1;
+    HIP_OK(launch_row_split(g->d_rp, g->d_ci, g->n, d_dist, dist_bytes, ci, ri, d1, s));
+    out->ci = ci;
+    out->rinfo = ri;
+    out->dist1 = d1;
+    return GC_OK;
+}
+
+void apply_split(WideArgs &a, const Split *sp) {
+    if (!sp || !sp->rinfo) return;
+    a.ci = sp->ci;
+    a.rinfo = sp->rinfo;
+    a.dist1 = sp->dist1;
+}
+
 // Marginal gains of count candidates with the device-wide engine.
 // nlev = number of BFS levels to expand (max d(S,.) - 1 suffices; < 0: measure
 // it).  d_cand may be device memory or host-mapped pinned memory.  With
@@ -566,7 +601,8 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
               const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
               int32_t *d_vis, hipStream_t s, int32_t nlev, int64_t *h_gain = nullptr,
               int64_t *h_edges = nullptr, const HostIO *io = nullptr,
-              LaunchShape *shape = nullptr) {
+              LaunchShape *shape = nullptr, const Split *split = nullptr,
+              bool timing_started = false) {
     if (count <= 0) return GC_OK;
     if (g->wg_engine) {
         int rc = run_gains_wg(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_vis, s);
@@ -588,7 +624,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     nlev = std::min(nlev, kMaxLevels - 1);
     const bool mapped = io && io->hm_flag;
     const int grid = wide_grid(g);
-    if (g_timing) HIP_OK(hipEventRecord(g_ev0, s));
+    if (g_timing && !timing_started) HIP_OK(hipEventRecord(g_ev0, s));
     // batches per launch and sources per batch; a caller-kept shape carries
     // what an earlier overflow taught across calls
     int64_t kb = (shape && shape->kb > 0) ? std::min<int64_t>(shape->kb, w.L.kmax) : w.L.kmax;
@@ -616,6 +652,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             a.tag = ++tag;
             a.dist_bytes = dist_bytes;
             a.words = w.words();
+            apply_split(a, split);
             if (mapped) {
                 a.h_gain = io->hm_gain ? io->hm_gain + off : nullptr;
                 a.h_edges = io->hm_edges ? io->hm_edges + off : nullptr;
@@ -664,6 +701,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                                (size_t)w.L.kmax * w.L.vis_stride * 8, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
                                (size_t)(nlev + 2) * sizeof(WideLevel) / 4, 0u, s));
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.zcnt()), 2, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
         if (kb > 1) kb = std::max<int64_t>(1, kb / 2);
         else if (spb > 1) spb = std::max(1, spb / 2);
@@ -677,7 +715,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
 // d(S,.) <- min(d(S,.), d(root,.)) and F(S) -= g(root, S) with the
 // edge-balanced engine (S != {}); asynchronous.  nlev = max d(S,.) - 1.
 int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int dist_bytes,
-                    int64_t *d_far, hipStream_t s, int32_t nlev) {
+                    int64_t *d_far, hipStream_t s, int32_t nlev, const Split *split = nullptr) {
     nlev = std::min(std::max(nlev, 0), kMaxLevels - 1);
     WideArgs a = w.wide();
     a.unroll = g->unroll;
@@ -694,6 +732,8 @@ int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, 
     a.tag = 1;
     a.write = true;
     a.far = d_far;
+    a.dist_bytes = dist_bytes;
+    apply_split(a, split);
     const int grid = wide_grid(g);
     HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
     HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
@@ -874,6 +914,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
                                    (size_t)w.L.kmax * w.L.vis_stride * 8, 0u, s));
             HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
                                    (size_t)(kMaxLevels + 2) * sizeof(WideLevel) / 4, 0u, s));
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.zcnt()), 2, 0u, s));
             HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
             if (kb > 1) kb /= 2;
             else if (spb > 1) spb = std::max(1, spb / 2);
@@ -947,7 +988,15 @@ extern "C" int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t 
     if (count < 0) return fail(GC_EINVAL, "count < 0");
     if (count > 0 && (!d_dist || !d_cand || !d_gain)) return fail(GC_EINVAL, "NULL device pointer");
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.words()), 2 * kWordCounters, 0u, stream));
-    return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream, -1);
+    if (count == 0) return GC_OK;
+    // the row split is built from these distances for this call (its time
+    // counts in the timed span)
+    if (g_timing) HIP_OK(hipEventRecord(g_ev0, stream));
+    Split sp;
+    int rc2 = build_split(g, w, d_dist, dist_bytes, stream, &sp);
+    if (rc2) return rc2;
+    return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream, -1,
+                     nullptr, nullptr, nullptr, nullptr, &sp, true);
 }
 
 extern "C" int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_bytes, hipStream_t stream,
@@ -1157,6 +1206,13 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     }
     if (st.h_evals_per_round)
         for (int32_t i = 0; i < k; ++i) st.h_evals_per_round[i] = 0;
+    // rows split by d(S,.) of the first gain round: d(S,.) never grows, so the
+    // split bounds every later round too
+    Split split;
+    if (!g->wg_engine) {
+        rc = build_split(g, w, d_dist, dist_bytes, s, &split);
+        if (rc) return rc;
+    }
 
     const bool verbose = getenv("GC_VERBOSE") != nullptr;
     LaunchShape shape_r1, shape_later;
@@ -1173,7 +1229,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         } else {
             r = run_gains(g, w, d_dist, dist_bytes, dc, cnt, w.gain(),
                           want_edges ? w.aux() : nullptr, nullptr, s,
-                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr, &io, shape);
+                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr, &io, shape,
+                          &split);
         }
         if (r) return r;
         st.gain_launches += 1;
@@ -1383,7 +1440,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         if (best_id < 0) return fail(GC_EINVAL, "no candidate left");
         // pick, then d(S,.) <- min(d(S,.), d(pick,.)) by pruned BFS
         t0 = now_ms();
-        rc = run_update_wide(g, w, best_id, d_dist, dist_bytes, w.far(), s, ecc_bound - 1);
+        rc = run_update_wide(g, w, best_id, d_dist, dist_bytes, w.far(), s, ecc_bound - 1, &split);
         if (rc) return rc;
         F -= best_gain;
         if (o.debug_checks || r == k - 1) {

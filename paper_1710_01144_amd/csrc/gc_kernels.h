@@ -27,6 +27,7 @@ enum : int {
     // entries of expanded levels / of the last level
     L_WORDS = 64,
     kWordCounters = 5,
+    L_TOUCHED = 72,    // records touched by the current launch (clean-up list length)
 };
 
 struct Slots {
@@ -105,6 +106,10 @@ struct WideArgs {
     int32_t *lb;                   //               batch
     int64_t *lo;                   //               first adjacency position (per level)
     int64_t cap;                   // log capacity (entries)
+    // clean-up list: every (batch << 32 | node) record the launch touches, named
+    // once by the claim that finds its visited word empty
+    int64_t *lz;
+    unsigned long long *zcnt;      // entries in lz (zero between launches)
     WideLevel *lvl;                // per-level records, nlev + 2 of them
     int32_t *flags;                // [0]: nonzero after an overflow (value = tag)
     int32_t tag;
@@ -132,7 +137,18 @@ struct WideArgs {
     int64_t *prev;                 // 2 x nsrc
     int64_t *far_out;              // nsrc
     int64_t *words;                // optional: kWordCounters totals, added to at the end
+    // optional row split by d1 = the d(S,.) it was built from, which bounds
+    // d(S,.) from above for the rest of the run: ci rows ordered
+    // [d1 > d1(y) | d1 == d1(y) | d1 < d1(y)] for the row's node y, and
+    // rinfo[y] = {row start, degree, #first segment, #first two segments}
+    const int4 *rinfo;
+    const void *dist1;             // d1, same width as dist
 };
+// Split every row of (rp, ci) by the distances dist (see WideArgs::rinfo);
+// dist1 receives a copy of dist.
+hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, const void *dist,
+                            int dist_bytes, int32_t *ci_out, int4 *rinfo, void *dist1,
+                            hipStream_t s);
 // After level L: BFScut test for every live source of a closeness launch
 // (distances from an all-INF 16-bit array, so F = reached*65535 - gain).
 hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, hipStream_t s);

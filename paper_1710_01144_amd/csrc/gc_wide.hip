@@ -19,6 +19,9 @@
 // So settlement is exact per claim, and every (batch, node) enters a level's
 // frontier once, carrying the union of the bits that reached it: sources that
 // share territory share the expansion (the point of the bit-parallel form).
+// A node with nothing left to expand (see expand_len) gets no frontier entry;
+// the claim that finds a record's visited word empty names the record in a
+// clean-up list, from which the end of the launch zeroes every record touched.
 // Level L+1 reads fr[(L+1)%3]; level L+2 writes fr[(L+3)%3] = fr[L%3], which
 // level L+1 clears first -- no word is read and written in the same kernel.
 //
@@ -70,6 +73,23 @@ __device__ __forceinline__ void log_entry(const WideArgs &a, int64_t pos, int32_
     } else {
         set_flag(a.flags, a.tag);
     }
+}
+
+// Adjacency entries of y worth expanding when y enters the frontier at level
+// lvl.  A neighbour z can be claimed at lvl + 1 only if d(S,z) >= lvl + 2, and
+// d(S,z) <= d1(z); along y's split row d1(z) is above, equal to, then below
+// d1(y), so the candidates are a prefix of the row.  (A claimed y has
+// lvl < d(S,y) <= d1(y), so lvl + 2 <= d1(y) + 1.)
+__device__ __forceinline__ int32_t expand_len(const int4 &ri, uint32_t d1, uint32_t lvl) {
+    const uint32_t need = lvl + 2;
+    if (need < d1) return ri.y;   // any neighbour may qualify
+    if (need == d1) return ri.w;  // neighbours with d1(z) >= d1(y)
+    return ri.z;                  // neighbours with d1(z) > d1(y)
+}
+
+template <typename DistT>
+__device__ __forceinline__ uint32_t load_d1(const WideArgs &a, int32_t y) {
+    return reinterpret_cast<const DistT *>(a.dist1)[y];
 }
 
 // Wave-level append (every lane of a fully active wave calls it).
@@ -164,6 +184,36 @@ __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int
     }
 }
 
+__device__ __forceinline__ void touch_entry(const WideArgs &a, int64_t pos, int32_t b, int32_t y) {
+    if (pos < a.cap) a.lz[pos] = ((int64_t)b << 32) | (uint32_t)y;
+    else set_flag(a.flags, a.tag);
+}
+
+// Wave-level append of touched records: thread t names up to U of them (t[r]).
+template <int U>
+__device__ __forceinline__ void touch_wave(const WideArgs &a, const bool *t, const int32_t *bb,
+                                           const int32_t *y) {
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < U; ++r) c += t[r] ? 1 : 0;
+    if (__ballot(c > 0) == 0) return;
+    const int lane = lane_id();
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 63);
+    unsigned long long old = 0;
+    if (lane == 0) old = atomicAdd(a.zcnt, (unsigned long long)total);
+    old = shfl64(old, 0);
+    int64_t pos = (int64_t)old + (incl - c);
+#pragma unroll
+    for (int r = 0; r < U; ++r)
+        if (t[r]) touch_entry(a, pos++, bb[r], y[r]);
+}
+
 // Level 0: every source claims its own node (weight d(S,v) - 0).
 // WRITE: the d(S,.) update after a pick -- a claimed node also stores its new
 // distance (in place: a later prune test against it fails, and the visited
@@ -173,7 +223,7 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
     if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool p = false;
+    bool p = false, touched = false;
     int32_t v = 0, b = 0, deg = 0, rs = 0;
     if (t < a.nsrc) {
         v = a.src ? a.src[t] : a.root;
@@ -196,17 +246,29 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
         if (d > 0u) {
             const uint64_t bit = 1ull << j;
             const uint64_t old = atomicOr(rec(a, b, v, 0), (unsigned long long)bit);
+            touched = old == 0ull;
             if (bit & ~old) {
                 if (WRITE) dist[v] = 0;
-                rs = a.rp[v];
-                deg = a.rp[v + 1] - rs;
+                int32_t full;
+                if (a.rinfo) {
+                    const int4 ri = a.rinfo[v];
+                    rs = ri.x;
+                    full = ri.y;
+                    deg = expand_len(ri, load_d1<DistT>(a, v), 0u);
+                } else {
+                    rs = a.rp[v];
+                    full = a.rp[v + 1] - rs;
+                    deg = full;
+                }
                 a.gain[t] = (int64_t)d;
-                if (a.edges) a.edges[t] = deg;
+                if (a.edges) a.edges[t] = full;
                 if (a.visited) a.visited[t] = 1;
-                p = atomicOr(rec(a, b, v, 1), (unsigned long long)bit) == 0ull;
+                // nothing to expand: no frontier word, no entry
+                p = deg > 0 && atomicOr(rec(a, b, v, 1), (unsigned long long)bit) == 0ull;
             }
         }
     }
+    touch_wave<1>(a, &touched, &b, &v);
     push_wave(a, &a.lvl[0], 0, p, v, rs, b, deg);
 }
 
@@ -354,7 +416,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
             carry = s_idx[kStep - 1];
             int32_t y[U], own[U], bb[U], deg[U], rs[U];
             uint32_t d[U];
-            bool p[U];
+            bool p[U], tz[U];
 #pragma unroll
             for (int r = 0; r < U; ++r) {
                 const int64_t e = e0 + tid + (int64_t)r * kWG;
@@ -373,6 +435,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
 #pragma unroll
             for (int r = 0; r < U; ++r) {
                 p[r] = false;
+                tz[r] = false;
                 bb[r] = 0;
                 deg[r] = 0;
                 rs[r] = 0;
@@ -380,37 +443,50 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                     bb[r] = s_b[own[r]];
                     unsigned long long *vw =
                         reinterpret_cast<unsigned long long *>(a.vis) + (s_rb[own[r]] + (size_t)y[r]) * 4;
-                    // row pointers are needed only for a claim: load them with the visited word
-                    rs[r] = rp[y[r]];
-                    const int32_t re = rp[y[r] + 1];
+                    // row data is needed only for a claim: load it with the visited word
+                    int4 ri;
+                    uint32_t d1 = 0;
+                    if (a.rinfo) {
+                        ri = a.rinfo[y[r]];
+                        d1 = load_d1<DistT>(a, y[r]);
+                    } else {
+                        const int32_t r0 = rp[y[r]];
+                        ri = make_int4(r0, rp[y[r] + 1] - r0, 0, 0);
+                    }
                     const uint64_t m = s_m[own[r]] & ~(uint64_t)(*vw);
                     if (m) {
-                        const uint64_t nw = m & ~(uint64_t)atomicOr(vw, (unsigned long long)m);
+                        const uint64_t ov = atomicOr(vw, (unsigned long long)m);
+                        tz[r] = ov == 0ull;
+                        const uint64_t nw = m & ~ov;
                         if (nw) {
                             if (WRITE) dist[y[r]] = (DistT)nl;
                             const unsigned long long c = d[r] - nl;
-                            deg[r] = re - rs[r];
+                            const int32_t full = ri.y;
+                            rs[r] = ri.x;
+                            deg[r] = a.rinfo ? expand_len(ri, d1, nl) : full;
                             const int64_t gb = (int64_t)bb[r] * a.spb;
                             for (uint64_t mm = nw; mm; mm &= mm - 1) {
                                 const int64_t j = gb + (__ffsll((unsigned long long)mm) - 1);
                                 if (lds_acc) {
                                     atomicAdd(&s_g[j], c);
-                                    if (a.edges) atomicAdd(&s_e[j], (unsigned long long)deg[r]);
+                                    if (a.edges) atomicAdd(&s_e[j], (unsigned long long)full);
                                     if (a.visited) atomicAdd(&s_v[j], 1u);
                                 } else {
                                     atomicAdd(reinterpret_cast<unsigned long long *>(a.gain + j), c);
                                     if (a.edges)
                                         atomicAdd(reinterpret_cast<unsigned long long *>(a.edges + j),
-                                                  (unsigned long long)deg[r]);
+                                                  (unsigned long long)full);
                                     if (a.visited) atomicAdd(a.visited + j, 1);
                                 }
                             }
-                            // first claim of (batch, node) at this level: one frontier entry
-                            p[r] = atomicOr(vw + fr_next, (unsigned long long)nw) == 0ull;
+                            // first claim of (batch, node) at this level: one frontier
+                            // entry, unless the node has nothing worth expanding
+                            p[r] = deg[r] > 0 && atomicOr(vw + fr_next, (unsigned long long)nw) == 0ull;
                         }
                     }
                 }
             }
+            touch_wave<U>(a, tz, bb, y);
             push_block<U>(a, next, nbase, p, y, rs, bb, deg, s_wc, s_wd, &s_old);
         }
         __syncthreads();
@@ -427,7 +503,7 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     }
 }
 
-// End of a launch: return every touched node record to zero, copy the results
+// End of a launch: return every touched record to zero, copy the results
 // to the host-mapped buffers if given and scatter them into the lazy-loop
 // state if asked.  After an overflow nothing is cleared here; the host clears
 // and retries.
@@ -437,13 +513,13 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
         if (a.h_flag && blockIdx.x == 0 && threadIdx.x == 0) *a.h_flag = flag;
         return;
     }
-    const WideLevel last = a.lvl[nlev];
-    int64_t tot = last.start + (int64_t)(last.packed >> kCntShift);
+    int64_t tot = (int64_t)*a.zcnt;
     if (tot > a.cap) tot = a.cap;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = t0; i < tot; i += nt) {
-        unsigned long long *r0 = rec(a, a.lb[i], a.ly[i], 0);
+        const int64_t z = a.lz[i];
+        unsigned long long *r0 = rec(a, z >> 32, (int32_t)(uint32_t)z, 0);
         r0[0] = 0ull;
         r0[1] = 0ull;
         r0[2] = 0ull;
@@ -485,6 +561,7 @@ __global__ void k_wide_reset(WideArgs a, int32_t nlev) {
         }
         if (a.h_flag) *a.h_flag = 0;
         if (a.far) *a.far -= a.gain[0];  // update: F(S + s) = F(S) - g(s, S)
+        *a.zcnt = 0ull;
     }
     __syncthreads();
     for (int32_t l = threadIdx.x; l <= nlev + 1; l += blockDim.x) {
@@ -545,6 +622,51 @@ __global__ __launch_bounds__(256) void k_twohop_i64(const int32_t *rp, const int
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane == 0) out[row] = acc;
+}
+
+// One wave per row: order the row [d > d(y) | d == d(y) | d < d(y)] (stable
+// within each part) and record the part sizes.
+template <typename DistT>
+__global__ __launch_bounds__(256) void k_row_split(const int32_t *rp, const int32_t *ci, int32_t n,
+                                                    const DistT *dist, int32_t *ci_out, int4 *rinfo,
+                                                    DistT *dist1) {
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (row >= n) return;
+    const int32_t rs = rp[row], re = rp[row + 1];
+    const uint32_t dy = dist[row];
+    int32_t nd = 0, ns = 0;
+    for (int32_t base = rs; base < re; base += 64) {
+        const int32_t e = base + lane;
+        uint32_t dz = dy;
+        bool ok = e < re;
+        if (ok) dz = dist[ci[e]];
+        nd += __popcll(__ballot(ok && dz > dy));
+        ns += __popcll(__ballot(ok && dz == dy));
+    }
+    int32_t pd = rs, ps = rs + nd, pu = rs + nd + ns;
+    for (int32_t base = rs; base < re; base += 64) {
+        const int32_t e = base + lane;
+        const bool ok = e < re;
+        int32_t z = 0;
+        uint32_t dz = dy;
+        if (ok) {
+            z = ci[e];
+            dz = dist[z];
+        }
+        const bool down = ok && dz > dy, same = ok && dz == dy, up = ok && dz < dy;
+        const uint64_t bd = __ballot(down), bs = __ballot(same), bu = __ballot(up);
+        if (down) ci_out[pd + bits_below(bd)] = z;
+        if (same) ci_out[ps + bits_below(bs)] = z;
+        if (up) ci_out[pu + bits_below(bu)] = z;
+        pd += __popcll(bd);
+        ps += __popcll(bs);
+        pu += __popcll(bu);
+    }
+    if (lane == 0) {
+        rinfo[row] = make_int4(rs, re - rs, nd, nd + ns);
+        dist1[row] = (DistT)dy;
+    }
 }
 
 template <typename DistT>
@@ -633,6 +755,22 @@ hipError_t launch_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n, in
                              hipStream_t s) {
     const int64_t g = ((int64_t)n * 64 + 255) / 256;
     hipLaunchKernelGGL(k_twohop_i64, dim3((int)(g < 1 ? 1 : g)), dim3(256), 0, s, rp, ci, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, const void *dist,
+                            int dist_bytes, int32_t *ci_out, int4 *rinfo, void *dist1,
+                            hipStream_t s) {
+    const int64_t g = ((int64_t)n * 64 + 255) / 256;
+    const dim3 grid((unsigned)(g < 1 ? 1 : g));
+    if (dist_bytes == 1)
+        hipLaunchKernelGGL((k_row_split<uint8_t>), grid, dim3(256), 0, s, rp, ci, n,
+                           reinterpret_cast<const uint8_t *>(dist), ci_out, rinfo,
+                           reinterpret_cast<uint8_t *>(dist1));
+    else
+        hipLaunchKernelGGL((k_row_split<uint16_t>), grid, dim3(256), 0, s, rp, ci, n,
+                           reinterpret_cast<const uint16_t *>(dist), ci_out, rinfo,
+                           reinterpret_cast<uint16_t *>(dist1));
     return hipGetLastError();
 }
 
