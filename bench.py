@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU baseline: repeat the oracle run until this much time is spent")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-order comparison (training + four timed orders)")
+    ap.add_argument("--learned-reps", type=int, default=3)
     ap.add_argument("--calib-bytes", type=int, default=1 << 30,
                     help="size of the plain device copy timed (and profiled) as the bandwidth "
                          "and counter calibration")
@@ -96,6 +99,43 @@ def measured_traffic(workload: str):
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def learned_comparison(G, g, k, args, grp, F):
+    """Train the candidate-ordering network on gains logged from plain runs
+    of the BA n=2000 (k=10) and R-MAT scale 16 (k=10, 50) workloads, then time
+    the plain, CELF, learned and untrained (seed 8) orders on this workload.
+    Every order must give the same group and farness."""
+    import torch
+    import graphgen
+    from paper_1710_01144_amd import gc, learned
+    t0 = time.perf_counter()
+    g16 = gc.Graph.from_graphgen(graphgen.workload("rmat16"))
+    runs = [(gc.Graph.from_graphgen(graphgen.workload("ba2000")), 10), (g16, 10), (g16, 50)]
+    X, Y = learned.collect(runs)
+    del runs, g16
+    steps = 1500
+    net, losses = learned.train(X, Y, steps=steps)
+    untrained = gc.Mlp(learned.init_master(8))
+    t_train = time.perf_counter() - t0
+    out = {"train": {"samples": int(X.shape[0]), "steps": steps, "loss_first": round(float(losses[0]), 4),
+                     "loss_last": round(float(losses[-1]), 4), "seconds": round(t_train, 2),
+                     "graphs": "BA n=2000 k=10, R-MAT scale 16 k=10 and k=50 (plain order logs)"},
+           "in_sample": args.workload in ("ba2000", "rmat16")}
+    for name, kw in [("plain", {"order": "plain"}), ("celf", {"order": "celf"}),
+                     ("learned", {"order": "learned", "mlp_params": net.block}),
+                     ("untrained", {"order": "learned", "mlp_params": untrained.block})]:
+        G.greedy_group(k, block=args.block, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.learned_reps):
+            gv, Fv, sv = G.greedy_group(k, block=args.block, **kw)
+        torch.cuda.synchronize()
+        ms = 1000 * (time.perf_counter() - t1) / args.learned_reps
+        assert gv.tolist() == grp.tolist() and Fv.tolist() == F.tolist(), name
+        out[name] = {"ms": round(ms, 3), "evals_round1": int(sv["evals_round1"]),
+                     "evals_later": int(sv["evals_later"]), "ms_mlp": round(float(sv["ms_mlp"]), 3)}
+    return out
 
 
 def main():
@@ -159,6 +199,12 @@ def main():
                 assert gv.tolist() == grp.tolist() and Fv.tolist() == F.tolist()
                 variants["%s_b%d" % (order, blk)] = {"ms": round(ms, 3), "evals_later": int(sv["evals_later"])}
         log("variants " + json.dumps(variants))
+
+    # ---- learned candidate order against plain, CELF and an untrained network
+    learned_cmp = None
+    if not args.no_learned:
+        learned_cmp = learned_comparison(G, g, k, args, grp, F)
+        log("learned vs plain " + json.dumps(learned_cmp))
 
     # ---- roofline of the dominant kernel: first gain round, all candidates
     s1 = int(grp[0])
@@ -261,6 +307,7 @@ def main():
         "group_wall_ms": round(ms_per_step, 4),
         "evals": {"round1": int(stats[-1]["evals_round1"]), "later": int(stats[-1]["evals_later"])},
         "variants": variants or None,
+        "learned_vs_plain": learned_cmp,
         "breakdown_ms": {kk: round(float(stats[-1][kk]), 3) for kk in
                          ("ms_closest", "ms_round1", "ms_later", "ms_update", "ms_mlp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

@@ -1126,13 +1126,17 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     const bool need_state = learned || logging;
     if (need_state && ws_bytes < w.L.total + gc_mlp_ws_bytes(n))
         return fail(GC_EWORKSPACE, "learned order / logging needs the full gc_workspace_size()");
-    PinnedBuf pin_score, pin_feat;
+    PinnedBuf pin_score, pin_feat, pin_pool;
     float *hscore = nullptr, *dscore = nullptr, *hfeat = nullptr, *dfeat = nullptr;
+    int32_t *hpool = nullptr, *dpool = nullptr;
     if (need_state) {
-        if (pin_score.ensure(sizeof(float) * (size_t)n) != hipSuccess)
+        if (pin_score.ensure(sizeof(float) * (size_t)n) != hipSuccess ||
+            pin_pool.ensure(sizeof(int32_t) * (size_t)n) != hipSuccess)
             return fail(GC_ENOMEM, "pinned score buffer");
         hscore = reinterpret_cast<float *>(pin_score.p);
         HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dscore), hscore, 0));
+        hpool = reinterpret_cast<int32_t *>(pin_pool.p);
+        HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dpool), hpool, 0));
         if (logging) {
             if (pin_feat.ensure(sizeof(float) * 8 * (size_t)n) != hipSuccess)
                 return fail(GC_ENOMEM, "pinned feature buffer");
@@ -1254,15 +1258,18 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         io.last_eval = mw.last_eval;
         io.dist_at_eval = mw.dist_at_eval;
     }
-    // features of every node and (learned order) their scores, at a round start
-    auto score_round = [&](int32_t r) -> int {
+    // Features (and, asked, learned scores) of cnt nodes listed in a host-mapped
+    // id buffer, in list order.  Within a round a node's features only change
+    // when it is evaluated, so computing them on demand gives the round-start
+    // values for every node not yet evaluated.
+    auto features_of = [&](const int32_t *d_ids, int32_t cnt, int32_t r, bool want_scores) -> int {
         const double tm = now_ms();
         FeatArgs fa;
         fa.rp = g->d_rp;
         fa.ci = g->d_ci;
         fa.dist = d_dist;
-        fa.cand = nullptr;
-        fa.count = n;
+        fa.cand = d_ids;
+        fa.count = cnt;
         fa.ub = mw.ub;
         fa.last_eval = mw.last_eval;
         fa.dist_at_eval = mw.dist_at_eval;
@@ -1272,17 +1279,14 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         fa.ecc1 = ecc_bound;
         fa.feat = logging ? dfeat : mw.feat;
         HIP_OK(launch_features(fa, dist_bytes, s));
-        if (learned)
-            HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(o.d_mlp), fa.feat, n, nullptr,
-                                      nullptr, nullptr, mw.ub, dscore, s));
+        if (want_scores)
+            HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(o.d_mlp), fa.feat, cnt, nullptr,
+                                      nullptr, nullptr, mw.ub, d_ids, dscore, s));
         HIP_OK(hipStreamSynchronize(s));
         st.ms_mlp += now_ms() - tm;
         return GC_OK;
     };
-    std::vector<int32_t> pool;
-    auto score_before = [&](int32_t x, int32_t y) {
-        return hscore[x] > hscore[y] || (hscore[x] == hscore[y] && x < y);
-    };
+    std::vector<int32_t> pool, rank;
     struct HeapEntry {
         int64_t ub;
         int32_t id;
@@ -1311,44 +1315,44 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         int32_t pos = 0;
         io.round = r;
         cur_round = r;
-        if (need_state && !first_round) {
-            rc = score_round(r);
-            if (rc) return rc;
-        }
-        bool learned_first_block = learned && !first_round;
         for (;;) {
             int32_t cnt = 0;
             if (learned && !first_round) {
+                // the candidates whose bound can still win (before anything is
+                // evaluated in the round: the 4 x block largest bounds), best
+                // scored first; the rest go back into the heap unchanged
                 pool.clear();
-                if (learned_first_block) {
-                    // nothing evaluated yet: every live candidate can win;
-                    // take the best-scored block of them
-                    for (int32_t v = 0; v < n; ++v)
-                        if (!inS[v]) pool.push_back(v);
-                    const size_t take = std::min<size_t>((size_t)blk, pool.size());
-                    std::partial_sort(pool.begin(), pool.begin() + take, pool.end(), score_before);
-                    for (size_t j = 0; j < take; ++j) hc[cnt++] = pool[j];
-                    learned_first_block = false;
-                } else {
-                    // candidates whose bound can still win, best-scored first
-                    while (!heap.empty()) {
-                        const HeapEntry top = heap.front();
-                        if (inS[top.id] || top.ver != ver[top.id]) {
-                            std::pop_heap(heap.begin(), heap.end(), heap_less);
-                            heap.pop_back();
-                            continue;
-                        }
-                        if (!can_beat(top.id)) break;
+                const size_t want = best_id < 0 ? (size_t)4 * blk : (size_t)n;
+                while (!heap.empty() && pool.size() < want) {
+                    const HeapEntry top = heap.front();
+                    if (inS[top.id] || top.ver != ver[top.id]) {
                         std::pop_heap(heap.begin(), heap.end(), heap_less);
                         heap.pop_back();
-                        pool.push_back(top.id);
+                        continue;
                     }
-                    std::sort(pool.begin(), pool.end(), score_before);
-                    for (size_t j = 0; j < pool.size(); ++j) {
+                    if (!can_beat(top.id)) break;
+                    std::pop_heap(heap.begin(), heap.end(), heap_less);
+                    heap.pop_back();
+                    pool.push_back(top.id);
+                }
+                if (!pool.empty() && pool.size() <= (size_t)blk) {
+                    // the whole pool fits in the block: its order cannot matter
+                    for (size_t j = 0; j < pool.size(); ++j) hc[cnt++] = pool[j];
+                } else if (!pool.empty()) {
+                    for (size_t j = 0; j < pool.size(); ++j) hpool[j] = pool[j];
+                    rc = features_of(dpool, (int32_t)pool.size(), r, true);
+                    if (rc) return rc;
+                    rank.resize(pool.size());
+                    for (size_t j = 0; j < pool.size(); ++j) rank[j] = (int32_t)j;
+                    std::sort(rank.begin(), rank.end(), [&](int32_t x, int32_t y) {
+                        return hscore[x] > hscore[y] || (hscore[x] == hscore[y] && pool[x] < pool[y]);
+                    });
+                    for (size_t j = 0; j < rank.size(); ++j) {
+                        const int32_t u = pool[rank[j]];
                         if (cnt < blk) {
-                            hc[cnt++] = pool[j];
-                        } else {  // not taken now: back into the heap unchanged
-                            heap.push_back(HeapEntry{ub[pool[j]], pool[j], ver[pool[j]]});
+                            hc[cnt++] = u;
+                        } else {
+                            heap.push_back(HeapEntry{ub[u], u, ver[u]});
                             std::push_heap(heap.begin(), heap.end(), heap_less);
                         }
                     }
@@ -1384,6 +1388,10 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 }
             }
             if (cnt == 0) break;
+            if (logging && !first_round) {
+                rc = features_of(dc, cnt, r, false);  // rows of hfeat in block order
+                if (rc) return rc;
+            }
             rc = evaluate(cnt);
             if (rc) return rc;
             if (logging && !first_round) {
@@ -1393,7 +1401,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     o.h_log_round[at] = r;
                     o.h_log_node[at] = hc[j];
                     o.h_log_gain[at] = hg[j];
-                    std::memcpy(o.h_log_feat + at * 8, hfeat + (size_t)hc[j] * 8, 8 * sizeof(float));
+                    std::memcpy(o.h_log_feat + at * 8, hfeat + (size_t)j * 8, 8 * sizeof(float));
                 }
             }
             for (int32_t j = 0; j < cnt; ++j) {
@@ -1492,7 +1500,7 @@ extern "C" int gc_mlp_forward(const void *d_block, const float *d_x, int32_t cou
     if (count < 0) return fail(GC_EINVAL, "count < 0");
     if (count > 0 && (!d_block || !d_x || !d_out)) return fail(GC_EINVAL, "NULL device pointer");
     HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(d_block), d_x, count, d_out, d_h1,
-                              d_h2, nullptr, nullptr, stream));
+                              d_h2, nullptr, nullptr, nullptr, stream));
     return GC_OK;
 }
 

@@ -44,8 +44,10 @@ struct FeatArgs {
     float *feat;               // count x 8
 };
 
+// score[i] = min(2^out - 1, ub[cand ? cand[i] : i]) when score and ub are given
 hipError_t launch_mlp_forward(const MlpBlock *p, const float *x, int32_t count, float *out,
-                              float *h1, float *h2, const int64_t *ub, float *score, hipStream_t s);
+                              float *h1, float *h2, const int64_t *ub, const int32_t *cand,
+                              float *score, hipStream_t s);
 // scratch: >= (round_up(count,64) + 2*count*64) floats
 hipError_t launch_mlp_backward(const MlpBlock *p, const float *x, const float *h1, const float *h2,
                                const float *out, const float *y, int32_t count, float *grad,

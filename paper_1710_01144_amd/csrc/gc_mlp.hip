@@ -58,7 +58,8 @@ __device__ void stage_params(const MlpBlock *p, SParams *sp) {
 // the candidate key of the learned order.
 __global__ __launch_bounds__(256) void k_mlp_forward(const MlpBlock *p, const float *x, int32_t count,
                                                      float *out, float *h1s, float *h2s,
-                                                     const int64_t *ub, float *score) {
+                                                     const int64_t *ub, const int32_t *cand,
+                                                     float *score) {
     __shared__ SParams sp;
     stage_params(p, &sp);
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const MlpBlock *p, const fl
     if (score) {
         float g = exp2f(fminf(o, 126.f)) - 1.f;
         if (ub) {
-            const float u = (float)ub[s];
+            const float u = (float)ub[cand ? cand[s] : s];
             g = fminf(g, u);
         }
         score[s] = g;
@@ -245,11 +246,11 @@ int grid_for(int64_t n, int bs) {
 }  // namespace
 
 hipError_t launch_mlp_forward(const MlpBlock *p, const float *x, int32_t count, float *out,
-                              float *h1, float *h2, const int64_t *ub, float *score,
-                              hipStream_t s) {
+                              float *h1, float *h2, const int64_t *ub, const int32_t *cand,
+                              float *score, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mlp_forward, dim3(grid_for(count, 256)), dim3(256), 0, s, p, x, count, out,
-                       h1, h2, ub, score);
+                       h1, h2, ub, cand, score);
     return hipGetLastError();
 }
 
