@@ -304,7 +304,8 @@ constexpr size_t kCtrBytes = 4096;
 
 struct WsLayout {
     size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
-    size_t wvis, ly, lr, lb, lo, lz, lvl, act, cutprev, farout, cisplit, rinfo, dist1, total;
+    size_t wvis, ly, lr, lb, lo, lz, lvl, act, cutprev, farout, cisplit, rinfo, dist1, order, two,
+        total;
     int32_t nslots;
     SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
@@ -378,6 +379,10 @@ WsLayout ws_layout(const gc_graph *g) {
     L.cisplit = o; o += al256((size_t)g->nnz * 4 + 4);
     L.rinfo = o; o += al256(n * 16);
     L.dist1 = o; o += al256(n * 2 + 4);
+    // graph tables written by gc_workspace_init: nodes by decreasing degree
+    // and the sum of neighbour degrees of every node
+    L.order = o; o += al256(n * 4);
+    L.two = o; o += al256(n * 8);
     L.total = o;
     return L;
 }
@@ -420,6 +425,9 @@ struct Ws {
     int32_t *maxd() const { return ctr() + kMaxdSlot; }
     int64_t *words() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_WORDS; }
     int64_t *zcnt() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_TOUCHED; }
+    int64_t *hdr() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_HDR; }
+    int32_t *order() const { return reinterpret_cast<int32_t *>(base + L.order); }
+    int64_t *two() const { return reinterpret_cast<int64_t *>(base + L.two); }
     WideArgs wide() const {
         WideArgs a{};
         a.vis = reinterpret_cast<uint64_t *>(base + L.wvis);
@@ -461,12 +469,30 @@ extern "C" int gc_workspace_size(const gc_graph *g, int32_t bitset_width, size_t
     return GC_OK;
 }
 
+namespace {
+
+// value of the workspace stamp for this graph
+int64_t ws_stamp(const gc_graph *g) {
+    return (int64_t)(0x4743575350414345ull ^ ((uint64_t)g->n << 1) ^ ((uint64_t)g->nnz << 29));
+}
+
+// degree order and two-hop sums of the graph into the workspace, then the stamp
+int write_graph_tables(const gc_graph *g, const Ws &w, hipStream_t s) {
+    HIP_OK(hipMemcpyAsync(w.order(), g->by_degree.data(), sizeof(int32_t) * (size_t)g->n,
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(launch_twohop_i64(g->d_rp, g->d_ci, g->n, w.two(), s));
+    HIP_OK(launch_set_i64(w.hdr(), ws_stamp(g), s));
+    return GC_OK;
+}
+
+}  // namespace
+
 extern "C" int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream) {
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
     if (rc) return rc;
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base), w.L.total / 4, 0u, stream));
-    return GC_OK;
+    return write_graph_tables(g, w, stream);
 }
 
 // ------------------------------------------------------------- operations
@@ -812,30 +838,42 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     int32_t last = 0;
     int rc = run_full_bfs(g, w, v0, w.dist16(), w.far(), s, &last);
     if (rc) return rc;
-    int64_t F0 = 0;
+    int64_t F0 = 0, stamp = 0;
     HIP_OK(hipMemcpyAsync(&F0, w.far(), sizeof(F0), hipMemcpyDeviceToHost, s));
-    HIP_OK(launch_twohop_i64(g->d_rp, g->d_ci, n, w.aux(), s));
-    std::vector<int64_t> two((size_t)n);
-    HIP_OK(hipMemcpyAsync(two.data(), w.aux(), sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(&stamp, w.hdr(), sizeof(stamp), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (last >= 65535) return fail(GC_ERANGE, "a node is 65535 or more hops from node %d", v0);
+    // the degree order and two-hop sums come from gc_workspace_init; a
+    // workspace without its stamp gets them now
+    if (stamp != ws_stamp(g)) {
+        int rc2 = write_graph_tables(g, w, s);
+        if (rc2) return rc2;
+    }
     int32_t best = v0;
     int64_t bestF = F0;
-    auto lb1 = [&](int32_t v) -> int64_t {
-        const int64_t d = rp[v + 1] - rp[v];
-        const int64_t rem = (int64_t)n - 1 - d;
-        int64_t near = two[v] - d;
-        if (near > rem) near = rem;
-        if (near < 0) near = 0;
-        return d + 2 * near + 3 * (rem - near);
-    };
-    auto may_win = [&](int32_t v) {
-        const int64_t b = lb1(v);
-        return b < bestF || (b == bestF && v < best);
-    };
-    std::vector<int32_t> list;
+    // level-1 bound of every node against F0, on the device, in degree order;
+    // the bounds of the survivors come back to re-test them as the best improves
+    uint8_t *keep_d = reinterpret_cast<uint8_t *>(w.base + w.L.q0);
+    HIP_OK(launch_lb1_filter(w.order(), g->d_rp, w.two(), n, bestF, best, keep_d, w.aux(), s));
+    std::vector<uint8_t> keep((size_t)n);
+    HIP_OK(hipMemcpyAsync(keep.data(), keep_d, (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    std::vector<int32_t> list, lpos;
     for (int32_t i = 1; i < n; ++i)
-        if (may_win(order[i])) list.push_back(order[i]);
+        if (keep[i]) {
+            list.push_back(order[i]);
+            lpos.push_back(i);
+        }
+    std::vector<int64_t> lbound(list.size());
+    if (!list.empty()) {
+        HIP_OK(hipMemcpyAsync(w.cand(), lpos.data(), sizeof(int32_t) * lpos.size(), hipMemcpyHostToDevice, s));
+        HIP_OK(launch_gather_i64(w.aux(), w.cand(), (int32_t)lpos.size(), w.gain(), s));
+        HIP_OK(hipMemcpyAsync(lbound.data(), w.gain(), sizeof(int64_t) * lbound.size(), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    auto may_win_at = [&](size_t j) {
+        return lbound[j] < bestF || (lbound[j] == bestF && list[j] < best);
+    };
     int64_t nsources = 1;
     const bool verbose = getenv("GC_VERBOSE") != nullptr;
     double t_print = now_ms();
@@ -861,8 +899,8 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
         chunk.clear();
         const size_t pos0 = pos;
         while (pos < list.size() && (int64_t)chunk.size() < kb * spb) {
-            const int32_t v = list[pos++];
-            if (may_win(v)) chunk.push_back(v);
+            const size_t j = pos++;
+            if (may_win_at(j)) chunk.push_back(list[j]);
         }
         if (chunk.empty()) break;
         const int64_t cnt = (int64_t)chunk.size();

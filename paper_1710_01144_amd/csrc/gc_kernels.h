@@ -28,6 +28,7 @@ enum : int {
     L_WORDS = 64,
     kWordCounters = 5,
     L_TOUCHED = 72,    // records touched by the current launch (clean-up list length)
+    L_HDR = 80,        // stamp of gc_workspace_init: graph-derived tables are valid
 };
 
 struct Slots {
@@ -153,6 +154,14 @@ hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, con
 // (distances from an all-INF 16-bit array, so F = reached*65535 - gain).
 hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, hipStream_t s);
 hipError_t launch_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n, int64_t *out,
+                             hipStream_t s);
+// bound[i] = level-1 farness bound of node order[i]; keep[i] = 1 if it may
+// beat (best_f, best_v) (i >= 1), else 0
+hipError_t launch_lb1_filter(const int32_t *order, const int32_t *rp, const int64_t *two, int32_t n,
+                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound,
+                             hipStream_t s);
+// out[j] = src[idx[j]]
+hipError_t launch_gather_i64(const int64_t *src, const int32_t *idx, int32_t cnt, int64_t *out,
                              hipStream_t s);
 hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s);
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,

@@ -669,6 +669,34 @@ __global__ __launch_bounds__(256) void k_row_split(const int32_t *rp, const int3
     }
 }
 
+// Level-1 bound of F({v}) (Section 3.1 with the BFS stopped after one level):
+// deg(v) nodes at distance 1, at most two(v) - deg(v) at distance 2 (the
+// adjacency of v's neighbours minus one back-edge each), the rest at 3 or more.
+__global__ void k_lb1_filter(const int32_t *order, const int32_t *rp, const int64_t *two, int32_t n,
+                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0) {
+        keep[0] = 0;
+        bound[0] = 0;
+        return;
+    }
+    const int32_t v = order[i];
+    const int64_t d = rp[v + 1] - rp[v];
+    const int64_t rem = (int64_t)n - 1 - d;
+    int64_t near = two[v] - d;
+    if (near > rem) near = rem;
+    if (near < 0) near = 0;
+    const int64_t b = d + 2 * near + 3 * (rem - near);
+    bound[i] = b;
+    keep[i] = (b < best_f || (b == best_f && v < best_v)) ? 1 : 0;
+}
+
+__global__ void k_gather_i64(const int64_t *src, const int32_t *idx, int32_t cnt, int64_t *out) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j < cnt) out[j] = src[idx[j]];
+}
+
 template <typename DistT>
 __global__ void k_max_dist(const DistT *dist, int64_t n, int32_t *out) {
     uint32_t m = 0;
@@ -771,6 +799,23 @@ hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, con
         hipLaunchKernelGGL((k_row_split<uint16_t>), grid, dim3(256), 0, s, rp, ci, n,
                            reinterpret_cast<const uint16_t *>(dist), ci_out, rinfo,
                            reinterpret_cast<uint16_t *>(dist1));
+    return hipGetLastError();
+}
+
+hipError_t launch_lb1_filter(const int32_t *order, const int32_t *rp, const int64_t *two, int32_t n,
+                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound,
+                             hipStream_t s) {
+    const int64_t g = ((int64_t)n + 255) / 256;
+    hipLaunchKernelGGL(k_lb1_filter, dim3((unsigned)(g < 1 ? 1 : g)), dim3(256), 0, s, order, rp, two, n,
+                       best_f, best_v, keep, bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_i64(const int64_t *src, const int32_t *idx, int32_t cnt, int64_t *out,
+                             hipStream_t s) {
+    if (cnt <= 0) return hipSuccess;
+    const int64_t g = ((int64_t)cnt + 255) / 256;
+    hipLaunchKernelGGL(k_gather_i64, dim3((unsigned)g), dim3(256), 0, s, src, idx, cnt, out);
     return hipGetLastError();
 }
 

@@ -217,6 +217,17 @@ class Graph:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.row_ptr.device)
         _check(load_library().gc_workspace_init(self.handle, _ptr(self.ws), self.ws_bytes, _stream()))
 
+    def use_workspace(self, buf):
+        """Run on a caller-owned uint8 device buffer (at least workspace_size()
+        bytes, e.g. one buffer shared by graphs processed one after another);
+        it is initialised for this graph."""
+        need = self.workspace_size()
+        if buf.numel() < need:
+            raise ValueError("workspace buffer has %d bytes, graph needs %d" % (buf.numel(), need))
+        self.ws = buf
+        self.ws_bytes = need
+        _check(load_library().gc_workspace_init(self.handle, _ptr(self.ws), self.ws_bytes, _stream()))
+
     # ------------------------------------------------------------ operations
     def closest_node(self):
         node, far = ctypes.c_int32(), ctypes.c_int64()

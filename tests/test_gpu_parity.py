@@ -271,3 +271,28 @@ def test_greedy_rmat20_k100_full_size(gclib):
     G.update_dist(int(grp[0]), dist, st["dist_bytes"], far)
     got = G.marginal_gains(dist, st["dist_bytes"], torch.from_numpy(cand)).cpu().numpy()
     assert np.array_equal(got, oracle.gains(g, dS, cand))
+
+
+def test_batched_ba_sample(gclib):
+    """The batched Barabasi-Albert workload (256 graphs, n in [1000, 50000],
+    m in [2, 8], k in [5, 50], seeds from SplitMix64 of 3): the three smallest
+    and the largest graph, each with its own k, give the CPU Greedy++ group,
+    farness, evaluation counts and scanned edges; the smallest also matches the
+    plain greedy of the definition."""
+    params = graphgen.batch_ba_params(3, 256)
+    order = sorted(range(len(params)), key=lambda i: params[i][1])
+    for idx in order[:3] + order[-1:]:
+        sg, n_g, m_g, k_g = params[idx]
+        g = graphgen.ba(n_g, m_g, sg)
+        G = _graph(gclib, g)
+        grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, k_g, block=64)
+        for ordr in ("plain", "celf"):
+            _note("batched BA graph %d (n=%d m=%d) k=%d %s" % (idx, g.n, m_g, k_g, ordr))
+            grp, F, st = G.greedy_group(k_g, order=ordr, block=64)
+            assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+            if ordr == "plain":
+                assert st["evals_per_round"].tolist() == ev_b.tolist()
+                assert st["edges_alg"] == int(ed_b.sum())
+        if idx == order[0]:
+            grp_a, F_a = oracle.greedy(g, k_g)
+            assert grp_b.tolist() == grp_a.tolist() and F_b.tolist() == F_a.tolist()
