@@ -679,6 +679,10 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             a.dist_bytes = dist_bytes;
             a.words = w.words();
             apply_split(a, split);
+            // one atomic per claim for gain and edge count when neither can
+            // overflow its field: edges <= nnz, gain <= n * max d(S,.)
+            a.pack = d_edges && g->nnz < (1ll << kPackShift) &&
+                     (int64_t)g->n * (int64_t)(nlev + 1) < (1ll << (62 - kPackShift));
             if (mapped) {
                 a.h_gain = io->hm_gain ? io->hm_gain + off : nullptr;
                 a.h_edges = io->hm_edges ? io->hm_edges + off : nullptr;

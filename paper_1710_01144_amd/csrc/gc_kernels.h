@@ -144,7 +144,13 @@ struct WideArgs {
     // rinfo[y] = {row start, degree, #first segment, #first two segments}
     const int4 *rinfo;
     const void *dist1;             // d1, same width as dist
+    // gain and edge count of a source summed in one 64-bit word during the
+    // launch, (gain << kPackShift) + edges, unpacked by the final kernel; the
+    // host sets it only when edges < 2^kPackShift and the gain cannot reach
+    // 2^(63 - kPackShift)
+    int32_t pack;
 };
+constexpr int kPackShift = 30;
 // Split every row of (rp, ci) by the distances dist (see WideArgs::rinfo);
 // dist1 receives a copy of dist.
 hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, const void *dist,

@@ -260,8 +260,12 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
                     full = a.rp[v + 1] - rs;
                     deg = full;
                 }
-                a.gain[t] = (int64_t)d;
-                if (a.edges) a.edges[t] = full;
+                if (a.pack) {
+                    a.gain[t] = ((int64_t)d << kPackShift) + full;
+                } else {
+                    a.gain[t] = (int64_t)d;
+                    if (a.edges) a.edges[t] = full;
+                }
                 if (a.visited) a.visited[t] = 1;
                 // nothing to expand: no frontier word, no entry
                 p = deg > 0 && atomicOr(rec(a, b, v, 1), (unsigned long long)bit) == 0ull;
@@ -465,9 +469,18 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
                             rs[r] = ri.x;
                             deg[r] = a.rinfo ? expand_len(ri, d1, nl) : full;
                             const int64_t gb = (int64_t)bb[r] * a.spb;
+                            const unsigned long long cp =
+                                a.pack ? (c << kPackShift) + (unsigned long long)full : c;
                             for (uint64_t mm = nw; mm; mm &= mm - 1) {
                                 const int64_t j = gb + (__ffsll((unsigned long long)mm) - 1);
-                                if (lds_acc) {
+                                if (a.pack) {
+                                    if (lds_acc) atomicAdd(&s_g[j], cp);
+                                    else atomicAdd(reinterpret_cast<unsigned long long *>(a.gain + j), cp);
+                                    if (a.visited) {
+                                        if (lds_acc) atomicAdd(&s_v[j], 1u);
+                                        else atomicAdd(a.visited + j, 1);
+                                    }
+                                } else if (lds_acc) {
                                     atomicAdd(&s_g[j], c);
                                     if (a.edges) atomicAdd(&s_e[j], (unsigned long long)full);
                                     if (a.visited) atomicAdd(&s_v[j], 1u);
@@ -525,6 +538,12 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
         r0[2] = 0ull;
         r0[3] = 0ull;
     }
+    if (a.pack)
+        for (int64_t i = t0; i < a.nsrc; i += nt) {
+            const int64_t v = a.gain[i];
+            a.gain[i] = v >> kPackShift;
+            if (a.edges) a.edges[i] = v & ((1ll << kPackShift) - 1);
+        }
     if (a.h_gain)
         for (int64_t i = t0; i < a.nsrc; i += nt) a.h_gain[i] = a.gain[i];
     if (a.h_edges && a.edges)
@@ -635,6 +654,28 @@ __global__ __launch_bounds__(256) void k_row_split(const int32_t *rp, const int3
     if (row >= n) return;
     const int32_t rs = rp[row], re = rp[row + 1];
     const uint32_t dy = dist[row];
+    if (re - rs <= 64) {
+        // one chunk: classify and place in one pass
+        const int32_t e = rs + lane;
+        const bool ok = e < re;
+        int32_t z = 0;
+        uint32_t dz = dy;
+        if (ok) {
+            z = ci[e];
+            dz = dist[z];
+        }
+        const bool down = ok && dz > dy, same = ok && dz == dy, up = ok && dz < dy;
+        const uint64_t bd = __ballot(down), bs = __ballot(same), bu = __ballot(up);
+        const int32_t nd1 = __popcll(bd), ns1 = __popcll(bs);
+        if (down) ci_out[rs + bits_below(bd)] = z;
+        if (same) ci_out[rs + nd1 + bits_below(bs)] = z;
+        if (up) ci_out[rs + nd1 + ns1 + bits_below(bu)] = z;
+        if (lane == 0) {
+            rinfo[row] = make_int4(rs, re - rs, nd1, nd1 + ns1);
+            dist1[row] = (DistT)dy;
+        }
+        return;
+    }
     int32_t nd = 0, ns = 0;
     for (int32_t base = rs; base < re; base += 64) {
         const int32_t e = base + lane;
