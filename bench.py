@@ -9,11 +9,13 @@ workload graph, inputs already resident in HBM.  Prints ONE JSON line:
             exact gain evaluations of the step (sum over evaluated v of
             sum_{w in V(v)} deg(w), the adjacency entries a per-candidate
             pruned BFS scans) divided by the step's wall time;
-  roofline  the dominant kernel (the first gain round: all n-1 candidates in
-            one launch), timed with HIP events on the stream it runs on;
-            algorithmic bytes = 8*|V(v)| + (4 + dist_bytes)*E_alg(v) summed
-            over the launch's candidates (row_ptr pair per expanded node,
-            col_idx entry plus d(S,.) byte per scanned edge);
+  roofline  the gain launches of the job (k_wide_level dominates their GPU
+            time), timed by the library with HIP events on the launch stream;
+            algorithmic bytes from the word-level counts of the launches
+            (alg_bytes_of); traffic from the committed rocprofv3 counters;
+  first_gain_round  the same for one call over all n-1 candidates;
+  learned_vs_plain  the candidate-ordering network trained on plain-order
+            logs, timed against plain, CELF and an untrained network;
   cpu_baseline  the CPU oracle's Greedy++ (tier B) on the same job, timed on
             this host's cores.
 """
@@ -86,17 +88,30 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per first-round launch from the committed rocprofv3 counter
-    summary, or None if there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", "k_wide_level_%s_traffic.json" % workload)
+def measured_traffic(workload: str, k: int, order: str):
+    """HBM bytes per gain launch of the greedy job from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE over the job's gain
+    launches, each scaled by what the counter reads for a 1 GiB copy), or None
+    if there is none for this job or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "k_wide_gain_%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
+    if rec.get("k") != k or rec.get("order") != order:
+        return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def alg_bytes_of(entries_expanded, edges, touched, dist_bytes):
+    """Bit-parallel top-down bytes (64 sources per word): an expanded frontier
+    entry reads its row record and frontier word (16 B) and 4 B of column index
+    per adjacency entry it expands; an adjacency entry reads the target's
+    visited word and ORs its next-frontier word (16 B); a touched (batch, node)
+    record is written (visited and frontier words, 24 B) and its d(S,.) read."""
+    return 16 * entries_expanded + 20 * edges + (24 + dist_bytes) * touched
 
 
 def log(msg):
@@ -280,32 +295,39 @@ def main():
         learned_cmp = learned_comparison(G, g, k, args, grp, F)
         log("learned vs plain " + json.dumps(learned_cmp))
 
-    # ---- roofline of the dominant kernel: first gain round, all candidates
+    # ---- roofline of the gain launches of the job (every round): word counts
+    # and the GPU time of the launches, measured by the library with HIP
+    # events on the launch stream in one more run of the same job (the events
+    # stay out of the wall-timed steps)
+    gc.timing_enable(True)
+    _, _, st = G.greedy_group(k, order=args.order, block=args.block)
+    gc.timing_enable(False)
+    dist_bytes = int(st["dist_bytes"])
+    launches = int(st["gain_launches"])
+    job_alg = alg_bytes_of(int(st["entries_word"]) - int(st["entries_last"]), int(st["edges_word"]),
+                           int(st["touched_word"]), dist_bytes)
+    gain_gpu_ms = float(st["ms_gain_gpu"])
+    achieved = job_alg / (gain_gpu_ms / 1000.0) / 1e9
+    traffic = measured_traffic(args.workload, k, args.order)
+    log("gain launches of the job: %d launches, %.3f ms GPU (%.2f us each), %d bytes algorithmic, "
+        "%.1f GB/s" % (launches, gain_gpu_ms, 1000 * gain_gpu_ms / launches, job_alg, achieved))
+
+    # ---- the first gain round alone (all n-1 candidates, one call)
     s1 = int(grp[0])
     dist = G.new_dist(1)
     far = torch.zeros(1, dtype=torch.int64, device=dev)
     G.update_dist(s1, dist, 1, far)
-    dist_bytes = 1
-    if int(stats[-1]["dist_bytes"]) == 2:
+    if dist_bytes == 2:
         dist = G.new_dist(2)
         G.update_dist(s1, dist, 2, far)
-        dist_bytes = 2
     cand = torch.from_numpy(np.delete(np.arange(g.n, dtype=np.int32), s1)).to(dev)
     gain, e_c, v_c = G.marginal_gains(dist, dist_bytes, cand, stats=True)
     torch.cuda.synchronize()
     E1 = int(e_c.sum().item())
     V1 = int(v_c.to(torch.int64).sum().item())
     words = G.gain_words()
-    # bit-parallel top-down bytes per batch and level (64 sources per word):
-    # each expanded entry reads its row-pointer pair and frontier word (16 B)
-    # and 4 B of column index per adjacency entry; each adjacency entry reads
-    # the target's visited word and ORs its next-frontier word (16 B); each
-    # touched target writes next / visited / frontier words (24 B) and reads
-    # its d(S,.) byte(s)
-    X = words["entries"] - words["entries_last"]
-    Y = words["entries"] - words["entries_root"]
     Ew = words["edges"]
-    alg_bytes = 16 * X + 20 * Ew + (24 + dist_bytes) * Y
+    r1_alg = alg_bytes_of(words["entries"] - words["entries_last"], Ew, words["touched"], dist_bytes)
     stream = torch.cuda.current_stream()
     # kernel time of the launch: HIP events recorded by the library on this
     # stream right before its first and after its last gain kernel
@@ -317,11 +339,10 @@ def main():
         times.append(gc.timing_last_ms())
     gc.timing_enable(False)
     kern_ms = float(np.mean(times))
-    achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
-    traffic = measured_traffic(args.workload)
-    log("round-1 gain launch: %d candidates, E_alg %d, |V| %d, word entries %d, word edges %d, "
-        "%.3f ms, %.1f GB/s algorithmic, GTEPS alg %.1f word %.1f"
-        % (cand.numel(), E1, V1, words["entries"], Ew, kern_ms, achieved,
+    r1_gbs = r1_alg / (kern_ms / 1000.0) / 1e9
+    log("first gain round: %d candidates, E_alg %d, |V| %d, word entries %d, word edges %d, "
+        "touched %d, %.3f ms, %.1f GB/s algorithmic, GTEPS alg %.1f word %.1f"
+        % (cand.numel(), E1, V1, words["entries"], Ew, words["touched"], kern_ms, r1_gbs,
            E1 / kern_ms / 1e6, Ew / kern_ms / 1e6))
 
     # ---- a plain copy of known size: measured bandwidth and counter scale
@@ -386,11 +407,15 @@ def main():
                          ("ms_closest", "ms_round1", "ms_later", "ms_update", "ms_mlp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "kernel": "k_wide_level (first gain round, %d candidates)" % cand.numel(),
-                     "kernel_ms": round(kern_ms, 4), "alg_bytes": alg_bytes,
-                     "words": words, "gteps_alg": round(E1 / kern_ms / 1e6, 2),
-                     "gteps_word": round(Ew / kern_ms / 1e6, 2),
+                     "kernel": "gain launches of the job (k_wide_roots, k_wide_level, k_wide_end, "
+                               "k_wide_reset; rows split by k_row_split)",
+                     "launches": launches, "launch_ms": round(gain_gpu_ms / launches, 5),
+                     "alg_bytes_per_launch": round(job_alg / launches, 1),
                      "copy_gbs_measured": round(copy_gbs, 1) if copy_gbs else None},
+        "first_gain_round": {"candidates": int(cand.numel()), "ms": round(kern_ms, 4),
+                             "alg_bytes": r1_alg, "gbs": round(r1_gbs, 2), "words": words,
+                             "gteps_alg": round(E1 / kern_ms / 1e6, 2),
+                             "gteps_word": round(Ew / kern_ms / 1e6, 2)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -113,6 +113,9 @@ typedef struct gc_stats {
     int64_t entries_last;   /* of which entries of the last level (not expanded) */
     int64_t edges_word;     /* adjacency entries expanded (levels before the last) */
     int64_t edges_last;     /* adjacency entries of the last level's entries */
+    int64_t touched_word;   /* (batch, node) records the gain launches touched */
+    double ms_gain_gpu;     /* GPU time of the gain launches (HIP events), all rounds;
+                             * measured only while gc_timing_enable(1) is in force */
     int64_t *h_evals_per_round; /* optional, caller-owned, k entries */
 } gc_stats;
 
@@ -216,11 +219,15 @@ int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
  * gc_gain_words -- word-level work of the last gc_marginal_gains call on this
  * workspace (the bit-parallel form of Section 4.3: one frontier entry carries
  * every source of a batch that reached a node at the same level).
- *   h_words  host int64[5] out: frontier entries of all levels, of level 0
+ *   h_words  host int64[6] out: frontier entries of all levels, of level 0
  *            (roots), of the last level (logged, not expanded); adjacency
- *            entries expanded; adjacency entries of the last level.
- * With one candidate per call, entries = |V(v)| and the two adjacency counts
- * add up to the d_edges output.  Synchronises the stream.
+ *            entries expanded; adjacency entries of the last level; (batch,
+ *            node) records touched (claimed at least once).
+ * A frontier entry is a node with neighbours that can still be claimed; its
+ * adjacency entries are those neighbours only (rows are split by the d(S,.)
+ * of the call, so a node at distance L from its sources expands the
+ * neighbours z with d(S,z) >= L + 2).  With one candidate per call the
+ * records touched equal |V(v)|.  Synchronises the stream.
  */
 int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_bytes, hipStream_t stream,
                   int64_t *h_words);

@@ -616,6 +616,10 @@ struct HostIO {
     int32_t *last_eval = nullptr;
     uint16_t *dist_at_eval = nullptr;
     int32_t round = 0;
+    // optional: GPU time of each call from ev0 (start) to ev1 (all launches
+    // done), added to *gpu_ms
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double *gpu_ms = nullptr;
 };
 
 struct LaunchShape {
@@ -651,6 +655,8 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     const bool mapped = io && io->hm_flag;
     const int grid = wide_grid(g);
     if (g_timing && !timing_started) HIP_OK(hipEventRecord(g_ev0, s));
+    const bool timed = io && io->ev0 && io->gpu_ms;
+    if (timed) HIP_OK(hipEventRecord(io->ev0, s));
     // batches per launch and sources per batch; a caller-kept shape carries
     // what an earlier overflow taught across calls
     int64_t kb = (shape && shape->kb > 0) ? std::min<int64_t>(shape->kb, w.L.kmax) : w.L.kmax;
@@ -701,6 +707,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         }
         int32_t flag = 0;
         if (g_timing) HIP_OK(hipEventRecord(g_ev1, s));
+        if (timed) HIP_OK(hipEventRecord(io->ev1, s));
         if (mapped) {
             HIP_OK(hipStreamSynchronize(s));
             flag = *io->h_flag;
@@ -715,6 +722,11 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         }
         if (flag == 0) {
             if (g_timing) HIP_OK(hipEventElapsedTime(&g_timing_ms, g_ev0, g_ev1));
+            if (timed) {
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, io->ev0, io->ev1));
+                *io->gpu_ms += ms;
+            }
             if (shape) {
                 shape->kb = kb;
                 shape->spb = spb;
@@ -1156,7 +1168,23 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dc), hc, 0));
     HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dg), hg, 0));
     HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dflag), hflag, 0));
+    // with gc_timing_enable(1): events timing the gain launches (their GPU
+    // time is reported in gc_stats)
+    struct EvPair {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~EvPair() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
     HostIO io;
+    if (g_timing) {
+        HIP_OK(hipEventCreate(&ev.a));
+        HIP_OK(hipEventCreate(&ev.b));
+        io.ev0 = ev.a;
+        io.ev1 = ev.b;
+        io.gpu_ms = &st.ms_gain_gpu;
+    }
     io.hm_gain = dg;
     io.hm_edges = dg + n;
     io.hm_flag = dflag;
@@ -1522,6 +1550,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         st.entries_last = wc[2];
         st.edges_word = wc[3];
         st.edges_last = wc[4];
+        st.touched_word = wc[5];
         *h_stats = st;
     }
     return GC_OK;

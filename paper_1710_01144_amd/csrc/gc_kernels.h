@@ -23,10 +23,10 @@ enum : int {
     L_BFS_SUM = 0,     // sum of contributions of the level BFS
     L_BEST_FAR = 1,    // best farness found by the closeness engine
     // word-level work of the device-wide engine, summed over gain launches:
-    // frontier entries (all levels, root level, last level) and adjacency
-    // entries of expanded levels / of the last level
+    // frontier entries (all levels, root level, last level), adjacency entries
+    // of expanded levels / of the last level, and (batch, node) records touched
     L_WORDS = 64,
-    kWordCounters = 5,
+    kWordCounters = 6,
     L_TOUCHED = 72,    // records touched by the current launch (clean-up list length)
     L_HDR = 80,        // stamp of gc_workspace_init: graph-derived tables are valid
 };

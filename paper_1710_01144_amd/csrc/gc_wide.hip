@@ -577,6 +577,7 @@ __global__ void k_wide_reset(WideArgs a, int32_t nlev) {
             a.words[2] += (int64_t)(pl >> kCntShift);
             a.words[3] += eexp;
             a.words[4] += (int64_t)(pl & kMEdges);
+            a.words[5] += (int64_t)*a.zcnt;
         }
         if (a.h_flag) *a.h_flag = 0;
         if (a.far) *a.far -= a.gain[0];  // update: F(S + s) = F(S) - g(s, S)

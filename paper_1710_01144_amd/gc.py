@@ -73,7 +73,8 @@ class GcStats(ctypes.Structure):
                 ("ms_mlp", ctypes.c_double),
                 ("entries_word", ctypes.c_int64), ("entries_root", ctypes.c_int64),
                 ("entries_last", ctypes.c_int64), ("edges_word", ctypes.c_int64),
-                ("edges_last", ctypes.c_int64),
+                ("edges_last", ctypes.c_int64), ("touched_word", ctypes.c_int64),
+                ("ms_gain_gpu", ctypes.c_double),
                 ("h_evals_per_round", ctypes.POINTER(ctypes.c_int64))]
 
     def as_dict(self):
@@ -261,9 +262,9 @@ class Graph:
 
     def gain_words(self) -> dict:
         """Word-level work of the last marginal_gains call (see gc_gain_words)."""
-        out = (ctypes.c_int64 * 5)()
+        out = (ctypes.c_int64 * 6)()
         _check(load_library().gc_gain_words(self.handle, _ptr(self.ws), self.ws_bytes, _stream(), out))
-        return dict(zip(("entries", "entries_root", "entries_last", "edges", "edges_last"),
+        return dict(zip(("entries", "entries_root", "entries_last", "edges", "edges_last", "touched"),
                         (int(x) for x in out)))
 
     def node_features(self, dist, dist_bytes, ub, last_eval, dist_at_eval, round_, k, ecc1,

@@ -126,6 +126,7 @@ def test_word_counters_ba2000(gclib, device):
         assert w["entries"] == int(np.count_nonzero(terr & (cnt > 0)))
         assert w["edges"] + w["edges_last"] == int(cnt[terr].sum())
         assert w["entries_root"] == int(v != s1 and cnt[v] > 0)
+        assert w["touched"] == int(vv[0])
     _note("word counters, one launch over all candidates")
     cand = torch.arange(g.n, dtype=torch.int32)
     gain, edges, vis = G.marginal_gains(dist, 1, cand, stats=True)
@@ -135,6 +136,7 @@ def test_word_counters_ba2000(gclib, device):
     roots = _expansions(g, dS, np.zeros(g.n, dtype=np.int64))
     assert w["entries_root"] == int(np.count_nonzero(roots[np.arange(g.n) != s1] > 0))
     assert tv >= w["entries"] >= w["entries_root"]
+    assert tv >= w["touched"] >= -(-tv // 64)
     assert te >= w["edges"] + w["edges_last"]
 
 
