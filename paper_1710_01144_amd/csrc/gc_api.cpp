@@ -97,6 +97,8 @@ struct gc_graph {
     // tuning read once at load time so the workspace layout never changes
     int64_t slots_target;   // GC_SLOTS
     int64_t vis_budget;     // GC_VIS_BUDGET_MB (bytes)
+    int32_t fused_grid;     // workgroups of the one-kernel small launch (0: off; GC_FUSED, GC_FUSED_WGS)
+    bool fused_gains;       // also for gain launches of <= 1024 sources (GC_FUSED_GAINS=1)
     int64_t log_entries;    // GC_LOG_ENTRIES
     bool wg_engine;         // GC_ENGINE=wg
     int32_t level_wgs_per_cu;  // GC_LEVEL_WGS (workgroups per CU of a level kernel)
@@ -268,6 +270,22 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
     if (const char *e = getenv("GC_VIS_BUDGET_MB")) {
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->vis_budget = (int64_t)v << 20;
+    }
+    g->fused_grid = 0;
+    {
+        // off by default: on MI355X the grid barriers of the cooperative
+        // kernel cost more than the kernel boundaries they replace
+        const char *e = getenv("GC_FUSED");
+        if (e && strcmp(e, "1") == 0) {
+            int want = cus / 2;
+            if (const char *w = getenv("GC_FUSED_WGS")) {
+                const long v = strtol(w, nullptr, 10);
+                if (v >= 1) want = (int)v;
+            }
+            g->fused_grid = std::max(0, std::min(want, fused_max_grid(cus)));
+        }
+        const char *fg = getenv("GC_FUSED_GAINS");
+        g->fused_gains = fg && strcmp(fg, "1") == 0;
     }
     g->level_wgs_per_cu = 4;
     if (const char *e = getenv("GC_LEVEL_WGS")) {
@@ -700,9 +718,13 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                 a.dsat_out = io->dist_at_eval;
                 a.round = io->round;
             }
-            HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
-            HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
-            HIP_OK(launch_wide_end(a, nlev, grid, s));
+            if (g->fused_grid > 0 && g->fused_gains && a.nsrc <= 1024) {
+                HIP_OK(launch_wide_fused(a, dist_bytes, nlev, g->fused_grid, s));
+            } else {
+                HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
+                HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
+                HIP_OK(launch_wide_end(a, nlev, grid, s));
+            }
             off += a.nsrc;
         }
         int32_t flag = 0;
@@ -776,6 +798,10 @@ int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, 
     a.far = d_far;
     a.dist_bytes = dist_bytes;
     apply_split(a, split);
+    if (g->fused_grid > 0) {
+        HIP_OK(launch_wide_fused(a, dist_bytes, nlev, g->fused_grid, s));
+        return GC_OK;
+    }
     const int grid = wide_grid(g);
     HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
     HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));

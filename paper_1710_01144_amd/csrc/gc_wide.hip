@@ -34,6 +34,8 @@
 //
 // A pruned BFS never goes deeper than max_y d(S,y) - 1, so the host launches
 // that many levels without reading anything back.
+#include <hip/hip_cooperative_groups.h>
+
 #include "gc_kernels.h"
 
 namespace gck {
@@ -218,11 +220,11 @@ __device__ __forceinline__ void touch_wave(const WideArgs &a, const bool *t, con
 // WRITE: the d(S,.) update after a pick -- a claimed node also stores its new
 // distance (in place: a later prune test against it fails, and the visited
 // bit settles concurrent claims); the single source's gain is F(S) - F(S+s).
+// Thread t of the launch (wave-uniform calls: the log append is a wave op).
 template <typename DistT, bool WRITE>
-__global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
+__device__ __forceinline__ void roots_body(const WideArgs &a, int64_t t) {
     if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     bool p = false, touched = false;
     int32_t v = 0, b = 0, deg = 0, rs = 0;
     if (t < a.nsrc) {
@@ -276,11 +278,16 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
     push_wave(a, &a.lvl[0], 0, p, v, rs, b, deg);
 }
 
+template <typename DistT, bool WRITE>
+__global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
+    roots_body<DistT, WRITE>(a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
 // One BFS level.  LDS: per-source sums in LDS (launches of <= kLdsSrc
 // sources); large launches add straight to global memory and keep LDS small
 // for occupancy.  U: edges per thread per step.
 template <typename DistT, bool WRITE, bool LDS, int U>
-__global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
+__device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     constexpr int kStep = kWG * U;  // adjacency entries per workgroup step
     __shared__ int64_t s_off[kWin + 1];
     __shared__ int32_t s_rs[kWin];
@@ -295,8 +302,14 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     __shared__ unsigned long long s_g[LDS ? kLdsSrc : 1];
     __shared__ unsigned long long s_e[LDS ? kLdsSrc : 1];
     __shared__ unsigned int s_v[LDS ? kLdsSrc : 1];
+    __shared__ int32_t s_flag;
 
-    if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    // another workgroup may raise the overflow flag while this one starts:
+    // read it once, so that every wave of the workgroup takes the same exit
+    // (the barriers below need all of them)
+    if (threadIdx.x == 0) s_flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_flag) return;
     const WideLevel me = a.lvl[L];
     const int64_t N = (int64_t)(me.packed >> kCntShift);
     const int64_t E = (int64_t)(me.packed & kMEdges);
@@ -516,11 +529,16 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     }
 }
 
+template <typename DistT, bool WRITE, bool LDS, int U>
+__global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
+    level_body<DistT, WRITE, LDS, U>(a, L);
+}
+
 // End of a launch: return every touched record to zero, copy the results
 // to the host-mapped buffers if given and scatter them into the lazy-loop
 // state if asked.  After an overflow nothing is cleared here; the host clears
 // and retries.
-__global__ void k_wide_end(WideArgs a, int32_t nlev) {
+__device__ __forceinline__ void end_body(const WideArgs &a) {
     const int32_t flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (flag) {
         if (a.h_flag && blockIdx.x == 0 && threadIdx.x == 0) *a.h_flag = flag;
@@ -558,10 +576,15 @@ __global__ void k_wide_end(WideArgs a, int32_t nlev) {
         }
 }
 
+__global__ void k_wide_end(WideArgs a, int32_t nlev) {
+    (void)nlev;
+    end_body(a);
+}
+
 // After k_wide_end (one workgroup): count the launch's word-level work, zero
 // the level records so the next launch starts clean, clear the host-visible
 // flag and (update mode) F(S + s) = F(S) - g(s, S).
-__global__ void k_wide_reset(WideArgs a, int32_t nlev) {
+__device__ __forceinline__ void reset_body(const WideArgs &a, int32_t nlev) {
     if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     if (threadIdx.x == 0) {
         if (a.words) {
@@ -588,6 +611,34 @@ __global__ void k_wide_reset(WideArgs a, int32_t nlev) {
         a.lvl[l].start = 0;
         a.lvl[l].packed = 0ull;
     }
+}
+
+__global__ void k_wide_reset(WideArgs a, int32_t nlev) { reset_body(a, nlev); }
+
+// A whole small launch (at most kLdsSrc sources) in one cooperative kernel:
+// roots, the levels, the clean-up and the reset, separated by grid-wide
+// barriers.  Every workgroup passes every barrier (early exits stay inside the
+// bodies), and the loop stops after the first level that appends nothing: the
+// count is read after a barrier, so all workgroups see the same value.
+template <typename DistT, bool WRITE, int U>
+__global__ __launch_bounds__(256) void k_wide_fused(WideArgs a, int32_t nlev) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int64_t span = (a.nsrc + kWG - 1) / kWG * kWG;
+    for (int64_t t = blockIdx.x * (int64_t)kWG + threadIdx.x; t < span; t += (int64_t)gridDim.x * kWG)
+        roots_body<DistT, WRITE>(a, t);
+    grid.sync();
+    int32_t run = 0;
+    while (run < nlev) {
+        level_body<DistT, WRITE, true, U>(a, run);
+        grid.sync();
+        ++run;
+        const unsigned long long pk =
+            __hip_atomic_load(&a.lvl[run].packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((pk >> kCntShift) == 0) break;
+    }
+    end_body(a);
+    grid.sync();
+    if (blockIdx.x == 0) reset_body(a, run);
 }
 
 // BFScut test (Section 3.1) after level L of a closeness launch: every node at
@@ -813,6 +864,36 @@ hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_
     hipLaunchKernelGGL(k_wide_end, dim3(g), dim3(256), 0, s, a, nlev);
     hipLaunchKernelGGL(k_wide_reset, dim3(1), dim3(256), 0, s, a, nlev);
     return hipGetLastError();
+}
+
+template <typename DistT, bool WRITE>
+static const void *fused_fn() {
+    return reinterpret_cast<const void *>(&k_wide_fused<DistT, WRITE, 8>);
+}
+
+int fused_max_grid(int num_cu) {
+    static int per_cu = -1;
+    if (per_cu < 0) {
+        int coop = 0, dev = 0, m = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, fused_fn<uint8_t, false>(), kWG, 0) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            m = 0;
+        }
+        per_cu = m;
+    }
+    return per_cu * num_cu;
+}
+
+hipError_t launch_wide_fused(const WideArgs &a, int dist_bytes, int32_t nlev, int grid, hipStream_t s) {
+    WideArgs arg = a;
+    int32_t nl = nlev;
+    void *params[] = {&arg, &nl};
+    const void *f = dist_bytes == 1 ? (a.write ? fused_fn<uint8_t, true>() : fused_fn<uint8_t, false>())
+                                    : (a.write ? fused_fn<uint16_t, true>() : fused_fn<uint16_t, false>());
+    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kWG), params, 0, s);
 }
 
 hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, hipStream_t s) {

@@ -171,10 +171,12 @@ def test_greedy_rmat16(gclib, block):
     assert grp_c.tolist() == grp_b.tolist() and F_c.tolist() == F_b.tolist()
 
 
-ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_ENGINE": "wg"}]
+ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_ENGINE": "wg"},
+               {"GC_FUSED": "1", "GC_FUSED_GAINS": "1", "GC_FUSED_WGS": "64"}]
 
 
-@pytest.mark.parametrize("env", ENGINE_ENVS, ids=["default", "chunked", "log-overflow", "wg-engine"])
+@pytest.mark.parametrize("env", ENGINE_ENVS,
+                         ids=["default", "chunked", "log-overflow", "wg-engine", "fused"])
 def test_engine_configurations(gclib, device, monkeypatch, env):
     """Launch chunking, frontier-log overflow retries and the per-workgroup
     engine all give the oracle's gains and greedy picks."""
