@@ -629,6 +629,12 @@ struct HostIO {
     int64_t *hm_edges = nullptr;
     int32_t *hm_flag = nullptr;
     volatile int32_t *h_flag = nullptr;  // host view of hm_flag
+    // done word (device pointer and host view of one pinned int64): the last
+    // launch of a call writes its sequence number there once its results are
+    // in the mapped buffers, so the host can wait by polling
+    int64_t *hm_done = nullptr;
+    volatile int64_t *h_done = nullptr;
+    int64_t seq = 0;
     // device copies of the lazy-loop state (learned order features)
     int64_t *ub = nullptr;
     int32_t *last_eval = nullptr;
@@ -711,6 +717,10 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                 a.h_gain = io->hm_gain ? io->hm_gain + off : nullptr;
                 a.h_edges = io->hm_edges ? io->hm_edges + off : nullptr;
                 a.h_flag = io->hm_flag;
+                if (io->hm_done && off + a.nsrc >= count) {
+                    a.h_done = io->hm_done;
+                    a.seq = ++const_cast<HostIO *>(io)->seq;
+                }
             }
             if (io && io->ub) {
                 a.ub_out = io->ub;
@@ -731,7 +741,21 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         if (g_timing) HIP_OK(hipEventRecord(g_ev1, s));
         if (timed) HIP_OK(hipEventRecord(io->ev1, s));
         if (mapped) {
-            HIP_OK(hipStreamSynchronize(s));
+            // poll the done word (no wake-up latency of a blocking wait); an
+            // overflow, a fault or a long launch ends up in the blocking wait
+            bool done = false;
+            if (io->hm_done) {
+                const double t0 = now_ms();
+                for (uint32_t spin = 0;; ++spin) {
+                    if (*io->h_done == io->seq) {
+                        done = true;
+                        break;
+                    }
+                    if (*io->h_flag) break;
+                    if ((spin & 255) == 255 && now_ms() - t0 > 2.0) break;
+                }
+            }
+            if (!done) HIP_OK(hipStreamSynchronize(s));
             flag = *io->h_flag;
         } else {
             HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
@@ -743,9 +767,14 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             HIP_OK(hipStreamSynchronize(s));
         }
         if (flag == 0) {
-            if (g_timing) HIP_OK(hipEventElapsedTime(&g_timing_ms, g_ev0, g_ev1));
+            // (after a polled wait the events behind the last kernel may still be pending)
+            if (g_timing) {
+                HIP_OK(hipEventSynchronize(g_ev1));
+                HIP_OK(hipEventElapsedTime(&g_timing_ms, g_ev0, g_ev1));
+            }
             if (timed) {
                 float ms = 0.f;
+                HIP_OK(hipEventSynchronize(io->ev1));
                 HIP_OK(hipEventElapsedTime(&ms, io->ev0, io->ev1));
                 *io->gpu_ms += ms;
             }
@@ -1215,6 +1244,9 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     io.hm_edges = dg + n;
     io.hm_flag = dflag;
     io.h_flag = hflag;
+    io.hm_done = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(dflag) + 64);
+    io.h_done = reinterpret_cast<volatile int64_t *>(reinterpret_cast<char *>(hflag) + 64);
+    *io.h_done = 0;
     const bool want_edges = true;
     const bool learned = o.order == GC_ORDER_LEARNED;
     const bool logging = o.log_capacity > 0 && o.h_log_round && o.h_log_node && o.h_log_gain &&

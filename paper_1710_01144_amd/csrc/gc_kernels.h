@@ -120,6 +120,8 @@ struct WideArgs {
     int64_t *h_gain;
     int64_t *h_edges;
     int32_t *h_flag;
+    int64_t *h_done;               // optional host-mapped word: = seq once everything is written
+    int64_t seq;
     // d(S,.) update mode: one source (the pick), distances written in place,
     // *far -= its gain at the end
     bool write;

@@ -566,6 +566,8 @@ __device__ __forceinline__ void end_body(const WideArgs &a) {
         for (int64_t i = t0; i < a.nsrc; i += nt) a.h_gain[i] = a.gain[i];
     if (a.h_edges && a.edges)
         for (int64_t i = t0; i < a.nsrc; i += nt) a.h_edges[i] = a.edges[i];
+    // host-mapped results written by this thread are visible before the done word
+    if (a.h_done && t0 < a.nsrc && (a.h_gain || a.h_edges)) __threadfence_system();
     if (a.ub_out)
         for (int64_t i = t0; i < a.nsrc; i += nt) {
             const int32_t v = a.src[i];
@@ -605,6 +607,10 @@ __device__ __forceinline__ void reset_body(const WideArgs &a, int32_t nlev) {
         if (a.h_flag) *a.h_flag = 0;
         if (a.far) *a.far -= a.gain[0];  // update: F(S + s) = F(S) - g(s, S)
         *a.zcnt = 0ull;
+        if (a.h_done) {
+            __threadfence_system();
+            *reinterpret_cast<volatile int64_t *>(a.h_done) = a.seq;
+        }
     }
     __syncthreads();
     for (int32_t l = threadIdx.x; l <= nlev + 1; l += blockDim.x) {
