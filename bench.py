@@ -221,7 +221,10 @@ def learned_comparison(G, g, k, args, grp, F):
         ms = 1000 * (time.perf_counter() - t1) / args.learned_reps
         assert gv.tolist() == grp.tolist() and Fv.tolist() == F.tolist(), name
         out[name] = {"ms": round(ms, 3), "evals_round1": int(sv["evals_round1"]),
-                     "evals_later": int(sv["evals_later"]), "ms_mlp": round(float(sv["ms_mlp"]), 3)}
+                     "evals_later": int(sv["evals_later"]), "ms_mlp": round(float(sv["ms_mlp"]), 3),
+                     "ms_later": round(float(sv["ms_later"]), 3), "ms_first": round(
+                         float(sv["ms_closest"]) + float(sv["ms_round1"]), 3),
+                     "gain_launches": int(sv["gain_launches"])}
     return out
 
 

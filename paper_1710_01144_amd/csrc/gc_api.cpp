@@ -503,6 +503,14 @@ int write_graph_tables(const gc_graph *g, const Ws &w, hipStream_t s) {
     return GC_OK;
 }
 
+// the graph tables, rebuilt if the workspace lacks the stamp (synchronises)
+int ensure_graph_tables(const gc_graph *g, const Ws &w, hipStream_t s) {
+    int64_t stamp = 0;
+    HIP_OK(hipMemcpyAsync(&stamp, w.hdr(), sizeof(stamp), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return stamp == ws_stamp(g) ? GC_OK : write_graph_tables(g, w, s);
+}
+
 }  // namespace
 
 extern "C" int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream) {
@@ -1378,7 +1386,9 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     //   plain: ascending id scan; CELF: a lazy max-heap on (ub, -id).
     const Ws::Mlp mw = w.mlp(n);
     if (need_state) {
-        HIP_OK(launch_twohop(g->d_rp, g->d_ci, n, mw.twohop, s));
+        // two-hop sums come from the workspace table
+        rc = ensure_graph_tables(g, w, s);
+        if (rc) return rc;
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(mw.ub), (size_t)n * 2, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(mw.last_eval), (size_t)n, 0xFFFFFFFFu, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(mw.dist_at_eval), ((size_t)n + 1) / 2, 0u, s));
@@ -1390,9 +1400,10 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     // id buffer, in list order.  Within a round a node's features only change
     // when it is evaluated, so computing them on demand gives the round-start
     // values for every node not yet evaluated.
-    auto features_of = [&](const int32_t *d_ids, int32_t cnt, int32_t r, bool want_scores) -> int {
+    auto features_of = [&](const int32_t *d_ids, int32_t cnt, int32_t r, bool want_scores,
+                           bool wait = true) -> int {
         const double tm = now_ms();
-        FeatArgs fa;
+        FeatArgs fa{};
         fa.rp = g->d_rp;
         fa.ci = g->d_ci;
         fa.dist = d_dist;
@@ -1401,7 +1412,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         fa.ub = mw.ub;
         fa.last_eval = mw.last_eval;
         fa.dist_at_eval = mw.dist_at_eval;
-        fa.twohop = mw.twohop;
+        fa.twohop = nullptr;
+        fa.two64 = w.two();
         fa.round = r;
         fa.k = k;
         fa.ecc1 = ecc_bound;
@@ -1410,11 +1422,16 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         if (want_scores)
             HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(o.d_mlp), fa.feat, cnt, nullptr,
                                       nullptr, nullptr, mw.ub, d_ids, dscore, s));
-        HIP_OK(hipStreamSynchronize(s));
+        if (wait) HIP_OK(hipStreamSynchronize(s));
         st.ms_mlp += now_ms() - tm;
         return GC_OK;
     };
     std::vector<int32_t> pool, rank;
+    // learned order: the first pool of round r + 1 (the 4 x block largest
+    // stale gains) is scored right behind the update of round r, on the
+    // stream, and waited for when the round starts
+    std::vector<int32_t> next_pool;
+    int32_t next_pool_round = -1;
     struct HeapEntry {
         int64_t ub;
         int32_t id;
@@ -1450,8 +1467,13 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 // evaluated in the round: the 4 x block largest bounds), best
                 // scored first; the rest go back into the heap unchanged
                 pool.clear();
+                const bool prefetched = best_id < 0 && next_pool_round == r;
+                if (prefetched) {
+                    pool.swap(next_pool);
+                    next_pool_round = -1;
+                }
                 const size_t want = best_id < 0 ? (size_t)4 * blk : (size_t)n;
-                while (!heap.empty() && pool.size() < want) {
+                while (!prefetched && !heap.empty() && pool.size() < want) {
                     const HeapEntry top = heap.front();
                     if (inS[top.id] || top.ver != ver[top.id]) {
                         std::pop_heap(heap.begin(), heap.end(), heap_less);
@@ -1467,9 +1489,15 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     // the whole pool fits in the block: its order cannot matter
                     for (size_t j = 0; j < pool.size(); ++j) hc[cnt++] = pool[j];
                 } else if (!pool.empty()) {
-                    for (size_t j = 0; j < pool.size(); ++j) hpool[j] = pool[j];
-                    rc = features_of(dpool, (int32_t)pool.size(), r, true);
-                    if (rc) return rc;
+                    if (prefetched) {
+                        const double tm = now_ms();
+                        HIP_OK(hipStreamSynchronize(s));  // the scores enqueued after the update
+                        st.ms_mlp += now_ms() - tm;
+                    } else {
+                        for (size_t j = 0; j < pool.size(); ++j) hpool[j] = pool[j];
+                        rc = features_of(dpool, (int32_t)pool.size(), r, true);
+                        if (rc) return rc;
+                    }
                     rank.resize(pool.size());
                     for (size_t j = 0; j < pool.size(); ++j) rank[j] = (int32_t)j;
                     std::sort(rank.begin(), rank.end(), [&](int32_t x, int32_t y) {
@@ -1593,6 +1621,25 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         Fs.push_back(F);
         inS[best_id] = 1;
         if (plain_scan && !tree.t.empty()) tree.set(best_id, -1);
+        if (learned && r + 1 < k && !heap.empty()) {
+            // score the next round's first pool now (asynchronously); only a
+            // pool larger than one block needs scores
+            next_pool.clear();
+            const size_t want = (size_t)4 * block;
+            while (!heap.empty() && next_pool.size() < want) {
+                const HeapEntry top = heap.front();
+                std::pop_heap(heap.begin(), heap.end(), heap_less);
+                heap.pop_back();
+                if (inS[top.id] || top.ver != ver[top.id]) continue;
+                next_pool.push_back(top.id);
+            }
+            if (next_pool.size() > (size_t)block) {
+                for (size_t j = 0; j < next_pool.size(); ++j) hpool[j] = next_pool[j];
+                rc = features_of(dpool, (int32_t)next_pool.size(), r + 1, true, false);
+                if (rc) return rc;
+            }
+            next_pool_round = r + 1;
+        }
     }
     for (int32_t i = 0; i < k; ++i) {
         h_group[i] = group[i];
@@ -1668,7 +1715,7 @@ extern "C" int gc_node_features(const gc_graph *g, const void *d_dist, int32_t d
     if (count < 0) return fail(GC_EINVAL, "count < 0");
     if (count > 0 && (!d_dist || !d_ub || !d_last_eval || !d_dist_at_eval || !d_feat))
         return fail(GC_EINVAL, "NULL device pointer");
-    FeatArgs fa;
+    FeatArgs fa{};
     fa.rp = g->d_rp;
     fa.ci = g->d_ci;
     fa.dist = d_dist;

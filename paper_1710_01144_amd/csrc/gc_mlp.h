@@ -39,7 +39,8 @@ struct FeatArgs {
     const int64_t *ub;         // stale gain per node
     const int32_t *last_eval;  // round of the last evaluation (-1: never)
     const uint16_t *dist_at_eval;  // d(S,v) at that evaluation
-    const float *twohop;       // sum of neighbour degrees (null: computed)
+    const float *twohop;       // sum of neighbour degrees (null: two64, else computed)
+    const int64_t *two64;      // the same as int64 (the workspace table), or null
     int32_t round, k, ecc1;
     float *feat;               // count x 8
 };

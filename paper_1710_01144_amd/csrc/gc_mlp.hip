@@ -203,6 +203,8 @@ __global__ void k_features(FeatArgs a) {
     float two = 0.f;
     if (a.twohop) {
         two = a.twohop[v];
+    } else if (a.two64) {
+        two = (float)a.two64[v];
     } else {
         int64_t acc = 0;
         for (int32_t e = rs; e < re; ++e) {
