@@ -224,7 +224,7 @@ def learned_comparison(G, g, k, args, grp, F):
                      "evals_later": int(sv["evals_later"]), "ms_mlp": round(float(sv["ms_mlp"]), 3),
                      "ms_later": round(float(sv["ms_later"]), 3), "ms_first": round(
                          float(sv["ms_closest"]) + float(sv["ms_round1"]), 3),
-                     "gain_launches": int(sv["gain_launches"])}
+                     "gain_launches": int(sv["gain_launches"]), "mlp_launches": int(sv["mlp_launches"])}
     return out
 
 
@@ -310,6 +310,8 @@ def main():
     job_alg = alg_bytes_of(int(st["entries_word"]) - int(st["entries_last"]), int(st["edges_word"]),
                            int(st["touched_word"]), dist_bytes)
     gain_gpu_ms = float(st["ms_gain_gpu"])
+    if gain_gpu_ms <= 0:
+        raise SystemExit("the library timed no gain launch (the per-workgroup engine is not timed)")
     achieved = job_alg / (gain_gpu_ms / 1000.0) / 1e9
     traffic = measured_traffic(args.workload, k, args.order)
     log("gain launches of the job: %d launches, %.3f ms GPU (%.2f us each), %d bytes algorithmic, "

@@ -116,6 +116,7 @@ typedef struct gc_stats {
     int64_t touched_word;   /* (batch, node) records the gain launches touched */
     double ms_gain_gpu;     /* GPU time of the gain launches (HIP events), all rounds;
                              * measured only while gc_timing_enable(1) is in force */
+    int64_t mlp_launches;   /* feature + MLP scoring launches (learned order) */
     int64_t *h_evals_per_round; /* optional, caller-owned, k entries */
 } gc_stats;
 

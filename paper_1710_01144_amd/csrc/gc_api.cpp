@@ -104,6 +104,8 @@ struct gc_graph {
     int32_t level_wgs_per_cu;  // GC_LEVEL_WGS (workgroups per CU of a level kernel)
     int32_t unroll;         // GC_UNROLL (4 or 8)
     int32_t min_edges;      // GC_MIN_EDGES (adjacency entries per workgroup)
+    int32_t learned_pool;   // GC_LEARNED_POOL: learned order ranks this many blocks of
+                            // the largest bounds (1..16)
 };
 
 extern "C" int32_t gc_graph_n(const gc_graph *g) { return g ? g->n : -1; }
@@ -296,6 +298,11 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
     if (const char *e = getenv("GC_UNROLL")) {
         const long v = strtol(e, nullptr, 10);
         g->unroll = v >= 16 ? 16 : (v >= 8 ? 8 : 4);
+    }
+    g->learned_pool = 2;
+    if (const char *e = getenv("GC_LEARNED_POOL")) {
+        const long v = strtol(e, nullptr, 10);
+        if (v >= 1 && v <= 16) g->learned_pool = (int32_t)v;
     }
     g->min_edges = 512;
     if (const char *e = getenv("GC_MIN_EDGES")) {
@@ -1163,6 +1170,42 @@ struct MaxTree {
     }
 };
 
+// Tournament tree over candidate keys (value, -id): every node holds the
+// leaf that wins its subtree and that leaf's value, so the best candidate is
+// read at the root and a key changes in O(log n).  A value below zero means
+// "not a candidate".
+struct ArgTree {
+    int32_t leaves = 1;
+    std::vector<int32_t> t;   // winning leaf of each node (padding leaves hold their own index)
+    std::vector<int64_t> tv;  // its value
+    void pull(size_t j) {
+        const int64_t va = tv[2 * j], vb = tv[2 * j + 1];
+        const int32_t ia = t[2 * j], ib = t[2 * j + 1];
+        const bool left = (va > vb) | ((va == vb) & (ia < ib));  // no branch on random keys
+        t[j] = left ? ia : ib;
+        tv[j] = left ? va : vb;
+    }
+    void build(const std::vector<int64_t> &ub, const std::vector<uint8_t> &inS, int32_t skip) {
+        const int32_t n = (int32_t)ub.size();
+        leaves = 1;
+        while (leaves < n) leaves <<= 1;
+        t.resize((size_t)2 * leaves);
+        tv.resize((size_t)2 * leaves);
+        for (int32_t i = 0; i < leaves; ++i) {
+            t[(size_t)leaves + i] = i;
+            tv[(size_t)leaves + i] = (i >= n || inS[i] || i == skip) ? -1 : ub[i];
+        }
+        for (size_t j = (size_t)leaves - 1; j >= 1; --j) pull(j);
+    }
+    // the best candidate, or -1 when none is left
+    int32_t top() const { return tv[1] >= 0 ? t[1] : -1; }
+    void set(int32_t i, int64_t x) {
+        size_t j = (size_t)leaves + i;
+        tv[j] = x;
+        for (j >>= 1; j >= 1; j >>= 1) pull(j);
+    }
+};
+
 struct PinnedBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -1383,7 +1426,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     // candidate is left that could.  With the key (ub, -id) compared
     // lexicographically the pick is the plain greedy's pick (smallest id among
     // equal gains) for every candidate order.
-    //   plain: ascending id scan; CELF: a lazy max-heap on (ub, -id).
+    //   plain: ascending id scan; CELF: the largest (ub, -id) first, from a
+    //   tournament tree.
     const Ws::Mlp mw = w.mlp(n);
     if (need_state) {
         // two-hop sums come from the workspace table
@@ -1419,6 +1463,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         fa.ecc1 = ecc_bound;
         fa.feat = logging ? dfeat : mw.feat;
         HIP_OK(launch_features(fa, dist_bytes, s));
+        ++st.mlp_launches;
         if (want_scores)
             HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(o.d_mlp), fa.feat, cnt, nullptr,
                                       nullptr, nullptr, mw.ub, d_ids, dscore, s));
@@ -1426,22 +1471,26 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         st.ms_mlp += now_ms() - tm;
         return GC_OK;
     };
-    std::vector<int32_t> pool, rank;
-    // learned order: the first pool of round r + 1 (the 4 x block largest
-    // stale gains) is scored right behind the update of round r, on the
-    // stream, and waited for when the round starts
-    std::vector<int32_t> next_pool;
-    int32_t next_pool_round = -1;
-    struct HeapEntry {
-        int64_t ub;
-        int32_t id;
-        uint32_t ver;
-    };
-    auto heap_less = [](const HeapEntry &x, const HeapEntry &y) {
-        return x.ub < y.ub || (x.ub == y.ub && x.id > y.id);
-    };
-    std::vector<HeapEntry> heap;
-    std::vector<uint32_t> ver;
+    std::vector<int32_t> pool, rank, fresh;
+    // learned scores by node, valid in round sc_round[u]: an unevaluated
+    // node's features do not change within a round, so a score is computed
+    // once per round however many blocks the round takes
+    std::vector<float> sc;
+    std::vector<int32_t> sc_round;
+    if (learned) {
+        sc.assign((size_t)n, 0.0f);
+        sc_round.assign((size_t)n, -1);
+    }
+    // learned order: the first pool of round r + 1 is scored right behind
+    // the update of round r, on the stream, and waited for when the round
+    // starts; later blocks score only the nodes the round has not scored
+    std::vector<int32_t> pending;
+    int32_t pending_round = -1;
+    bool pending_scored = false;
+    const int64_t pool_size = (int64_t)g->learned_pool * block;
+    // CELF and learned: candidates keyed by (ub, -id); a candidate taken for
+    // evaluation leaves the tree and comes back with its new gain
+    ArgTree keys;
     const bool plain_scan = o.order != GC_ORDER_CELF && !learned;
     MaxTree tree;
     const int32_t first_gain_round = (int32_t)group.size();
@@ -1455,7 +1504,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         };
         // no bounds exist yet in the first round: every candidate is evaluated at once
         const bool first_round = (r == first_gain_round);
-        const bool use_heap = !first_round && (o.order == GC_ORDER_CELF || learned);
+        const bool use_keys = !first_round && (o.order == GC_ORDER_CELF || learned);
         const int32_t blk = first_round ? n : block;
         int32_t pos = 0;
         io.round = r;
@@ -1463,68 +1512,63 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         for (;;) {
             int32_t cnt = 0;
             if (learned && !first_round) {
-                // the candidates whose bound can still win (before anything is
-                // evaluated in the round: the 4 x block largest bounds), best
-                // scored first; the rest go back into the heap unchanged
+                // the learned_pool x block largest bounds that can still win,
+                // best scored first; the rest go back into the tree unchanged
                 pool.clear();
-                const bool prefetched = best_id < 0 && next_pool_round == r;
-                if (prefetched) {
-                    pool.swap(next_pool);
-                    next_pool_round = -1;
-                }
-                const size_t want = best_id < 0 ? (size_t)4 * blk : (size_t)n;
-                while (!prefetched && !heap.empty() && pool.size() < want) {
-                    const HeapEntry top = heap.front();
-                    if (inS[top.id] || top.ver != ver[top.id]) {
-                        std::pop_heap(heap.begin(), heap.end(), heap_less);
-                        heap.pop_back();
-                        continue;
+                if (pending_round == r) {
+                    // the round's first pool, taken from the tree and scored
+                    // behind the update that ended the last round
+                    const double tm = now_ms();
+                    HIP_OK(hipStreamSynchronize(s));
+                    st.ms_mlp += now_ms() - tm;
+                    for (size_t j = 0; pending_scored && j < pending.size(); ++j) {
+                        sc[pending[j]] = hscore[j];
+                        sc_round[pending[j]] = r;
                     }
-                    if (!can_beat(top.id)) break;
-                    std::pop_heap(heap.begin(), heap.end(), heap_less);
-                    heap.pop_back();
-                    pool.push_back(top.id);
+                    pool.swap(pending);
+                    pending_round = -1;
                 }
-                if (!pool.empty() && pool.size() <= (size_t)blk) {
+                while (pool.size() < (size_t)pool_size) {
+                    const int32_t u = keys.top();
+                    if (u < 0 || !can_beat(u)) break;
+                    keys.set(u, -1);
+                    pool.push_back(u);
+                }
+                if (pool.size() <= (size_t)blk) {
                     // the whole pool fits in the block: its order cannot matter
                     for (size_t j = 0; j < pool.size(); ++j) hc[cnt++] = pool[j];
-                } else if (!pool.empty()) {
-                    if (prefetched) {
-                        const double tm = now_ms();
-                        HIP_OK(hipStreamSynchronize(s));  // the scores enqueued after the update
-                        st.ms_mlp += now_ms() - tm;
-                    } else {
-                        for (size_t j = 0; j < pool.size(); ++j) hpool[j] = pool[j];
-                        rc = features_of(dpool, (int32_t)pool.size(), r, true);
+                } else {
+                    // score only the nodes this round has not scored yet
+                    fresh.clear();
+                    for (size_t j = 0; j < pool.size(); ++j)
+                        if (sc_round[pool[j]] != r) fresh.push_back(pool[j]);
+                    if (!fresh.empty()) {
+                        for (size_t j = 0; j < fresh.size(); ++j) hpool[j] = fresh[j];
+                        rc = features_of(dpool, (int32_t)fresh.size(), r, true);
                         if (rc) return rc;
-                    }
-                    rank.resize(pool.size());
-                    for (size_t j = 0; j < pool.size(); ++j) rank[j] = (int32_t)j;
-                    std::sort(rank.begin(), rank.end(), [&](int32_t x, int32_t y) {
-                        return hscore[x] > hscore[y] || (hscore[x] == hscore[y] && pool[x] < pool[y]);
-                    });
-                    for (size_t j = 0; j < rank.size(); ++j) {
-                        const int32_t u = pool[rank[j]];
-                        if (cnt < blk) {
-                            hc[cnt++] = u;
-                        } else {
-                            heap.push_back(HeapEntry{ub[u], u, ver[u]});
-                            std::push_heap(heap.begin(), heap.end(), heap_less);
+                        for (size_t j = 0; j < fresh.size(); ++j) {
+                            sc[fresh[j]] = hscore[j];
+                            sc_round[fresh[j]] = r;
                         }
                     }
-                }
-            } else if (use_heap) {
-                while (cnt < blk && !heap.empty()) {
-                    const HeapEntry top = heap.front();
-                    if (inS[top.id] || top.ver != ver[top.id]) {
-                        std::pop_heap(heap.begin(), heap.end(), heap_less);
-                        heap.pop_back();
-                        continue;
+                    rank.assign(pool.begin(), pool.end());
+                    std::sort(rank.begin(), rank.end(), [&](int32_t x, int32_t y) {
+                        return sc[x] > sc[y] || (sc[x] == sc[y] && x < y);
+                    });
+                    for (size_t j = 0; j < rank.size(); ++j) {
+                        const int32_t u = rank[j];
+                        if (cnt < blk)
+                            hc[cnt++] = u;
+                        else
+                            keys.set(u, ub[u]);
                     }
-                    if (!can_beat(top.id)) break;  // nothing below the top can either
-                    std::pop_heap(heap.begin(), heap.end(), heap_less);
-                    heap.pop_back();
-                    hc[cnt++] = top.id;
+                }
+            } else if (use_keys) {
+                while (cnt < blk) {
+                    const int32_t u = keys.top();
+                    if (u < 0 || !can_beat(u)) break;  // nothing below the top can either
+                    keys.set(u, -1);
+                    hc[cnt++] = u;
                 }
             } else if (first_round) {
                 for (; pos < n && cnt < blk; ++pos)
@@ -1571,21 +1615,13 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     best_gain = gu;
                     best_id = u;
                 }
-                if (use_heap) {
-                    ++ver[u];
-                    heap.push_back(HeapEntry{gu, u, ver[u]});
-                    std::push_heap(heap.begin(), heap.end(), heap_less);
-                }
+                if (use_keys) keys.set(u, gu);
             }
             nev += cnt;
         }
         if (first_round && plain_scan) tree.build(ub, inS);
         if (first_round && (o.order == GC_ORDER_CELF || learned)) {
-            ver.assign((size_t)n, 0u);
-            heap.clear();
-            for (int32_t v = 0; v < n; ++v)
-                if (!inS[v] && v != best_id) heap.push_back(HeapEntry{ub[v], v, 0u});
-            std::make_heap(heap.begin(), heap.end(), heap_less);
+            keys.build(ub, inS, best_id);
         }
         if (first_round) {
             st.evals_round1 += nev;
@@ -1621,24 +1657,26 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         Fs.push_back(F);
         inS[best_id] = 1;
         if (plain_scan && !tree.t.empty()) tree.set(best_id, -1);
-        if (learned && r + 1 < k && !heap.empty()) {
-            // score the next round's first pool now (asynchronously); only a
-            // pool larger than one block needs scores
-            next_pool.clear();
-            const size_t want = (size_t)4 * block;
-            while (!heap.empty() && next_pool.size() < want) {
-                const HeapEntry top = heap.front();
-                std::pop_heap(heap.begin(), heap.end(), heap_less);
-                heap.pop_back();
-                if (inS[top.id] || top.ver != ver[top.id]) continue;
-                next_pool.push_back(top.id);
+        if (!keys.t.empty()) keys.set(best_id, -1);
+        if (learned && r + 1 < k) {
+            // take the next round's first pool now and score it on the
+            // stream behind the update (nothing is evaluated before it is
+            // used, so every one of them can still win)
+            pending.clear();
+            while (pending.size() < (size_t)pool_size) {
+                const int32_t u = keys.top();
+                if (u < 0) break;
+                keys.set(u, -1);
+                pending.push_back(u);
             }
-            if (next_pool.size() > (size_t)block) {
-                for (size_t j = 0; j < next_pool.size(); ++j) hpool[j] = next_pool[j];
-                rc = features_of(dpool, (int32_t)next_pool.size(), r + 1, true, false);
+            // a pool that fits in one block is evaluated whole, unscored
+            pending_scored = pending.size() > (size_t)block;
+            if (pending_scored) {
+                for (size_t j = 0; j < pending.size(); ++j) hpool[j] = pending[j];
+                rc = features_of(dpool, (int32_t)pending.size(), r + 1, true, false);
                 if (rc) return rc;
             }
-            next_pool_round = r + 1;
+            pending_round = r + 1;
         }
     }
     for (int32_t i = 0; i < k; ++i) {

@@ -74,7 +74,7 @@ class GcStats(ctypes.Structure):
                 ("entries_word", ctypes.c_int64), ("entries_root", ctypes.c_int64),
                 ("entries_last", ctypes.c_int64), ("edges_word", ctypes.c_int64),
                 ("edges_last", ctypes.c_int64), ("touched_word", ctypes.c_int64),
-                ("ms_gain_gpu", ctypes.c_double),
+                ("ms_gain_gpu", ctypes.c_double), ("mlp_launches", ctypes.c_int64),
                 ("h_evals_per_round", ctypes.POINTER(ctypes.c_int64))]
 
     def as_dict(self):
