@@ -70,6 +70,12 @@ def parse():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-order comparison (training + four timed orders)")
     ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--reduce-profile", metavar="PREFIX",
+                    help="no GPU run: reduce the rocprofv3 output in PREFIX_trace/, PREFIX_fetch/ "
+                         "and PREFIX_write/ (runs of this bench on --workload/--k; pass the "
+                         "--steps/--warmup of the counter runs) to the summary files named for "
+                         "the workload in --profile-out")
+    ap.add_argument("--profile-out", default="profiles")
     ap.add_argument("--calib-bytes", type=int, default=1 << 30,
                     help="size of the plain device copy timed (and profiled) as the bandwidth "
                          "and counter calibration")
@@ -166,7 +172,7 @@ def run_batched(args):
             if t_cpu >= args.cpu_seconds:
                 break
             t1 = time.perf_counter()
-            grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, k, block=64)
+            grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, k, block=64, growth=2)
             t_cpu += time.perf_counter() - t1
             assert grp_b.tolist() == grp.tolist() and F_b.tolist() == F.tolist(), "oracle disagrees"
             e_cpu += int(ed_b.sum())
@@ -228,12 +234,96 @@ def learned_comparison(G, g, k, args, grp, F):
     return out
 
 
+def _short_kernel(name):
+    for junk in ("void ", "gck::(anonymous namespace)::", "gck::"):
+        name = name.replace(junk, "")
+    return name.split("(gck")[0].split("(unsigned int*")[0][:70]
+
+
+def _dispatch_counter(path, counter):
+    """[name, value in KiB] per dispatch of a rocprofv3 --pmc csv, in dispatch order."""
+    import collections
+    import csv
+    d = collections.OrderedDict()
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            e = d.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])
+            if r["Counter_Name"] == counter:
+                e[1] += float(r["Counter_Value"])
+    return list(d.values())
+
+
+def reduce_profile(prefix, workload, k, order, out_dir, jobs):
+    """Summaries of three rocprofv3 runs of this bench (kernel trace with
+    --stats; --pmc FETCH_SIZE; --pmc WRITE_SIZE, each with --steps 1
+    --warmup 0): the top kernels by time, and the HBM bytes of the greedy job's
+    gain launches.  The job is every dispatch before the first k_bfs_level (the
+    bench's own d(S,.) update that follows it); its gain launches run from a
+    k_wide_roots<., false> dispatch through the next k_wide_reset.  Each
+    counter is scaled by what it reads for the bench's 1 GiB device copy.
+    `jobs` greedy jobs run before that update (the counter runs' warm-up and
+    timed steps plus the event-timed job), all the same job."""
+    import collections
+    import csv
+    lines = []
+    with open(prefix + "_trace/run_kernel_stats.csv") as f:
+        rows = list(csv.DictReader(f))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    for r in rows[:14]:
+        lines.append("%-70s calls %6s total %9.3f ms avg %9.2f us %5.1f%%" % (
+            _short_kernel(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e3, 100 * float(r["TotalDurationNs"]) / tot))
+    job = {}
+    for kind, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        disp = _dispatch_counter(prefix + "_%s/run_counter_collection.csv" % kind, counter)
+        copy_kib = max(v for name, v in disp if "copyBuffer" in name)
+        scale = (1 << 30) / (copy_kib * 1024)
+        end = next(i for i, (name, _) in enumerate(disp) if "k_bfs_level" in name)
+        gain, kib, launches = False, 0.0, 0
+        by = collections.defaultdict(float)
+        for name, val in disp[:end]:
+            if "k_wide_roots" in name:
+                gain = "false>" in name
+                launches += gain
+            if gain and "k_wide_" in name:
+                kib += val
+                by[_short_kernel(name)] += val
+            if "k_wide_reset" in name:
+                gain = False
+        job[counter] = {"copy_kib": copy_kib, "scale": scale, "bytes": kib * 1024 * scale,
+                        "launches": launches, "by_kernel": by}
+    rec = {"workload": workload, "k": k, "order": order, "jobs": jobs,
+           "launches": job["FETCH_SIZE"]["launches"],
+           "fetch_bytes": round(job["FETCH_SIZE"]["bytes"]), "write_bytes": round(job["WRITE_SIZE"]["bytes"]),
+           "fetch_scale": round(job["FETCH_SIZE"]["scale"], 4),
+           "write_scale": round(job["WRITE_SIZE"]["scale"], 4),
+           "kernel_source_sha256_16": kernel_source_hash()}
+    rec["traffic_bytes_per_launch"] = round((rec["fetch_bytes"] + rec["write_bytes"]) /
+                                            max(rec["launches"], 1), 1)
+    os.makedirs(out_dir, exist_ok=True)
+    base = os.path.join(out_dir, "k_wide_gain_%s" % workload)
+    with open(base + "_traffic.json", "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(base + "_reduced.txt", "w") as f:
+        f.write("top kernels by time (kernel trace run):\n" + "\n".join(lines) + "\n")
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            j = job[counter]
+            f.write("%s: 1 GiB copy reads %.1f KiB (scale %.4f); %d jobs: %d gain launches, %.1f MB\n" % (
+                counter, j["copy_kib"], j["scale"], jobs, j["launches"], j["bytes"] / 1e6))
+            for name, v in sorted(j["by_kernel"].items(), key=lambda kv: -kv[1]):
+                f.write("    %-68s %10.1f MB\n" % (name, v * 1024 * j["scale"] / 1e6))
+        f.write("HBM traffic per gain launch: %.1f KB\n" % (rec["traffic_bytes_per_launch"] / 1e3))
+    print(open(base + "_reduced.txt").read())
+
+
 def main():
     args = parse()
+    if args.reduce_profile:
+        return reduce_profile(args.reduce_profile, args.workload, args.k, args.order, args.profile_out,
+                              args.warmup + args.steps + 1)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the method's data-parallel path is sharded by "
-              "candidates across GPUs in the design notes, but this build measures one MI355X "
-              "(use --gpus 1).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the gain evaluations would shard by candidate "
+              "across GPUs, but only the one-GPU path exists (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
     import torch
     import graphgen
@@ -376,7 +466,7 @@ def main():
         reps, t_cpu = 0, 0.0
         while t_cpu < args.cpu_seconds and reps < 1000:
             t1 = time.perf_counter()
-            grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, k, block=64)
+            grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, k, block=64, growth=2)
             t_cpu += time.perf_counter() - t1
             reps += 1
         assert grp_b.tolist() == grp.tolist() and F_b.tolist() == F.tolist(), "oracle disagrees"

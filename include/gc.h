@@ -71,13 +71,17 @@ typedef struct gc_opts {
     int32_t order;          /* GC_ORDER_* */
     int32_t bitset_width;   /* sources per bit-parallel BFS: 64 (0 = default 64) */
     int32_t block;          /* rounds >= 2: candidates evaluated between two
-                               threshold updates (0 = bitset_width) */
+                               threshold updates (0 = bitset_width); the picks
+                               never depend on it */
     int32_t nprefix;        /* resume: the first nprefix picks are given */
     const int32_t *h_prefix;/* host, nprefix ids (a previous run's pick order) */
     const void *d_mlp;      /* GC_ORDER_LEARNED: device inference block made by
                                gc_mlp_pack(); NULL otherwise */
     int32_t debug_checks;   /* 1: re-check F(S) == sum_w d(S,w) after every pick */
-    int32_t reserved;
+    int32_t block_growth;   /* each further launch of a round takes this many
+                               times the block of the one before, up to
+                               16 x block (1..8; 0 = default: 2 for the plain
+                               order, 1 for the others) */
     /* optional logging of every exact evaluation (host buffers, may be NULL):
        round, node, gain and the 8 MLP features at evaluation time */
     int64_t log_capacity;

@@ -69,7 +69,7 @@ def _load():
         lib.or_greedy.restype = ctypes.c_int
         lib.or_greedy.argtypes = [I64, i32p, i32p, I32, i32p, i64p, ctypes.c_void_p]
         lib.or_greedypp.restype = ctypes.c_int
-        lib.or_greedypp.argtypes = [I64, i32p, i32p, I32, I32, i32p, i64p, i64p, i64p]
+        lib.or_greedypp.argtypes = [I64, i32p, i32p, I32, I32, I32, i32p, i64p, i64p, i64p]
         lib.or_pruned_stats.restype = ctypes.c_int
         lib.or_pruned_stats.argtypes = [I64, i32p, i32p, i32p, i32p, I64, i64p, i64p, i64p]
         lib.or_num_threads.restype = ctypes.c_int
@@ -160,14 +160,17 @@ def greedy(g, k: int, with_gains: bool = False):
     return group, F
 
 
-def greedypp(g, k: int, block: int = 64):
-    """Tier B CPU Greedy++.  Returns (group, F, evals per round, edges per round)."""
+def greedypp(g, k: int, block: int = 64, growth: int = 1):
+    """Tier B CPU Greedy++.  Returns (group, F, evals per round, edges per round).
+    Candidates are evaluated in batches of `block` between threshold updates;
+    from the second round on each further batch of a round is `growth` times
+    the one before (up to 16 x block).  The batches only change the counts."""
     n, rp, ci = _csr(g)
     group = np.empty(k, dtype=np.int32)
     F = np.empty(k, dtype=np.int64)
     ev = np.zeros(k, dtype=np.int64)
     ed = np.zeros(k, dtype=np.int64)
-    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), group, F, ev, ed))
+    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed))
     return group, F, ev, ed
 
 

@@ -29,7 +29,11 @@
  *   - the skip test of Section 4.2 compares (stale gain, -id) lexicographically
  *     with the best (gain, -id) found so far in the round, so the result equals
  *     tier A for any candidate order;
- *   - the candidate scan order of the while-loop is ascending node id.
+ *   - the candidate scan order of the while-loop is ascending node id;
+ *   - candidates are skip-tested a batch at a time against the best of the
+ *     batches already evaluated in the round (a batch of one is the paper's
+ *     sequential loop); batch sizes change the evaluation counts, never the
+ *     picks.
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so
  */
@@ -328,8 +332,11 @@ static int64_t bfscut(int64_t n, const int32_t *rp, const int32_t *ci, int32_t v
  * edges (nullable) receives, per round, the summed adjacency entries scanned.
  */
 int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t block,
-                int32_t *group, int64_t *Fout, int64_t *evals, int64_t *edges) {
-    if (k < 1 || k > n || block < 1) return OR_EINVAL;
+                int32_t growth, int32_t *group, int64_t *Fout, int64_t *evals, int64_t *edges) {
+    if (k < 1 || k > n || block < 1 || growth < 1 || growth > 8) return OR_EINVAL;
+    /* the largest batch: block grows by `growth` per batch of a round, up to 16 x block */
+    int64_t maxb = growth > 1 ? 16 * (int64_t)block : block;
+    if (maxb > n) maxb = n;
     int nthr = 1;
 #ifdef _OPENMP
     nthr = omp_get_max_threads();
@@ -347,9 +354,9 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
     int32_t *dS = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *dnew = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int64_t *ub = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    int32_t *batch = (int32_t *)malloc(sizeof(int32_t) * (size_t)block);
-    int64_t *bg = (int64_t *)malloc(sizeof(int64_t) * (size_t)block);
-    int64_t *be = (int64_t *)malloc(sizeof(int64_t) * (size_t)block);
+    int32_t *batch = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxb);
+    int64_t *bg = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxb);
+    int64_t *be = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxb);
     int rc = OR_OK;
 
     /* first node: decreasing degree, BFScut (sequential) */
@@ -385,9 +392,10 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
         int64_t bgain = -1;
         int32_t bid = -1;
         int64_t pos = 0, nev = 0, ned = 0;
+        int64_t cur = block < maxb ? block : maxb; /* batch size; the first round takes every node anyway */
         for (;;) {
             int32_t nb = 0;
-            while (pos < n && nb < block) {
+            while (pos < n && nb < cur) {
                 int32_t u = (int32_t)pos++;
                 if (dS[u] == 0) continue; /* u in S */
                 if (bid >= 0 && (ub[u] < bgain || (ub[u] == bgain && u > bid))) continue;
@@ -411,6 +419,11 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
                 if (bid < 0 || bg[j] > bgain || (bg[j] == bgain && u < bid)) { bgain = bg[j]; bid = u; }
             }
             nev += nb;
+            /* the skip test sees the threshold only between batches: the
+             * batch sizes decide how many candidates are evaluated, never
+             * which one is picked */
+            if (r >= 2 && cur * growth <= maxb) cur *= growth;
+            else if (r >= 2) cur = maxb;
         }
         if (evals) evals[r] = nev;
         if (edges) edges[r] = ned;

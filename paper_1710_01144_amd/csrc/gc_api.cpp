@@ -1241,6 +1241,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     if (o.order < GC_ORDER_PLAIN || o.order > GC_ORDER_LEARNED) return fail(GC_EINVAL, "bad order");
     if (o.order == GC_ORDER_LEARNED && !o.d_mlp) return fail(GC_EINVAL, "learned order needs d_mlp");
     const int32_t block = o.block > 0 ? o.block : kSrc;
+    if (o.block_growth < 0 || o.block_growth > 8) return fail(GC_EINVAL, "block_growth outside [0, 8]");
     if (o.nprefix < 0 || o.nprefix > k || (o.nprefix > 0 && !o.h_prefix))
         return fail(GC_EINVAL, "bad prefix");
     for (int32_t i = 0; i < o.nprefix; ++i)
@@ -1492,6 +1493,13 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     // evaluation leaves the tree and comes back with its new gain
     ArgTree keys;
     const bool plain_scan = o.order != GC_ORDER_CELF && !learned;
+    // Each later launch of a round may take a larger block than the one
+    // before (up to kMaxBlockGrowth x block).  Plain order default 2: the
+    // first block of a round sets a threshold, and the ascending-id scan
+    // behind it then runs in fewer, larger launches, which pays on a GPU where
+    // a launch of a few hundred candidates costs little more than one of 64.
+    constexpr int64_t kMaxBlockGrowth = 16;
+    const int32_t growth = o.block_growth > 0 ? o.block_growth : (plain_scan ? 2 : 1);
     MaxTree tree;
     const int32_t first_gain_round = (int32_t)group.size();
     for (int32_t r = first_gain_round; r < k; ++r) {
@@ -1505,7 +1513,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         // no bounds exist yet in the first round: every candidate is evaluated at once
         const bool first_round = (r == first_gain_round);
         const bool use_keys = !first_round && (o.order == GC_ORDER_CELF || learned);
-        const int32_t blk = first_round ? n : block;
+        int32_t blk = first_round ? n : block;
         int32_t pos = 0;
         io.round = r;
         cur_round = r;
@@ -1594,6 +1602,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             }
             rc = evaluate(cnt);
             if (rc) return rc;
+            if (!first_round && growth > 1)
+                blk = (int32_t)std::min<int64_t>((int64_t)blk * growth, std::min<int64_t>((int64_t)kMaxBlockGrowth * block, n));
             if (logging && !first_round) {
                 for (int32_t j = 0; j < cnt; ++j) {
                     const int64_t at = (*o.h_log_count)++;

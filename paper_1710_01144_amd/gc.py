@@ -53,7 +53,7 @@ class GcOpts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("bitset_width", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("nprefix", ctypes.c_int32),
                 ("h_prefix", ctypes.POINTER(ctypes.c_int32)), ("d_mlp", ctypes.c_void_p),
-                ("debug_checks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("debug_checks", ctypes.c_int32), ("block_growth", ctypes.c_int32),
                 ("log_capacity", ctypes.c_int64),
                 ("h_log_round", ctypes.POINTER(ctypes.c_int32)),
                 ("h_log_node", ctypes.POINTER(ctypes.c_int32)),
@@ -279,12 +279,14 @@ class Graph:
         return feat[:count]
 
     def greedy_group(self, k: int, order: str = "plain", block: int = 0, prefix=None,
-                     mlp_params=None, log_capacity: int = 0, debug: bool = False):
+                     mlp_params=None, log_capacity: int = 0, debug: bool = False,
+                     block_growth: int = 0):
         lib = load_library()
         opts = GcOpts()
         opts.order = ORDERS[order]
         opts.bitset_width = 64
         opts.block = int(block)
+        opts.block_growth = int(block_growth)
         opts.debug_checks = 1 if debug else 0
         keep = []
         if prefix is not None and len(prefix) > 0:

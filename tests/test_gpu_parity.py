@@ -156,19 +156,46 @@ def test_greedy_ba2000_k10(gclib):
 def test_greedy_rmat16(gclib, block):
     g = graphgen.workload("rmat16")
     G = _graph(gclib, g)
-    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 50, block=block)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 50, block=block, growth=2)
     _note("greedy rmat16 k=50 plain block %d" % block)
     grp, F, st = G.greedy_group(50, order="plain", block=block, debug=True)
     assert grp.tolist() == grp_b.tolist()
     assert F.tolist() == F_b.tolist()
-    # same scan order and block: the same evaluations as the CPU Greedy++
+    # same scan order and batch schedule (the plain order doubles its block
+    # per launch of a round): the same evaluations as the CPU Greedy++
     assert st["evals_per_round"].tolist() == ev_b.tolist()
     assert st["edges_alg"] == int(ed_b.sum())
+    _note("greedy rmat16 k=50 plain fixed block %d" % block)
+    _, _, ev_1, ed_1 = oracle.greedypp(g, 50, block=block, growth=1)
+    grp1, F1, st1 = G.greedy_group(50, order="plain", block=block, block_growth=1)
+    assert grp1.tolist() == grp_b.tolist() and F1.tolist() == F_b.tolist()
+    assert st1["evals_per_round"].tolist() == ev_1.tolist()
+    assert st1["edges_alg"] == int(ed_1.sum())
     # F(S) against the definition
     assert int(F[-1]) == oracle.farness(g, grp)
     _note("greedy rmat16 k=50 celf block %d" % block)
     grp_c, F_c, st_c = G.greedy_group(50, order="celf", block=block)
     assert grp_c.tolist() == grp_b.tolist() and F_c.tolist() == F_b.tolist()
+
+
+def test_greedy_block_growth(gclib):
+    """Every batch schedule gives the same group; the CELF order with a
+    growing block matches the CPU Greedy++ picks; out-of-range factors are
+    rejected before any work."""
+    g = graphgen.ba(3000, 3, 41)
+    G = _graph(gclib, g)
+    grp_b, F_b, _, _ = oracle.greedypp(g, 15, block=16, growth=1)
+    for order in ("plain", "celf"):
+        for gr in (1, 3, 8):
+            _note("greedy ba3000 k=15 %s block 16 growth %d" % (order, gr))
+            grp, F, st = G.greedy_group(15, order=order, block=16, block_growth=gr)
+            assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+            if order == "plain":
+                _, _, ev, _ = oracle.greedypp(g, 15, block=16, growth=gr)
+                assert st["evals_per_round"].tolist() == ev.tolist()
+    for bad in (-1, 9):
+        with pytest.raises(gclib.GCError):
+            G.greedy_group(5, block_growth=bad)
 
 
 ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_ENGINE": "wg"},
@@ -228,7 +255,7 @@ def test_greedy_grid_u16(gclib):
     """High-diameter perturbed grid (16-bit distances when ecc > 254)."""
     g = graphgen.grid(900, 5, 9, shortcut_frac=0.0)
     G = _graph(gclib, g)
-    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 12, block=64)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 12, block=64, growth=2)
     for order in ("plain", "celf"):
         _note("greedy grid900x5 k=12 %s" % order)
         grp, F, st = G.greedy_group(12, order=order, debug=True)
@@ -242,7 +269,7 @@ def test_greedy_grid_u16(gclib):
 def test_greedy_grid_square(gclib, side):
     g = graphgen.grid(side, side, 10 + side)
     G = _graph(gclib, g)
-    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 20, block=64)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 20, block=64, growth=2)
     _note("greedy grid%d k=20" % side)
     grp, F, st = G.greedy_group(20, debug=True)
     assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
@@ -258,7 +285,7 @@ def test_greedy_rmat20_k100_full_size(gclib):
     _note("greedy rmat20 k=100 (GPU)")
     grp, F, st = G.greedy_group(100, order="plain")
     _note("greedy rmat20 k=100 (CPU oracle, tier B)")
-    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 100, block=64)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 100, block=64, growth=2)
     assert grp.tolist() == grp_b.tolist()
     assert F.tolist() == F_b.tolist()
     assert st["evals_per_round"].tolist() == ev_b.tolist()
@@ -289,7 +316,7 @@ def test_batched_ba_sample(gclib):
         sg, n_g, m_g, k_g = params[idx]
         g = graphgen.ba(n_g, m_g, sg)
         G = _graph(gclib, g)
-        grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, k_g, block=64)
+        grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, k_g, block=64, growth=2)
         for ordr in ("plain", "celf"):
             _note("batched BA graph %d (n=%d m=%d) k=%d %s" % (idx, g.n, m_g, k_g, ordr))
             grp, F, st = G.greedy_group(k_g, order=ordr, block=64)

@@ -261,17 +261,32 @@ TIERB = [lambda: graphgen.ba(400, 3, 21), lambda: graphgen.ba(300, 1, 22),
 
 
 @pytest.mark.parametrize("mk", TIERB)
-@pytest.mark.parametrize("block", [1, 7, 64])
-def test_tier_b_equals_tier_a(mk, block):
+@pytest.mark.parametrize("block,growth", [(1, 1), (7, 1), (64, 1), (1, 2), (5, 3)])
+def test_tier_b_equals_tier_a(mk, block, growth):
     g = mk()
     k = min(g.n, 12)
     grp_a, F_a = oracle.greedy(g, k)
-    grp_b, F_b, ev, ed = oracle.greedypp(g, k, block=block)
+    grp_b, F_b, ev, ed = oracle.greedypp(g, k, block=block, growth=growth)
     assert grp_b.tolist() == grp_a.tolist()
     assert F_b.tolist() == F_a.tolist()
     if k > 1:
         assert ev[1] == g.n - 1          # no bounds in the first round after s_1
         assert np.all(ev[2:] <= g.n - np.arange(2, k))
+
+
+def test_tier_b_batch_schedule():
+    """Batch sizes only move evaluation counts: every schedule gives the same
+    picks and farness; a batch as large as the graph skips nothing, so every
+    round evaluates all n - r candidates outside S."""
+    g = graphgen.ba(500, 2, 31)
+    k = 15
+    runs = [oracle.greedypp(g, k, block=b, growth=gr) for b, gr in [(1, 1), (4, 1), (4, 2), (16, 4)]]
+    for grp, F, ev, ed in runs[1:]:
+        assert grp.tolist() == runs[0][0].tolist() and F.tolist() == runs[0][1].tolist()
+        assert np.all(ev[1:] <= g.n - np.arange(1, k))
+    grp, F, ev, ed = oracle.greedypp(g, k, block=g.n)
+    assert grp.tolist() == runs[0][0].tolist()
+    assert ev[1:].tolist() == (g.n - np.arange(1, k)).tolist()
 
 
 def test_tier_b_equals_tier_a_ba2000():
