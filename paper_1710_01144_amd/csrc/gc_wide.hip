@@ -307,10 +307,13 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     // another workgroup may raise the overflow flag while this one starts:
     // read it once, so that every wave of the workgroup takes the same exit
     // (the barriers below need all of them)
+    // (the level records were written by earlier kernels: load them while
+    // the flag is read)
+    const WideLevel me = a.lvl[L];
+    const int64_t pstart = L >= 1 ? a.lvl[L - 1].start : 0;
     if (threadIdx.x == 0) s_flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (s_flag) return;
-    const WideLevel me = a.lvl[L];
     const int64_t N = (int64_t)(me.packed >> kCntShift);
     const int64_t E = (int64_t)(me.packed & kMEdges);
     const int64_t start = me.start;
@@ -318,23 +321,28 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) a.lvl[L + 1].start = nbase;
     const int fr_cur = 1 + L % 3, fr_next = 1 + (L + 1) % 3;
-    // clear the frontier words of level L-1 (read in the previous kernel; the
-    // next kernel writes this slot again)
-    if (L >= 1) {
-        const int fr_prev = 1 + (L + 2) % 3;
-        const int64_t pstart = a.lvl[L - 1].start;
-        for (int64_t q = pstart + blockIdx.x * (int64_t)kWG + tid; q < start && q < a.cap;
-             q += (int64_t)gridDim.x * kWG)
-            *rec(a, a.lb[q], a.ly[q], fr_prev) = 0ull;
-    }
-    if (E == 0) return;
     // small levels use few workgroups: each takes at least min_edges entries
-    int64_t G = (E + a.min_edges - 1) / a.min_edges;
+    int64_t G = E == 0 ? 0 : (E + a.min_edges - 1) / a.min_edges;
     if (G > (int64_t)gridDim.x) G = gridDim.x;
-    if ((int64_t)blockIdx.x >= G) return;
+    // Clear the frontier words of level L-1 (read by the previous kernel; the
+    // next kernel writes this slot again).  The workgroups without expansion
+    // work do it, off the others' path; if every workgroup expands, each
+    // clears its share after its expansion.
+    auto clear_prev = [&](int64_t w, int64_t nw) {
+        const int fr_prev = 1 + (L + 2) % 3;
+        for (int64_t q = pstart + w * kWG + tid; q < start && q < a.cap; q += nw * kWG)
+            *rec(a, a.lb[q], a.ly[q], fr_prev) = 0ull;
+    };
+    if ((int64_t)blockIdx.x >= G) {
+        if (L >= 1) clear_prev((int64_t)blockIdx.x - G, (int64_t)gridDim.x - G);
+        return;
+    }
     const int64_t eb = E * (int64_t)blockIdx.x / G;
     const int64_t ee = E * ((int64_t)blockIdx.x + 1) / G;
-    if (eb >= ee) return;
+    if (eb >= ee) {
+        if (L >= 1 && G == (int64_t)gridDim.x) clear_prev(blockIdx.x, gridDim.x);
+        return;
+    }
 
     DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
     const int32_t *__restrict__ rp = a.rp;
@@ -527,6 +535,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
             if (a.visited && s_v[q]) atomicAdd(a.visited + q, (int)s_v[q]);
         }
     }
+    if (L >= 1 && G == (int64_t)gridDim.x) clear_prev(blockIdx.x, gridDim.x);
 }
 
 template <typename DistT, bool WRITE, bool LDS, int U>
