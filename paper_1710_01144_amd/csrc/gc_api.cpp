@@ -1278,10 +1278,11 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     // with gc_timing_enable(1): events timing the gain launches (their GPU
     // time is reported in gc_stats)
     struct EvPair {
-        hipEvent_t a = nullptr, b = nullptr;
+        hipEvent_t a = nullptr, b = nullptr, score = nullptr;
         ~EvPair() {
             if (a) (void)hipEventDestroy(a);
             if (b) (void)hipEventDestroy(b);
+            if (score) (void)hipEventDestroy(score);
         }
     } ev;
     HostIO io;
@@ -1469,6 +1470,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             HIP_OK(launch_mlp_forward(reinterpret_cast<const MlpBlock *>(o.d_mlp), fa.feat, cnt, nullptr,
                                       nullptr, nullptr, mw.ub, d_ids, dscore, s));
         if (wait) HIP_OK(hipStreamSynchronize(s));
+        else HIP_OK(hipEventRecord(ev.score, s));
         st.ms_mlp += now_ms() - tm;
         return GC_OK;
     };
@@ -1489,17 +1491,19 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     int32_t pending_round = -1;
     bool pending_scored = false;
     const int64_t pool_size = (int64_t)g->learned_pool * block;
+    if (learned) HIP_OK(hipEventCreateWithFlags(&ev.score, hipEventDisableTiming));
     // CELF and learned: candidates keyed by (ub, -id); a candidate taken for
     // evaluation leaves the tree and comes back with its new gain
     ArgTree keys;
     const bool plain_scan = o.order != GC_ORDER_CELF && !learned;
     // Each later launch of a round may take a larger block than the one
-    // before (up to kMaxBlockGrowth x block).  Plain order default 2: the
-    // first block of a round sets a threshold, and the ascending-id scan
-    // behind it then runs in fewer, larger launches, which pays on a GPU where
-    // a launch of a few hundred candidates costs little more than one of 64.
+    // before (up to kMaxBlockGrowth x block).  Default 2 for the plain and
+    // learned orders: the first block of a round sets a threshold, and what
+    // still passes it then goes in fewer, larger launches, which pays on a
+    // GPU where a launch of a few hundred candidates costs little more than
+    // one of 64.  CELF's first block nearly always ends the round.
     constexpr int64_t kMaxBlockGrowth = 16;
-    const int32_t growth = o.block_growth > 0 ? o.block_growth : (plain_scan ? 2 : 1);
+    const int32_t growth = o.block_growth > 0 ? o.block_growth : (o.order == GC_ORDER_CELF ? 1 : 2);
     MaxTree tree;
     const int32_t first_gain_round = (int32_t)group.size();
     for (int32_t r = first_gain_round; r < k; ++r) {
@@ -1526,8 +1530,16 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 if (pending_round == r) {
                     // the round's first pool, taken from the tree and scored
                     // behind the update that ended the last round
+                    // (polled: a blocking wait adds its wake-up latency to every round)
                     const double tm = now_ms();
-                    HIP_OK(hipStreamSynchronize(s));
+                    if (pending_scored) {
+                        hipError_t q = hipErrorNotReady;
+                        for (uint32_t spin = 0; q == hipErrorNotReady; ++spin) {
+                            q = hipEventQuery(ev.score);
+                            if ((spin & 255) == 255 && now_ms() - tm > 2.0) break;
+                        }
+                        if (q != hipSuccess) HIP_OK(hipEventSynchronize(ev.score));
+                    }
                     st.ms_mlp += now_ms() - tm;
                     for (size_t j = 0; pending_scored && j < pending.size(); ++j) {
                         sc[pending[j]] = hscore[j];
