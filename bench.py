@@ -42,7 +42,8 @@ WORKLOADS = {
     "grid1024": ("1024x1024 grid, 5% edges dropped, 0.1%*n shortcuts, largest component", "grid1024"),
     "rmat24": ("R-MAT scale 24, edge factor 16, largest component", "rmat24"),
     "batchba": ("256 Barabasi-Albert graphs, n~U{1000..50000}, m~U{2..8}, k~U{5..50}, "
-                "SplitMix64 seeds from 3; run one after another on one shared workspace", "batchba"),
+                "SplitMix64 seeds from 3; jobs spread over host worker threads, each with its own stream "
+                "and workspace", "batchba"),
 }
 # Workloads whose GPU run is switched off: the first R-MAT scale 24 run ended in
 # a GPU memory fault inside the first-pick search, and its cause has not been
@@ -70,6 +71,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-order comparison (training + four timed orders)")
     ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--workers", type=int, default=8,
+                    help="batched workload: host threads (each with its own stream and workspace)")
     ap.add_argument("--reduce-profile", metavar="PREFIX",
                     help="no GPU run: reduce the rocprofv3 output in PREFIX_trace/, PREFIX_fetch/ "
                          "and PREFIX_write/ (runs of this bench on --workload/--k; pass the "
@@ -126,8 +129,9 @@ def log(msg):
 
 def run_batched(args):
     """The batched BA workload: every graph with its own k through
-    gc_greedy_group, one after another on one workspace buffer sized for the
-    largest graph (initialised per graph inside the timed region)."""
+    gc_greedy_many -- `--workers` host threads, each with its own stream and
+    a workspace sized for the largest graph (initialised per graph inside the
+    timed region), largest graphs first."""
     import torch
     import graphgen
     from paper_1710_01144_amd import gc
@@ -139,20 +143,15 @@ def run_batched(args):
     log("256 graphs generated in %.1fs, total n=%d nnz=%d" % (time.time() - t0, sum(g.n for g, _ in items),
                                                             sum(g.nnz for g, _ in items)))
     Gs = [gc.Graph.from_graphgen(g, workspace=False) for g, _ in items]
-    need = max(G.workspace_size() for G in Gs)
-    buf = torch.empty(need, dtype=torch.uint8, device=dev)
-    log("shared workspace %.1f MiB" % (need / 2**20))
+    many = gc.Many(Gs, workers=args.workers)
+    log("%d workers, workspace %.1f MiB each" % (many.workers, many.ws_bytes / 2**20))
+    ks = [k for _, k in items]
 
     def one_pass():
-        edges = evals = 0
-        groups = []
-        for G, (g, k) in zip(Gs, items):
-            G.use_workspace(buf)
-            grp, F, st = G.greedy_group(k, order=args.order, block=args.block)
-            edges += int(st["edges_alg"])
-            evals += int(st["evals_total"])
-            groups.append((grp, F))
-        return edges, evals, groups
+        grps, fars, sts = many.run(ks, order=args.order, block=args.block)
+        edges = sum(int(st["edges_alg"]) for st in sts)
+        evals = sum(int(st["evals_total"]) for st in sts)
+        return edges, evals, list(zip(grps, fars))
 
     for _ in range(args.warmup):
         one_pass()
@@ -188,7 +187,8 @@ def run_batched(args):
         "dtype": "int64", "data": "synthetic",
         "config": {"workload": "%s, %s lazy order" % (desc, args.order), "graphs": len(items),
                    "n_total": sum(g.n for g, _ in items), "nnz_total": sum(g.nnz for g, _ in items),
-                   "k_total": sum(k for _, k in items), "order": args.order, "block": args.block},
+                   "k_total": sum(k for _, k in items), "order": args.order, "block": args.block,
+                   "workers": many.workers},
         "evals": evals, "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -251,6 +251,30 @@ int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts, void *d_w
                     size_t ws_bytes, hipStream_t stream, int32_t *h_group, int64_t *h_farness,
                     gc_stats *h_stats);
 
+/*
+ * gc_greedy_many -- gc_greedy_group for `count` independent jobs (graph
+ * graphs[i], k[i]) run by `nworkers` host threads.  Worker w works on its own
+ * stream streams[w] with its own workspace d_ws[w] of ws_bytes[w] bytes (at
+ * least gc_workspace_size of every graph), which it re-initialises
+ * (gc_workspace_init) for each job; jobs go to the next free worker, largest
+ * graph first, so independent jobs overlap their launch latencies on the GPU.
+ * Every job gets the same picks as gc_greedy_group would give it alone.
+ *   count       >= 0 jobs; graphs[i] and k[i] as for gc_greedy_group
+ *   opts        NULL or one gc_opts for every job (nprefix must be 0, no log)
+ *   nworkers    1..64; streams must not be the null stream when nworkers > 1
+ *   h_group     host out int32[sum k]: job i's picks from offset k[0]+..+k[i-1]
+ *   h_farness   host out int64[sum k], same offsets
+ *   h_stats     NULL or host out gc_stats[count] (h_evals_per_round ignored)
+ * Returns when every job has ended: GC_OK, or the error of the lowest-numbered
+ * failed job (gc_last_error names it); the other jobs still run.  The graphs
+ * are only read; the workspaces and streams must not be used concurrently
+ * by anything else.
+ */
+int gc_greedy_many(int32_t count, const gc_graph *const *graphs, const int32_t *k,
+                   const gc_opts *opts, int32_t nworkers, void *const *d_ws, const size_t *ws_bytes,
+                   const hipStream_t *streams, int32_t *h_group, int64_t *h_farness,
+                   gc_stats *h_stats);
+
 /* --------------------------------------------- candidate-ordering MLP --- */
 /*
  * Not part of the paper's method: a small network that predicts marginal

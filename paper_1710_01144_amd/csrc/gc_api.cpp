@@ -1765,6 +1765,68 @@ extern "C" int gc_mlp_adam(float *d_master, float *d_m, float *d_v, const float 
     return GC_OK;
 }
 
+extern "C" int gc_greedy_many(int32_t count, const gc_graph *const *graphs, const int32_t *k,
+                              const gc_opts *opts, int32_t nworkers, void *const *d_ws,
+                              const size_t *ws_bytes, const hipStream_t *streams, int32_t *h_group,
+                              int64_t *h_farness, gc_stats *h_stats) {
+    if (count < 0) return fail(GC_EINVAL, "count < 0");
+    if (count == 0) return GC_OK;
+    if (!graphs || !k || !d_ws || !ws_bytes || !streams || !h_group || !h_farness)
+        return fail(GC_EINVAL, "NULL argument");
+    if (nworkers < 1 || nworkers > 64) return fail(GC_EINVAL, "nworkers = %d outside [1, 64]", nworkers);
+    if (opts && (opts->nprefix != 0 || opts->log_capacity > 0))
+        return fail(GC_EINVAL, "gc_greedy_many takes no prefix and no log");
+    for (int32_t w = 0; w < nworkers; ++w) {
+        if (!d_ws[w]) return fail(GC_EINVAL, "workspace %d is NULL", w);
+        if (nworkers > 1 && !streams[w]) return fail(GC_EINVAL, "worker %d on the null stream", w);
+    }
+    std::vector<int64_t> off((size_t)count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        if (!graphs[i]) return fail(GC_EINVAL, "graph %d is NULL", i);
+        if (k[i] < 1 || k[i] > graphs[i]->n) return fail(GC_EINVAL, "job %d: k = %d outside [1, n]", i, k[i]);
+        off[(size_t)i + 1] = off[(size_t)i] + k[i];
+    }
+    // largest graph first (ties by job index): the long jobs start early
+    std::vector<int32_t> order((size_t)count);
+    for (int32_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return graphs[a]->nnz + graphs[a]->n > graphs[b]->nnz + graphs[b]->n;
+    });
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::atomic<int32_t> next{0};
+    // a job no worker could take keeps this error
+    std::vector<int> rc((size_t)count, GC_EDEVICE);
+    std::vector<std::string> msg((size_t)count, std::string("not run: no worker could select the device"));
+    auto work = [&](int32_t w) {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        for (;;) {
+            const int32_t t = next.fetch_add(1);
+            if (t >= count) break;
+            const int32_t i = order[(size_t)t];
+            if (h_stats) h_stats[i].h_evals_per_round = nullptr;
+            int r = gc_workspace_init(graphs[i], d_ws[w], ws_bytes[w], streams[w]);
+            if (r == GC_OK)
+                r = gc_greedy_group(graphs[i], k[i], opts, d_ws[w], ws_bytes[w], streams[w],
+                                    h_group + off[(size_t)i], h_farness + off[(size_t)i],
+                                    h_stats ? &h_stats[i] : nullptr);
+            rc[(size_t)i] = r;
+            if (r != GC_OK) msg[(size_t)i] = g_last_error;
+        }
+    };
+    if (nworkers == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        th.reserve((size_t)nworkers);
+        for (int32_t w = 0; w < nworkers; ++w) th.emplace_back(work, w);
+        for (auto &t : th) t.join();
+    }
+    for (int32_t i = 0; i < count; ++i)
+        if (rc[(size_t)i] != GC_OK) return fail(rc[(size_t)i], "job %d: %s", i, msg[(size_t)i].c_str());
+    return GC_OK;
+}
+
 extern "C" int gc_node_features(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
                                 const int32_t *d_cand, int32_t count, const int64_t *d_ub,
                                 const int32_t *d_last_eval, const uint16_t *d_dist_at_eval,

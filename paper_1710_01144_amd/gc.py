@@ -37,7 +37,7 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_workspace_init", "gc_closest_node", "gc_update_dist", "gc_marginal_gains",
             "gc_gain_words", "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
-            "gc_node_features", "gc_timing_enable", "gc_timing_last_ms"]
+            "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many"]
 MLP_PARAMS = 4801
 MLP_IN = 8
 MLP_HIDDEN = 64
@@ -119,6 +119,11 @@ def load_library():
     lib.gc_greedy_group.argtypes = [vp, i32, ctypes.POINTER(GcOpts), vp, ctypes.c_size_t, vp,
                                     ctypes.POINTER(i32), ctypes.POINTER(i64),
                                     ctypes.POINTER(GcStats)]
+    lib.gc_greedy_many.restype = ctypes.c_int
+    lib.gc_greedy_many.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(GcOpts),
+                                   i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                   ctypes.POINTER(GcStats)]
     lib.gc_mlp_block_bytes.restype = ctypes.c_size_t
     lib.gc_mlp_block_bytes.argtypes = []
     lib.gc_mlp_pack.restype = ctypes.c_int
@@ -323,6 +328,57 @@ class Graph:
             c = int(min(log["count"][0], log_capacity))
             stats["log"] = {key: v[:c] for key, v in log.items() if key != "count"}
         return group, far, stats
+
+
+class Many:
+    """Runs many independent greedy jobs through gc_greedy_many: `workers`
+    host threads, each with its own stream and a workspace sized for the
+    largest graph (allocated here once and reused across calls)."""
+
+    def __init__(self, graphs, workers: int = 4):
+        self.graphs = list(graphs)
+        self.workers = max(1, min(int(workers), 64))
+        dev = self.graphs[0].row_ptr.device
+        need = max(G.workspace_size() for G in self.graphs)
+        self.ws = [torch.empty(need, dtype=torch.uint8, device=dev) for _ in range(self.workers)]
+        self.ws_bytes = need
+        # default-priority streams, one per worker
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(self.workers)]
+
+    def run(self, ks, order: str = "plain", block: int = 0, block_growth: int = 0,
+            mlp_params=None):
+        """(groups, farness, stats): per job, in the order of `graphs`."""
+        lib = load_library()
+        cnt = len(self.graphs)
+        ks = [int(k) for k in ks]
+        assert len(ks) == cnt
+        opts = GcOpts()
+        opts.order = ORDERS[order]
+        opts.bitset_width = 64
+        opts.block = int(block)
+        opts.block_growth = int(block_growth)
+        if mlp_params is not None:
+            opts.d_mlp = ctypes.c_void_p(mlp_params.data_ptr())
+        handles = (ctypes.c_void_p * cnt)(*[G.handle for G in self.graphs])
+        karr = (ctypes.c_int32 * cnt)(*ks)
+        ws = (ctypes.c_void_p * self.workers)(*[t.data_ptr() for t in self.ws])
+        wsb = (ctypes.c_size_t * self.workers)(*([self.ws_bytes] * self.workers))
+        st = (ctypes.c_void_p * self.workers)(*[s.cuda_stream for s in self.streams])
+        tot = sum(ks)
+        group = np.zeros(tot, dtype=np.int32)
+        far = np.zeros(tot, dtype=np.int64)
+        stats = (GcStats * cnt)()
+        # the jobs must see every earlier write of the caller's stream
+        torch.cuda.current_stream().synchronize()
+        _check(lib.gc_greedy_many(cnt, handles, karr, ctypes.byref(opts), self.workers, ws, wsb, st,
+                                  group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  far.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), stats))
+        out_g, out_f, off = [], [], 0
+        for k in ks:
+            out_g.append(group[off:off + k])
+            out_f.append(far[off:off + k])
+            off += k
+        return out_g, out_f, [stats[i].as_dict() for i in range(cnt)]
 
 
 class Mlp:

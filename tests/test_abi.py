@@ -38,3 +38,16 @@ def test_strerror_without_device():
     out = ctypes.c_void_p()
     assert lib.gc_load_csr(0, 0, None, None, 1, None, ctypes.byref(out)) == gc.GC_EINVAL
     assert lib.gc_load_csr(5, -1, None, None, 1, None, ctypes.byref(out)) == gc.GC_EINVAL
+
+
+def test_greedy_many_argument_checks_without_device():
+    from paper_1710_01144_amd import gc
+    lib = gc.load_library()
+    g = (ctypes.c_void_p * 1)()
+    k = (ctypes.c_int32 * 1)(1)
+    assert lib.gc_greedy_many(-1, g, k, None, 1, None, None, None, None, None, None) == gc.GC_EINVAL
+    # no jobs: nothing to do, nothing touched
+    assert lib.gc_greedy_many(0, None, None, None, 1, None, None, None, None, None, None) == gc.GC_OK
+    # NULL outputs and arrays are rejected before any device call
+    assert lib.gc_greedy_many(1, g, k, None, 1, None, None, None, None, None, None) == gc.GC_EINVAL
+    assert b"NULL" in lib.gc_last_error()

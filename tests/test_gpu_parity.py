@@ -327,3 +327,27 @@ def test_batched_ba_sample(gclib):
         if idx == order[0]:
             grp_a, F_a = oracle.greedy(g, k_g)
             assert grp_b.tolist() == grp_a.tolist() and F_b.tolist() == F_a.tolist()
+
+
+@pytest.mark.parametrize("workers", [1, 3])
+def test_greedy_many_matches_single_jobs(gclib, workers):
+    """gc_greedy_many: jobs of uneven size on several host threads and
+    streams give each job the group, farness and evaluation counts it gets
+    alone, and the CPU Greedy++ group."""
+    specs = [(graphgen.ba(4000, 3, 51), 12), (graphgen.ba(700, 2, 52), 5),
+             (graphgen.rmat(12, 16, 53), 20), (graphgen.ba(1500, 5, 54), 9),
+             (graphgen.grid(30, 25, 55), 7)]
+    Gs = [_graph(gclib, g) for g, _ in specs]
+    ks = [k for _, k in specs]
+    many = gclib.Many(Gs, workers=workers)
+    for order in ("plain", "celf"):
+        _note("greedy_many %d workers, %s" % (workers, order))
+        groups, fars, stats = many.run(ks, order=order)
+        for (g, k), G, grp, F, st in zip(specs, Gs, groups, fars, stats):
+            grp1, F1, st1 = G.greedy_group(k, order=order)
+            assert grp.tolist() == grp1.tolist() and F.tolist() == F1.tolist()
+            assert st["evals_total"] == st1["evals_total"]
+            if order == "plain":
+                grp_b, F_b, ev_b, _ = oracle.greedypp(g, k, block=64, growth=2)
+                assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+                assert st["evals_total"] == int(ev_b.sum())
