@@ -40,6 +40,7 @@ WORKLOADS = {
     "ba2000": ("Barabasi-Albert n=2000, m=4", "ba2000"),
     "rmat20": ("R-MAT scale 20, edge factor 16, largest component", "rmat20"),
     "grid1024": ("1024x1024 grid, 5% edges dropped, 0.1%*n shortcuts, largest component", "grid1024"),
+    "grid256": ("256x256 grid, 5% edges dropped, 0.1%*n shortcuts, largest component", "grid256"),
     "rmat24": ("R-MAT scale 24, edge factor 16, largest component", "rmat24"),
     "batchba": ("256 Barabasi-Albert graphs, n~U{1000..50000}, m~U{2..8}, k~U{5..50}, "
                 "SplitMix64 seeds from 3; jobs spread over host worker threads, each with its own stream "

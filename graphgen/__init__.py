@@ -245,13 +245,16 @@ def gnp_connected(n: int, p: float, seed: int) -> Graph:
 # --------------------------------------------------------- named workloads
 
 def workload(name: str) -> Graph:
-    """Graphs by workload name: ba2000, rmat16, rmat20, rmat24, grid1024."""
+    """Graphs by workload name: ba2000, rmat16, rmat20, rmat24, grid1024, and
+    grid256 (the grid recipe at 256 x 256)."""
     if name == "ba2000":
         return ba(2000, 4, 1)
     if name == "rmat16":
         return rmat(16, 16, 2)
     if name == "grid1024":
         return grid(1024, 1024, 4)
+    if name == "grid256":
+        return grid(256, 256, 7)
     if name == "rmat20":
         return rmat(20, 16, 5)
     if name == "rmat24":

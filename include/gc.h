@@ -80,8 +80,7 @@ typedef struct gc_opts {
     int32_t debug_checks;   /* 1: re-check F(S) == sum_w d(S,w) after every pick */
     int32_t block_growth;   /* each further launch of a round takes this many
                                times the block of the one before, up to
-                               16 x block (1..8; 0 = default: 2 for the plain
-                               and learned orders, 1 for CELF) */
+                               16 x block (1..8; 0 = default 2) */
     /* optional logging of every exact evaluation (host buffers, may be NULL):
        round, node, gain and the 8 MLP features at evaluation time */
     int64_t log_capacity;

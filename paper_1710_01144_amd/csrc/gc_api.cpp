@@ -1497,13 +1497,13 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     ArgTree keys;
     const bool plain_scan = o.order != GC_ORDER_CELF && !learned;
     // Each later launch of a round may take a larger block than the one
-    // before (up to kMaxBlockGrowth x block).  Default 2 for the plain and
-    // learned orders: the first block of a round sets a threshold, and what
-    // still passes it then goes in fewer, larger launches, which pays on a
-    // GPU where a launch of a few hundred candidates costs little more than
-    // one of 64.  CELF's first block nearly always ends the round.
+    // before (up to kMaxBlockGrowth x block); default 2.  The first block of
+    // a round sets a threshold, and what still passes it then goes in fewer,
+    // larger launches, which pays on a GPU where a launch of a few hundred
+    // candidates costs little more than one of 64 -- most on graphs whose
+    // rounds need thousands of evaluations (grids).
     constexpr int64_t kMaxBlockGrowth = 16;
-    const int32_t growth = o.block_growth > 0 ? o.block_growth : (o.order == GC_ORDER_CELF ? 1 : 2);
+    const int32_t growth = o.block_growth > 0 ? o.block_growth : 2;
     MaxTree tree;
     const int32_t first_gain_round = (int32_t)group.size();
     for (int32_t r = first_gain_round; r < k; ++r) {
@@ -1548,7 +1548,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     pool.swap(pending);
                     pending_round = -1;
                 }
-                while (pool.size() < (size_t)pool_size) {
+                // (the pool grows with the block)
+                while (pool.size() < (size_t)g->learned_pool * (size_t)blk) {
                     const int32_t u = keys.top();
                     if (u < 0 || !can_beat(u)) break;
                     keys.set(u, -1);
