@@ -650,6 +650,10 @@ struct HostIO {
     int64_t *hm_done = nullptr;
     volatile int64_t *h_done = nullptr;
     int64_t seq = 0;
+    // optional: max d(S,.) as last computed on the device (maxd_src), copied by
+    // the last launch to the host-mapped hm_maxd
+    const int32_t *maxd_src = nullptr;
+    int32_t *hm_maxd = nullptr;
     // device copies of the lazy-loop state (learned order features)
     int64_t *ub = nullptr;
     int32_t *last_eval = nullptr;
@@ -735,6 +739,8 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                 if (io->hm_done && off + a.nsrc >= count) {
                     a.h_done = io->hm_done;
                     a.seq = ++const_cast<HostIO *>(io)->seq;
+                    a.maxd_src = io->maxd_src;
+                    a.h_maxd = io->maxd_src ? io->hm_maxd : nullptr;
                 }
             }
             if (io && io->ub) {
@@ -1389,6 +1395,25 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         Fs.push_back(F);
         inS[v] = 1;
     }
+    // max d(S,.) bounds the levels a pruned BFS can claim (it never grows).
+    // On graphs of large eccentricity it is computed on the device after
+    // every update and copied to the host by the next gain launch, so later
+    // launches run only the levels that can still claim a node.  On small
+    // ones (R-MAT: 4) it rarely drops and the reduction would only add a
+    // kernel to every round.
+    constexpr int32_t kTrackMaxdFrom = 8;
+    const bool track_maxd = ecc_bound >= kTrackMaxdFrom;
+    volatile int32_t *h_maxd = hflag + 32;  // byte 128 of the flag page
+    *h_maxd = ecc_bound;
+    if (track_maxd) {
+        io.hm_maxd = dflag + 32;
+        io.maxd_src = w.maxd();
+        HIP_OK(launch_max_dist(d_dist, dist_bytes, n, w.maxd(), s));
+    }
+    auto nlev_now = [&]() {
+        const int32_t md = *h_maxd;
+        return std::max(std::min(ecc_bound, md) - 1, 0);
+    };
     if (st.h_evals_per_round)
         for (int32_t i = 0; i < k; ++i) st.h_evals_per_round[i] = 0;
     // rows split by d(S,.) of the first gain round: d(S,.) never grows, so the
@@ -1410,11 +1435,11 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
             r = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(),
                           want_edges ? w.aux() : nullptr, nullptr, s,
-                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr);
+                          nlev_now(), hg, want_edges ? he : nullptr);
         } else {
             r = run_gains(g, w, d_dist, dist_bytes, dc, cnt, w.gain(),
                           want_edges ? w.aux() : nullptr, nullptr, s,
-                          std::max(ecc_bound - 1, 0), hg, want_edges ? he : nullptr, &io, shape,
+                          nlev_now(), hg, want_edges ? he : nullptr, &io, shape,
                           &split);
         }
         if (r) return r;
@@ -1663,8 +1688,9 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         if (best_id < 0) return fail(GC_EINVAL, "no candidate left");
         // pick, then d(S,.) <- min(d(S,.), d(pick,.)) by pruned BFS
         t0 = now_ms();
-        rc = run_update_wide(g, w, best_id, d_dist, dist_bytes, w.far(), s, ecc_bound - 1, &split);
+        rc = run_update_wide(g, w, best_id, d_dist, dist_bytes, w.far(), s, nlev_now(), &split);
         if (rc) return rc;
+        if (track_maxd && r + 1 < k) HIP_OK(launch_max_dist(d_dist, dist_bytes, n, w.maxd(), s));
         F -= best_gain;
         if (o.debug_checks || r == k - 1) {
             // the update BFS tracks F(S) on its own: it must agree with the gains

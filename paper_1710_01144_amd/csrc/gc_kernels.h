@@ -122,6 +122,10 @@ struct WideArgs {
     int32_t *h_flag;
     int64_t *h_done;               // optional host-mapped word: = seq once everything is written
     int64_t seq;
+    // optional: the reset copies *maxd_src (a device value written before the
+    // launch) to the host-mapped *h_maxd ahead of the done word
+    const int32_t *maxd_src;
+    int32_t *h_maxd;
     // d(S,.) update mode: one source (the pick), distances written in place,
     // *far -= its gain at the end
     bool write;

@@ -616,6 +616,7 @@ __device__ __forceinline__ void reset_body(const WideArgs &a, int32_t nlev) {
         if (a.h_flag) *a.h_flag = 0;
         if (a.far) *a.far -= a.gain[0];  // update: F(S + s) = F(S) - g(s, S)
         *a.zcnt = 0ull;
+        if (a.h_maxd) *a.h_maxd = *a.maxd_src;
         if (a.h_done) {
             __threadfence_system();
             *reinterpret_cast<volatile int64_t *>(a.h_done) = a.seq;
