@@ -981,7 +981,10 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     // a batch logs each node once per distinct distance from its sources; the
     // hubs of one batch are close to each other, so plan for two per node and
     // let an overflow halve the launch
-    int64_t kb = std::max<int64_t>(1, std::min<int64_t>(w.L.kmax, w.L.cap / (2 * (int64_t)n + 64)));
+    // Chunks start at one batch and double up to kb_cap: the first sources
+    // set a best that the bounds cut the later, larger chunks against.
+    int64_t kb_cap = std::max<int64_t>(1, std::min<int64_t>(w.L.kmax, w.L.cap / (2 * (int64_t)n + 64)));
+    int64_t kb = 1;
     int32_t spb = 64;
     std::vector<int64_t> fo;
     std::vector<int32_t> chunk;
@@ -1046,7 +1049,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
                                    (size_t)(kMaxLevels + 2) * sizeof(WideLevel) / 4, 0u, s));
             HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.zcnt()), 2, 0u, s));
             HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
-            if (kb > 1) kb /= 2;
+            if (kb > 1) kb_cap = kb = kb / 2;
             else if (spb > 1) spb = std::max(1, spb / 2);
             else return fail(GC_EWORKSPACE, "frontier log too small for one source");
             pos = pos0;  // the filtered-out nodes before the chunk's end are checked again
@@ -1057,6 +1060,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
         HIP_OK(hipMemcpyAsync(fo.data(), a.far_out, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         nsources += cnt;
+        kb = std::min(kb * 2, kb_cap);
         for (int64_t i = 0; i < cnt; ++i) {
             if (fo[i] < 0) continue;
             if (fo[i] < bestF || (fo[i] == bestF && chunk[i] < best)) {
