@@ -670,13 +670,24 @@ struct LaunchShape {
     int32_t spb = 64; // sources per batch
 };
 
+// phase: kGainsRun launches and waits; kGainsLaunch only enqueues (one
+// launch over all candidates with host-mapped results: io->hm_done set and the
+// candidates fit one chunk; *queued tells whether it did, else it ran the
+// call through); kGainsWait then waits for that launch (redoing it on an
+// overflow) with the same arguments.
+enum GainsPhase { kGainsRun = 0, kGainsLaunch = 1, kGainsWait = 2 };
+
 int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
               const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
               int32_t *d_vis, hipStream_t s, int32_t nlev, int64_t *h_gain = nullptr,
               int64_t *h_edges = nullptr, const HostIO *io = nullptr,
               LaunchShape *shape = nullptr, const Split *split = nullptr,
-              bool timing_started = false) {
+              bool timing_started = false, int phase = kGainsRun, bool *queued = nullptr) {
+    if (queued) *queued = false;
     if (count <= 0) return GC_OK;
+    if (phase == kGainsLaunch && (g->wg_engine || nlev < 0 || !io || !io->hm_flag || !io->hm_done ||
+                                  (g->fused_grid > 0 && g->fused_gains)))
+        phase = kGainsRun;
     if (g->wg_engine) {
         int rc = run_gains_wg(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_vis, s);
         if (rc) return rc;
@@ -697,19 +708,22 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     nlev = std::min(nlev, kMaxLevels - 1);
     const bool mapped = io && io->hm_flag;
     const int grid = wide_grid(g);
-    if (g_timing && !timing_started) HIP_OK(hipEventRecord(g_ev0, s));
     const bool timed = io && io->ev0 && io->gpu_ms;
-    if (timed) HIP_OK(hipEventRecord(io->ev0, s));
+    if (phase != kGainsWait) {
+        if (g_timing && !timing_started) HIP_OK(hipEventRecord(g_ev0, s));
+        if (timed) HIP_OK(hipEventRecord(io->ev0, s));
+    }
     // batches per launch and sources per batch; a caller-kept shape carries
     // what an earlier overflow taught across calls
     int64_t kb = (shape && shape->kb > 0) ? std::min<int64_t>(shape->kb, w.L.kmax) : w.L.kmax;
     int32_t spb = shape ? shape->spb : 64;
+    if (phase == kGainsLaunch && count > kb * spb) phase = kGainsRun;
     int64_t done = 0;
     while (done < count) {
         // launch chunks of kb batches, then check the overflow flag once
         const int64_t per = kb * spb;
         int32_t tag = 0;
-        int64_t off = done;
+        int64_t off = phase == kGainsWait ? count : done;  // (already launched)
         while (off < count) {
             WideArgs a = w.wide();
             a.unroll = g->unroll;
@@ -759,8 +773,15 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             off += a.nsrc;
         }
         int32_t flag = 0;
-        if (g_timing) HIP_OK(hipEventRecord(g_ev1, s));
-        if (timed) HIP_OK(hipEventRecord(io->ev1, s));
+        if (phase != kGainsWait) {
+            if (g_timing) HIP_OK(hipEventRecord(g_ev1, s));
+            if (timed) HIP_OK(hipEventRecord(io->ev1, s));
+        }
+        if (phase == kGainsLaunch) {
+            if (queued) *queued = true;
+            return GC_OK;
+        }
+        phase = kGainsRun;  // an overflow below relaunches normally
         if (mapped) {
             // poll the done word (no wake-up latency of a blocking wait); an
             // overflow, a fault or a long launch ends up in the blocking wait
@@ -1519,6 +1540,12 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     std::vector<int32_t> pending;
     int32_t pending_round = -1;
     bool pending_scored = false;
+    // the next round's first block, chosen on the device from the scored pool
+    // and launched behind the update: 0 none, 1 queued, 2 already done
+    int first_state = 0;
+    int32_t first_cnt = 0, first_nlev = 0;
+    std::vector<int32_t> chosen;  // round in which a pooled node went into that block
+    if (learned) chosen.assign((size_t)n, -1);
     const int64_t pool_size = (int64_t)g->learned_pool * block;
     if (learned) HIP_OK(hipEventCreateWithFlags(&ev.score, hipEventDisableTiming));
     // CELF and learned: candidates keyed by (ub, -id); a candidate taken for
@@ -1552,11 +1579,33 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         cur_round = r;
         for (;;) {
             int32_t cnt = 0;
+            bool prelaunched = false;
             if (learned && !first_round) {
                 // the learned_pool x block largest bounds that can still win,
                 // best scored first; the rest go back into the tree unchanged
                 pool.clear();
-                if (pending_round == r) {
+                if (pending_round == r && first_state != 0) {
+                    // the round's first block is on the GPU already: wait for it,
+                    // cache the pool's scores and return the nodes it did not
+                    // take to the tree
+                    if (first_state == 1) {
+                        rc = run_gains(g, w, d_dist, dist_bytes, dc, first_cnt, w.gain(), w.aux(), nullptr, s,
+                                       first_nlev, hg, he, &io, &shape_later, &split, false, kGainsWait);
+                        if (rc) return rc;
+                    }
+                    for (size_t j = 0; pending_scored && j < pending.size(); ++j) {
+                        sc[pending[j]] = hscore[j];
+                        sc_round[pending[j]] = r;
+                    }
+                    for (int32_t j = 0; j < first_cnt; ++j) chosen[hc[j]] = r;
+                    for (const int32_t u : pending)
+                        if (chosen[u] != r) keys.set(u, ub[u]);
+                    cnt = first_cnt;
+                    prelaunched = true;
+                    pending.clear();
+                    pending_round = -1;
+                    first_state = 0;
+                } else if (pending_round == r) {
                     // the round's first pool, taken from the tree and scored
                     // behind the update that ended the last round
                     // (polled: a blocking wait adds its wake-up latency to every round)
@@ -1578,13 +1627,14 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     pending_round = -1;
                 }
                 // (the pool grows with the block)
-                while (pool.size() < (size_t)g->learned_pool * (size_t)blk) {
+                while (!prelaunched && pool.size() < (size_t)g->learned_pool * (size_t)blk) {
                     const int32_t u = keys.top();
                     if (u < 0 || !can_beat(u)) break;
                     keys.set(u, -1);
                     pool.push_back(u);
                 }
-                if (pool.size() <= (size_t)blk) {
+                if (prelaunched) {
+                } else if (pool.size() <= (size_t)blk) {
                     // the whole pool fits in the block: its order cannot matter
                     for (size_t j = 0; j < pool.size(); ++j) hc[cnt++] = pool[j];
                 } else {
@@ -1642,8 +1692,10 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 rc = features_of(dc, cnt, r, false);  // rows of hfeat in block order
                 if (rc) return rc;
             }
-            rc = evaluate(cnt);
-            if (rc) return rc;
+            if (!prelaunched) {
+                rc = evaluate(cnt);
+                if (rc) return rc;
+            }
             if (!first_round && growth > 1)
                 blk = (int32_t)std::min<int64_t>((int64_t)blk * growth, std::min<int64_t>((int64_t)kMaxBlockGrowth * block, n));
             if (logging && !first_round) {
@@ -1730,6 +1782,26 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 if (rc) return rc;
             }
             pending_round = r + 1;
+            // ... and, without logging, its first block: the block best
+            // scored, chosen on the device into the host-mapped candidate
+            // list, and its gain launch, all on the stream behind the update
+            if (!logging && !pending.empty() && pending.size() <= (size_t)kSelectMax) {
+                if (pending_scored) {
+                    first_cnt = block;
+                    HIP_OK(launch_select_top(dscore, dpool, (int32_t)pending.size(), first_cnt, dc, s));
+                } else {
+                    first_cnt = (int32_t)pending.size();
+                    for (int32_t j = 0; j < first_cnt; ++j) hc[j] = pending[(size_t)j];
+                }
+                io.round = r + 1;
+                first_nlev = nlev_now();
+                bool q = false;
+                rc = run_gains(g, w, d_dist, dist_bytes, dc, first_cnt, w.gain(), w.aux(), nullptr, s,
+                               first_nlev, hg, he, &io, &shape_later, &split, false, kGainsLaunch, &q);
+                if (rc) return rc;
+                st.gain_launches += 1;
+                first_state = q ? 1 : 2;
+            }
         }
     }
     for (int32_t i = 0; i < k; ++i) {

@@ -57,6 +57,12 @@ hipError_t launch_mlp_pack(const float *master, MlpBlock *p, hipStream_t s);
 hipError_t launch_mlp_adam(float *w, float *m, float *v, const float *g, int32_t step, float lr,
                            float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_features(const FeatArgs &a, int dist_bytes, hipStream_t s);
+// out[0..take) = the take ids of ids[0..count) with the largest scores
+// (score[i] belongs to ids[i]; ties to the smaller id), in that order.
+// count <= kSelectMax, take <= count; one workgroup.
+constexpr int kSelectMax = 4096;
+hipError_t launch_select_top(const float *score, const int32_t *ids, int32_t count, int32_t take,
+                             int32_t *out, hipStream_t s);
 hipError_t launch_twohop(const int32_t *rp, const int32_t *ci, int32_t n, float *out, hipStream_t s);
 
 }  // namespace gck

@@ -240,6 +240,44 @@ __global__ void k_twohop(const int32_t *rp, const int32_t *ci, int32_t n, float 
     out[v] = (float)acc;
 }
 
+// Top `take` of count (score, id) pairs by score descending, id ascending:
+// a bitonic sort of 64-bit keys in LDS.  The key puts the score's bits in an
+// order-preserving form in the high word (inverted, so that ascending keys
+// are descending scores) and the id in the low word.
+__global__ __launch_bounds__(1024) void k_select_top(const float *score, const int32_t *ids,
+                                                     int32_t count, int32_t take, int32_t *out) {
+    __shared__ unsigned long long key[kSelectMax];
+    int m = 1;
+    while (m < count) m <<= 1;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        unsigned long long k = ~0ull;
+        if (i < count) {
+            uint32_t u = __float_as_uint(score[i]);
+            u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // ascending as the float
+            k = ((unsigned long long)(~u) << 32) | (uint32_t)ids[i];
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= m; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < m; i += blockDim.x) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = key[i], b = key[j];
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < take; i += blockDim.x) out[i] = (int32_t)(uint32_t)key[i];
+}
+
 int grid_for(int64_t n, int bs) {
     int64_t g = (n + bs - 1) / bs;
     return (int)(g < 1 ? 1 : g);
@@ -288,6 +326,14 @@ hipError_t launch_features(const FeatArgs &a, int dist_bytes, hipStream_t s) {
         hipLaunchKernelGGL((k_features<uint8_t>), dim3(grid_for(a.count, 256)), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((k_features<uint16_t>), dim3(grid_for(a.count, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_top(const float *score, const int32_t *ids, int32_t count, int32_t take,
+                             int32_t *out, hipStream_t s) {
+    if (count < 0 || count > kSelectMax || take < 0 || take > count) return hipErrorInvalidValue;
+    if (take == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select_top, dim3(1), dim3(1024), 0, s, score, ids, count, take, out);
     return hipGetLastError();
 }
 
