@@ -23,6 +23,8 @@ def _graph(gclib, g):
 
 
 SMALL = [
+    lambda: graphgen.path(1),            # one node, no edges: k = n = 1
+    lambda: graphgen.path(2),
     lambda: graphgen.path(7),
     lambda: graphgen.path(300),          # eccentricity > 254: 16-bit distances
     lambda: graphgen.cycle(9),
@@ -340,11 +342,14 @@ def test_greedy_many_matches_single_jobs(gclib, workers):
     Gs = [_graph(gclib, g) for g, _ in specs]
     ks = [k for _, k in specs]
     many = gclib.Many(Gs, workers=workers)
-    for order in ("plain", "celf"):
+    from paper_1710_01144_amd import learned
+    net = gclib.Mlp(learned.init_master(5))
+    for order in ("plain", "celf", "learned"):
         _note("greedy_many %d workers, %s" % (workers, order))
-        groups, fars, stats = many.run(ks, order=order)
+        kw = {"mlp_params": net.block} if order == "learned" else {}
+        groups, fars, stats = many.run(ks, order=order, **kw)
         for (g, k), G, grp, F, st in zip(specs, Gs, groups, fars, stats):
-            grp1, F1, st1 = G.greedy_group(k, order=order)
+            grp1, F1, st1 = G.greedy_group(k, order=order, **kw)
             assert grp.tolist() == grp1.tolist() and F.tolist() == F1.tolist()
             assert st["evals_total"] == st1["evals_total"]
             if order == "plain":
