@@ -430,7 +430,6 @@ struct Ws {
     struct Mlp {
         float *feat;
         float *score;
-        float *twohop;
         int64_t *ub;
         int32_t *last_eval;
         uint16_t *dist_at_eval;
@@ -441,7 +440,6 @@ struct Ws {
         Mlp m;
         m.feat = reinterpret_cast<float *>(p); p += al((size_t)n * 8 * 4);
         m.score = reinterpret_cast<float *>(p); p += al((size_t)n * 4);
-        m.twohop = reinterpret_cast<float *>(p); p += al((size_t)n * 4);
         m.ub = reinterpret_cast<int64_t *>(p); p += al((size_t)n * 8);
         m.last_eval = reinterpret_cast<int32_t *>(p); p += al((size_t)n * 4);
         m.dist_at_eval = reinterpret_cast<uint16_t *>(p);
@@ -1508,7 +1506,6 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         fa.ub = mw.ub;
         fa.last_eval = mw.last_eval;
         fa.dist_at_eval = mw.dist_at_eval;
-        fa.twohop = nullptr;
         fa.two64 = w.two();
         fa.round = r;
         fa.k = k;
@@ -1949,7 +1946,6 @@ extern "C" int gc_node_features(const gc_graph *g, const void *d_dist, int32_t d
     fa.ub = d_ub;
     fa.last_eval = d_last_eval;
     fa.dist_at_eval = d_dist_at_eval;
-    fa.twohop = nullptr;
     fa.round = round;
     fa.k = k;
     fa.ecc1 = ecc1;

@@ -39,7 +39,6 @@ struct FeatArgs {
     const int64_t *ub;         // stale gain per node
     const int32_t *last_eval;  // round of the last evaluation (-1: never)
     const uint16_t *dist_at_eval;  // d(S,v) at that evaluation
-    const float *twohop;       // sum of neighbour degrees (null: two64, else computed)
     const int64_t *two64;      // the same as int64 (the workspace table), or null
     int32_t round, k, ecc1;
     float *feat;               // count x 8
@@ -63,7 +62,6 @@ hipError_t launch_features(const FeatArgs &a, int dist_bytes, hipStream_t s);
 constexpr int kSelectMax = 4096;
 hipError_t launch_select_top(const float *score, const int32_t *ids, int32_t count, int32_t take,
                              int32_t *out, hipStream_t s);
-hipError_t launch_twohop(const int32_t *rp, const int32_t *ci, int32_t n, float *out, hipStream_t s);
 
 }  // namespace gck
 

@@ -201,9 +201,7 @@ __global__ void k_features(FeatArgs a) {
     const int32_t rs = a.rp[v], re = a.rp[v + 1];
     const float deg = (float)(re - rs);
     float two = 0.f;
-    if (a.twohop) {
-        two = a.twohop[v];
-    } else if (a.two64) {
+    if (a.two64) {
         two = (float)a.two64[v];
     } else {
         int64_t acc = 0;
@@ -227,17 +225,6 @@ __global__ void k_features(FeatArgs a) {
     f[5] = dat - d;
     f[6] = (float)a.round / (float)(a.k > 0 ? a.k : 1);
     f[7] = log2f(1.f + d);
-}
-
-__global__ void k_twohop(const int32_t *rp, const int32_t *ci, int32_t n, float *out) {
-    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int64_t acc = 0;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-        const int32_t u = ci[e];
-        acc += rp[u + 1] - rp[u];
-    }
-    out[v] = (float)acc;
 }
 
 // Top `take` of count (score, id) pairs by score descending, id ascending:
@@ -337,16 +324,11 @@ hipError_t launch_select_top(const float *score, const int32_t *ids, int32_t cou
     return hipGetLastError();
 }
 
-hipError_t launch_twohop(const int32_t *rp, const int32_t *ci, int32_t n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_twohop, dim3(grid_for(n, 256)), dim3(256), 0, s, rp, ci, n, out);
-    return hipGetLastError();
-}
-
 }  // namespace gck
 
 size_t gc_mlp_ws_bytes(int64_t n) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    // features (n x 8), scores, two-hop sizes, device copies of the lazy state
-    return al((size_t)n * 8 * 4) + al((size_t)n * 4) + al((size_t)n * 4) + al((size_t)n * 8) +
-           al((size_t)n * 4) + al((size_t)n * 2);
+    // features (n x 8), scores, device copies of the lazy state
+    return al((size_t)n * 8 * 4) + al((size_t)n * 4) + al((size_t)n * 8) + al((size_t)n * 4) +
+           al((size_t)n * 2);
 }
