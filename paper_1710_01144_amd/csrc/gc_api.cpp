@@ -1289,8 +1289,9 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     std::vector<uint8_t> ds_at_eval;  // d(S,v) when v was last evaluated (features)
     // pinned host buffers the kernels read and write directly (no copy calls)
     PinnedBuf pin_cand, pin_gain, pin_flag;
-    if (pin_cand.ensure(sizeof(int32_t) * (size_t)n) != hipSuccess ||
-        pin_gain.ensure(sizeof(int64_t) * (size_t)n * 2) != hipSuccess ||
+    // (two sets: a block's bookkeeping overlaps the next block's launch)
+    if (pin_cand.ensure(sizeof(int32_t) * (size_t)n * 2) != hipSuccess ||
+        pin_gain.ensure(sizeof(int64_t) * (size_t)n * 4) != hipSuccess ||
         pin_flag.ensure(256) != hipSuccess)
         return fail(GC_ENOMEM, "pinned host buffers");
     int32_t *hc = reinterpret_cast<int32_t *>(pin_cand.p);
@@ -1574,9 +1575,39 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         int32_t pos = 0;
         io.round = r;
         cur_round = r;
+        // Plain and CELF, rounds >= 2: a block's launch is enqueued before the
+        // previous block's bookkeeping (stale gains, trees, counters) is done,
+        // so the host work overlaps the GPU's.  The next selection needs only
+        // the best gain, which is taken first; the deferred candidates are
+        // behind the plain scan's position or out of CELF's tree until then.
+        const bool overlap = !first_round && !learned && !logging && !g->wg_engine;
+        int dbuf = -1;        // buffer of the deferred block (-1: none)
+        int32_t dcnt = 0;
+        int cur = 0;          // buffer the next block goes to
+        int32_t *const hc_base = hc;
+        auto book = [&](int b, int32_t c) {
+            const int32_t *ids = hc_base + (size_t)b * n;
+            const int64_t *gs = hg + (size_t)b * 2 * n;
+            const int64_t *es = gs + n;
+            for (int32_t j = 0; j < c; ++j) {
+                const int32_t u = ids[j];
+                ub[u] = gs[j];
+                if (plain_scan) tree.set(u, gs[j]);
+                last_eval[u] = r;
+                st.edges_alg += es[j];
+                if (use_keys) keys.set(u, gs[j]);
+            }
+        };
         for (;;) {
             int32_t cnt = 0;
             bool prelaunched = false;
+            // the selection fills hc, redirected to the free buffer when overlapping
+            int32_t *const hc0 = hc;
+            if (overlap) hc = hc0 + (size_t)cur * n;
+            struct Restore {
+                int32_t *&p, *v;
+                ~Restore() { p = v; }
+            } restore_hc{hc, hc0};
             if (learned && !first_round) {
                 // the learned_pool x block largest bounds that can still win,
                 // best scored first; the rest go back into the tree unchanged
@@ -1689,6 +1720,41 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 rc = features_of(dc, cnt, r, false);  // rows of hfeat in block order
                 if (rc) return rc;
             }
+            if (overlap) {
+                int32_t *const dcl = dc + (size_t)cur * n;
+                io.hm_gain = dg + (size_t)cur * 2 * n;
+                io.hm_edges = io.hm_gain + n;
+                int64_t *const hgl = hg + (size_t)cur * 2 * n;
+                bool queued = false;
+                rc = run_gains(g, w, d_dist, dist_bytes, dcl, cnt, w.gain(), w.aux(), nullptr, s, nlev_now(),
+                               hgl, hgl + n, &io, &shape_later, &split, false, kGainsLaunch, &queued);
+                if (rc) return rc;
+                st.gain_launches += 1;
+                if (dbuf >= 0) book(dbuf, dcnt);
+                if (queued) {
+                    rc = run_gains(g, w, d_dist, dist_bytes, dcl, cnt, w.gain(), w.aux(), nullptr, s, nlev_now(),
+                                   hgl, hgl + n, &io, &shape_later, &split, false, kGainsWait);
+                    if (rc) return rc;
+                }
+                io.hm_gain = dg;
+                io.hm_edges = dg + n;
+                for (int32_t j = 0; j < cnt; ++j) {
+                    const int32_t u = hc[j];
+                    const int64_t gu = hgl[j];
+                    if (best_id < 0 || gu > best_gain || (gu == best_gain && u < best_id)) {
+                        best_gain = gu;
+                        best_id = u;
+                    }
+                }
+                nev += cnt;
+                dbuf = cur;
+                dcnt = cnt;
+                cur ^= 1;
+                if (growth > 1)
+                    blk = (int32_t)std::min<int64_t>((int64_t)blk * growth,
+                                                     std::min<int64_t>((int64_t)kMaxBlockGrowth * block, n));
+                continue;
+            }
             if (!prelaunched) {
                 rc = evaluate(cnt);
                 if (rc) return rc;
@@ -1720,6 +1786,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             }
             nev += cnt;
         }
+        if (dbuf >= 0) book(dbuf, dcnt);
         if (first_round && plain_scan) tree.build(ub, inS);
         if (first_round && (o.order == GC_ORDER_CELF || learned)) {
             keys.build(ub, inS, best_id);
