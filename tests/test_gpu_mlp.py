@@ -120,3 +120,20 @@ def test_learned_order_picks_and_evaluations(gclib, device):
         assert sl["evals_later"] < sp["evals_later"], (sl["evals_later"], sp["evals_later"])
         print("evals later: plain %d learned %d untrained %d" %
               (sp["evals_later"], sl["evals_later"], su["evals_later"]), flush=True)
+
+
+def test_learned_device_first_block_matches_host_ranking(gclib, device):
+    """The first block of each learned round is chosen on the device (top-k of
+    the scored pool, launched behind the update); with logging on it is ranked
+    on the host instead.  Both must evaluate the same candidates: the same
+    evaluation counts in every round and the same picks."""
+    from paper_1710_01144_amd import learned
+    net = gclib.Mlp(learned.init_master(17))
+    for g, k in [(graphgen.rmat(13, 16, 31), 25), (graphgen.ba(5000, 3, 32), 20)]:
+        G = gclib.Graph.from_graphgen(g)
+        _note("learned first block, device vs host, %s k=%d" % (g.name, k))
+        gd, Fd, sd = G.greedy_group(k, order="learned", mlp_params=net.block)
+        gh, Fh, sh = G.greedy_group(k, order="learned", mlp_params=net.block, log_capacity=1 << 16)
+        assert gd.tolist() == gh.tolist() and Fd.tolist() == Fh.tolist()
+        assert sd["evals_per_round"].tolist() == sh["evals_per_round"].tolist()
+        assert sd["gain_launches"] == sh["gain_launches"]
