@@ -1584,9 +1584,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         int dbuf = -1;        // buffer of the deferred block (-1: none)
         int32_t dcnt = 0;
         int cur = 0;          // buffer the next block goes to
-        int32_t *const hc_base = hc;
         auto book = [&](int b, int32_t c) {
-            const int32_t *ids = hc_base + (size_t)b * n;
+            const int32_t *ids = hc + (size_t)b * n;
             const int64_t *gs = hg + (size_t)b * 2 * n;
             const int64_t *es = gs + n;
             for (int32_t j = 0; j < c; ++j) {
@@ -1601,13 +1600,9 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         for (;;) {
             int32_t cnt = 0;
             bool prelaunched = false;
-            // the selection fills hc, redirected to the free buffer when overlapping
-            int32_t *const hc0 = hc;
-            if (overlap) hc = hc0 + (size_t)cur * n;
-            struct Restore {
-                int32_t *&p, *v;
-                ~Restore() { p = v; }
-            } restore_hc{hc, hc0};
+            // the CELF and plain selections fill `sel`: the free buffer when
+            // overlapping, else hc
+            int32_t *const sel = overlap ? hc + (size_t)cur * n : hc;
             if (learned && !first_round) {
                 // the learned_pool x block largest bounds that can still win,
                 // best scored first; the rest go back into the tree unchanged
@@ -1696,7 +1691,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     const int32_t u = keys.top();
                     if (u < 0 || !can_beat(u)) break;  // nothing below the top can either
                     keys.set(u, -1);
-                    hc[cnt++] = u;
+                    sel[cnt++] = u;
                 }
             } else if (first_round) {
                 for (; pos < n && cnt < blk; ++pos)
@@ -1712,7 +1707,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                         break;
                     }
                     pos = u + 1;
-                    if (can_beat(u)) hc[cnt++] = u;  // an equal bound with a larger id cannot
+                    if (can_beat(u)) sel[cnt++] = u;  // an equal bound with a larger id cannot
                 }
             }
             if (cnt == 0) break;
@@ -1739,7 +1734,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 io.hm_gain = dg;
                 io.hm_edges = dg + n;
                 for (int32_t j = 0; j < cnt; ++j) {
-                    const int32_t u = hc[j];
+                    const int32_t u = sel[j];
                     const int64_t gu = hgl[j];
                     if (best_id < 0 || gu > best_gain || (gu == best_gain && u < best_id)) {
                         best_gain = gu;
