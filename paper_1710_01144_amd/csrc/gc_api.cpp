@@ -104,6 +104,10 @@ struct gc_graph {
     int32_t level_wgs_per_cu;  // GC_LEVEL_WGS (workgroups per CU of a level kernel)
     int32_t unroll;         // GC_UNROLL (4 or 8)
     int32_t min_edges;      // GC_MIN_EDGES (adjacency entries per workgroup)
+    // the same two for gain launches of at most 1024 sources (later rounds):
+    // GC_UNROLL_SMALL, GC_MIN_EDGES_SMALL
+    int32_t unroll_small;
+    int32_t min_edges_small;
     int32_t learned_pool;   // GC_LEARNED_POOL: learned order ranks this many blocks of
                             // the largest bounds (1..16)
 };
@@ -308,6 +312,13 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
     if (const char *e = getenv("GC_MIN_EDGES")) {
         long v = strtol(e, nullptr, 10);
         if (v >= 16) g->min_edges = (int32_t)v;
+    }
+    g->unroll_small = 4;
+    if (const char *e = getenv("GC_UNROLL_SMALL")) g->unroll_small = strtol(e, nullptr, 10) >= 8 ? 8 : 4;
+    g->min_edges_small = 512;
+    if (const char *e = getenv("GC_MIN_EDGES_SMALL")) {
+        long v = strtol(e, nullptr, 10);
+        if (v >= 16) g->min_edges_small = (int32_t)v;
     }
     // frontier log: 16 entries per node, between 8M and 256M entries (20 bytes each)
     g->log_entries = std::min<int64_t>((int64_t)256 << 20, std::max<int64_t>((int64_t)8 << 20, 16LL * n));
@@ -733,6 +744,11 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             a.src = d_cand + off;
             a.nsrc = std::min<int64_t>(per, count - off);
             a.spb = spb;
+            if (a.nsrc <= 1024) {
+                // small launches: narrower steps keep more of each workgroup busy
+                a.unroll = g->unroll_small;
+                a.min_edges = g->min_edges_small;
+            }
             a.gain = d_gain + off;
             a.edges = d_edges ? d_edges + off : nullptr;
             a.visited = d_vis ? d_vis + off : nullptr;
