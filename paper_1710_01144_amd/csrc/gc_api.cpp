@@ -104,7 +104,8 @@ struct gc_graph {
     int32_t level_wgs_per_cu;  // GC_LEVEL_WGS (workgroups per CU of a level kernel)
     int32_t unroll;         // GC_UNROLL (4 or 8)
     int32_t min_edges;      // GC_MIN_EDGES (adjacency entries per workgroup)
-    // the same two for gain launches of at most 1024 sources (later rounds):
+    // the same two for gain launches of at most 1024 sources (later rounds)
+    // and the d(S,.) updates:
     // GC_UNROLL_SMALL, GC_MIN_EDGES_SMALL
     int32_t unroll_small;
     int32_t min_edges_small;
@@ -867,7 +868,7 @@ int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, 
                     int64_t *d_far, hipStream_t s, int32_t nlev, const Split *split = nullptr) {
     nlev = std::min(std::max(nlev, 0), kMaxLevels - 1);
     WideArgs a = w.wide();
-    a.unroll = g->unroll;
+    a.unroll = g->unroll_small;  // one source: a small launch
     a.min_edges = g->min_edges;
     a.rp = g->d_rp;
     a.ci = g->d_ci;
