@@ -109,8 +109,8 @@ struct gc_graph {
     // GC_UNROLL_SMALL, GC_MIN_EDGES_SMALL
     int32_t unroll_small;
     int32_t min_edges_small;
-    int32_t learned_pool;   // GC_LEARNED_POOL: learned order ranks this many blocks of
-                            // the largest bounds (1..16)
+    int32_t learned_pool_pct;  // GC_LEARNED_POOL_PCT: the learned order ranks the
+                               // largest bounds, this many percent of a block (110..1600)
 };
 
 extern "C" int32_t gc_graph_n(const gc_graph *g) { return g ? g->n : -1; }
@@ -304,10 +304,10 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         const long v = strtol(e, nullptr, 10);
         g->unroll = v >= 16 ? 16 : (v >= 8 ? 8 : 4);
     }
-    g->learned_pool = 2;
-    if (const char *e = getenv("GC_LEARNED_POOL")) {
+    g->learned_pool_pct = 110;
+    if (const char *e = getenv("GC_LEARNED_POOL_PCT")) {
         const long v = strtol(e, nullptr, 10);
-        if (v >= 1 && v <= 16) g->learned_pool = (int32_t)v;
+        if (v >= 110 && v <= 1600) g->learned_pool_pct = (int32_t)v;
     }
     g->min_edges = 512;
     if (const char *e = getenv("GC_MIN_EDGES")) {
@@ -1561,7 +1561,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     int32_t first_cnt = 0, first_nlev = 0;
     std::vector<int32_t> chosen;  // round in which a pooled node went into that block
     if (learned) chosen.assign((size_t)n, -1);
-    const int64_t pool_size = (int64_t)g->learned_pool * block;
+    auto pool_of = [&](int64_t b) { return std::max<int64_t>(b + 1, b * g->learned_pool_pct / 100); };
+    const int64_t pool_size = pool_of(block);
     if (learned) HIP_OK(hipEventCreateWithFlags(&ev.score, hipEventDisableTiming));
     // CELF and learned: candidates keyed by (ub, -id); a candidate taken for
     // evaluation leaves the tree and comes back with its new gain
@@ -1621,7 +1622,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             // overlapping, else hc
             int32_t *const sel = overlap ? hc + (size_t)cur * n : hc;
             if (learned && !first_round) {
-                // the learned_pool x block largest bounds that can still win,
+                // the pool_of(block) largest bounds that can still win,
                 // best scored first; the rest go back into the tree unchanged
                 pool.clear();
                 if (pending_round == r && first_state != 0) {
@@ -1667,7 +1668,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     pending_round = -1;
                 }
                 // (the pool grows with the block)
-                while (!prelaunched && pool.size() < (size_t)g->learned_pool * (size_t)blk) {
+                while (!prelaunched && pool.size() < (size_t)pool_of(blk)) {
                     const int32_t u = keys.top();
                     if (u < 0 || !can_beat(u)) break;
                     keys.set(u, -1);
