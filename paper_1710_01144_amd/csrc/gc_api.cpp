@@ -92,6 +92,10 @@ struct gc_graph {
     const int32_t *d_ci;
     std::vector<int32_t> h_rp;  // host copy of row_ptr (degrees, orders)
     std::vector<int32_t> by_degree;  // nodes by decreasing degree, ties ascending id
+    // source order of the closeness search and of the first gain round: balls
+    // of 64 nearby nodes (GC_BALLS=0: the degree order and ascending ids)
+    std::vector<int32_t> by_ball;
+    std::vector<int32_t> ball_rank;  // position of every node in by_ball
     int32_t max_deg;
     int32_t num_cu;
     // tuning read once at load time so the workspace layout never changes
@@ -100,6 +104,7 @@ struct gc_graph {
     int32_t fused_grid;     // workgroups of the one-kernel small launch (0: off; GC_FUSED, GC_FUSED_WGS)
     bool fused_gains;       // also for gain launches of <= 1024 sources (GC_FUSED_GAINS=1)
     int64_t log_entries;    // GC_LOG_ENTRIES
+    int64_t touch_entries;  // GC_TOUCH_ENTRIES (0: n per batch, at most 64M)
     bool wg_engine;         // GC_ENGINE=wg
     int32_t level_wgs_per_cu;  // GC_LEVEL_WGS (workgroups per CU of a level kernel)
     int32_t unroll;         // GC_UNROLL (4 or 8)
@@ -111,6 +116,8 @@ struct gc_graph {
     int32_t min_edges_small;
     int32_t learned_pool_pct;  // GC_LEARNED_POOL_PCT: the learned order ranks the
                                // largest bounds, this many percent of a block (110..1600)
+    bool balls;                // GC_BALLS (default on)
+    const std::vector<int32_t> &search_order() const { return balls ? by_ball : by_degree; }
 };
 
 extern "C" int32_t gc_graph_n(const gc_graph *g) { return g ? g->n : -1; }
@@ -188,6 +195,38 @@ static int validate_csr(int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
     return GC_OK;
 }
 
+// Nodes grouped into balls of up to 64: the first ball grows breadth-first
+// from the node of largest degree over nodes not yet taken, the next from the
+// largest-degree node left, and so on.  Sources of one 64-bit batch then lie
+// close together, so a node is reached by them at few distinct distances and
+// enters the batch's frontier few times (on a grid, a diamond of radius ~6
+// instead of a row segment of 64).  Any order gives the same exact results.
+static void ball_order(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                       const std::vector<int32_t> &by_degree, std::vector<int32_t> &out,
+                       std::vector<int32_t> &rank) {
+    out.clear();
+    out.reserve((size_t)n);
+    std::vector<uint8_t> taken((size_t)n, 0);
+    for (const int32_t seed : by_degree) {
+        if (taken[seed]) continue;
+        const size_t b0 = out.size();
+        taken[seed] = 1;
+        out.push_back(seed);
+        for (size_t h = b0; h < out.size() && out.size() - b0 < 64; ++h) {
+            const int32_t u = out[h];
+            for (int32_t e = rp[u]; e < rp[u + 1] && out.size() - b0 < 64; ++e) {
+                const int32_t v = ci[e];
+                if (!taken[v]) {
+                    taken[v] = 1;
+                    out.push_back(v);
+                }
+            }
+        }
+    }
+    rank.assign((size_t)n, 0);
+    for (int32_t i = 0; i < n; ++i) rank[(size_t)out[i]] = i;
+}
+
 extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
                            const int32_t *d_col_idx, uint32_t flags, hipStream_t stream,
                            gc_graph **out) {
@@ -228,8 +267,10 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         md = std::max(md, rp[u + 1] - rp[u]);
     }
     g->max_deg = md;
-    if (flags & GC_VALIDATE) {
-        std::vector<int32_t> ci;
+    g->balls = true;
+    if (const char *e = getenv("GC_BALLS")) g->balls = strcmp(e, "0") != 0;
+    std::vector<int32_t> ci;
+    if ((flags & GC_VALIDATE) || g->balls) {
         try {
             ci.resize((size_t)nnz);
         } catch (...) {
@@ -245,6 +286,8 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
                 return fail(GC_EDEVICE, "copying col_idx: %s", hipGetErrorString(e));
             }
         }
+    }
+    if (flags & GC_VALIDATE) {
         int rc = validate_csr(n, nnz, rp, ci);
         if (rc != GC_OK) {
             delete g;
@@ -266,6 +309,14 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
     std::stable_sort(g->by_degree.begin(), g->by_degree.end(), [&](int32_t x, int32_t y) {
         return (rp[x + 1] - rp[x]) > (rp[y + 1] - rp[y]);
     });
+    if (g->balls) {
+        try {
+            ball_order(n, rp, ci, g->by_degree, g->by_ball, g->ball_rank);
+        } catch (...) {
+            delete g;
+            return fail(GC_ENOMEM, "no memory for the ball order");
+        }
+    }
     g->wg_engine = false;
     if (const char *e = getenv("GC_ENGINE")) g->wg_engine = strcmp(e, "wg") == 0;
     g->slots_target = (g->wg_engine ? 4LL : 1LL) * cus;
@@ -327,6 +378,11 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->log_entries = v;
     }
+    g->touch_entries = 0;
+    if (const char *e = getenv("GC_TOUCH_ENTRIES")) {
+        long long v = strtoll(e, nullptr, 10);
+        if (v > 0) g->touch_entries = v;
+    }
     *out = g;
     return GC_OK;
 }
@@ -347,7 +403,8 @@ struct WsLayout {
     SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
     size_t vis_stride;  // words per batch
-    int64_t cap;        // frontier log entries
+    int64_t cap;        // frontier log entries (a ring: a power of two)
+    int64_t zcap;       // clean-up list entries
 };
 
 constexpr int32_t kMaxLevels = 65536;  // 16-bit distances: at most 65534 levels
@@ -401,13 +458,18 @@ WsLayout ws_layout(const gc_graph *g) {
     cap = std::max<int64_t>(cap, (int64_t)n + 128);
     // (a level holds fewer than 2^27 entries and 2^35 adjacency entries: the
     // append flags more as an overflow)
-    L.cap = cap;
+    int64_t ring = 1;
+    while (ring < cap) ring <<= 1;
+    L.cap = ring;
+    // the clean-up list names every touched record once: at most n per batch
+    L.zcap = g->touch_entries > 0 ? std::max<int64_t>(g->touch_entries, (int64_t)n + 128)
+                                  : std::max<int64_t>(cap, std::min<int64_t>(kmax * (int64_t)n, (int64_t)64 << 20));
     L.wvis = o; o += al256((size_t)kmax * L.vis_stride * 32);
-    L.ly = o; o += al256((size_t)cap * 4);
-    L.lr = o; o += al256((size_t)cap * 4);
-    L.lb = o; o += al256((size_t)cap * 4);
-    L.lo = o; o += al256((size_t)cap * 8);
-    L.lz = o; o += al256((size_t)cap * 8);
+    L.ly = o; o += al256((size_t)L.cap * 4);
+    L.lr = o; o += al256((size_t)L.cap * 4);
+    L.lb = o; o += al256((size_t)L.cap * 4);
+    L.lo = o; o += al256((size_t)L.cap * 8);
+    L.lz = o; o += al256((size_t)L.zcap * 8);
     L.lvl = o; o += al256((size_t)(kMaxLevels + 2) * sizeof(WideLevel));
     L.act = o; o += al256((size_t)kmax * 8);
     L.cutprev = o; o += al256(n * 16);
@@ -474,6 +536,7 @@ struct Ws {
         a.lz = reinterpret_cast<int64_t *>(base + L.lz);
         a.zcnt = reinterpret_cast<unsigned long long *>(zcnt());
         a.cap = L.cap;
+        a.zcap = L.zcap;
         a.lvl = reinterpret_cast<WideLevel *>(base + L.lvl);
         a.flags = flags();
         a.min_edges = 1024;
@@ -513,7 +576,7 @@ int64_t ws_stamp(const gc_graph *g) {
 
 // degree order and two-hop sums of the graph into the workspace, then the stamp
 int write_graph_tables(const gc_graph *g, const Ws &w, hipStream_t s) {
-    HIP_OK(hipMemcpyAsync(w.order(), g->by_degree.data(), sizeof(int32_t) * (size_t)g->n,
+    HIP_OK(hipMemcpyAsync(w.order(), g->search_order().data(), sizeof(int32_t) * (size_t)g->n,
                           hipMemcpyHostToDevice, s));
     HIP_OK(launch_twohop_i64(g->d_rp, g->d_ci, g->n, w.two(), s));
     HIP_OK(launch_set_i64(w.hdr(), ws_stamp(g), s));
@@ -950,8 +1013,9 @@ int run_full_bfs(const gc_graph *g, const Ws &w, int32_t root, uint16_t *dist16,
 //   deg(v) + 2*min(rem, two(v) - deg(v)) + 3*(rem - min(...)),  rem = n-1-deg(v),
 // (nodes at distance 2 are at most the adjacency of v's neighbours minus one
 // back-edge each; two(v) = sum of neighbour degrees), so nodes whose bound
-// exceeds the best are dropped on the host.  The rest run, by decreasing
-// degree and 64 to a batch, as full multi-source BFS on the device-wide engine
+// exceeds the best are dropped on the host.  The rest run 64 to a batch, in
+// ball order (balls seeded by decreasing degree; the degree order of the
+// paper's search with GC_BALLS=0), as full multi-source BFS on the device-wide engine
 // (distances from an all-INF array), each source cut as soon as its BFScut
 // bound exceeds the best farness found so far; the bound is re-applied on the
 // host between chunks as the best improves.  Ties: smallest id.
@@ -959,7 +1023,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
                 int64_t *sources, int32_t *ecc_out, int32_t *v0_out = nullptr) {
     const int32_t n = g->n;
     const auto &rp = g->h_rp;
-    const auto &order = g->by_degree;
+    const auto &order = g->search_order();
     const int32_t v0 = order[0];
     if (v0_out) *v0_out = v0;
     // full BFS from v0 in 16-bit distances (kept in dist16 for reuse)
@@ -1014,12 +1078,12 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     uint16_t *inf16 = reinterpret_cast<uint16_t *>(w.base + w.L.q1);
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(inf16), ((size_t)n * 2 + 3) / 4, 0xFFFFFFFFu, s));
     int64_t *dbest = reinterpret_cast<int64_t *>(w.ctr() + C_I64_BASE) + L_BEST_FAR;
-    // a batch logs each node once per distinct distance from its sources; the
-    // hubs of one batch are close to each other, so plan for two per node and
-    // let an overflow halve the launch
+    // a batch touches each record once (the clean-up list bounds the batches
+    // of a launch); the log holds three levels at a time, and an overflow of
+    // either halves the launch.
     // Chunks start at one batch and double up to kb_cap: the first sources
     // set a best that the bounds cut the later, larger chunks against.
-    int64_t kb_cap = std::max<int64_t>(1, std::min<int64_t>(w.L.kmax, w.L.cap / (2 * (int64_t)n + 64)));
+    int64_t kb_cap = std::max<int64_t>(1, std::min<int64_t>(w.L.kmax, w.L.zcap / ((int64_t)n + 64)));
     int64_t kb = 1;
     int32_t spb = 64;
     std::vector<int64_t> fo;
@@ -1058,8 +1122,10 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
         HIP_OK(launch_wide_begin(a, 2, 0, s));
         int32_t L = 0;
         bool overflow = false;
-        for (;;) {
-            const int32_t step = 4;
+        // levels between host checks: 4, then doubling up to 32 (a deep
+        // search waits less often; levels past the end find nothing to do)
+        int32_t step = 4;
+        for (;; step = std::min(step * 2, 32)) {
             for (int32_t i = 0; i < step && L + i < kMaxLevels - 1; ++i) {
                 HIP_OK(launch_wide_levels(a, 2, L + i, L + i + 1, grid, s));
                 HIP_OK(launch_wide_cut(a, L + i, dbest, s));
@@ -1712,8 +1778,12 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     sel[cnt++] = u;
                 }
             } else if (first_round) {
-                for (; pos < n && cnt < blk; ++pos)
-                    if (!inS[pos]) hc[cnt++] = pos;
+                // every candidate at once, packed into batches ball by ball
+                const int32_t *r1 = g->balls ? g->by_ball.data() : nullptr;
+                for (; pos < n && cnt < blk; ++pos) {
+                    const int32_t u = r1 ? r1[pos] : pos;
+                    if (!inS[u]) hc[cnt++] = u;
+                }
             } else {
                 // ascending ids that can still beat the best: the tree skips
                 // every id whose bound is below the best gain
@@ -1729,6 +1799,12 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 }
             }
             if (cnt == 0) break;
+            if (g->balls && !first_round && !learned && !logging && cnt > 64 && nlev_now() >= 32) {
+                // deep launches (high diameter): batches of nearby candidates
+                // share more frontier entries; results go back by position
+                const int32_t *rk = g->ball_rank.data();
+                std::sort(sel, sel + cnt, [rk](int32_t x, int32_t y) { return rk[x] < rk[y]; });
+            }
             if (logging && !first_round) {
                 rc = features_of(dc, cnt, r, false);  // rows of hfeat in block order
                 if (rc) return rc;

@@ -106,10 +106,11 @@ struct WideArgs {
     int32_t *lr;                   //               row start of the node
     int32_t *lb;                   //               batch
     int64_t *lo;                   //               first adjacency position (per level)
-    int64_t cap;                   // log capacity (entries)
+    int64_t cap;                   // log capacity (entries, a power of two: a ring)
     // clean-up list: every (batch << 32 | node) record the launch touches, named
     // once by the claim that finds its visited word empty
     int64_t *lz;
+    int64_t zcap;                  // capacity of lz (entries)
     unsigned long long *zcnt;      // entries in lz (zero between launches)
     WideLevel *lvl;                // per-level records, nlev + 2 of them
     int32_t *flags;                // [0]: nonzero after an overflow (value = tag)

@@ -65,13 +65,19 @@ __device__ __forceinline__ unsigned long long *rec(const WideArgs &a, int64_t b,
     return reinterpret_cast<unsigned long long *>(a.vis) + ((size_t)b * a.vis_stride + (size_t)y) * 4 + k;
 }
 
-__device__ __forceinline__ void log_entry(const WideArgs &a, int64_t pos, int32_t y, int32_t rs,
-                                          int32_t b, int64_t off) {
-    if (pos < a.cap) {
-        a.ly[pos] = y;
-        a.lr[pos] = rs;
-        a.lb[pos] = b;
-        a.lo[pos] = off;
+// The log is a ring of a.cap (a power of two) entries addressed by position
+// mod a.cap: positions grow through a launch, and only three levels are live
+// at a time (the one being cleared, the one being expanded, the one being
+// appended).  An append may not reach a.cap positions past the oldest live
+// entry, `live`.
+__device__ __forceinline__ void log_entry(const WideArgs &a, int64_t live, int64_t pos, int32_t y,
+                                          int32_t rs, int32_t b, int64_t off) {
+    if (pos - live < a.cap) {
+        const int64_t q = pos & (a.cap - 1);
+        a.ly[q] = y;
+        a.lr[q] = rs;
+        a.lb[q] = b;
+        a.lo[q] = off;
     } else {
         set_flag(a.flags, a.tag);
     }
@@ -95,8 +101,8 @@ __device__ __forceinline__ uint32_t load_d1(const WideArgs &a, int32_t y) {
 }
 
 // Wave-level append (every lane of a fully active wave calls it).
-__device__ __forceinline__ void push_wave(const WideArgs &a, WideLevel *nl, int64_t nbase, bool p,
-                                          int32_t y, int32_t rs, int32_t b, int32_t deg) {
+__device__ __forceinline__ void push_wave(const WideArgs &a, WideLevel *nl, int64_t nbase, int64_t live,
+                                          bool p, int32_t y, int32_t rs, int32_t b, int32_t deg) {
     const uint64_t bal = __ballot(p);
     if (bal == 0) return;
     const int lane = lane_id();
@@ -117,7 +123,7 @@ __device__ __forceinline__ void push_wave(const WideArgs &a, WideLevel *nl, int6
     }
     old = shfl64(old, 0);
     if (!p) return;
-    log_entry(a, nbase + (int64_t)(old >> kCntShift) + bits_below(bal), y, rs, b,
+    log_entry(a, live, nbase + (int64_t)(old >> kCntShift) + bits_below(bal), y, rs, b,
               (int64_t)(old & kMEdges) + (incl - dp));
 }
 
@@ -125,7 +131,7 @@ __device__ __forceinline__ void push_wave(const WideArgs &a, WideLevel *nl, int6
 // atomic reserves the slots and adjacency ranges of all of them.
 template <int U>
 __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int64_t nbase,
-                                           const bool *p, const int32_t *y, const int32_t *rs,
+                                           int64_t live, const bool *p, const int32_t *y, const int32_t *rs,
                                            const int32_t *bb, const int32_t *deg, int64_t *s_wc,
                                            int64_t *s_wd, uint64_t *s_old) {
     const int lane = lane_id();
@@ -180,14 +186,14 @@ __device__ __forceinline__ void push_block(const WideArgs &a, WideLevel *nl, int
 #pragma unroll
     for (int r = 0; r < U; ++r) {
         if (!p[r]) continue;
-        log_entry(a, nbase + idx, y[r], rs[r], bb[r], off);
+        log_entry(a, live, nbase + idx, y[r], rs[r], bb[r], off);
         idx += 1;
         off += deg[r];
     }
 }
 
 __device__ __forceinline__ void touch_entry(const WideArgs &a, int64_t pos, int32_t b, int32_t y) {
-    if (pos < a.cap) a.lz[pos] = ((int64_t)b << 32) | (uint32_t)y;
+    if (pos < a.zcap) a.lz[pos] = ((int64_t)b << 32) | (uint32_t)y;
     else set_flag(a.flags, a.tag);
 }
 
@@ -275,7 +281,7 @@ __device__ __forceinline__ void roots_body(const WideArgs &a, int64_t t) {
         }
     }
     touch_wave<1>(a, &touched, &b, &v);
-    push_wave(a, &a.lvl[0], 0, p, v, rs, b, deg);
+    push_wave(a, &a.lvl[0], 0, 0, p, v, rs, b, deg);
 }
 
 template <typename DistT, bool WRITE>
@@ -318,6 +324,9 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     const int64_t E = (int64_t)(me.packed & kMEdges);
     const int64_t start = me.start;
     const int64_t nbase = start + N;
+    const int64_t lmask = a.cap - 1;
+    // oldest live log entry: the previous level's (cleared by this kernel)
+    const int64_t live = L >= 1 ? pstart : start;
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) a.lvl[L + 1].start = nbase;
     const int fr_cur = 1 + L % 3, fr_next = 1 + (L + 1) % 3;
@@ -330,8 +339,10 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     // clears its share after its expansion.
     auto clear_prev = [&](int64_t w, int64_t nw) {
         const int fr_prev = 1 + (L + 2) % 3;
-        for (int64_t q = pstart + w * kWG + tid; q < start && q < a.cap; q += nw * kWG)
-            *rec(a, a.lb[q], a.ly[q], fr_prev) = 0ull;
+        for (int64_t q = pstart + w * kWG + tid; q < start; q += nw * kWG) {
+            const int64_t m = q & lmask;
+            *rec(a, a.lb[m], a.ly[m], fr_prev) = 0ull;
+        }
     };
     if ((int64_t)blockIdx.x >= G) {
         if (L >= 1) clear_prev((int64_t)blockIdx.x - G, (int64_t)gridDim.x - G);
@@ -366,7 +377,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
         int64_t lo = 0, hi = N - 1;
         while (lo < hi) {
             const int64_t p = lo + ((hi - lo) * tid) / 63;
-            const bool pr = a.lo[start + p] <= eb;
+            const bool pr = a.lo[(start + p) & lmask] <= eb;
             const uint64_t bal = __ballot(pr);
             const int last = 63 - __clzll((long long)bal);  // lane 0 always true
             const int64_t plast = lo + ((hi - lo) * last) / 63;
@@ -383,7 +394,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
         const int64_t cnt64 = N - i < kWin ? N - i : kWin;
         const int cnt = (int)cnt64;
         if (tid < cnt) {
-            const int64_t q = start + i + tid;
+            const int64_t q = (start + i + tid) & lmask;
             const int32_t b = a.lb[q];
             s_off[tid] = a.lo[q];
             s_rs[tid] = a.lr[q];
@@ -392,7 +403,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
             const uint64_t f = *rec(a, b, a.ly[q], fr_cur);
             s_m[tid] = a.active ? (f & a.active[b]) : f;
         }
-        if (tid == 0) s_off[cnt] = (i + cnt < N) ? a.lo[start + i + cnt] : E;
+        if (tid == 0) s_off[cnt] = (i + cnt < N) ? a.lo[(start + i + cnt) & lmask] : E;
         __syncthreads();
         const int64_t wlo = eb > s_off[0] ? eb : s_off[0];
         const int64_t whi = ee < s_off[cnt] ? ee : s_off[cnt];
@@ -521,7 +532,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
                 }
             }
             touch_wave<U>(a, tz, bb, y);
-            push_block<U>(a, next, nbase, p, y, rs, bb, deg, s_wc, s_wd, &s_old);
+            push_block<U>(a, next, nbase, live, p, y, rs, bb, deg, s_wc, s_wd, &s_old);
         }
         __syncthreads();
         if (whi >= ee || i + cnt >= N) break;
@@ -554,7 +565,7 @@ __device__ __forceinline__ void end_body(const WideArgs &a) {
         return;
     }
     int64_t tot = (int64_t)*a.zcnt;
-    if (tot > a.cap) tot = a.cap;
+    if (tot > a.zcap) tot = a.zcap;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = t0; i < tot; i += nt) {

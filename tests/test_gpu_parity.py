@@ -200,15 +200,18 @@ def test_greedy_block_growth(gclib):
             G.greedy_group(5, block_growth=bad)
 
 
-ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_ENGINE": "wg"},
-               {"GC_FUSED": "1", "GC_FUSED_GAINS": "1", "GC_FUSED_WGS": "64"}]
+ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_TOUCH_ENTRIES": "3000"},
+               {"GC_ENGINE": "wg"}, {"GC_FUSED": "1", "GC_FUSED_GAINS": "1", "GC_FUSED_WGS": "64"},
+               {"GC_BALLS": "0"}]
 
 
 @pytest.mark.parametrize("env", ENGINE_ENVS,
-                         ids=["default", "chunked", "log-overflow", "wg-engine", "fused"])
+                         ids=["default", "chunked", "log-overflow", "touch-overflow", "wg-engine", "fused",
+                              "id-order"])
 def test_engine_configurations(gclib, device, monkeypatch, env):
-    """Launch chunking, frontier-log overflow retries and the per-workgroup
-    engine all give the oracle's gains and greedy picks."""
+    """Launch chunking, overflow retries of the frontier ring and of the
+    clean-up list, the per-workgroup engine and the source order all give the
+    oracle's gains and greedy picks."""
     for key, v in env.items():
         monkeypatch.setenv(key, v)
     g = graphgen.rmat(12, 16, 7)
