@@ -1799,7 +1799,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 }
             }
             if (cnt == 0) break;
-            if (g->balls && !first_round && !learned && !logging && cnt > 64 && nlev_now() >= 32) {
+            if (g->balls && !first_round && !prelaunched && !logging && cnt > 64 && nlev_now() >= 32) {
                 // deep launches (high diameter): batches of nearby candidates
                 // share more frontier entries; results go back by position
                 const int32_t *rk = g->ball_rank.data();
