@@ -8,7 +8,7 @@ import this package.  It shares no code with the GPU library: the C part
 Contents
   * ``oracle.c`` / this module: tier A plain greedy (full BFS per candidate),
     tier B CPU Greedy++ (pruned BFS, lazy skip, BFScut), single gains,
-    group distances and farness.
+    group distances and farness, top-k closeness by definition.
   * ``small.py``: tier C -- Floyd-Warshall, brute force over k-subsets, the
     matrix form of the greedy of Chen et al., the bit-vector identity of the
     paper's theorem, all for tiny graphs.
@@ -130,6 +130,19 @@ def farness_all(g) -> np.ndarray:
     F = np.empty(n, dtype=np.int64)
     _check(_load().or_farness_all(n, rp, ci, F))
     return F
+
+
+def topk_closeness(g, k: int):
+    """Top-k closeness (the TopKCloseness search of Section 3.1 for general k):
+    the k nodes of least F({v}), in increasing (F({v}), v) order -- ties go to
+    the smaller id.  Written as its definition: every F({v}) by full BFS, then
+    a sort.  Returns (nodes int32[k], F int64[k])."""
+    n = int(g.n)
+    if k < 1 or k > n:
+        raise OracleError("k out of range")
+    F = farness_all(g)
+    order = np.lexsort((np.arange(n), F))[:k]
+    return order.astype(np.int32), F[order].astype(np.int64)
 
 
 def gain(g, dS, v: int) -> int:

@@ -102,6 +102,36 @@ def test_complete_bipartite(a, b):
     assert np.all(F[a:] == a + 2 * (b - 1))
 
 
+# top-k closeness: rankings the closed forms above fix
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 31])
+def test_topk_closeness_path(n):
+    g = graphgen.path(n)
+    # |v - (n-1)/2| orders the path's farness; ties (even n) to the smaller id
+    exp = sorted(range(n), key=lambda v: (abs(2 * v - (n - 1)), v))
+    for k in sorted({1, min(2, n), max(n // 2, 1), n}):
+        nodes, F = oracle.topk_closeness(g, k)
+        assert nodes.tolist() == exp[:k]
+        assert F.tolist() == [v * (v + 1) // 2 + (n - 1 - v) * (n - v) // 2 for v in exp[:k]]
+
+
+@pytest.mark.parametrize("n", [3, 6, 9])
+def test_topk_closeness_star_and_cycle(n):
+    nodes, F = oracle.topk_closeness(graphgen.star(n), n)
+    assert nodes.tolist() == list(range(n))
+    assert F.tolist() == [n - 1] + [2 * n - 3] * (n - 1)
+    nodes, F = oracle.topk_closeness(graphgen.cycle(n), 3)
+    assert nodes.tolist() == [0, 1, 2] and F.tolist() == [n * n // 4] * 3
+
+
+@pytest.mark.parametrize("a,b", [(2, 3), (3, 5), (4, 4)])
+def test_topk_closeness_complete_bipartite(a, b):
+    # the smaller side is closer (b + 2(a-1) < a + 2(b-1) when a < b)
+    nodes, _ = oracle.topk_closeness(graphgen.complete_bipartite(a, b), a + 1)
+    exp = list(range(a)) + [a] if a < b else list(range(a + 1))
+    assert nodes.tolist() == exp
+
+
 def _h(L):
     """Farness of L path nodes strictly between two group members."""
     return (L + 1) * (L + 1) // 4
@@ -180,6 +210,20 @@ def test_bfs_and_farness_vs_floyd_warshall(n, p, seed):
         S = rng.choice(n, size=k, replace=False).tolist()
         assert oracle.farness(g, S) == small.farness(D, S)
         assert np.array_equal(oracle.group_dist(g, S), D[S].min(axis=0))
+
+
+@pytest.mark.parametrize("n,p,seed", TINY)
+def test_topk_closeness_vs_floyd_warshall(n, p, seed):
+    g = graphgen.gnp_connected(n, p, seed)
+    D = small.floyd_warshall(g)
+    F = D.sum(axis=1)
+    exp = sorted(range(n), key=lambda v: (int(F[v]), v))
+    for k in (1, 3, n):
+        nodes, Fk = oracle.topk_closeness(g, k)
+        assert nodes.tolist() == exp[:k]
+        assert Fk.tolist() == [int(F[v]) for v in exp[:k]]
+    grp, _ = oracle.greedy(g, 1)
+    assert int(grp[0]) == exp[0]
 
 
 @pytest.mark.parametrize("n,p,seed", TINY)
