@@ -16,6 +16,8 @@ workload graph, inputs already resident in HBM.  Prints ONE JSON line:
   first_gain_round  the same for one call over all n-1 candidates;
   learned_vs_plain  the candidate-ordering network trained on plain-order
             logs, timed against plain, CELF and an untrained network;
+  overlap   share of the group among the k nodes of highest closeness
+            (gc_topk_closeness) and of highest degree;
   cpu_baseline  the CPU oracle's Greedy++ (tier B) on the same job, timed on
             this host's cores.
 """
@@ -69,6 +71,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU baseline: repeat the oracle run until this much time is spent")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the group vs top-k closeness/degree overlap (one top-k search)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-order comparison (training + four timed orders)")
     ap.add_argument("--learned-reps", type=int, default=3)
@@ -441,6 +445,22 @@ def main():
         % (cand.numel(), E1, V1, words["entries"], Ew, words["touched"], kern_ms, r1_gbs,
            E1 / kern_ms / 1e6, Ew / kern_ms / 1e6))
 
+    # ---- the group against the top-k closeness and top-k degree nodes
+    # (the overlap study of the paper's experiments, on this synthetic graph)
+    overlap = None
+    if not args.no_overlap:
+        t1 = time.perf_counter()
+        top_nodes, _ = G.topk_closeness(k)
+        topk_ms = 1000 * (time.perf_counter() - t1)
+        deg = np.diff(g.row_ptr).astype(np.int64)
+        top_deg = np.lexsort((np.arange(g.n), -deg))[:k]
+        grp_set = set(int(x) for x in grp)
+        overlap = {"k": k,
+                   "group_vs_topk_closeness_pct": round(100.0 * len(grp_set & set(top_nodes.tolist())) / k, 1),
+                   "group_vs_topk_degree_pct": round(100.0 * len(grp_set & set(top_deg.tolist())) / k, 1),
+                   "topk_closeness_ms": round(topk_ms, 3)}
+        log("overlap %s" % json.dumps(overlap))
+
     # ---- a plain copy of known size: measured bandwidth and counter scale
     copy_gbs = None
     if args.calib_bytes > 0:
@@ -512,6 +532,7 @@ def main():
                              "alg_bytes": r1_alg, "gbs": round(r1_gbs, 2), "words": words,
                              "gteps_alg": round(E1 / kern_ms / 1e6, 2),
                              "gteps_word": round(Ew / kern_ms / 1e6, 2)},
+        "overlap": overlap,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

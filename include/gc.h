@@ -171,15 +171,31 @@ int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_
  * gc_closest_node -- s_1 = argmin_v F({v}), the node of maximum closeness
  * c(v) = (n-1)/sum_w d(v,w) (Section 2), first line of the memory-efficient
  * greedy (Appendix, Algorithm "mem-greedy").  Found as in top-k closeness with
- * k = 1 (Section 3.1, Algorithm "topk"): sources visited by decreasing degree,
- * each BFS cut as soon as a lower bound on its farness exceeds the best
- * farness found.  Ties go to the smallest id.
+ * k = 1 (Section 3.1, Algorithm "topk"): a level-1 bound drops most nodes, the
+ * rest run as BFS in batches of 64 nearby nodes (balls seeded by decreasing
+ * degree), each BFS cut as soon as a lower bound on its farness exceeds the
+ * best farness found.  Ties go to the smallest id.
  *   h_node     host out: s_1
  *   h_farness  host out: F({s_1})
  * Synchronises the stream.
  */
 int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream,
                     int32_t *h_node, int64_t *h_farness);
+
+/*
+ * gc_topk_closeness -- the k nodes of maximum closeness, i.e. of least F({v}),
+ * in increasing (F({v}), v) order (top-k closeness, Section 3.1, Algorithm
+ * "topk", for general k; ties go to the smaller id).  The same search as
+ * gc_closest_node with the k-th best farness found so far as the cut
+ * threshold; no BFS is cut before k farness values are known.
+ *   k          1..n (else GC_EINVAL)
+ *   h_nodes    host out, k entries
+ *   h_farness  host out, k entries: F({h_nodes[i]})
+ * Uses the workspace as gc_closest_node does; synchronises the stream.
+ * Outputs are untouched on error.
+ */
+int gc_topk_closeness(const gc_graph *g, int32_t k, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                      int32_t *h_nodes, int64_t *h_farness);
 
 /*
  * gc_update_dist -- add `node` to S: d(S,.) <- min(d(S,.), d(node,.))

@@ -1019,8 +1019,13 @@ int run_full_bfs(const gc_graph *g, const Ws &w, int32_t root, uint16_t *dist16,
 // (distances from an all-INF array), each source cut as soon as its BFScut
 // bound exceeds the best farness found so far; the bound is re-applied on the
 // host between chunks as the best improves.  Ties: smallest id.
+// General k (top-k closeness): the cut threshold is the k-th best (F, id)
+// found so far, raised on the host between chunks only (a source's own
+// farness must not become the device's threshold), and no node is cut before
+// k farness values are known.  `top` receives the k best (F, id), ascending.
 int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, int64_t *far,
-                int64_t *sources, int32_t *ecc_out, int32_t *v0_out = nullptr) {
+                int64_t *sources, int32_t *ecc_out, int32_t *v0_out = nullptr, int32_t k = 1,
+                std::vector<std::pair<int64_t, int32_t>> *top_out = nullptr) {
     const int32_t n = g->n;
     const auto &rp = g->h_rp;
     const auto &order = g->search_order();
@@ -1041,9 +1046,19 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
         int rc2 = write_graph_tables(g, w, s);
         if (rc2) return rc2;
     }
-    int32_t best = v0;
-    int64_t bestF = F0;
-    // level-1 bound of every node against F0, on the device, in degree order;
+    // the k best (F, id) known, ascending; (bestF, best) is the k-th once k
+    // are known, else no bound
+    std::vector<std::pair<int64_t, int32_t>> top{{F0, v0}};
+    int32_t best = INT32_MAX;
+    int64_t bestF = INT64_MAX;
+    auto set_threshold = [&]() {
+        if ((int32_t)top.size() >= k) {
+            bestF = top[(size_t)k - 1].first;
+            best = top[(size_t)k - 1].second;
+        }
+    };
+    set_threshold();
+    // level-1 bound of every node against the threshold, on the device, in search order;
     // the bounds of the survivors come back to re-test them as the best improves
     uint8_t *keep_d = reinterpret_cast<uint8_t *>(w.base + w.L.q0);
     HIP_OK(launch_lb1_filter(w.order(), g->d_rp, w.two(), n, bestF, best, keep_d, w.aux(), s));
@@ -1128,7 +1143,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
         for (;; step = std::min(step * 2, 32)) {
             for (int32_t i = 0; i < step && L + i < kMaxLevels - 1; ++i) {
                 HIP_OK(launch_wide_levels(a, 2, L + i, L + i + 1, grid, s));
-                HIP_OK(launch_wide_cut(a, L + i, dbest, s));
+                HIP_OK(launch_wide_cut(a, L + i, dbest, k > 1, s));
             }
             L = std::min(L + step, kMaxLevels - 1);
             WideLevel rec;
@@ -1166,8 +1181,10 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
         for (int64_t i = 0; i < cnt; ++i) {
             if (fo[i] < 0) continue;
             if (fo[i] < bestF || (fo[i] == bestF && chunk[i] < best)) {
-                bestF = fo[i];
-                best = chunk[i];
+                const std::pair<int64_t, int32_t> e{fo[i], chunk[i]};
+                top.insert(std::upper_bound(top.begin(), top.end(), e), e);
+                if ((int32_t)top.size() > k) top.pop_back();
+                set_threshold();
             }
         }
         if (verbose && now_ms() - t_print > 2000.0) {
@@ -1178,8 +1195,11 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
             fflush(stderr);
         }
     }
-    *node = best;
-    *far = bestF;
+    if ((int32_t)top.size() < k) return fail(GC_EDEVICE, "closeness search ended with %zu of %d nodes",
+                                             top.size(), k);
+    *node = top[0].second;
+    *far = top[0].first;
+    if (top_out) *top_out = top;
     if (sources) *sources = nsources;
     if (ecc_out) *ecc_out = last;
     return GC_OK;
@@ -1199,6 +1219,25 @@ extern "C" int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, h
     if (rc) return rc;
     *h_node = node;
     *h_farness = far;
+    return GC_OK;
+}
+
+extern "C" int gc_topk_closeness(const gc_graph *g, int32_t k, void *d_ws, size_t ws_bytes,
+                                 hipStream_t stream, int32_t *h_nodes, int64_t *h_farness) {
+    Ws w;
+    int rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    if (!h_nodes || !h_farness) return fail(GC_EINVAL, "NULL output");
+    if (k < 1 || k > g->n) return fail(GC_EINVAL, "k = %d out of range 1..%d", k, g->n);
+    int32_t node;
+    int64_t far;
+    std::vector<std::pair<int64_t, int32_t>> top;
+    rc = run_closest(g, w, stream, &node, &far, nullptr, nullptr, nullptr, k, &top);
+    if (rc) return rc;
+    for (int32_t i = 0; i < k; ++i) {
+        h_nodes[i] = top[(size_t)i].second;
+        h_farness[i] = top[(size_t)i].first;
+    }
     return GC_OK;
 }
 

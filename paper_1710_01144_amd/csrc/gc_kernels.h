@@ -165,7 +165,7 @@ hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, con
                             hipStream_t s);
 // After level L: BFScut test for every live source of a closeness launch
 // (distances from an all-INF 16-bit array, so F = reached*65535 - gain).
-hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, hipStream_t s);
+hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, bool fixed, hipStream_t s);
 // Whole launch (roots, up to nlev levels, clean-up, reset) as one cooperative
 // kernel, for launches of at most 1024 sources; grid <= fused_max_grid().
 hipError_t launch_wide_fused(const WideArgs &a, int dist_bytes, int32_t nlev, int grid, hipStream_t s);

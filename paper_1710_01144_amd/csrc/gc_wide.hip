@@ -673,7 +673,9 @@ __global__ __launch_bounds__(256) void k_wide_fused(WideArgs a, int32_t nlev) {
 // the rem = n - r others at most ef (adjacency entries of the distance-(L+1)
 // nodes, minus one back-edge each) are at distance L+2, the rest are farther.
 // A source whose bound exceeds the best farness known is dropped.
-__global__ void k_wide_cut(WideArgs a, int32_t L, int64_t *best) {
+// fixed: *best is a threshold set by the host (top-k with k > 1), not
+// lowered by finished sources.
+__global__ void k_wide_cut(WideArgs a, int32_t L, int64_t *best, int32_t fixed) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= a.nsrc) return;
     const int64_t b = t / a.spb;
@@ -688,7 +690,7 @@ __global__ void k_wide_cut(WideArgs a, int32_t L, int64_t *best) {
     const int64_t sum = r * 65535 - a.gain[t];
     if (r == a.n) {
         a.far_out[t] = sum;
-        atomicMin(reinterpret_cast<unsigned long long *>(best), (unsigned long long)sum);
+        if (!fixed) atomicMin(reinterpret_cast<unsigned long long *>(best), (unsigned long long)sum);
         atomicAnd(&a.active[b], ~bit);
         return;
     }
@@ -923,9 +925,9 @@ hipError_t launch_wide_fused(const WideArgs &a, int dist_bytes, int32_t nlev, in
     return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kWG), params, 0, s);
 }
 
-hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, hipStream_t s) {
+hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, bool fixed, hipStream_t s) {
     const int g = (int)((a.nsrc + 255) / 256);
-    hipLaunchKernelGGL(k_wide_cut, dim3(g < 1 ? 1 : g), dim3(256), 0, s, a, L, best);
+    hipLaunchKernelGGL(k_wide_cut, dim3(g < 1 ? 1 : g), dim3(256), 0, s, a, L, best, (int32_t)fixed);
     return hipGetLastError();
 }
 

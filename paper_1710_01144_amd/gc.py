@@ -37,7 +37,8 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_workspace_init", "gc_closest_node", "gc_update_dist", "gc_marginal_gains",
             "gc_gain_words", "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
-            "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many"]
+            "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many",
+            "gc_topk_closeness"]
 MLP_PARAMS = 4801
 MLP_IN = 8
 MLP_HIDDEN = 64
@@ -107,6 +108,9 @@ def load_library():
     lib.gc_workspace_init.restype = ctypes.c_int
     lib.gc_workspace_init.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.gc_closest_node.restype = ctypes.c_int
+    lib.gc_topk_closeness.restype = ctypes.c_int
+    lib.gc_topk_closeness.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32),
+                                      ctypes.POINTER(ctypes.c_int64)]
     lib.gc_closest_node.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32),
                                     ctypes.POINTER(i64)]
     lib.gc_update_dist.restype = ctypes.c_int
@@ -240,6 +244,16 @@ class Graph:
         _check(load_library().gc_closest_node(self.handle, _ptr(self.ws), self.ws_bytes, _stream(),
                                               ctypes.byref(node), ctypes.byref(far)))
         return int(node.value), int(far.value)
+
+    def topk_closeness(self, k: int):
+        """The k nodes of least F({v}) and their farness, ascending (F, id)."""
+        nodes = np.zeros(int(k), dtype=np.int32)
+        far = np.zeros(int(k), dtype=np.int64)
+        _check(load_library().gc_topk_closeness(
+            self.handle, int(k), _ptr(self.ws), self.ws_bytes, _stream(),
+            nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            far.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return nodes, far
 
     def new_dist(self, dist_bytes: int = 1):
         """A d(S,.) buffer for S = {} (all INF), padded to whole 4-byte words."""

@@ -49,6 +49,24 @@ def test_closest_node_small(gclib, mk):
     assert (s, f) == (s_ref, int(F[s_ref]))
 
 
+@pytest.mark.parametrize("mk", SMALL + [lambda: graphgen.rmat(12, 16, 7), lambda: graphgen.grid(64, 64, 4)],
+                         ids=lambda f: "topk")
+def test_topk_closeness(gclib, mk):
+    """Top-k closeness for several k, including k = n on the small graphs:
+    nodes and farness equal the definition's ranking."""
+    g = mk()
+    G = _graph(gclib, g)
+    for k in sorted({1, min(3, g.n), min(25, g.n)} | ({g.n} if g.n <= 300 else set())):
+        _note("topk %s k=%d" % (g.name, k))
+        nodes, F = G.topk_closeness(k)
+        nodes_ref, F_ref = oracle.topk_closeness(g, k)
+        assert nodes.tolist() == nodes_ref.tolist() and F.tolist() == F_ref.tolist()
+    for bad in (0, g.n + 1):
+        with pytest.raises(gclib.GCError):
+            G.topk_closeness(bad)
+    assert G.closest_node() == (int(nodes_ref[0]), int(F_ref[0]))
+
+
 @pytest.mark.parametrize("mk", SMALL, ids=lambda f: "small")
 def test_greedy_small(gclib, mk):
     g = mk()
