@@ -132,11 +132,14 @@ typedef struct gc_stats {
  *   nnz        entries of d_col_idx = 2|E| (each undirected edge stored twice)
  *   d_row_ptr  device int32[n+1], d_row_ptr[0] = 0, d_row_ptr[n] = nnz
  *   d_col_idx  device int32[nnz], each row strictly ascending
- *   flags      GC_VALIDATE: copy the CSR to the host once and check it --
- *              GC_EINVAL for a bad row_ptr, an id out of range, an unsorted
- *              row, a self-loop or a duplicate; GC_ENOTSYM for a missing
- *              reverse edge; GC_EDISCONNECTED if not connected.
- *   stream     used for the copies
+ *   flags      GC_VALIDATE: check the CSR on the host -- GC_EINVAL for a bad
+ *              row_ptr, an id out of range, an unsorted row, a self-loop or a
+ *              duplicate; GC_ENOTSYM for a missing reverse edge;
+ *              GC_EDISCONNECTED if not connected.
+ *   stream     used for the copies: the CSR is copied to the host once (the
+ *              degree order and the balls of nearby nodes that batch the
+ *              closeness search are built there; host memory 4(n + nnz)
+ *              bytes while loading)
  *   out        receives the handle (free with gc_free_graph)
  * The handle borrows the two device arrays: they must stay valid and
  * unchanged until gc_free_graph.  The handle may be used from several host

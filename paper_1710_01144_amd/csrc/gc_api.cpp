@@ -478,7 +478,7 @@ WsLayout ws_layout(const gc_graph *g) {
     L.cisplit = o; o += al256((size_t)g->nnz * 4 + 4);
     L.rinfo = o; o += al256(n * 16);
     L.dist1 = o; o += al256(n * 2 + 4);
-    // graph tables written by gc_workspace_init: nodes by decreasing degree
+    // graph tables written by gc_workspace_init: the closeness search order
     // and the sum of neighbour degrees of every node
     L.order = o; o += al256(n * 4);
     L.two = o; o += al256(n * 8);
@@ -574,7 +574,7 @@ int64_t ws_stamp(const gc_graph *g) {
     return (int64_t)(0x4743575350414345ull ^ ((uint64_t)g->n << 1) ^ ((uint64_t)g->nnz << 29));
 }
 
-// degree order and two-hop sums of the graph into the workspace, then the stamp
+// search order and two-hop sums of the graph into the workspace, then the stamp
 int write_graph_tables(const gc_graph *g, const Ws &w, hipStream_t s) {
     HIP_OK(hipMemcpyAsync(w.order(), g->search_order().data(), sizeof(int32_t) * (size_t)g->n,
                           hipMemcpyHostToDevice, s));
@@ -1040,7 +1040,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     HIP_OK(hipMemcpyAsync(&stamp, w.hdr(), sizeof(stamp), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (last >= 65535) return fail(GC_ERANGE, "a node is 65535 or more hops from node %d", v0);
-    // the degree order and two-hop sums come from gc_workspace_init; a
+    // the search order and two-hop sums come from gc_workspace_init; a
     // workspace without its stamp gets them now
     if (stamp != ws_stamp(g)) {
         int rc2 = write_graph_tables(g, w, s);
