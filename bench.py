@@ -103,10 +103,11 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(workload: str, k: int, order: str):
-    """HBM bytes per gain launch of the greedy job from the committed
+    """HBM bytes of the greedy job's gain launches from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE over the job's gain
-    launches, each scaled by what the counter reads for a 1 GiB copy), or None
-    if there is none for this job or the kernel sources changed since."""
+    launches, each scaled by what the counter reads for a 1 GiB copy), per
+    job, or None if there is none for this job or the kernel sources changed
+    since."""
     path = os.path.join(ROOT, "profiles", "k_wide_gain_%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None
@@ -116,7 +117,7 @@ def measured_traffic(workload: str, k: int, order: str):
         return None
     if rec.get("k") != k or rec.get("order") != order:
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec.get("traffic_bytes_per_job")
 
 
 def alg_bytes_of(entries_expanded, edges, touched, dist_bytes):
@@ -264,8 +265,9 @@ def reduce_profile(prefix, workload, k, order, out_dir, jobs):
     --warmup 0): the top kernels by time, and the HBM bytes of the greedy job's
     gain launches.  The job is every dispatch before the first k_bfs_level (the
     bench's own d(S,.) update that follows it); its gain launches run from a
-    k_wide_roots<., false> dispatch through the next k_wide_reset.  Each
-    counter is scaled by what it reads for the bench's 1 GiB device copy.
+    k_wide_roots<., false> dispatch through the next k_wide_reset, except the
+    closeness search's (they contain k_wide_cut).  Each counter is scaled by
+    what it reads for the bench's 1 GiB device copy.
     `jobs` greedy jobs run before that update (the counter runs' warm-up and
     timed steps plus the event-timed job), all the same job."""
     import collections
@@ -286,15 +288,20 @@ def reduce_profile(prefix, workload, k, order, out_dir, jobs):
         end = next(i for i, (name, _) in enumerate(disp) if "k_bfs_level" in name)
         gain, kib, launches = False, 0.0, 0
         by = collections.defaultdict(float)
+        seq = []  # (kernel, KiB) of the open sequence
         for name, val in disp[:end]:
             if "k_wide_roots" in name:
                 gain = "false>" in name
-                launches += gain
+                seq = []
             if gain and "k_wide_" in name:
-                kib += val
-                by[_short_kernel(name)] += val
-            if "k_wide_reset" in name:
+                seq.append((_short_kernel(name), val))
+            if "k_wide_reset" in name and gain:
                 gain = False
+                if not any("k_wide_cut" in kname for kname, _ in seq):
+                    launches += 1
+                    for kname, v in seq:
+                        kib += v
+                        by[kname] += v
         job[counter] = {"copy_kib": copy_kib, "scale": scale, "bytes": kib * 1024 * scale,
                         "launches": launches, "by_kernel": by}
     rec = {"workload": workload, "k": k, "order": order, "jobs": jobs,
@@ -303,8 +310,7 @@ def reduce_profile(prefix, workload, k, order, out_dir, jobs):
            "fetch_scale": round(job["FETCH_SIZE"]["scale"], 4),
            "write_scale": round(job["WRITE_SIZE"]["scale"], 4),
            "kernel_source_sha256_16": kernel_source_hash()}
-    rec["traffic_bytes_per_launch"] = round((rec["fetch_bytes"] + rec["write_bytes"]) /
-                                            max(rec["launches"], 1), 1)
+    rec["traffic_bytes_per_job"] = round((rec["fetch_bytes"] + rec["write_bytes"]) / max(jobs, 1), 1)
     os.makedirs(out_dir, exist_ok=True)
     base = os.path.join(out_dir, "k_wide_gain_%s" % workload)
     with open(base + "_traffic.json", "w") as f:
@@ -313,11 +319,11 @@ def reduce_profile(prefix, workload, k, order, out_dir, jobs):
         f.write("top kernels by time (kernel trace run):\n" + "\n".join(lines) + "\n")
         for counter in ("FETCH_SIZE", "WRITE_SIZE"):
             j = job[counter]
-            f.write("%s: 1 GiB copy reads %.1f KiB (scale %.4f); %d jobs: %d gain launches, %.1f MB\n" % (
+            f.write("%s: 1 GiB copy reads %.1f KiB (scale %.4f); %d jobs: %d gain kernel sequences, %.1f MB\n" % (
                 counter, j["copy_kib"], j["scale"], jobs, j["launches"], j["bytes"] / 1e6))
             for name, v in sorted(j["by_kernel"].items(), key=lambda kv: -kv[1]):
                 f.write("    %-68s %10.1f MB\n" % (name, v * 1024 * j["scale"] / 1e6))
-        f.write("HBM traffic per gain launch: %.1f KB\n" % (rec["traffic_bytes_per_launch"] / 1e3))
+        f.write("HBM traffic of the gain launches per job: %.1f MB\n" % (rec["traffic_bytes_per_job"] / 1e6))
     print(open(base + "_reduced.txt").read())
 
 
@@ -408,7 +414,10 @@ def main():
     if gain_gpu_ms <= 0:
         raise SystemExit("the library timed no gain launch (the per-workgroup engine is not timed)")
     achieved = job_alg / (gain_gpu_ms / 1000.0) / 1e9
-    traffic = measured_traffic(args.workload, k, args.order)
+    traffic_job = measured_traffic(args.workload, k, args.order)
+    # per gain call of the library (a first-round call may run several kernel
+    # sequences; the job's bytes are divided like its algorithmic bytes)
+    traffic = round(traffic_job / launches, 1) if traffic_job else None
     log("gain launches of the job: %d launches, %.3f ms GPU (%.2f us each), %d bytes algorithmic, "
         "%.1f GB/s" % (launches, gain_gpu_ms, 1000 * gain_gpu_ms / launches, job_alg, achieved))
 
