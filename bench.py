@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU baseline: repeat the oracle run until this much time is spent")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the engine's launch shapes for this graph and job before timing "
+                         "(results do not depend on them; cache in $GC_TUNE_CACHE if set)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="skip the group vs top-k closeness/degree overlap (one top-k search)")
     ap.add_argument("--no-learned", action="store_true",
@@ -356,6 +359,11 @@ def main():
     G = gc.Graph.from_graphgen(g)
     log("workspace %.1f MiB" % (G.ws_bytes / 2**20))
     k = args.k
+    tuning = None
+    if args.tune:
+        from paper_1710_01144_amd import tune
+        tuning = tune.autotune(G, k, order=args.order, block=args.block, reps=3)
+        log("tuning " + json.dumps(tuning))
 
     # ---- timed job
     for _ in range(args.warmup):
@@ -522,7 +530,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s, k=%d, %s lazy order" % (desc, k, args.order),
                    "n": g.n, "nnz": g.nnz, "k": k, "order": args.order, "block": args.block,
-                   "bitset_width": 64,
+                   "bitset_width": 64, "tuning": G.get_tuning(),
+                   "tuned": tuning,
                    "dist_bytes": int(stats[-1]["dist_bytes"])},
         "group_wall_ms": round(ms_per_step, 4),
         "evals": {"round1": int(stats[-1]["evals_round1"]), "later": int(stats[-1]["evals_later"])},

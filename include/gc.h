@@ -151,6 +151,32 @@ void gc_free_graph(gc_graph *g);
 int32_t gc_graph_n(const gc_graph *g);
 int64_t gc_graph_nnz(const gc_graph *g);
 
+/*
+ * gc_tuning -- launch shapes of the device-wide engine for one graph.  No
+ * field changes any result (groups, farness, gains, evaluation counts, word
+ * counters aside from the batching of the closeness search): they decide only
+ * how the work is spread over the GPU, so a tuner may pick them per graph.
+ * gc_load_csr sets them from the environment (GC_UNROLL, GC_UNROLL_SMALL,
+ * GC_MIN_EDGES, GC_MIN_EDGES_SMALL, GC_LEVEL_WGS) or to the defaults.
+ */
+typedef struct gc_tuning {
+    int32_t unroll;           /* adjacency entries per thread per step in
+                               * launches of > 1024 sources: 4, 8 or 16 */
+    int32_t unroll_small;     /* the same for launches of <= 1024 sources and
+                               * the d(S,.) updates: 4 or 8 */
+    int32_t min_edges;        /* adjacency entries per workgroup before a level
+                               * takes more workgroups, large launches (>= 16) */
+    int32_t min_edges_small;  /* the same for small launches (>= 16) */
+    int32_t level_wgs_per_cu; /* workgroups per CU of a level kernel, 1..64 */
+    int32_t reserved[3];      /* zero */
+} gc_tuning;
+
+/* gc_get_tuning -- the handle's current shapes into *out (GC_EINVAL on NULL). */
+int gc_get_tuning(const gc_graph *g, gc_tuning *out);
+/* gc_set_tuning -- replace them; GC_EINVAL (nothing changed) if a field is
+ * out of range.  Not while another call on the same handle is running. */
+int gc_set_tuning(gc_graph *g, const gc_tuning *t);
+
 /* ------------------------------------------------------------ workspace --- */
 
 /*

@@ -389,6 +389,36 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
 
 extern "C" void gc_free_graph(gc_graph *g) { delete g; }
 
+extern "C" int gc_get_tuning(const gc_graph *g, gc_tuning *out) {
+    if (!g || !out) return fail(GC_EINVAL, "NULL argument");
+    gc_tuning t{};
+    t.unroll = g->unroll;
+    t.unroll_small = g->unroll_small;
+    t.min_edges = g->min_edges;
+    t.min_edges_small = g->min_edges_small;
+    t.level_wgs_per_cu = g->level_wgs_per_cu;
+    *out = t;
+    return GC_OK;
+}
+
+extern "C" int gc_set_tuning(gc_graph *g, const gc_tuning *t) {
+    if (!g || !t) return fail(GC_EINVAL, "NULL argument");
+    if (t->unroll != 4 && t->unroll != 8 && t->unroll != 16)
+        return fail(GC_EINVAL, "unroll must be 4, 8 or 16 (got %d)", t->unroll);
+    if (t->unroll_small != 4 && t->unroll_small != 8)
+        return fail(GC_EINVAL, "unroll_small must be 4 or 8 (got %d)", t->unroll_small);
+    if (t->min_edges < 16 || t->min_edges_small < 16)
+        return fail(GC_EINVAL, "min_edges and min_edges_small must be >= 16");
+    if (t->level_wgs_per_cu < 1 || t->level_wgs_per_cu > 64)
+        return fail(GC_EINVAL, "level_wgs_per_cu must be 1..64 (got %d)", t->level_wgs_per_cu);
+    g->unroll = t->unroll;
+    g->unroll_small = t->unroll_small;
+    g->min_edges = t->min_edges;
+    g->min_edges_small = t->min_edges_small;
+    g->level_wgs_per_cu = t->level_wgs_per_cu;
+    return GC_OK;
+}
+
 // --------------------------------------------------------------- workspace
 
 namespace {

@@ -38,7 +38,8 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_gain_words", "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
             "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many",
-            "gc_topk_closeness"]
+            "gc_topk_closeness", "gc_get_tuning", "gc_set_tuning"]
+TUNING_FIELDS = ("unroll", "unroll_small", "min_edges", "min_edges_small", "level_wgs_per_cu")
 MLP_PARAMS = 4801
 MLP_IN = 8
 MLP_HIDDEN = 64
@@ -61,6 +62,10 @@ class GcOpts(ctypes.Structure):
                 ("h_log_gain", ctypes.POINTER(ctypes.c_int64)),
                 ("h_log_feat", ctypes.POINTER(ctypes.c_float)),
                 ("h_log_count", ctypes.POINTER(ctypes.c_int64))]
+
+
+class GcTuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in TUNING_FIELDS] + [("reserved", ctypes.c_int32 * 3)]
 
 
 class GcStats(ctypes.Structure):
@@ -143,6 +148,10 @@ def load_library():
                                 ctypes.c_float, vp]
     lib.gc_node_features.restype = ctypes.c_int
     lib.gc_node_features.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp]
+    lib.gc_get_tuning.restype = ctypes.c_int
+    lib.gc_get_tuning.argtypes = [vp, ctypes.POINTER(GcTuning)]
+    lib.gc_set_tuning.restype = ctypes.c_int
+    lib.gc_set_tuning.argtypes = [vp, ctypes.POINTER(GcTuning)]
     lib.gc_timing_enable.restype = ctypes.c_int
     lib.gc_timing_enable.argtypes = [ctypes.c_int]
     lib.gc_timing_last_ms.restype = ctypes.c_double
@@ -296,6 +305,22 @@ class Graph:
                                                _ptr(dist_at_eval), int(round_), int(k), int(ecc1),
                                                _ptr(feat), _stream()))
         return feat[:count]
+
+    def get_tuning(self) -> dict:
+        """The engine's launch shapes for this graph (gc_tuning)."""
+        t = GcTuning()
+        _check(load_library().gc_get_tuning(self.handle, ctypes.byref(t)))
+        return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+
+    def set_tuning(self, **shape):
+        """Change some launch shapes; results do not depend on them."""
+        cur = self.get_tuning()
+        unknown = set(shape) - set(cur)
+        if unknown:
+            raise ValueError("unknown tuning fields: %s" % sorted(unknown))
+        cur.update({k: int(v) for k, v in shape.items()})
+        t = GcTuning(*[cur[f] for f in TUNING_FIELDS])
+        _check(load_library().gc_set_tuning(self.handle, ctypes.byref(t)))
 
     def greedy_group(self, k: int, order: str = "plain", block: int = 0, prefix=None,
                      mlp_params=None, log_capacity: int = 0, debug: bool = False,

@@ -377,3 +377,34 @@ def test_greedy_many_matches_single_jobs(gclib, workers):
                 grp_b, F_b, ev_b, _ = oracle.greedypp(g, k, block=64, growth=2)
                 assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
                 assert st["evals_total"] == int(ev_b.sum())
+
+
+def test_tuning_shapes_do_not_change_results(gclib):
+    """Every launch shape (gc_set_tuning) and the autotuner's pick give the
+    oracle's group, farness and evaluation counts; bad shapes are rejected."""
+    from paper_1710_01144_amd import tune
+    g = graphgen.rmat(12, 16, 7)
+    G = _graph(gclib, g)
+    k = 8
+    grp_b, F_b, ev_b, _ = oracle.greedypp(g, k, block=64, growth=2)
+    default = G.get_tuning()
+    shapes = [dict(unroll=16, unroll_small=8), dict(min_edges=16, min_edges_small=16),
+              dict(min_edges=1 << 20, min_edges_small=1 << 20, level_wgs_per_cu=1), dict(level_wgs_per_cu=16)]
+    for shape in shapes:
+        G.set_tuning(**dict(default, **shape))
+        for order in ("plain", "celf"):
+            _note("tuning %s %s" % (shape, order))
+            grp, F, st = G.greedy_group(k, order=order)
+            assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+            if order == "plain":
+                assert st["evals_per_round"].tolist() == ev_b.tolist()
+    G.set_tuning(**default)
+    for bad in (dict(unroll=5), dict(unroll_small=16), dict(min_edges=8), dict(level_wgs_per_cu=0)):
+        with pytest.raises(gclib.GCError):
+            G.set_tuning(**bad)
+    assert G.get_tuning() == default
+    _note("autotune rmat12 k=%d" % k)
+    out = tune.autotune(G, k, reps=1, grid={"unroll_small": (4, 8), "level_wgs_per_cu": (2, 4)})
+    assert out["shape"] == G.get_tuning() and out["trials"] == 3
+    grp, F, _ = G.greedy_group(k)
+    assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
