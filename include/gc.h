@@ -227,6 +227,33 @@ int gc_topk_closeness(const gc_graph *g, int32_t k, void *d_ws, size_t ws_bytes,
                       int32_t *h_nodes, int64_t *h_farness);
 
 /*
+ * Bit-vector gains (Section 4.3, bit-parallel group closeness; the gain
+ * evaluation of bitGreedy++).  b^i_u is the set of nodes within distance i of
+ * u as an n-bit row; the gain of u is the sum over i of |b^i_u AND NOT b^i_S|
+ * (the theorem of Section 4.3).  The rows of every level are stored: n * n
+ * bits per level, so this is for graphs with n up to about 10^5 and a small
+ * diameter.
+ *
+ * gc_bits_size -- bytes of a caller buffer holding `levels` levels (2..256)
+ *   plus the b^i_S rows and a counter block.
+ * gc_bits_prepare -- compute b^0 (one bit per row), b^1, ... into d_bits until
+ *   a level equals the one before (the fixed point; as many levels as the
+ *   diameter + 1).  h_levels: the stored levels, the last the fixed point.
+ *   GC_EWORKSPACE if the buffer holds too few levels.  Synchronises once per
+ *   level.  The rows depend on the graph only.
+ * gc_bits_gains -- g(v, S) for the count candidates in d_cand (device int32,
+ *   ids in [0, n)) into d_gain (device int64), for the S whose distances
+ *   d_dist holds (uint8 only, dist_bytes = 1; INF everywhere is S = {}), from
+ *   a buffer gc_bits_prepare filled with `levels` levels.  The same values as
+ *   gc_marginal_gains.  Synchronises once (max d(S,.)).
+ */
+int gc_bits_size(const gc_graph *g, int32_t levels, size_t *bytes);
+int gc_bits_prepare(const gc_graph *g, void *d_bits, size_t bytes, hipStream_t stream, int32_t *h_levels);
+int gc_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t levels, const void *d_dist,
+                  int32_t dist_bytes, const int32_t *d_cand, int64_t count, int64_t *d_gain,
+                  hipStream_t stream);
+
+/*
  * gc_update_dist -- add `node` to S: d(S,.) <- min(d(S,.), d(node,.))
  * (Algorithm "mem-greedy", the update after each pick).  Done by BFS from
  * node pruned to nodes w with d(node,w) < d(S,w), which leaves every other

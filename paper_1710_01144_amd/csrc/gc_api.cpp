@@ -18,6 +18,7 @@
 #include "gc.h"
 #include "gc_kernels.h"
 #include "gc_mlp.h"
+#include "gc_bits.h"
 
 using namespace gck;
 
@@ -1269,6 +1270,88 @@ extern "C" int gc_topk_closeness(const gc_graph *g, int32_t k, void *d_ws, size_
         h_farness[i] = top[(size_t)i].first;
     }
     return GC_OK;
+}
+
+// ------------------------------------------------------------ bit vectors
+
+namespace {
+// bits buffer: `levels` stored levels of n rows of W words, then kBitsMaxS
+// rows of b^i_S, then a counter block (change flag, max distance)
+int64_t bits_words(const gc_graph *g) { return ((int64_t)g->n + 63) / 64; }
+size_t bits_level_bytes(const gc_graph *g) { return (size_t)g->n * (size_t)bits_words(g) * 8; }
+size_t bits_bytes(const gc_graph *g, int32_t levels) {
+    return (size_t)levels * bits_level_bytes(g) + (size_t)kBitsMaxS * (size_t)bits_words(g) * 8 + 256;
+}
+}  // namespace
+
+extern "C" int gc_bits_size(const gc_graph *g, int32_t levels, size_t *bytes) {
+    if (!g || !bytes) return fail(GC_EINVAL, "NULL argument");
+    if (levels < 2 || levels > kBitsMaxS) return fail(GC_EINVAL, "levels must be 2..%d", kBitsMaxS);
+    *bytes = bits_bytes(g, levels);
+    return GC_OK;
+}
+
+extern "C" int gc_bits_prepare(const gc_graph *g, void *d_bits, size_t bytes, hipStream_t s,
+                               int32_t *h_levels) {
+    if (!g || !d_bits || !h_levels) return fail(GC_EINVAL, "NULL argument");
+    const size_t lb = bits_level_bytes(g);
+    const size_t fixed = (size_t)kBitsMaxS * (size_t)bits_words(g) * 8 + 256;
+    if (bytes < fixed + 2 * lb) return fail(GC_EWORKSPACE, "bits buffer too small for two levels");
+    const int32_t cap = (int32_t)std::min<size_t>((bytes - fixed) / lb, (size_t)kBitsMaxS);
+    char *base = reinterpret_cast<char *>(d_bits);
+    auto level = [&](int32_t l) { return reinterpret_cast<uint64_t *>(base + (size_t)l * lb); };
+    int32_t *flag = reinterpret_cast<int32_t *>(base + (size_t)cap * lb + (size_t)kBitsMaxS * bits_words(g) * 8);
+    HIP_OK(launch_bits_identity(level(0), g->n, s));
+    for (int32_t i = 1; i < cap; ++i) {
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(flag), 1, 0u, s));
+        HIP_OK(launch_bits_level(g->d_rp, g->d_ci, g->n, level(i - 1), level(i), flag, s));
+        int32_t changed = 0;
+        HIP_OK(hipMemcpyAsync(&changed, flag, sizeof(changed), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (!changed) {
+            *h_levels = i;  // levels 0 .. i-1; level i-1 is the fixed point
+            return GC_OK;
+        }
+    }
+    return fail(GC_EWORKSPACE, "bit vectors need more than %d levels", cap);
+}
+
+namespace {
+// gains by the theorem's sum over the stored levels; b^i_S rebuilt from
+// d(S,.) for i below max d(S,.) (every later term is zero)
+int run_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t levels, const void *d_dist,
+                   int dist_bytes, const int32_t *d_cand, int64_t count, int64_t *d_gain, hipStream_t s,
+                   int32_t maxd = -1) {
+    const size_t lb = bits_level_bytes(g);
+    const size_t fixed = (size_t)kBitsMaxS * (size_t)bits_words(g) * 8 + 256;
+    if (bytes < fixed + (size_t)levels * lb) return fail(GC_EWORKSPACE, "bits buffer smaller than its levels");
+    const int32_t cap = (int32_t)std::min<size_t>((bytes - fixed) / lb, (size_t)kBitsMaxS);
+    const char *base = reinterpret_cast<const char *>(d_bits);
+    uint64_t *bs = reinterpret_cast<uint64_t *>(const_cast<char *>(base) + (size_t)cap * lb);
+    int32_t *ctr = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(bs) + (size_t)kBitsMaxS * bits_words(g) * 8);
+    if (maxd < 0) {
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctr + 1), 1, 0u, s));
+        HIP_OK(launch_max_dist(d_dist, dist_bytes, g->n, ctr + 1, s));
+        HIP_OK(hipMemcpyAsync(&maxd, ctr + 1, sizeof(maxd), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    const int32_t levels_s = std::min(maxd, kBitsMaxS);
+    HIP_OK(launch_bits_group(d_dist, dist_bytes, g->n, levels_s, bs, s));
+    HIP_OK(launch_bits_gains(reinterpret_cast<const uint64_t *>(base), g->n, levels, bs, levels_s, d_cand, count,
+                             d_gain, s));
+    return GC_OK;
+}
+}  // namespace
+
+extern "C" int gc_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t levels,
+                             const void *d_dist, int32_t dist_bytes, const int32_t *d_cand, int64_t count,
+                             int64_t *d_gain, hipStream_t stream) {
+    if (!g || !d_bits || !d_dist || (count > 0 && (!d_cand || !d_gain))) return fail(GC_EINVAL, "NULL argument");
+    if (dist_bytes != 1) return fail(GC_EINVAL, "the bit-vector gains take uint8 distances");
+    if (levels < 1 || levels > kBitsMaxS) return fail(GC_EINVAL, "levels out of range");
+    if (count < 0) return fail(GC_EINVAL, "negative count");
+    if (count == 0) return GC_OK;
+    return run_bits_gains(g, d_bits, bytes, levels, d_dist, dist_bytes, d_cand, count, d_gain, stream);
 }
 
 extern "C" int gc_update_dist(const gc_graph *g, int32_t node, void *d_dist, int32_t dist_bytes,

@@ -38,7 +38,8 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_gain_words", "gc_greedy_group", "gc_strerror", "gc_last_error", "gc_mlp_block_bytes", "gc_mlp_pack",
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
             "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many",
-            "gc_topk_closeness", "gc_get_tuning", "gc_set_tuning"]
+            "gc_topk_closeness", "gc_get_tuning", "gc_set_tuning", "gc_bits_size", "gc_bits_prepare",
+            "gc_bits_gains"]
 TUNING_FIELDS = ("unroll", "unroll_small", "min_edges", "min_edges_small", "level_wgs_per_cu")
 MLP_PARAMS = 4801
 MLP_IN = 8
@@ -148,6 +149,12 @@ def load_library():
                                 ctypes.c_float, vp]
     lib.gc_node_features.restype = ctypes.c_int
     lib.gc_node_features.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp]
+    lib.gc_bits_size.restype = ctypes.c_int
+    lib.gc_bits_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.gc_bits_prepare.restype = ctypes.c_int
+    lib.gc_bits_prepare.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32)]
+    lib.gc_bits_gains.restype = ctypes.c_int
+    lib.gc_bits_gains.argtypes = [vp, vp, ctypes.c_size_t, i32, vp, i32, vp, ctypes.c_int64, vp, vp]
     lib.gc_get_tuning.restype = ctypes.c_int
     lib.gc_get_tuning.argtypes = [vp, ctypes.POINTER(GcTuning)]
     lib.gc_set_tuning.restype = ctypes.c_int
@@ -305,6 +312,27 @@ class Graph:
                                                _ptr(dist_at_eval), int(round_), int(k), int(ecc1),
                                                _ptr(feat), _stream()))
         return feat[:count]
+
+    def bits_prepare(self, levels: int):
+        """Bit-vector rows of every level (gc_bits_prepare) in a new device
+        buffer that holds `levels` levels; returns the number stored."""
+        lib = load_library()
+        nb = ctypes.c_size_t()
+        _check(lib.gc_bits_size(self.handle, int(levels), ctypes.byref(nb)))
+        self.bits = torch.empty(nb.value, dtype=torch.uint8, device=self.row_ptr.device)
+        lv = ctypes.c_int32()
+        _check(lib.gc_bits_prepare(self.handle, _ptr(self.bits), nb.value, _stream(), ctypes.byref(lv)))
+        self.bits_levels = int(lv.value)
+        return self.bits_levels
+
+    def bits_gains(self, dist, dist_bytes: int, cand) -> torch.Tensor:
+        """g(v, S) of the candidates by the bit-vector sum (gc_bits_gains)."""
+        cand = cand.to(device=self.row_ptr.device, dtype=torch.int32).contiguous()
+        gain = torch.zeros(cand.numel(), dtype=torch.int64, device=self.row_ptr.device)
+        _check(load_library().gc_bits_gains(self.handle, _ptr(self.bits), self.bits.numel(), self.bits_levels,
+                                            _ptr(dist), dist_bytes, _ptr(cand), cand.numel(), _ptr(gain),
+                                            _stream()))
+        return gain
 
     def get_tuning(self) -> dict:
         """The engine's launch shapes for this graph (gc_tuning)."""
