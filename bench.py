@@ -16,6 +16,8 @@ workload graph, inputs already resident in HBM.  Prints ONE JSON line:
   first_gain_round  the same for one call over all n-1 candidates;
   learned_vs_plain  the candidate-ordering network trained on plain-order
             logs, timed against plain, CELF and an untrained network;
+  bitgreedy the same job as bitGreedy++ (bit-vector gains of Section 4.3):
+            row preparation and job times, the gain kernel's bytes per second;
   overlap   share of the group among the k nodes of highest closeness
             (gc_topk_closeness) and of highest degree;
   cpu_baseline  the CPU oracle's Greedy++ (tier B) on the same job, timed on
@@ -74,6 +76,8 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="autotune the engine's launch shapes for this graph and job before timing "
                          "(results do not depend on them; cache in $GC_TUNE_CACHE if set)")
+    ap.add_argument("--no-bitgreedy", action="store_true",
+                    help="skip bitGreedy++ (bit-vector gains; graphs of <= 70k nodes with uint8 distances)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="skip the group vs top-k closeness/degree overlap (one top-k search)")
     ap.add_argument("--no-learned", action="store_true",
@@ -462,6 +466,44 @@ def main():
         % (cand.numel(), E1, V1, words["entries"], Ew, words["touched"], kern_ms, r1_gbs,
            E1 / kern_ms / 1e6, Ew / kern_ms / 1e6))
 
+    # ---- bitGreedy++: the same lazy loop over bit-vector gains (Section 4.3)
+    bitg = None
+    if not args.no_bitgreedy and g.n <= 70000 and dist_bytes == 1:
+        t1 = time.perf_counter()
+        levels = G.bits_prepare(min(256, 2 * int(st["ecc_s1"]) + 2))
+        torch.cuda.synchronize()
+        prep_ms = 1000 * (time.perf_counter() - t1)
+        W = (g.n + 63) // 64
+        # levels 1 .. levels computed (the last one confirms the fixed point):
+        # every row ORs its own and its neighbours' previous rows, then is written
+        prep_bytes = levels * ((g.n + g.nnz) * W * 8 + g.n * W * 8)
+        G.greedy_group(k, order=args.order, block=args.block, bits=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            gb, Fb, sb = G.greedy_group(k, order=args.order, block=args.block, bits=True)
+        torch.cuda.synchronize()
+        bits_ms = 1000 * (time.perf_counter() - t1) / reps
+        assert gb.tolist() == grp.tolist() and Fb.tolist() == F.tolist(), "bitGreedy++ disagrees"
+        assert sb["evals_per_round"].tolist() == stats[-1]["evals_per_round"].tolist()
+        gc.timing_enable(True)
+        _, _, sb = G.greedy_group(k, order=args.order, block=args.block, bits=True)
+        gc.timing_enable(False)
+        gain_s = float(sb["ms_gain_gpu"]) / 1000.0
+        gain_gbs = int(sb["bits_words"]) * 8 / gain_s / 1e9 if gain_s > 0 else None
+        bitg = {"levels": levels, "prepare_ms": round(prep_ms, 3),
+                "prepare_alg_gbs": round(prep_bytes / (prep_ms / 1000.0) / 1e9, 1),
+                "ms": round(bits_ms, 3), "gain_gpu_ms": round(1000 * gain_s, 3),
+                "gain_launches": int(sb["gain_launches"]), "gain_row_bytes": int(sb["bits_words"]) * 8,
+                "gain_alg_gbs": round(gain_gbs, 1) if gain_gbs else None,
+                "gain_frac": round(gain_gbs / HBM_PEAK_GBS, 4) if gain_gbs else None,
+                "bits_bytes": int(G.bits.numel())}
+        log("bitgreedy %s" % json.dumps(bitg))
+        del G.bits
+        G.bits = None
+        torch.cuda.empty_cache()
+
     # ---- the group against the top-k closeness and top-k degree nodes
     # (the overlap study of the paper's experiments, on this synthetic graph)
     overlap = None
@@ -550,6 +592,7 @@ def main():
                              "alg_bytes": r1_alg, "gbs": round(r1_gbs, 2), "words": words,
                              "gteps_alg": round(E1 / kern_ms / 1e6, 2),
                              "gteps_word": round(Ew / kern_ms / 1e6, 2)},
+        "bitgreedy": bitg,
         "overlap": overlap,
         "cpu_baseline": cpu,
     }

@@ -89,6 +89,12 @@ typedef struct gc_opts {
     int64_t *h_log_gain;
     float *h_log_feat;      /* log_capacity x 8 */
     int64_t *h_log_count;   /* out: entries written (may exceed capacity: the rest dropped) */
+    /* bitGreedy++ (Section 4.3 with the lazy loop): exact gains by the
+       bit-vector sum from a buffer gc_bits_prepare filled (NULL: pruned BFS).
+       Plain and CELF orders; uint8 distances (GC_ERANGE if ecc(s_1) > 254). */
+    const void *d_bits;
+    size_t bits_bytes;
+    int32_t bits_levels;
 } gc_opts;
 
 /* Counters filled by gc_greedy_group (all optional). */
@@ -120,6 +126,7 @@ typedef struct gc_stats {
     double ms_gain_gpu;     /* GPU time of the gain launches (HIP events), all rounds;
                              * measured only while gc_timing_enable(1) is in force */
     int64_t mlp_launches;   /* feature + MLP scoring launches (learned order) */
+    int64_t bits_words;     /* bitGreedy++: 64-bit row words the bit-vector gains read */
     int64_t *h_evals_per_round; /* optional, caller-owned, k entries */
 } gc_stats;
 

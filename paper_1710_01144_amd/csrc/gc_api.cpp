@@ -1321,7 +1321,7 @@ namespace {
 // d(S,.) for i below max d(S,.) (every later term is zero)
 int run_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t levels, const void *d_dist,
                    int dist_bytes, const int32_t *d_cand, int64_t count, int64_t *d_gain, hipStream_t s,
-                   int32_t maxd = -1) {
+                   int32_t maxd = -1, bool count_words = false) {
     const size_t lb = bits_level_bytes(g);
     const size_t fixed = (size_t)kBitsMaxS * (size_t)bits_words(g) * 8 + 256;
     if (bytes < fixed + (size_t)levels * lb) return fail(GC_EWORKSPACE, "bits buffer smaller than its levels");
@@ -1337,9 +1337,20 @@ int run_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t 
     }
     const int32_t levels_s = std::min(maxd, kBitsMaxS);
     HIP_OK(launch_bits_group(d_dist, dist_bytes, g->n, levels_s, bs, s));
+    // (the row words read go to the counter block's second int64)
+    unsigned long long *words = count_words ? reinterpret_cast<unsigned long long *>(ctr) + 1 : nullptr;
     HIP_OK(launch_bits_gains(reinterpret_cast<const uint64_t *>(base), g->n, levels, bs, levels_s, d_cand, count,
-                             d_gain, s));
+                             d_gain, words, s));
     return GC_OK;
+}
+
+// the counter of row words read by the bit-vector gains of a greedy job
+unsigned long long *bits_words_counter(const gc_graph *g, const void *d_bits, size_t bytes) {
+    const size_t lb = bits_level_bytes(g);
+    const size_t fixed = (size_t)kBitsMaxS * (size_t)bits_words(g) * 8 + 256;
+    const int32_t cap = (int32_t)std::min<size_t>((bytes - fixed) / lb, (size_t)kBitsMaxS);
+    char *base = reinterpret_cast<char *>(const_cast<void *>(d_bits));
+    return reinterpret_cast<unsigned long long *>(base + (size_t)cap * lb + (size_t)kBitsMaxS * bits_words(g) * 8) + 1;
 }
 }  // namespace
 
@@ -1504,6 +1515,16 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     if (o.bitset_width != 0 && o.bitset_width != 64) return fail(GC_EINVAL, "bitset_width must be 64");
     if (o.order < GC_ORDER_PLAIN || o.order > GC_ORDER_LEARNED) return fail(GC_EINVAL, "bad order");
     if (o.order == GC_ORDER_LEARNED && !o.d_mlp) return fail(GC_EINVAL, "learned order needs d_mlp");
+    const bool bits = o.d_bits != nullptr;
+    if (bits && (o.order == GC_ORDER_LEARNED || g->wg_engine))
+        return fail(GC_EINVAL, "bit-vector gains: plain or CELF order on the device-wide engine");
+    if (bits && (o.bits_levels < 1 || o.bits_levels > kBitsMaxS))
+        return fail(GC_EINVAL, "bits_levels out of range (gc_bits_prepare returns it)");
+    if (bits && o.bits_bytes < bits_bytes(g, o.bits_levels))
+        return fail(GC_EINVAL, "bits_bytes smaller than %d levels need", o.bits_levels);
+    if (bits)
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(bits_words_counter(g, o.d_bits, o.bits_bytes)), 2, 0u,
+                               s));
     const int32_t block = o.block > 0 ? o.block : kSrc;
     if (o.block_growth < 0 || o.block_growth > 8) return fail(GC_EINVAL, "block_growth outside [0, 8]");
     if (o.nprefix < 0 || o.nprefix > k || (o.nprefix > 0 && !o.h_prefix))
@@ -1631,6 +1652,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         d_dist = w.dist16();
         dist_bytes = 2;
     }
+    if (bits && dist_bytes != 1) return fail(GC_ERANGE, "bit-vector gains need eccentricity(s1) <= 254");
     int64_t F = 0;
     HIP_OK(hipMemcpyAsync(&F, w.far(), sizeof(F), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -1690,6 +1712,27 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     auto evaluate = [&](int32_t cnt) -> int {
         LaunchShape *shape = cur_round == first_round_idx ? &shape_r1 : &shape_later;
         int r;
+        if (bits) {
+            // bitGreedy++: the theorem's popcount sum over the stored levels;
+            // max d(S,.) <= nlev_now() + 1 bounds the levels that can count
+            const bool timed = io.ev0 && io.gpu_ms;
+            if (timed) HIP_OK(hipEventRecord(io.ev0, s));
+            r = run_bits_gains(g, o.d_bits, o.bits_bytes, o.bits_levels, d_dist, dist_bytes, dc, cnt, w.gain(), s,
+                               nlev_now() + 1, true);
+            if (r) return r;
+            if (timed) HIP_OK(hipEventRecord(io.ev1, s));
+            HIP_OK(hipMemcpyAsync(hg, w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            if (timed) {
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, io.ev0, io.ev1));
+                *io.gpu_ms += ms;
+            }
+            if (want_edges)
+                for (int32_t j = 0; j < cnt; ++j) he[j] = 0;  // no per-source edge counts here
+            st.gain_launches += 1;
+            return GC_OK;
+        }
         if (g->wg_engine) {
             HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
             r = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(),
@@ -1816,7 +1859,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         // so the host work overlaps the GPU's.  The next selection needs only
         // the best gain, which is taken first; the deferred candidates are
         // behind the plain scan's position or out of CELF's tree until then.
-        const bool overlap = !first_round && !learned && !logging && !g->wg_engine;
+        const bool overlap = !first_round && !learned && !logging && !g->wg_engine && !bits;
         int dbuf = -1;        // buffer of the deferred block (-1: none)
         int32_t dcnt = 0;
         int cur = 0;          // buffer the next block goes to
@@ -2114,6 +2157,11 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         h_farness[i] = Fs[i];
     }
     st.ms_total = now_ms() - t_start;
+    if (bits) {
+        HIP_OK(hipMemcpyAsync(&st.bits_words, bits_words_counter(g, o.d_bits, o.bits_bytes), sizeof(int64_t),
+                              hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
     if (h_stats) {
         int64_t wc[kWordCounters];
         HIP_OK(hipMemcpyAsync(wc, w.words(), sizeof(wc), hipMemcpyDeviceToHost, s));

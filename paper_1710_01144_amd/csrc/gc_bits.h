@@ -15,6 +15,6 @@ hipError_t launch_bits_group(const void *dist, int dist_bytes, int32_t n, int32_
                              hipStream_t s);
 hipError_t launch_bits_gains(const uint64_t *bits, int32_t n, int32_t levels_b, const uint64_t *bs,
                              int32_t levels_s, const int32_t *cand, int64_t count, int64_t *gain,
-                             hipStream_t s);
+                             unsigned long long *words, hipStream_t s);
 
 }  // namespace gck

@@ -68,16 +68,19 @@ __global__ void k_bits_group(const DistT *dist, int32_t n, int64_t W, int32_t le
 // Gains of the candidates: one wave per candidate, the sum over levels
 // i < levels_s of popcount(b^i_u AND NOT b^i_S), level i read from stored
 // level min(i, levels_b - 1) (the last stored level is the fixed point),
-// stopping at the first zero term.
+// stopping at the first zero term.  words (optional): += the row words read.
 __global__ __launch_bounds__(256) void k_bits_gains(const uint64_t *bits, int32_t n, int64_t W,
                                                      int32_t levels_b, const uint64_t *bs, int32_t levels_s,
-                                                     const int32_t *cand, int64_t count, int64_t *gain) {
+                                                     const int32_t *cand, int64_t count, int64_t *gain,
+                                                     unsigned long long *words) {
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (wave >= count) return;
     const int64_t u = cand[wave];
     const int ln = lane();
     int64_t total = 0;
+    int32_t read = 0;
     for (int32_t i = 0; i < levels_s; ++i) {
+        ++read;
         const int32_t lb = i < levels_b ? i : levels_b - 1;
         const uint64_t *row = bits + ((int64_t)lb * n + u) * W;
         const uint64_t *srow = bs + (int64_t)i * W;
@@ -88,7 +91,10 @@ __global__ __launch_bounds__(256) void k_bits_gains(const uint64_t *bits, int32_
         if (c == 0) break;
         total += c;
     }
-    if (ln == 0) gain[wave] = total;
+    if (ln == 0) {
+        gain[wave] = total;
+        if (words) atomicAdd(words, (unsigned long long)read * (unsigned long long)W);
+    }
 }
 
 }  // namespace
@@ -125,12 +131,12 @@ hipError_t launch_bits_group(const void *dist, int dist_bytes, int32_t n, int32_
 
 hipError_t launch_bits_gains(const uint64_t *bits, int32_t n, int32_t levels_b, const uint64_t *bs,
                              int32_t levels_s, const int32_t *cand, int64_t count, int64_t *gain,
-                             hipStream_t s) {
+                             unsigned long long *words, hipStream_t s) {
     const int64_t W = ((int64_t)n + 63) / 64;
     const int64_t g = (count * 64 + 255) / 256;
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bits_gains, dim3((unsigned)g), dim3(256), 0, s, bits, n, W, levels_b, bs, levels_s,
-                       cand, count, gain);
+                       cand, count, gain, words);
     return hipGetLastError();
 }
 

@@ -62,7 +62,8 @@ class GcOpts(ctypes.Structure):
                 ("h_log_node", ctypes.POINTER(ctypes.c_int32)),
                 ("h_log_gain", ctypes.POINTER(ctypes.c_int64)),
                 ("h_log_feat", ctypes.POINTER(ctypes.c_float)),
-                ("h_log_count", ctypes.POINTER(ctypes.c_int64))]
+                ("h_log_count", ctypes.POINTER(ctypes.c_int64)),
+                ("d_bits", ctypes.c_void_p), ("bits_bytes", ctypes.c_size_t), ("bits_levels", ctypes.c_int32)]
 
 
 class GcTuning(ctypes.Structure):
@@ -82,6 +83,7 @@ class GcStats(ctypes.Structure):
                 ("entries_last", ctypes.c_int64), ("edges_word", ctypes.c_int64),
                 ("edges_last", ctypes.c_int64), ("touched_word", ctypes.c_int64),
                 ("ms_gain_gpu", ctypes.c_double), ("mlp_launches", ctypes.c_int64),
+                ("bits_words", ctypes.c_int64),
                 ("h_evals_per_round", ctypes.POINTER(ctypes.c_int64))]
 
     def as_dict(self):
@@ -352,9 +354,17 @@ class Graph:
 
     def greedy_group(self, k: int, order: str = "plain", block: int = 0, prefix=None,
                      mlp_params=None, log_capacity: int = 0, debug: bool = False,
-                     block_growth: int = 0):
+                     block_growth: int = 0, bits: bool = False):
+        """bits=True: bitGreedy++ (gains by the bit-vector sum from the rows
+        bits_prepare() stored)."""
         lib = load_library()
         opts = GcOpts()
+        if bits:
+            if getattr(self, "bits", None) is None:
+                raise ValueError("bits=True needs bits_prepare() first")
+            opts.d_bits = ctypes.c_void_p(self.bits.data_ptr())
+            opts.bits_bytes = self.bits.numel()
+            opts.bits_levels = self.bits_levels
         opts.order = ORDERS[order]
         opts.bitset_width = 64
         opts.block = int(block)

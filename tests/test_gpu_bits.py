@@ -63,3 +63,36 @@ def test_bits_rows_and_gains(gclib, device, mk):
             S.append(int(grp[step]))
     with pytest.raises(gclib.GCError):
         G.bits_gains(G.new_dist(2), 2, cand)
+
+
+@pytest.mark.parametrize("mk", GRAPHS + [lambda: graphgen.ba(2000, 4, 1)], ids=lambda f: "bitgreedy")
+def test_bitgreedy_matches_greedy(gclib, mk):
+    """bitGreedy++ (the lazy loop over bit-vector gains) picks the plain
+    greedy's group and evaluates exactly what CPU Greedy++ evaluates."""
+    g = mk()
+    k = min(g.n, 8)
+    G = gclib.Graph.from_graphgen(g)
+    G.bits_prepare(256)
+    grp_a, F_a = oracle.greedy(g, k)
+    grp_b, F_b, ev_b, _ = oracle.greedypp(g, k, block=64, growth=2)
+    for order in ("plain", "celf"):
+        _note("bitgreedy %s k=%d %s" % (g.name, k, order))
+        grp, F, st = G.greedy_group(k, order=order, bits=True)
+        assert grp.tolist() == grp_a.tolist() and F.tolist() == F_a.tolist()
+        if order == "plain":
+            assert st["evals_per_round"].tolist() == ev_b.tolist()
+    with pytest.raises(gclib.GCError):
+        G.greedy_group(k, order="learned", bits=True, mlp_params=torch.zeros(1, device=G.row_ptr.device))
+
+
+def test_bitgreedy_rmat16(gclib):
+    """The bench's graph: R-MAT scale 16, k = 50, against CPU Greedy++."""
+    g = graphgen.workload("rmat16")
+    G = gclib.Graph.from_graphgen(g)
+    _note("bitgreedy rmat16 prepare")
+    levels = G.bits_prepare(32)
+    grp_b, F_b, ev_b, _ = oracle.greedypp(g, 50, block=64, growth=2)
+    _note("bitgreedy rmat16 k=50 (%d levels)" % levels)
+    grp, F, st = G.greedy_group(50, bits=True)
+    assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+    assert st["evals_per_round"].tolist() == ev_b.tolist()
