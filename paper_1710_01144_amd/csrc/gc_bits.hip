@@ -41,7 +41,21 @@ __global__ __launch_bounds__(256) void k_bits_level(const int32_t *rp, const int
     uint64_t acc = in ? prev[u * W + j] : 0ull;
     const uint64_t old = acc;
     const int32_t e1 = rp[u + 1];
-    for (int32_t e = rp[u]; e < e1; ++e) {
+    int32_t e = rp[u];
+    // eight neighbours' rows in flight at a time
+    for (; e + 8 <= e1; e += 8) {
+        int64_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = ci[e + q];
+        if (in) {
+            uint64_t x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = prev[v[q] * W + j];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc |= x[q];
+        }
+    }
+    for (; e < e1; ++e) {
         const int64_t v = ci[e];
         if (in) acc |= prev[v * W + j];
     }
