@@ -1321,7 +1321,7 @@ namespace {
 // d(S,.) for i below max d(S,.) (every later term is zero)
 int run_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t levels, const void *d_dist,
                    int dist_bytes, const int32_t *d_cand, int64_t count, int64_t *d_gain, hipStream_t s,
-                   int32_t maxd = -1, bool count_words = false) {
+                   int32_t maxd = -1, bool count_words = false, bool build_bs = true) {
     const size_t lb = bits_level_bytes(g);
     const size_t fixed = (size_t)kBitsMaxS * (size_t)bits_words(g) * 8 + 256;
     if (bytes < fixed + (size_t)levels * lb) return fail(GC_EWORKSPACE, "bits buffer smaller than its levels");
@@ -1336,7 +1336,7 @@ int run_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t 
         HIP_OK(hipStreamSynchronize(s));
     }
     const int32_t levels_s = std::min(maxd, kBitsMaxS);
-    HIP_OK(launch_bits_group(d_dist, dist_bytes, g->n, levels_s, bs, s));
+    if (build_bs) HIP_OK(launch_bits_group(d_dist, dist_bytes, g->n, levels_s, bs, s));
     // (the row words read go to the counter block's second int64)
     unsigned long long *words = count_words ? reinterpret_cast<unsigned long long *>(ctr) + 1 : nullptr;
     HIP_OK(launch_bits_gains(reinterpret_cast<const uint64_t *>(base), g->n, levels, bs, levels_s, d_cand, count,
@@ -1709,6 +1709,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     LaunchShape shape_r1, shape_later;
     int32_t cur_round = 0, first_round_idx = (int32_t)group.size();
     // evaluate a list of candidates, returning gains (and edges) on the host
+    int32_t bs_round = -1, bs_levels = 0;  // bitGreedy++: round and levels of the built b^i_S rows
     auto evaluate = [&](int32_t cnt) -> int {
         LaunchShape *shape = cur_round == first_round_idx ? &shape_r1 : &shape_later;
         int r;
@@ -1717,8 +1718,16 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             // max d(S,.) <= nlev_now() + 1 bounds the levels that can count
             const bool timed = io.ev0 && io.gpu_ms;
             if (timed) HIP_OK(hipEventRecord(io.ev0, s));
+            // b^i_S changes only with d(S,.): once per round (again if more
+            // levels are asked for than were built)
+            const int32_t ls = nlev_now() + 1;
+            const bool build = bs_round != cur_round || ls > bs_levels;
             r = run_bits_gains(g, o.d_bits, o.bits_bytes, o.bits_levels, d_dist, dist_bytes, dc, cnt, w.gain(), s,
-                               nlev_now() + 1, true);
+                               ls, true, build);
+            if (build) {
+                bs_round = cur_round;
+                bs_levels = ls;
+            }
             if (r) return r;
             if (timed) HIP_OK(hipEventRecord(io.ev1, s));
             HIP_OK(hipMemcpyAsync(hg, w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
