@@ -1722,7 +1722,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             // levels are asked for than were built)
             const int32_t ls = nlev_now() + 1;
             const bool build = bs_round != cur_round || ls > bs_levels;
-            r = run_bits_gains(g, o.d_bits, o.bits_bytes, o.bits_levels, d_dist, dist_bytes, dc, cnt, w.gain(), s,
+            // (the gains go straight to the host-mapped buffer)
+            r = run_bits_gains(g, o.d_bits, o.bits_bytes, o.bits_levels, d_dist, dist_bytes, dc, cnt, dg, s,
                                ls, true, build);
             if (build) {
                 bs_round = cur_round;
@@ -1730,7 +1731,6 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             }
             if (r) return r;
             if (timed) HIP_OK(hipEventRecord(io.ev1, s));
-            HIP_OK(hipMemcpyAsync(hg, w.gain(), sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s));
             HIP_OK(hipStreamSynchronize(s));
             if (timed) {
                 float ms = 0.f;
