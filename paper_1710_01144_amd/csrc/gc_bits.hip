@@ -64,19 +64,22 @@ __global__ __launch_bounds__(256) void k_bits_level(const int32_t *rp, const int
     if (__ballot(in && acc != old) != 0ull && lane() == 0) atomicOr(changed, 1);
 }
 
-// b^i_S for i = 0 .. levels-1 from d(S,.): one thread per (level, word).
+// b^i_S for i = 0 .. levels-1 from d(S,.): one thread per word, which reads
+// its 64 distances once and writes the word of every level.
 template <typename DistT>
 __global__ void k_bits_group(const DistT *dist, int32_t n, int64_t W, int32_t levels, uint64_t *bs) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)levels * W) return;
-    const int64_t i = t / W, j = t - i * W;
-    uint64_t word = 0;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= W) return;
     const int64_t w0 = j * 64;
-    for (int b = 0; b < 64; ++b) {
-        const int64_t w = w0 + b;
-        if (w < n && (int64_t)dist[w] <= i) word |= 1ull << b;
+    uint32_t d[64];
+#pragma unroll
+    for (int b = 0; b < 64; ++b) d[b] = w0 + b < n ? (uint32_t)dist[w0 + b] : 0xFFFFFFFFu;
+    for (int32_t i = 0; i < levels; ++i) {
+        uint64_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 64; ++b) word |= (uint64_t)(d[b] <= (uint32_t)i) << b;
+        bs[(int64_t)i * W + j] = word;
     }
-    bs[t] = word;
 }
 
 // Gains of the candidates: one wave per candidate, the sum over levels
@@ -132,8 +135,8 @@ hipError_t launch_bits_level(const int32_t *rp, const int32_t *ci, int32_t n, co
 hipError_t launch_bits_group(const void *dist, int dist_bytes, int32_t n, int32_t levels, uint64_t *bs,
                              hipStream_t s) {
     const int64_t W = ((int64_t)n + 63) / 64;
-    const int64_t g = ((int64_t)levels * W + 255) / 256;
-    if (g == 0) return hipSuccess;
+    const int64_t g = (W + 255) / 256;
+    if (levels <= 0 || g == 0) return hipSuccess;
     if (dist_bytes == 1)
         hipLaunchKernelGGL((k_bits_group<uint8_t>), dim3((unsigned)g), dim3(256), 0, s,
                            reinterpret_cast<const uint8_t *>(dist), n, W, levels, bs);
