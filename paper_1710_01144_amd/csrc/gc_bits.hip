@@ -72,8 +72,25 @@ __global__ void k_bits_group(const DistT *dist, int32_t n, int64_t W, int32_t le
     if (j >= W) return;
     const int64_t w0 = j * 64;
     uint32_t d[64];
+    const DistT *src = dist + w0;
+    if (sizeof(DistT) == 1 && w0 + 64 <= n && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        // a whole word's 64 one-byte distances in four 16-byte loads
+        const uint4 *p = reinterpret_cast<const uint4 *>(src);
+        uint32_t x[16];
 #pragma unroll
-    for (int b = 0; b < 64; ++b) d[b] = w0 + b < n ? (uint32_t)dist[w0 + b] : 0xFFFFFFFFu;
+        for (int q = 0; q < 4; ++q) {
+            const uint4 v = p[q];
+            x[4 * q] = v.x;
+            x[4 * q + 1] = v.y;
+            x[4 * q + 2] = v.z;
+            x[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int b = 0; b < 64; ++b) d[b] = (x[b >> 2] >> (8 * (b & 3))) & 0xFFu;
+    } else {
+#pragma unroll
+        for (int b = 0; b < 64; ++b) d[b] = w0 + b < n ? (uint32_t)src[b] : 0xFFFFFFFFu;
+    }
     for (int32_t i = 0; i < levels; ++i) {
         uint64_t word = 0;
 #pragma unroll
