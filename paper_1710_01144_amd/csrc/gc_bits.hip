@@ -113,17 +113,32 @@ __global__ __launch_bounds__(256) void k_bits_gains(const uint64_t *bits, int32_
     const int ln = lane();
     int64_t total = 0;
     int32_t read = 0;
-    for (int32_t i = 0; i < levels_s; ++i) {
-        ++read;
-        const int32_t lb = i < levels_b ? i : levels_b - 1;
-        const uint64_t *row = bits + ((int64_t)lb * n + u) * W;
-        const uint64_t *srow = bs + (int64_t)i * W;
-        int64_t c = 0;
-        for (int64_t j = ln; j < W; j += 64) c += __popcll(row[j] & ~srow[j]);
+    // two levels per step (their loads overlap); the second one's term
+    // counts only if the first one's was not zero
+    for (int32_t i = 0; i < levels_s; i += 2) {
+        const bool two = i + 1 < levels_s;
+        read += two ? 2 : 1;
+        const int32_t l0 = i < levels_b ? i : levels_b - 1;
+        const int32_t l1 = i + 1 < levels_b ? i + 1 : levels_b - 1;
+        const uint64_t *r0 = bits + ((int64_t)l0 * n + u) * W;
+        const uint64_t *r1 = bits + ((int64_t)l1 * n + u) * W;
+        const uint64_t *s0 = bs + (int64_t)i * W;
+        const uint64_t *s1 = bs + (int64_t)(two ? i + 1 : i) * W;
+        int64_t c0 = 0, c1 = 0;
+#pragma unroll 4
+        for (int64_t j = ln; j < W; j += 64) {
+            c0 += __popcll(r0[j] & ~s0[j]);
+            if (two) c1 += __popcll(r1[j] & ~s1[j]);
+        }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-        if (c == 0) break;
-        total += c;
+        for (int o = 32; o > 0; o >>= 1) {
+            c0 += __shfl_xor(c0, o);
+            c1 += __shfl_xor(c1, o);
+        }
+        if (c0 == 0) break;
+        total += c0;
+        if (c1 == 0) break;
+        total += c1;
     }
     if (ln == 0) {
         gain[wave] = total;
