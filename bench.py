@@ -572,7 +572,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s, k=%d, %s lazy order" % (desc, k, args.order),
                    "n": g.n, "nnz": g.nnz, "k": k, "order": args.order, "block": args.block,
-                   "bitset_width": 64, "tuning": G.get_tuning(),
+                   "bitset_width": 64, "tuning": G.get_tuning(), "rocm_hip": torch.version.hip,
                    "tuned": tuning,
                    "dist_bytes": int(stats[-1]["dist_bytes"])},
         "group_wall_ms": round(ms_per_step, 4),
