@@ -91,7 +91,8 @@ typedef struct gc_opts {
     int64_t *h_log_count;   /* out: entries written (may exceed capacity: the rest dropped) */
     /* bitGreedy++ (Section 4.3 with the lazy loop): exact gains by the
        bit-vector sum from a buffer gc_bits_prepare filled (NULL: pruned BFS).
-       Plain and CELF orders; uint8 distances (GC_ERANGE if ecc(s_1) > 254). */
+       bits_bytes: the size given to gc_bits_prepare.  Plain and CELF orders;
+       uint8 distances (GC_ERANGE if ecc(s_1) > 254). */
     const void *d_bits;
     size_t bits_bytes;
     int32_t bits_levels;
@@ -251,8 +252,9 @@ int gc_topk_closeness(const gc_graph *g, int32_t k, void *d_ws, size_t ws_bytes,
  * gc_bits_gains -- g(v, S) for the count candidates in d_cand (device int32,
  *   ids in [0, n)) into d_gain (device int64), for the S whose distances
  *   d_dist holds (uint8 only, dist_bytes = 1; INF everywhere is S = {}), from
- *   a buffer gc_bits_prepare filled with `levels` levels.  The same values as
- *   gc_marginal_gains.  Synchronises once (max d(S,.)).
+ *   a buffer gc_bits_prepare filled with `levels` levels, passed with the same
+ *   `bytes` (the b^i_S rows sit after as many levels as that size holds).  The
+ *   same values as gc_marginal_gains.  Synchronises once (max d(S,.)).
  */
 int gc_bits_size(const gc_graph *g, int32_t levels, size_t *bytes);
 int gc_bits_prepare(const gc_graph *g, void *d_bits, size_t bytes, hipStream_t stream, int32_t *h_levels);
