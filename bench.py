@@ -487,6 +487,12 @@ def main():
         bits_ms = 1000 * (time.perf_counter() - t1) / reps
         assert gb.tolist() == grp.tolist() and Fb.tolist() == F.tolist(), "bitGreedy++ disagrees"
         assert sb["evals_per_round"].tolist() == stats[-1]["evals_per_round"].tolist()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            gc_, Fc, sc = G.greedy_group(k, order="celf", block=args.block, bits=True)
+        torch.cuda.synchronize()
+        bits_celf_ms = 1000 * (time.perf_counter() - t1) / reps
+        assert gc_.tolist() == grp.tolist() and Fc.tolist() == F.tolist(), "bitGreedy++ (CELF) disagrees"
         gc.timing_enable(True)
         _, _, sb = G.greedy_group(k, order=args.order, block=args.block, bits=True)
         gc.timing_enable(False)
@@ -494,7 +500,8 @@ def main():
         gain_gbs = int(sb["bits_words"]) * 8 / gain_s / 1e9 if gain_s > 0 else None
         bitg = {"levels": levels, "prepare_ms": round(prep_ms, 3),
                 "prepare_alg_gbs": round(prep_bytes / (prep_ms / 1000.0) / 1e9, 1),
-                "ms": round(bits_ms, 3), "gain_gpu_ms": round(1000 * gain_s, 3),
+                "ms": round(bits_ms, 3), "ms_celf": round(bits_celf_ms, 3),
+                "evals_later_celf": int(sc["evals_later"]), "gain_gpu_ms": round(1000 * gain_s, 3),
                 "gain_launches": int(sb["gain_launches"]), "gain_row_bytes": int(sb["bits_words"]) * 8,
                 "gain_alg_gbs": round(gain_gbs, 1) if gain_gbs else None,
                 "gain_frac": round(gain_gbs / HBM_PEAK_GBS, 4) if gain_gbs else None,

@@ -1731,7 +1731,17 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             }
             if (r) return r;
             if (timed) HIP_OK(hipEventRecord(io.ev1, s));
-            HIP_OK(hipStreamSynchronize(s));
+            // poll (no wake-up latency of a blocking wait), then block after 2 ms
+            HIP_OK(hipEventRecord(ev.score, s));
+            {
+                const double tw = now_ms();
+                hipError_t q = hipErrorNotReady;
+                for (uint32_t spin = 0; q == hipErrorNotReady; ++spin) {
+                    q = hipEventQuery(ev.score);
+                    if ((spin & 255) == 255 && now_ms() - tw > 2.0) break;
+                }
+                if (q != hipSuccess) HIP_OK(hipEventSynchronize(ev.score));
+            }
             if (timed) {
                 float ms = 0.f;
                 HIP_OK(hipEventElapsedTime(&ms, io.ev0, io.ev1));
@@ -1833,7 +1843,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     if (learned) chosen.assign((size_t)n, -1);
     auto pool_of = [&](int64_t b) { return std::max<int64_t>(b + 1, b * g->learned_pool_pct / 100); };
     const int64_t pool_size = pool_of(block);
-    if (learned) HIP_OK(hipEventCreateWithFlags(&ev.score, hipEventDisableTiming));
+    if (learned || bits) HIP_OK(hipEventCreateWithFlags(&ev.score, hipEventDisableTiming));
     // CELF and learned: candidates keyed by (ub, -id); a candidate taken for
     // evaluation leaves the tree and comes back with its new gain
     ArgTree keys;
