@@ -96,3 +96,20 @@ def test_bitgreedy_rmat16(gclib):
     grp, F, st = G.greedy_group(50, bits=True)
     assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
     assert st["evals_per_round"].tolist() == ev_b.tolist()
+
+
+def test_bits_errors(gclib, device):
+    """Too few levels for the fixed point, a bad level count and bitGreedy++
+    without rows are errors; after them the rows and bitGreedy++ still work."""
+    G = gclib.Graph.from_graphgen(graphgen.path(9))  # diameter 8: 9 levels and one to confirm
+    with pytest.raises(gclib.GCError):
+        G.bits_prepare(5)
+    with pytest.raises(gclib.GCError):
+        G.bits_prepare(1)
+    assert G.bits_prepare(10) == 9
+    G2 = gclib.Graph.from_graphgen(graphgen.path(300))  # eccentricity > 254: uint16 distances
+    with pytest.raises(ValueError):
+        G2.greedy_group(3, bits=True)
+    grp, F = oracle.greedy(graphgen.path(9), 3)
+    g3, F3, _ = G.greedy_group(3, bits=True)
+    assert g3.tolist() == grp.tolist() and F3.tolist() == F.tolist()
