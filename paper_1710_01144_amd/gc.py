@@ -321,10 +321,11 @@ class Graph:
         lib = load_library()
         nb = ctypes.c_size_t()
         _check(lib.gc_bits_size(self.handle, int(levels), ctypes.byref(nb)))
-        self.bits = torch.empty(nb.value, dtype=torch.uint8, device=self.row_ptr.device)
+        self.bits, self.bits_levels = None, 0
+        buf = torch.empty(nb.value, dtype=torch.uint8, device=self.row_ptr.device)
         lv = ctypes.c_int32()
-        _check(lib.gc_bits_prepare(self.handle, _ptr(self.bits), nb.value, _stream(), ctypes.byref(lv)))
-        self.bits_levels = int(lv.value)
+        _check(lib.gc_bits_prepare(self.handle, _ptr(buf), nb.value, _stream(), ctypes.byref(lv)))
+        self.bits, self.bits_levels = buf, int(lv.value)
         return self.bits_levels
 
     def bits_gains(self, dist, dist_bytes: int, cand) -> torch.Tensor:
