@@ -331,6 +331,20 @@ def reduce_profile(prefix, workload, k, order, out_dir, jobs):
             for name, v in sorted(j["by_kernel"].items(), key=lambda kv: -kv[1]):
                 f.write("    %-68s %10.1f MB\n" % (name, v * 1024 * j["scale"] / 1e6))
         f.write("HBM traffic of the gain launches per job: %.1f MB\n" % (rec["traffic_bytes_per_job"] / 1e6))
+        # the bitGreedy++ leg's kernels (k_bits_*), over the whole process
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            kind = "fetch" if counter == "FETCH_SIZE" else "write"
+            disp = _dispatch_counter(prefix + "_%s/run_counter_collection.csv" % kind, counter)
+            scale = job[counter]["scale"]
+            bits = collections.OrderedDict()
+            for name, v in disp:
+                if "k_bits_" in name:
+                    e = bits.setdefault(_short_kernel(name), [0, 0.0])
+                    e[0] += 1
+                    e[1] += v * 1024 * scale
+            for name, (calls, b) in bits.items():
+                f.write("bitGreedy++ %s %-40s calls %5d  %10.1f MB  (%.1f MB per call)\n" % (
+                    counter, name, calls, b / 1e6, b / 1e6 / max(calls, 1)))
     print(open(base + "_reduced.txt").read())
 
 
