@@ -408,3 +408,28 @@ def test_tuning_shapes_do_not_change_results(gclib):
     assert out["shape"] == G.get_tuning() and out["trials"] == 3
     grp, F, _ = G.greedy_group(k)
     assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+
+
+def test_resumed_runs_continue_the_greedy(gclib):
+    """A run resumed from a greedy prefix picks what the full run picks; from
+    an arbitrary start set it continues the greedy from that set."""
+    g = graphgen.ba(300, 2, 11)
+    G = _graph(gclib, g)
+    k = 8
+    grp_ref, F_ref = oracle.greedy(g, k)
+    for order in ("plain", "celf"):
+        for m in (1, 3, 7):
+            _note("resume %s m=%d" % (order, m))
+            grp, F, _ = G.greedy_group(k, order=order, prefix=grp_ref[:m])
+            assert grp.tolist() == grp_ref.tolist() and F.tolist() == F_ref.tolist()
+    start = [5, 77]
+    _note("resume from %s" % start)
+    grp, F, _ = G.greedy_group(5, prefix=np.array(start, dtype=np.int32))
+    S = list(start)
+    while len(S) < 5:
+        dS = oracle.group_dist(g, S)
+        cand = np.array([v for v in range(g.n) if v not in S], dtype=np.int32)
+        gains = oracle.gains(g, dS, cand)
+        S.append(int(cand[np.lexsort((cand, -gains))[0]]))
+    assert grp.tolist() == S
+    assert F.tolist() == [oracle.farness(g, S[: i + 1]) for i in range(5)]
