@@ -433,3 +433,20 @@ def test_resumed_runs_continue_the_greedy(gclib):
         S.append(int(cand[np.lexsort((cand, -gains))[0]]))
     assert grp.tolist() == S
     assert F.tolist() == [oracle.farness(g, S[: i + 1]) for i in range(5)]
+
+
+def test_repeated_runs_are_identical(gclib):
+    """Repeated jobs give the same picks, evaluation counts and word-level
+    work counters (the engine's results do not depend on claim races)."""
+    g = graphgen.rmat(12, 16, 7)
+    G = _graph(gclib, g)
+    keys = ("evals_round1", "evals_later", "edges_alg", "entries_word", "edges_word", "touched_word",
+            "gain_launches")
+    for order in ("plain", "celf"):
+        runs = []
+        for rep in range(3):
+            _note("repeat %s %d" % (order, rep))
+            grp, F, st = G.greedy_group(10, order=order)
+            runs.append((grp.tolist(), F.tolist(), st["evals_per_round"].tolist(),
+                         tuple(int(st[k]) for k in keys)))
+        assert runs[0] == runs[1] == runs[2]
