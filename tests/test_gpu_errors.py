@@ -1,0 +1,67 @@
+"""C-ABI error paths on the device: CSR contract violations found by the
+validating load, and out-of-range arguments of the calls.  Every case is an
+error code from the host side; no kernel runs on bad input."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _csr(edges, n, sort=True):
+    rows = [[] for _ in range(n)]
+    for a, b in edges:
+        rows[a].append(b)
+    if sort:
+        rows = [sorted(r) for r in rows]
+    rp = np.zeros(n + 1, np.int32)
+    for i in range(n):
+        rp[i + 1] = rp[i] + len(rows[i])
+    ci = np.array([x for r in rows for x in r], np.int32)
+    return rp, ci
+
+
+def _code(gclib, rp, ci):
+    with pytest.raises(gclib.GCError) as e:
+        gclib.Graph(rp, ci)
+    return e.value.code
+
+
+def test_load_rejects_bad_csr(gclib):
+    sym = [(0, 1), (1, 0), (1, 2), (2, 1)]
+    assert _code(gclib, *_csr(sym + [(2, 0)], 3)) == gclib.GC_ENOTSYM           # missing reverse edge
+    assert _code(gclib, *_csr([(0, 1), (1, 0), (2, 3), (3, 2)], 4)) == gclib.GC_EDISCONNECTED
+    assert _code(gclib, *_csr(sym + [(1, 1)], 3)) == gclib.GC_EINVAL            # self-loop
+    rp, ci = _csr([(0, 1), (0, 1), (1, 0), (1, 0)], 2)
+    assert _code(gclib, rp, ci) == gclib.GC_EINVAL                             # duplicate
+    rp, ci = _csr([(0, 2), (0, 1), (1, 0), (2, 0)], 3, sort=False)
+    assert _code(gclib, rp, ci) == gclib.GC_EINVAL                             # unsorted row
+    rp, ci = _csr(sym, 3)
+    bad = ci.copy()
+    bad[0] = 7
+    assert _code(gclib, rp, bad) == gclib.GC_EINVAL                            # id out of range
+    rp2 = rp.copy()
+    rp2[1], rp2[2] = rp2[2], rp2[1]
+    assert _code(gclib, rp2, ci) == gclib.GC_EINVAL                            # decreasing row_ptr
+
+
+def test_calls_reject_bad_arguments(gclib, device):
+    g = graphgen.gnp_connected(40, 0.1, 3)
+    G = gclib.Graph.from_graphgen(g)
+    for k in (0, g.n + 1):
+        with pytest.raises(gclib.GCError):
+            G.greedy_group(k)
+    dist = G.new_dist(1)
+    far = torch.zeros(1, dtype=torch.int64, device=device)
+    for node in (-1, g.n):
+        with pytest.raises(gclib.GCError):
+            G.update_dist(node, dist, 1, far)
+    with pytest.raises(gclib.GCError):
+        G.update_dist(0, dist, 3, far)
+    with pytest.raises(gclib.GCError):
+        G.greedy_group(5, order="learned")  # no network
+    # the handle still works after the errors
+    grp, F, _ = G.greedy_group(3)
+    assert len(grp) == 3 and F[0] > F[1] > F[2]
