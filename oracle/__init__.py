@@ -30,6 +30,7 @@ _lib = None
 
 OR_OK = 0
 OR_EINVAL = -1
+OR_ENOTSYM = -2
 OR_EDISCONNECTED = -3
 OR_EINVARIANT = -100
 
@@ -72,6 +73,8 @@ def _load():
         lib.or_greedypp.argtypes = [I64, i32p, i32p, I32, I32, I32, i32p, i64p, i64p, i64p]
         lib.or_pruned_stats.restype = ctypes.c_int
         lib.or_pruned_stats.argtypes = [I64, i32p, i32p, i32p, i32p, I64, i64p, i64p, i64p]
+        lib.or_validate.restype = ctypes.c_int
+        lib.or_validate.argtypes = [I64, i32p, i32p]
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_num_threads.argtypes = []
         _lib = lib
@@ -86,6 +89,10 @@ def _csr(g):
 def _check(rc):
     if rc == OR_EDISCONNECTED:
         raise OracleError("graph is disconnected")
+    if rc == OR_ENOTSYM:
+        raise OracleError("adjacency is not symmetric")
+    if rc == OR_EINVAL:
+        raise OracleError("invalid argument or malformed CSR (range, order, self-loop, duplicate)")
     if rc == OR_EINVARIANT:
         raise OracleError("greedy invariant violated")
     if rc != OR_OK:
@@ -94,6 +101,17 @@ def _check(rc):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def validate(g) -> None:
+    """The input contract of Section 2 (connected, undirected, simple): raises
+    OracleError for a bad row_ptr, an id out of range, an unsorted or
+    duplicate entry, a self-loop, a missing reverse edge or a second
+    component."""
+    n, rp, ci = _csr(g)
+    if rp.shape[0] != n + 1 or int(rp[n]) != ci.shape[0]:
+        raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
+    _check(_load().or_validate(n, rp, ci))
 
 
 def bfs(g, src: int) -> np.ndarray:
@@ -161,8 +179,11 @@ def gains(g, dS, cand) -> np.ndarray:
 
 
 def greedy(g, k: int, with_gains: bool = False):
-    """Tier A plain greedy.  Returns (group, F) or (group, F, gains[(k-1), n])."""
+    """Tier A plain greedy.  Returns (group, F) or (group, F, gains[(k-1), n]).
+    The CSR is checked first (validate); a violation raises OracleError."""
     n, rp, ci = _csr(g)
+    if rp.shape[0] != n + 1 or int(rp[n]) != ci.shape[0]:
+        raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
     group = np.empty(k, dtype=np.int32)
     F = np.empty(k, dtype=np.int64)
     G = np.empty((max(k - 1, 1), n), dtype=np.int64) if with_gains else None
@@ -177,8 +198,11 @@ def greedypp(g, k: int, block: int = 64, growth: int = 1):
     """Tier B CPU Greedy++.  Returns (group, F, evals per round, edges per round).
     Candidates are evaluated in batches of `block` between threshold updates;
     from the second round on each further batch of a round is `growth` times
-    the one before (up to 16 x block).  The batches only change the counts."""
+    the one before (up to 16 x block).  The batches only change the counts.
+    The CSR is checked first, as for greedy()."""
     n, rp, ci = _csr(g)
+    if rp.shape[0] != n + 1 or int(rp[n]) != ci.shape[0]:
+        raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
     group = np.empty(k, dtype=np.int32)
     F = np.empty(k, dtype=np.int64)
     ev = np.zeros(k, dtype=np.int64)

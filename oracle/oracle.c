@@ -14,7 +14,7 @@
  * Delta(v,S) of Section 4.2.
  *
  * Tier A  (or_greedy): the plain greedy of Section 3.2, computed from the
- *   definition: every round recomputes F(S u {v}) for every v not in S with a
+ *   definition (after checking the input contract, or_validate): every round recomputes F(S u {v}) for every v not in S with a
  *   full BFS from v (Section 2: SSSP is BFS on unweighted graphs), then picks
  *   the minimum.  Ties go to the smallest node id.
  * Tier B  (or_greedypp): Greedy++ of Section 4, i.e. the memory-efficient
@@ -47,6 +47,7 @@
 #define OR_OK 0
 #define OR_EDISCONNECTED -3
 #define OR_EINVAL -1
+#define OR_ENOTSYM -2
 #define OR_EINVARIANT -100
 
 /* ------------------------------------------------------------------ BFS --- */
@@ -167,6 +168,42 @@ int or_gains(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *dS,
     return OR_OK;
 }
 
+/* --------------------------------------------------------- input check --- */
+
+/*
+ * The input contract of the method (Section 2: a connected, undirected,
+ * unweighted graph), checked in full: row_ptr starts at 0 and never
+ * decreases, ids lie in [0, n), every row is strictly ascending (so no
+ * duplicate edges), no self-loops, every edge (u, v) has its reverse (v, u),
+ * and one BFS from node 0 reaches every node.  Returns OR_OK, OR_EINVAL,
+ * OR_ENOTSYM or OR_EDISCONNECTED.
+ */
+int or_validate(int64_t n, const int32_t *rp, const int32_t *ci) {
+    if (n < 1 || rp[0] != 0) return OR_EINVAL;
+    for (int64_t u = 0; u < n; ++u) {
+        if (rp[u + 1] < rp[u]) return OR_EINVAL;
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int32_t v = ci[e];
+            if (v < 0 || v >= n || v == u) return OR_EINVAL;
+            if (e > rp[u] && ci[e - 1] >= v) return OR_EINVAL;
+        }
+    }
+    for (int64_t u = 0; u < n; ++u)
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int32_t v = ci[e], lo = rp[v], hi = rp[v + 1];
+            while (lo < hi) { /* first entry of row v that is >= u */
+                int32_t mid = lo + (hi - lo) / 2;
+                if (ci[mid] < u) lo = mid + 1; else hi = mid;
+            }
+            if (lo == rp[v + 1] || ci[lo] != u) return OR_ENOTSYM;
+        }
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t r = or_bfs(n, rp, ci, 0, d, q);
+    free(d); free(q);
+    return r == n ? OR_OK : OR_EDISCONNECTED;
+}
+
 /* --------------------------------------------------------------- tier A --- */
 
 /*
@@ -183,6 +220,10 @@ int or_gains(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *dS,
 int or_greedy(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t *group,
               int64_t *Fout, int64_t *gains) {
     if (k < 1 || k > n) return OR_EINVAL;
+    {
+        int vrc = or_validate(n, rp, ci);
+        if (vrc != OR_OK) return vrc;
+    }
     int64_t *Fv = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     int32_t *dS = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -334,6 +375,10 @@ static int64_t bfscut(int64_t n, const int32_t *rp, const int32_t *ci, int32_t v
 int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t block,
                 int32_t growth, int32_t *group, int64_t *Fout, int64_t *evals, int64_t *edges) {
     if (k < 1 || k > n || block < 1 || growth < 1 || growth > 8) return OR_EINVAL;
+    {
+        int vrc = or_validate(n, rp, ci);
+        if (vrc != OR_OK) return vrc;
+    }
     /* the largest batch: block grows by `growth` per batch of a round, up to 16 x block */
     int64_t maxb = growth > 1 ? 16 * (int64_t)block : block;
     if (maxb > n) maxb = n;

@@ -339,3 +339,91 @@ def test_tier_b_equals_tier_a_ba2000():
     grp_b, F_b, _, _ = oracle.greedypp(g, 10)
     assert grp_a.tolist() == grp_b.tolist()
     assert F_a.tolist() == F_b.tolist()
+
+
+# ------------------------------------- gains and pruned-BFS statistics, pinned
+
+GAIN_PIN = [lambda s=s: graphgen.gnp_connected(n, p, s) for n, p, s in TINY] + [
+    lambda: graphgen.ba(150, 2, 41), lambda: graphgen.grid(9, 11, 42), lambda: graphgen.path(23),
+    lambda: graphgen.star(17)]
+
+
+@pytest.mark.parametrize("mk", GAIN_PIN)
+def test_gains_vs_definition(mk):
+    """or_gains (the checker of the GPU gain tests) equals g(v,S) = F(S) - F(S u {v})
+    from Floyd-Warshall distances (Section 2), for every node -- members of S
+    included (gain 0) -- and for random S of every size."""
+    g = mk()
+    n = g.n
+    D = small.floyd_warshall(g)
+    rng = np.random.default_rng(7 * n + 1)
+    for k in sorted({1, 2, max(1, n // 4), n - 1}):
+        S = rng.choice(n, size=k, replace=False).tolist()
+        dS = oracle.group_dist(g, S)
+        cand = np.concatenate([np.arange(n), rng.integers(0, n, size=5)]).astype(np.int32)
+        got = oracle.gains(g, dS, cand)
+        FS = small.farness(D, S)
+        exp = [FS - small.farness(D, S + [int(v)]) for v in cand]
+        assert got.tolist() == exp, (k, S)
+
+
+@pytest.mark.parametrize("mk", GAIN_PIN)
+def test_pruned_stats_vs_definition(mk):
+    """or_pruned_stats: the pruned BFS of Section 4.1 visits exactly
+    V(v) = {w : d(v,w) < d(S,w)} (a shortest path to such a w stays inside the
+    set, by the triangle inequality), so |V(v)| and sum_{w in V(v)} deg(w)
+    are fixed by Floyd-Warshall distances, and the gain is the definition."""
+    g = mk()
+    n = g.n
+    D = small.floyd_warshall(g)
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    rng = np.random.default_rng(11 * n + 3)
+    for k in sorted({1, max(1, n // 3), n - 1}):
+        S = rng.choice(n, size=k, replace=False).tolist()
+        dS = D[S].min(axis=0)
+        cand = np.arange(n, dtype=np.int32)
+        gg, vv, ee = oracle.pruned_stats(g, dS.astype(np.int32), cand)
+        inV = D < dS[None, :]              # row v: membership of every w in V(v)
+        assert vv.tolist() == inV.sum(axis=1).tolist()
+        assert ee.tolist() == (inV * deg[None, :]).sum(axis=1).tolist()
+        FS = int(dS.sum())
+        assert gg.tolist() == [FS - small.farness(D, S + [v]) for v in range(n)]
+        for v in S:
+            assert vv[v] == 0 and ee[v] == 0 and gg[v] == 0
+
+
+def _malformed():
+    """CSR contract violations (Section 2: connected, undirected, simple)."""
+    G = graphgen.Graph
+    rp = np.array([0, 2, 3, 4], np.int32)
+    return {
+        "missing reverse edge": G("x", 3, np.array([0, 2, 4, 5], np.int32),
+                                  np.array([1, 2, 0, 2, 0], np.int32)),
+        "self-loop": G("x", 3, np.array([0, 3, 5, 7], np.int32),
+                       np.array([0, 1, 2, 0, 2, 0, 1], np.int32)),
+        "duplicate": G("x", 3, np.array([0, 3, 5, 6], np.int32),
+                       np.array([1, 1, 2, 0, 0, 0], np.int32)),
+        "unsorted row": G("x", 3, rp, np.array([2, 1, 0, 0], np.int32)),
+        "id out of range": G("x", 3, rp, np.array([1, 3, 0, 0], np.int32)),
+        "disconnected": G("x", 4, np.array([0, 1, 2, 3, 4], np.int32),
+                          np.array([1, 0, 3, 2], np.int32)),
+        "row_ptr decreases": G("x", 3, np.array([0, 2, 1, 4], np.int32),
+                               np.array([1, 2, 0, 0], np.int32)),
+        "row_ptr[n] != nnz": G("x", 3, rp, np.array([1, 2, 0, 0, 0], np.int32)),
+    }
+
+
+@pytest.mark.parametrize("case", sorted(_malformed()))
+def test_oracle_rejects_malformed_csr(case):
+    g = _malformed()[case]
+    with pytest.raises(oracle.OracleError):
+        oracle.validate(g)
+    with pytest.raises(oracle.OracleError):
+        oracle.greedy(g, 1)
+    with pytest.raises(oracle.OracleError):
+        oracle.greedypp(g, 1)
+
+
+def test_oracle_accepts_valid_csr():
+    for g in (graphgen.path(1), graphgen.path(2), graphgen.ba(50, 2, 3), graphgen.grid(5, 6, 4)):
+        oracle.validate(g)
