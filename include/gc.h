@@ -74,7 +74,8 @@ typedef struct gc_opts {
                                threshold updates (0 = bitset_width); the picks
                                never depend on it */
     int32_t nprefix;        /* resume: the first nprefix picks are given */
-    const int32_t *h_prefix;/* host, nprefix ids (a previous run's pick order) */
+    const int32_t *h_prefix;/* host, nprefix distinct ids (a previous run's pick
+                               order); a repeated id gives GC_EINVAL */
     const void *d_mlp;      /* GC_ORDER_LEARNED: device inference block made by
                                gc_mlp_pack(); NULL otherwise */
     int32_t debug_checks;   /* 1: re-check F(S) == sum_w d(S,w) after every pick */
@@ -214,7 +215,10 @@ int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_
  * best farness found.  Ties go to the smallest id.
  *   h_node     host out: s_1
  *   h_farness  host out: F({s_1})
- * Synchronises the stream.
+ * Synchronises the stream.  GC_ERANGE for graphs with more than 2^20 nodes
+ * or 2^25 adjacency entries (the largest class this search has been run
+ * on; the same limit holds for gc_topk_closeness and for gc_greedy_group
+ * without a prefix).
  */
 int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream,
                     int32_t *h_node, int64_t *h_farness);
@@ -293,8 +297,8 @@ int gc_update_dist(const gc_graph *g, int32_t node, void *d_dist, int32_t dist_b
  *   d_visited   device int32[count] out or NULL: |V(v)|
  * Synchronises the stream twice: to read max d(S,.) (the BFS depth) and to
  * check the frontier log (an overflowed launch is redone with fewer sources
- * per launch; the results are the same).  Candidate ids are not range-checked
- * on the device; pass ids in [0, n).
+ * per launch; the results are the same).  An id outside [0, n) touches no
+ * memory and gets gain 0 (the Python binding rejects such ids instead).
  */
 int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
                       const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,

@@ -1054,9 +1054,24 @@ int run_full_bfs(const gc_graph *g, const Ws &w, int32_t root, uint16_t *dist16,
 // found so far, raised on the host between chunks only (a source's own
 // farness must not become the device's threshold), and no node is cut before
 // k farness values are known.  `top` receives the k best (F, id), ascending.
+// Largest graphs the closeness search has been run on (R-MAT scale 20,
+// edge factor 16); a larger run of an earlier version of this search ended in
+// a GPU memory fault whose cause was not found, so larger graphs are refused.
+constexpr int64_t kSearchMaxN = (int64_t)1 << 20;
+constexpr int64_t kSearchMaxNnz = (int64_t)1 << 25;
+
+int search_size_ok(const gc_graph *g) {
+    if (g->n > kSearchMaxN || g->nnz > kSearchMaxNnz)
+        return fail(GC_ERANGE, "closeness search: graphs above %lld nodes or %lld adjacency entries "
+                    "are not supported (n = %d, nnz = %lld)", (long long)kSearchMaxN,
+                    (long long)kSearchMaxNnz, g->n, (long long)g->nnz);
+    return GC_OK;
+}
+
 int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, int64_t *far,
                 int64_t *sources, int32_t *ecc_out, int32_t *v0_out = nullptr, int32_t k = 1,
                 std::vector<std::pair<int64_t, int32_t>> *top_out = nullptr) {
+    if (int rc0 = search_size_ok(g)) return rc0;
     const int32_t n = g->n;
     const auto &rp = g->h_rp;
     const auto &order = g->search_order();
@@ -1240,6 +1255,8 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
 
 extern "C" int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream,
                                int32_t *h_node, int64_t *h_farness) {
+    if (!g) return fail(GC_EINVAL, "graph is NULL");
+    if (int rc0 = search_size_ok(g)) return rc0;
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
     if (rc) return rc;
@@ -1255,6 +1272,8 @@ extern "C" int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, h
 
 extern "C" int gc_topk_closeness(const gc_graph *g, int32_t k, void *d_ws, size_t ws_bytes,
                                  hipStream_t stream, int32_t *h_nodes, int64_t *h_farness) {
+    if (!g) return fail(GC_EINVAL, "graph is NULL");
+    if (int rc0 = search_size_ok(g)) return rc0;
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
     if (rc) return rc;
@@ -1504,6 +1523,10 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                                size_t ws_bytes, hipStream_t s, int32_t *h_group,
                                int64_t *h_farness, gc_stats *h_stats) {
     const double t_start = now_ms();
+    if (!g) return fail(GC_EINVAL, "graph is NULL");
+    // without a prefix the first pick comes from the closeness search
+    if (!opts || opts->nprefix == 0)
+        if (int rc0 = search_size_ok(g)) return rc0;
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
     if (rc) return rc;
@@ -1531,6 +1554,13 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         return fail(GC_EINVAL, "bad prefix");
     for (int32_t i = 0; i < o.nprefix; ++i)
         if (o.h_prefix[i] < 0 || o.h_prefix[i] >= n) return fail(GC_EINVAL, "prefix id out of range");
+    if (o.nprefix > 1) {
+        // a group holds each node once: a repeated id is not a valid prefix
+        std::vector<int32_t> ids(o.h_prefix, o.h_prefix + o.nprefix);
+        std::sort(ids.begin(), ids.end());
+        if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+            return fail(GC_EINVAL, "prefix repeats a node id");
+    }
 
     gc_stats st{};
     if (h_stats) st.h_evals_per_round = h_stats->h_evals_per_round;

@@ -250,7 +250,8 @@ __device__ __forceinline__ void roots_body(const WideArgs &a, int64_t t) {
                 a.active[b] = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
             }
         }
-        const uint32_t d = dist[v];
+        // an id outside [0, n) touches nothing and gets gain 0
+        const uint32_t d = (uint32_t)v < (uint32_t)a.n ? (uint32_t)dist[v] : 0u;
         if (d > 0u) {
             const uint64_t bit = 1ull << j;
             const uint64_t old = atomicOr(rec(a, b, v, 0), (unsigned long long)bit);
@@ -591,6 +592,7 @@ __device__ __forceinline__ void end_body(const WideArgs &a) {
     if (a.ub_out)
         for (int64_t i = t0; i < a.nsrc; i += nt) {
             const int32_t v = a.src[i];
+            if ((uint32_t)v >= (uint32_t)a.n) continue;
             a.ub_out[v] = a.gain[i];
             a.le_out[v] = a.round;
             a.dsat_out[v] = a.dist_bytes == 1 ? (uint16_t)reinterpret_cast<const uint8_t *>(a.dist)[v]

@@ -287,6 +287,10 @@ class Graph:
     def marginal_gains(self, dist, dist_bytes: int, cand, stats: bool = False):
         cand = cand.to(self.row_ptr.device, dtype=torch.int32).contiguous()
         count = int(cand.numel())
+        if count > 0:
+            lo, hi = int(cand.min()), int(cand.max())
+            if lo < 0 or hi >= self.n:
+                raise ValueError("candidate ids must lie in [0, %d) (got %d..%d)" % (self.n, lo, hi))
         gain = torch.empty(max(count, 1), dtype=torch.int64, device=self.row_ptr.device)
         edges = torch.empty_like(gain) if stats else None
         vis = torch.empty(max(count, 1), dtype=torch.int32, device=self.row_ptr.device) if stats else None

@@ -62,6 +62,36 @@ def test_calls_reject_bad_arguments(gclib, device):
         G.update_dist(0, dist, 3, far)
     with pytest.raises(gclib.GCError):
         G.greedy_group(5, order="learned")  # no network
+    with pytest.raises(gclib.GCError):
+        G.greedy_group(5, prefix=[3, 7, 3])  # a repeated id is not a group
+    full = G.new_dist(1)
+    G.update_dist(0, full, 1, far)
+    for bad in ([-1, 2], [0, g.n]):
+        with pytest.raises(ValueError):
+            G.marginal_gains(full, 1, torch.tensor(bad, dtype=torch.int32))
     # the handle still works after the errors
     grp, F, _ = G.greedy_group(3)
     assert len(grp) == 3 and F[0] > F[1] > F[2]
+
+
+@pytest.mark.gpu
+def test_closeness_search_refuses_graphs_above_its_verified_size(gclib, device):
+    """The closeness search (first pick) refuses graphs above 2^20 nodes or
+    2^25 adjacency entries with GC_ERANGE, before touching the workspace."""
+    import ctypes
+    n = (1 << 20) + 1
+    g = graphgen.path(n)
+    G = gclib.Graph.from_graphgen(g, workspace=False)
+    lib = gclib.load_library()
+    dummy = torch.zeros(256, dtype=torch.uint8, device=device)
+    node, far = ctypes.c_int32(-1), ctypes.c_int64(-1)
+    rc = lib.gc_closest_node(G.handle, ctypes.c_void_p(dummy.data_ptr()), 256,
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                             ctypes.byref(node), ctypes.byref(far))
+    assert rc == -4 and node.value == -1 and far.value == -1
+    assert "not supported" in lib.gc_last_error().decode()
+    grp = (ctypes.c_int32 * 1)()
+    fr = (ctypes.c_int64 * 1)()
+    rc = lib.gc_greedy_group(G.handle, 1, None, ctypes.c_void_p(dummy.data_ptr()), 256,
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), grp, fr, None)
+    assert rc == -4
