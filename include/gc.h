@@ -305,6 +305,30 @@ int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
                       int32_t *d_visited, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * gc_marginal_gains_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same gains as gc_marginal_gains, with every device
+ * scratch buffer taken from one array of GC_NOALLOC_SCRATCH_BYTES bytes that
+ * the library holds on each GPU it runs on until the process ends.  No
+ * workspace argument and no allocation of any kind; the caller passes only
+ * inputs and outputs, laid out as for gc_marginal_gains.
+ *   Size limit: the graph's split rows (4 nnz bytes), per-node tables (18 n
+ *   bytes), frontier ring and clean-up list (28 bytes per entry, n + 128
+ *   entries rounded up to a power of two), the level records (1 MiB) and at
+ *   least one batch of per-node records (32 n bytes) must fit; otherwise
+ *   GC_EWORKSPACE with the bytes needed, and nothing is run.
+ *   Every call on one GPU uses the same array and first clears what it reads
+ *   before writing, so calls run one after another on that GPU may use
+ *   different graphs; calls that overlap in time on one GPU (two streams,
+ *   two host threads) race and give undefined results.
+ * Synchronises the stream as gc_marginal_gains does.
+ */
+#define GC_NOALLOC_SCRATCH_BYTES (256u << 20)
+int gc_marginal_gains_noalloc(const gc_graph *g, const void *d_dist, int32_t dist_bytes,
+                              const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
+                              int32_t *d_visited, hipStream_t stream);
+
+/*
  * gc_gain_words -- word-level work of the last gc_marginal_gains call on this
  * workspace (the bit-parallel form of Section 4.3: one frontier entry carries
  * every source of a batch that reached a node at the same level).

@@ -24,7 +24,8 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["gc_kernels.hip", "gc_wide.hip", "gc_mlp.hip", "gc_bits.hip", "gc_api.cpp"]
+SOURCES = ["gc_kernels.hip", "gc_wide.hip", "gc_mlp.hip", "gc_bits.hip", "gc_noalloc.hip",
+           "gc_api.cpp"]
 
 
 def _compile(src: str) -> str:

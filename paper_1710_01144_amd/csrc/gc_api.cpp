@@ -19,6 +19,7 @@
 #include "gc_kernels.h"
 #include "gc_mlp.h"
 #include "gc_bits.h"
+#include "gc_internal.h"
 
 using namespace gck;
 
@@ -1416,6 +1417,92 @@ extern "C" int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t 
     return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream, -1,
                      nullptr, nullptr, nullptr, nullptr, &sp, true);
 }
+
+namespace {
+
+// Layout of the marginal-gain path alone in a buffer of `bytes` bytes: the
+// counter block, the level records, the row split, the frontier ring, the
+// clean-up list and as many per-batch record blocks as fit, at most `kwant`
+// (none of the closeness-search, level-BFS, graph-table or learned-order
+// regions).  The ring and the clean-up list hold one source's BFS (n + 128
+// entries, rounded up to a power of two); an overflow of a launch with more
+// batches is redone with fewer.  False if not even one batch fits.
+bool gains_layout(const gc_graph *g, size_t bytes, int64_t kwant, WsLayout *out) {
+    WsLayout L{};
+    const size_t n = (size_t)g->n;
+    size_t o = 0;
+    L.ctr = o; o += kCtrBytes;
+    L.lvl = o; o += al256((size_t)(kMaxLevels + 2) * sizeof(WideLevel));
+    L.cisplit = o; o += al256((size_t)g->nnz * 4 + 4);
+    L.rinfo = o; o += al256(n * 16);
+    L.dist1 = o; o += al256(n * 2 + 4);
+    int64_t ring = 1;
+    while (ring < (int64_t)n + 128) ring <<= 1;
+    L.cap = ring;
+    L.zcap = ring;
+    L.ly = o; o += al256((size_t)ring * 4);
+    L.lr = o; o += al256((size_t)ring * 4);
+    L.lb = o; o += al256((size_t)ring * 4);
+    L.lo = o; o += al256((size_t)ring * 8);
+    L.lz = o; o += al256((size_t)ring * 8);
+    L.vis_stride = (n + 31) & ~(size_t)31;
+    const size_t per = L.vis_stride * 32;
+    if (o > bytes || bytes - o < per) return false;
+    int64_t kmax = (int64_t)((bytes - o) / per);
+    kmax = std::max<int64_t>(1, std::min<int64_t>(kmax, std::max<int64_t>(kwant, 1)));
+    L.kmax = kmax;
+    L.wvis = o; o += (size_t)kmax * per;
+    L.nslots = 0;
+    L.total = o;
+    *out = L;
+    return true;
+}
+
+}  // namespace
+
+namespace gck {
+
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+size_t gains_buffer_min_bytes(const gc_graph *g) {
+    // the layout with exactly one batch
+    WsLayout L;
+    gains_layout(g, (size_t)1 << 62, 1, &L);
+    return L.total;
+}
+
+int gains_in_buffer(const gc_graph *g, const void *d_dist, int32_t dist_bytes, const int32_t *d_cand,
+                    int32_t count, int64_t *d_gain, int64_t *d_edges, int32_t *d_visited, void *d_buf,
+                    size_t buf_bytes, hipStream_t stream) {
+    if (!g) return fail(GC_EINVAL, "graph is NULL");
+    if (g->wg_engine) return fail(GC_EINVAL, "the per-workgroup engine (GC_ENGINE=wg) needs a workspace");
+    if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
+    if (count < 0) return fail(GC_EINVAL, "count < 0");
+    if (count > 0 && (!d_dist || !d_cand || !d_gain)) return fail(GC_EINVAL, "NULL device pointer");
+    Ws w;
+    const int64_t kwant = ((int64_t)count + kSrc - 1) / kSrc;
+    if (!gains_layout(g, buf_bytes, kwant, &w.L))
+        return fail(GC_EWORKSPACE, "graph needs %zu bytes of scratch for one batch, %zu available",
+                    gains_buffer_min_bytes(g), buf_bytes);
+    w.base = reinterpret_cast<char *>(d_buf);
+    w.bytes = buf_bytes;
+    // the buffer holds whatever the last call left: zero the counters, the
+    // level records and the batch records this call reads before writing
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.ctr), kCtrBytes / 4, 0u, stream));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
+                           (size_t)(kMaxLevels + 2) * sizeof(WideLevel) / 4, 0u, stream));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.wvis),
+                           (size_t)w.L.kmax * w.L.vis_stride * 8, 0u, stream));
+    if (count == 0) return GC_OK;
+    if (g_timing) HIP_OK(hipEventRecord(g_ev0, stream));
+    Split sp;
+    int rc = build_split(g, w, d_dist, dist_bytes, stream, &sp);
+    if (rc) return rc;
+    return run_gains(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_visited, stream, -1,
+                     nullptr, nullptr, nullptr, nullptr, &sp, true);
+}
+
+}  // namespace gck
 
 extern "C" int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_bytes, hipStream_t stream,
                              int64_t *h_words) {

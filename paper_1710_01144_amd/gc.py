@@ -39,7 +39,7 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
             "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many",
             "gc_topk_closeness", "gc_get_tuning", "gc_set_tuning", "gc_bits_size", "gc_bits_prepare",
-            "gc_bits_gains"]
+            "gc_bits_gains", "gc_marginal_gains_noalloc"]
 TUNING_FIELDS = ("unroll", "unroll_small", "min_edges", "min_edges_small", "level_wgs_per_cu")
 MLP_PARAMS = 4801
 MLP_IN = 8
@@ -125,6 +125,8 @@ def load_library():
     lib.gc_update_dist.argtypes = [vp, i32, vp, i32, vp, ctypes.c_size_t, vp, vp]
     lib.gc_marginal_gains.restype = ctypes.c_int
     lib.gc_marginal_gains.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.gc_marginal_gains_noalloc.restype = ctypes.c_int
+    lib.gc_marginal_gains_noalloc.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp]
     lib.gc_gain_words.restype = ctypes.c_int
     lib.gc_gain_words.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i64)]
     lib.gc_greedy_group.restype = ctypes.c_int
@@ -300,6 +302,15 @@ class Graph:
         if stats:
             return gain[:count], edges[:count], vis[:count]
         return gain[:count]
+
+    def marginal_gains_noalloc(self, dist, dist_bytes: int, cand, gain, edges=None, visited=None):
+        """gc_marginal_gains_noalloc into caller-given output tensors (int64
+        gain[count], optional int64 edges and int32 visited): no allocation
+        by the library, and none here."""
+        count = int(cand.numel())
+        _check(load_library().gc_marginal_gains_noalloc(self.handle, _ptr(dist), dist_bytes, _ptr(cand),
+                                                        count, _ptr(gain), _ptr(edges), _ptr(visited),
+                                                        _stream()))
 
     def gain_words(self) -> dict:
         """Word-level work of the last marginal_gains call (see gc_gain_words)."""
