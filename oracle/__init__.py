@@ -70,9 +70,12 @@ def _load():
         lib.or_greedy.restype = ctypes.c_int
         lib.or_greedy.argtypes = [I64, i32p, i32p, I32, i32p, i64p, ctypes.c_void_p]
         lib.or_greedypp.restype = ctypes.c_int
-        lib.or_greedypp.argtypes = [I64, i32p, i32p, I32, I32, I32, i32p, i64p, i64p, i64p]
+        lib.or_greedypp.argtypes = [I64, i32p, i32p, I32, I32, I32, i32p, i64p, i64p, i64p, I32, I32,
+                                    i64p]
         lib.or_pruned_stats.restype = ctypes.c_int
         lib.or_pruned_stats.argtypes = [I64, i32p, i32p, i32p, i32p, I64, i64p, i64p, i64p]
+        lib.or_gains_cut.restype = ctypes.c_int
+        lib.or_gains_cut.argtypes = [I64, i32p, i32p, i32p, i32p, I64, I64, I32, i64p, i32p]
         lib.or_validate.restype = ctypes.c_int
         lib.or_validate.argtypes = [I64, i32p, i32p]
         lib.or_num_threads.restype = ctypes.c_int
@@ -207,8 +210,41 @@ def greedypp(g, k: int, block: int = 64, growth: int = 1):
     F = np.empty(k, dtype=np.int64)
     ev = np.zeros(k, dtype=np.int64)
     ed = np.zeros(k, dtype=np.int64)
-    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed))
+    cuts = np.zeros(k, dtype=np.int64)
+    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed, 0, 0, cuts))
     return group, F, ev, ed
+
+
+def greedypp_cut(g, k: int, block: int = 64, growth: int = 1, mode: int = 1, seed: int = 1024):
+    """Tier B with the early exit inside each candidate's pruned BFS (the
+    BFScut-style bound g <= g_l + e_l + T[l+1], see oracle.c): mode 1 in the
+    first round (after the `seed` candidates of largest degree, evaluated
+    exactly), mode 2 in every round.  Returns (group, F, evals per round,
+    edges per round, cut candidates per round)."""
+    n, rp, ci = _csr(g)
+    if rp.shape[0] != n + 1 or int(rp[n]) != ci.shape[0]:
+        raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
+    group = np.empty(k, dtype=np.int32)
+    F = np.empty(k, dtype=np.int64)
+    ev = np.zeros(k, dtype=np.int64)
+    ed = np.zeros(k, dtype=np.int64)
+    cuts = np.zeros(k, dtype=np.int64)
+    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed, int(mode),
+                               int(seed), cuts))
+    return group, F, ev, ed, cuts
+
+
+def gains_cut(g, dS, cand, thr: int, thr_id: int):
+    """The early-exit pruned BFS of tier B against one threshold: (value,
+    cut) per candidate -- the exact gain (cut 0) or the bound it stopped at
+    (cut 1)."""
+    n, rp, ci = _csr(g)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    out = np.empty(cand.shape[0], dtype=np.int64)
+    cut = np.empty(cand.shape[0], dtype=np.int32)
+    _check(_load().or_gains_cut(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), cand,
+                                int(cand.shape[0]), int(thr), int(thr_id), out, cut))
+    return out, cut
 
 
 def pruned_stats(g, dS, cand):

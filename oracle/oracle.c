@@ -330,6 +330,77 @@ static int64_t pruned_gain(const int32_t *rp, const int32_t *ci, const int32_t *
     return g;
 }
 
+/*
+ * Early exit inside a candidate's pruned BFS: a BFScut-style bound (Section
+ * 3.1) on the pruned BFS of Section 4.1.  After the nodes at distance l from
+ * u are claimed (gain so far g, e_l the adjacency entries of the nodes
+ * claimed at distance l), every node u can still claim lies at distance
+ * >= l+1 with d_S >= l+2: at most e_l of them at distance l+1 (each is a
+ * neighbour of a node claimed at distance l), each worth 1 + (d_S - l - 2),
+ * and the others worth at most d_S - l - 2.  Hence
+ *     g(u,S) <= g + e_l + T[l+1],   T[j] = sum_w max(0, d_S[w] - j - 1).
+ * The test is made after every level that claimed a node while a deeper
+ * level can still claim one (l + 1 < max d_S).  When the bound cannot beat
+ * (thr, thr_id) -- bound < thr, or bound == thr and u > thr_id -- the search
+ * stops, *cut = 1, and the bound is returned (an upper bound on the gain,
+ * kept as the candidate's stale gain).  thr_id < 0: no threshold.
+ * *edges and *visited count the nodes claimed until the stop.
+ */
+static int64_t pruned_gain_cut(const int32_t *rp, const int32_t *ci, const int32_t *dS, int32_t u,
+                               int32_t *lvl, int32_t *mark, int32_t stamp, int32_t *q, const int64_t *T,
+                               int32_t maxd, int64_t thr, int32_t thr_id, int64_t *edges, int64_t *visited,
+                               int *cut) {
+    *cut = 0;
+    if (!(0 < dS[u])) { *edges = 0; *visited = 0; return 0; } /* u in S */
+    int64_t g = dS[u], e_cnt = rp[u + 1] - rp[u], v_cnt = 1;
+    int64_t lo = 0, hi = 1;
+    mark[u] = stamp; lvl[u] = 0; q[0] = u;
+    for (int32_t l = 0; lo < hi; ++l) {
+        if (thr_id >= 0 && l + 1 < maxd) {
+            int64_t el = 0;
+            for (int64_t i = lo; i < hi; ++i) el += rp[q[i] + 1] - rp[q[i]];
+            const int64_t bound = g + el + T[l + 1];
+            if (bound < thr || (bound == thr && u > thr_id)) {
+                *cut = 1; *edges = e_cnt; *visited = v_cnt;
+                return bound;
+            }
+        }
+        int64_t tail = hi;
+        for (int64_t i = lo; i < hi; ++i) {
+            int32_t x = q[i];
+            for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
+                int32_t y = ci[e];
+                if (mark[y] == stamp) continue;
+                mark[y] = stamp;
+                if (l + 1 < dS[y]) {
+                    lvl[y] = l + 1;
+                    q[tail++] = y;
+                    g += dS[y] - (l + 1);
+                    e_cnt += rp[y + 1] - rp[y];
+                    v_cnt += 1;
+                }
+            }
+        }
+        lo = hi; hi = tail;
+    }
+    *edges = e_cnt; *visited = v_cnt;
+    return g;
+}
+
+/* T[j] = sum_w max(0, d_S[w] - j - 1) for j = 0..maxd (T[maxd] = 0), and max d_S. */
+static int32_t tail_sums(int64_t n, const int32_t *dS, int64_t **T_out) {
+    int32_t maxd = 0;
+    for (int64_t w = 0; w < n; ++w) if (dS[w] > maxd) maxd = dS[w];
+    int64_t *cnt = (int64_t *)calloc((size_t)maxd + 2, sizeof(int64_t));
+    int64_t *T = (int64_t *)calloc((size_t)maxd + 2, sizeof(int64_t));
+    for (int64_t w = 0; w < n; ++w) cnt[dS[w]]++;
+    for (int32_t j = 0; j <= maxd; ++j)
+        for (int32_t d = j + 2; d <= maxd; ++d) T[j] += (int64_t)(d - j - 1) * cnt[d];
+    free(cnt);
+    *T_out = T;
+    return maxd;
+}
+
 /* Full BFS from v with the BFScut lower bound of Section 3.1; returns F({v})
  * or -1 when the bound proves (F({v}), v) cannot beat (bestF, bestId). */
 static int64_t bfscut(int64_t n, const int32_t *rp, const int32_t *ci, int32_t v, int64_t bestF,
@@ -371,10 +442,20 @@ static int64_t bfscut(int64_t n, const int32_t *rp, const int32_t *ci, int32_t v
  * after s_1 no bound exists and every candidate is evaluated.
  * evals[i] (i = 1..k-1) receives the number of evaluations in round i;
  * edges (nullable) receives, per round, the summed adjacency entries scanned.
+ *
+ * cut_mode 1 adds the early exit of pruned_gain_cut to the first round, 2 to
+ * every round (0: none).  In the first round the cut_seed candidates of
+ * largest degree are evaluated first, exactly, and every other candidate of
+ * the round against their best (fixed for the round); in later rounds a
+ * batch is cut against the best of the batches before it.  A cut candidate
+ * keeps its bound as stale gain; it counts as an evaluation, and cuts
+ * (nullable) receives the cut candidates per round.  The picks never change.
  */
 int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t block,
-                int32_t growth, int32_t *group, int64_t *Fout, int64_t *evals, int64_t *edges) {
+                int32_t growth, int32_t *group, int64_t *Fout, int64_t *evals, int64_t *edges,
+                int32_t cut_mode, int32_t cut_seed, int64_t *cuts) {
     if (k < 1 || k > n || block < 1 || growth < 1 || growth > 8) return OR_EINVAL;
+    if (cut_mode < 0 || cut_mode > 2 || (cut_mode > 0 && cut_seed < 1)) return OR_EINVAL;
     {
         int vrc = or_validate(n, rp, ci);
         if (vrc != OR_OK) return vrc;
@@ -402,6 +483,7 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
     int32_t *batch = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxb);
     int64_t *bg = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxb);
     int64_t *be = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxb);
+    int *bc = (int *)malloc(sizeof(int) * (size_t)maxb);
     int rc = OR_OK;
 
     /* first node: decreasing degree, BFScut (sequential) */
@@ -432,13 +514,67 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
     for (int64_t v = 0; v < n; ++v) ub[v] = INT64_MAX;
     if (evals) evals[0] = 0;
     if (edges) edges[0] = 0;
+    if (cuts) cuts[0] = 0;
     int64_t F = bestF;
     for (int32_t r = 1; r < k; ++r) {
         int64_t bgain = -1;
         int32_t bid = -1;
-        int64_t pos = 0, nev = 0, ned = 0;
+        int64_t pos = 0, nev = 0, ned = 0, ncut = 0;
         int64_t cur = block < maxb ? block : maxb; /* batch size; the first round takes every node anyway */
-        for (;;) {
+        /* early exit inside the candidates' BFS: in the first round (mode 1)
+           or every round (mode 2) */
+        const int use_cut = cut_mode == 2 || (cut_mode == 1 && r == 1);
+        int64_t *T = NULL;
+        int32_t maxd = 0;
+        if (use_cut) maxd = tail_sums(n, dS, &T);
+        if (use_cut && r == 1) {
+            /* the cut_seed candidates of largest degree (ties: smaller id)
+               exactly, then every other candidate against their best, which
+               stays fixed for the rest of the round; the order of those
+               evaluations cannot change any result */
+            int32_t *all = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+            int64_t *ag = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+            int64_t *ae = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+            int *ac = (int *)calloc((size_t)n, sizeof(int));
+            uint8_t *seeded = (uint8_t *)calloc((size_t)n, 1);
+            int64_t ns = 0, na = 0;
+            for (int64_t i = 0; i < n && ns < cut_seed; ++i)
+                if (dS[order[i]] > 0) { all[ns++] = order[i]; seeded[order[i]] = 1; }
+            for (int pass = 0; pass < 2; ++pass) {
+                int64_t b0 = pass == 0 ? 0 : ns;
+                if (pass == 1) {
+                    na = ns;
+                    for (int64_t u = 0; u < n; ++u)
+                        if (dS[u] > 0 && !seeded[u]) all[na++] = (int32_t)u;
+                }
+                int64_t b1 = pass == 0 ? ns : na;
+                const int64_t thr = bgain;
+                const int32_t thr_id = pass == 0 ? -1 : bid;
+#pragma omp parallel for schedule(dynamic, 16)
+                for (int64_t j = b0; j < b1; ++j) {
+                    int t = 0;
+#ifdef _OPENMP
+                    t = omp_get_thread_num();
+#endif
+                    int64_t vis;
+                    int32_t st = ++stamps[t];
+                    ag[j] = pruned_gain_cut(rp, ci, dS, all[j], lvl[t], mark[t], st, qs[t], T, maxd, thr,
+                                            thr_id, &ae[j], &vis, &ac[j]);
+                }
+                for (int64_t j = b0; j < b1; ++j) {
+                    int32_t u = all[j];
+                    ub[u] = ag[j];
+                    ned += ae[j];
+                    ncut += ac[j];
+                    if (ac[j]) continue; /* a bound below the threshold, never the best */
+                    if (bid < 0 || ag[j] > bgain || (ag[j] == bgain && u < bid)) { bgain = ag[j]; bid = u; }
+                }
+                nev += b1 - b0;
+            }
+            free(all); free(ag); free(ae); free(ac); free(seeded);
+            pos = n; /* every candidate done */
+        }
+        for (; pos < n;) {
             int32_t nb = 0;
             while (pos < n && nb < cur) {
                 int32_t u = (int32_t)pos++;
@@ -447,6 +583,8 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
                 batch[nb++] = u;
             }
             if (nb == 0) break;
+            const int64_t thr = bgain;
+            const int32_t thr_id = use_cut ? bid : -1;
 #pragma omp parallel for schedule(dynamic, 1)
             for (int32_t j = 0; j < nb; ++j) {
                 int t = 0;
@@ -455,12 +593,20 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
 #endif
                 int64_t vis;
                 int32_t st = ++stamps[t];
-                bg[j] = pruned_gain(rp, ci, dS, batch[j], lvl[t], mark[t], st, qs[t], &be[j], &vis);
+                if (use_cut)
+                    bg[j] = pruned_gain_cut(rp, ci, dS, batch[j], lvl[t], mark[t], st, qs[t], T, maxd, thr,
+                                            thr_id, &be[j], &vis, &bc[j]);
+                else {
+                    bc[j] = 0;
+                    bg[j] = pruned_gain(rp, ci, dS, batch[j], lvl[t], mark[t], st, qs[t], &be[j], &vis);
+                }
             }
             for (int32_t j = 0; j < nb; ++j) {
                 int32_t u = batch[j];
                 ub[u] = bg[j];
                 ned += be[j];
+                ncut += bc[j];
+                if (bc[j]) continue;
                 if (bid < 0 || bg[j] > bgain || (bg[j] == bgain && u < bid)) { bgain = bg[j]; bid = u; }
             }
             nev += nb;
@@ -470,8 +616,10 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
             if (r >= 2 && cur * growth <= maxb) cur *= growth;
             else if (r >= 2) cur = maxb;
         }
+        free(T);
         if (evals) evals[r] = nev;
         if (edges) edges[r] = ned;
+        if (cuts) cuts[r] = ncut;
         /* pick and update d_S by a pruned BFS from the pick (Section 4.1: only
          * nodes with d(s,w) < d_S[w] change) */
         group[r] = bid;
@@ -498,8 +646,36 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
 done:
     for (int t = 0; t < nthr; ++t) { free(lvl[t]); free(mark[t]); free(qs[t]); }
     free(lvl); free(mark); free(qs); free(stamps);
-    free(order); free(dS); free(dnew); free(ub); free(batch); free(bg); free(be);
+    free(order); free(dS); free(dnew); free(ub); free(batch); free(bg); free(be); free(bc);
     return rc;
+}
+
+/*
+ * The early-exit search (pruned_gain_cut) for a candidate list against one
+ * threshold: out[i] is the exact gain, or the bound at which the search
+ * stopped when cut[i] = 1.
+ */
+int or_gains_cut(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *dS, const int32_t *cand,
+                 int64_t count, int64_t thr, int32_t thr_id, int64_t *out, int32_t *cut) {
+    int64_t *T = NULL;
+    const int32_t maxd = tail_sums(n, dS, &T);
+#pragma omp parallel
+    {
+        int32_t *lv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *mk = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t st = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < count; ++i) {
+            int64_t e, v;
+            int c;
+            out[i] = pruned_gain_cut(rp, ci, dS, cand[i], lv, mk, ++st, q, T, maxd, thr, thr_id, &e, &v, &c);
+            cut[i] = c;
+        }
+        free(lv); free(mk); free(q);
+    }
+    free(T);
+    return OR_OK;
 }
 
 /*

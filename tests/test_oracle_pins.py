@@ -427,3 +427,61 @@ def test_oracle_rejects_malformed_csr(case):
 def test_oracle_accepts_valid_csr():
     for g in (graphgen.path(1), graphgen.path(2), graphgen.ba(50, 2, 3), graphgen.grid(5, 6, 4)):
         oracle.validate(g)
+
+
+# ------------------------------------------- early exit (BFScut-style bound)
+
+@pytest.mark.parametrize("mk", GAIN_PIN)
+def test_early_exit_bound_vs_definition(mk):
+    """The early-exit search stops only when its bound cannot beat the
+    threshold, and the bound it keeps is never below the gain of the
+    definition (Floyd-Warshall); a search that runs to the end returns the
+    gain itself."""
+    g = mk()
+    n = g.n
+    D = small.floyd_warshall(g)
+    rng = np.random.default_rng(13 * n + 5)
+    for k in sorted({1, 2, max(1, n // 5)}):
+        S = rng.choice(n, size=k, replace=False).tolist()
+        dS = D[S].min(axis=0).astype(np.int32)
+        FS = int(dS.sum())
+        exact = [FS - small.farness(D, S + [v]) for v in range(n)]
+        for thr in sorted({0, 1, int(np.median(exact)), max(exact), max(exact) + 5}):
+            thr_id = int(rng.integers(0, n))
+            val, cut = oracle.gains_cut(g, dS, np.arange(n, dtype=np.int32), thr, thr_id)
+            for v in range(n):
+                if cut[v]:
+                    assert val[v] >= exact[v]
+                    assert val[v] < thr or (val[v] == thr and v > thr_id)
+                else:
+                    assert val[v] == exact[v]
+
+
+@pytest.mark.parametrize("mk", TIERB)
+@pytest.mark.parametrize("mode,seed,block,growth", [(1, 1, 1, 1), (1, 5, 7, 2), (1, 1024, 64, 2),
+                                                    (2, 3, 4, 1), (2, 64, 64, 2)])
+def test_tier_b_early_exit_equals_tier_a(mk, mode, seed, block, growth):
+    """Greedy++ with the early exit (first round, or every round) picks
+    exactly the plain greedy's group; the first round still evaluates every
+    candidate once."""
+    g = mk()
+    k = min(g.n, 12)
+    grp_a, F_a = oracle.greedy(g, k)
+    grp, F, ev, ed, cuts = oracle.greedypp_cut(g, k, block=block, growth=growth, mode=mode, seed=seed)
+    assert grp.tolist() == grp_a.tolist()
+    assert F.tolist() == F_a.tolist()
+    if k > 1:
+        assert ev[1] == g.n - 1
+        assert np.all(cuts <= ev)
+        if mode == 1:
+            assert np.all(cuts[2:] == 0)
+
+
+def test_early_exit_cuts_the_first_round():
+    """On a 2,000-node Barabasi-Albert graph the first round's searches stop
+    early for most candidates and scan fewer adjacency entries."""
+    g = graphgen.workload("ba2000")
+    _, _, ev0, ed0 = oracle.greedypp(g, 10, block=64, growth=2)
+    _, _, ev1, ed1, cuts = oracle.greedypp_cut(g, 10, block=64, growth=2, mode=1, seed=64)
+    assert cuts[1] > g.n // 4
+    assert ed1[1] < ed0[1]
