@@ -63,6 +63,10 @@ def _load():
         lib.gg_build_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, ctypes.c_int32,
                                      i64p, i32p, i32p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]
+        lib.gg_build_csr_directed.restype = ctypes.c_int
+        lib.gg_build_csr_directed.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, ctypes.c_int32,
+                                              i64p, i32p, i32p, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int64)]
         lib.gg_splitmix_at.restype = ctypes.c_uint64
         lib.gg_splitmix_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         _lib = lib
@@ -121,6 +125,28 @@ def from_edges(name: str, nv: int, src, dst, keep_lcc: bool = True) -> Graph:
     rp = row_ptr[: n + 1].astype(np.int32)
     ci = col_idx[:nnz].copy()
     return Graph(name, int(n), rp, ci, old_id[:n].copy())
+
+
+def from_arcs(name: str, nv: int, src, dst, keep_scc: bool = True) -> Graph:
+    """Directed graph: arcs src -> dst (rows are out-neighbours), self-loops and
+    repeated arcs dropped, optionally the largest strongly connected component,
+    relabelled in ascending old-id order, rows sorted."""
+    lib = _load()
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    ne = int(src.shape[0])
+    row_ptr = np.zeros(nv + 1, dtype=np.int64)
+    col_idx = np.zeros(max(ne, 1), dtype=np.int32)
+    old_id = np.zeros(max(nv, 1), dtype=np.int32)
+    out_n, out_nnz = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib.gg_build_csr_directed(nv, ne, src, dst, 1 if keep_scc else 0, row_ptr, col_idx, old_id,
+                                   ctypes.byref(out_n), ctypes.byref(out_nnz))
+    if rc != 0:
+        raise ValueError("arc list holds an id outside [0, nv)")
+    n, nnz = out_n.value, out_nnz.value
+    g = Graph(name, int(n), row_ptr[: n + 1].astype(np.int32), col_idx[:nnz].copy(), old_id[:n].copy())
+    g.directed = True
+    return g
 
 
 # ---------------------------------------------------------------- generators
@@ -240,6 +266,43 @@ def gnp_connected(n: int, p: float, seed: int) -> Graph:
             if splitmix_at(seed ^ 0x5DEECE66D, i * n + j) < thr:
                 pairs.add((i, j))
     return _from_pairs("gnp%d_%g_s%d" % (n, p, seed), n, sorted(pairs))
+
+
+# ------------------------------------------------------- directed graphs
+
+def directed_cycle(n: int) -> Graph:
+    """Arcs v -> v+1 (mod n)."""
+    v = np.arange(n, dtype=np.int32)
+    return from_arcs("dcycle%d" % n, n, v, (v + 1) % n)
+
+
+def gnp_directed(n: int, p: float, seed: int) -> Graph:
+    """A directed cycle through a seeded random permutation (so the graph is
+    strongly connected) plus each other arc u -> v with probability p."""
+    perm = sorted(range(n), key=lambda i: splitmix_at(seed, i))
+    arcs = {(perm[i], perm[(i + 1) % n]) for i in range(n)} if n > 1 else set()
+    thr = int(p * 2**64)
+    for u in range(n):
+        for v in range(n):
+            if u != v and splitmix_at(seed ^ 0x2545F4914F6CDD1D, u * n + v) < thr:
+                arcs.add((u, v))
+    arcs = sorted(arcs)
+    src = np.array([a for a, _ in arcs], dtype=np.int32)
+    dst = np.array([b for _, b in arcs], dtype=np.int32)
+    return from_arcs("gnpdir%d_%g_s%d" % (n, p, seed), n, src, dst, keep_scc=True)
+
+
+def rmat_directed(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19) -> Graph:
+    """R-MAT arcs (permuted ids, not symmetrised), largest strongly connected
+    component."""
+    lib = _load()
+    nv = 1 << scale
+    m = edge_factor * nv
+    src = np.zeros(m, dtype=np.int32)
+    dst = np.zeros(m, dtype=np.int32)
+    if lib.gg_rmat(scale, m, a, b, c, seed, src, dst) != 0:
+        raise ValueError("bad R-MAT arguments")
+    return from_arcs("rmatdir%d_ef%d_s%d" % (scale, edge_factor, seed), nv, src, dst, keep_scc=True)
 
 
 # --------------------------------------------------------- named workloads

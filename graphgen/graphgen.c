@@ -286,3 +286,117 @@ int gg_build_csr(int64_t nv, int64_t ne, const int32_t *src, const int32_t *dst,
     free(comp); free(queue); free(cnt); free(adj); free(fill); free(deg);
     return 0;
 }
+
+/*
+ * Directed CSR: the edge list read as arcs src[e] -> dst[e] (not
+ * symmetrised), self-loops and repeated arcs dropped, rows (out-neighbours)
+ * sorted ascending.  With keep_scc the largest strongly connected component
+ * is kept (ties: the component holding the smallest id) and relabelled in
+ * ascending order of the old ids.  Strong components by Kosaraju's two
+ * passes (finish order of a depth-first search on the arcs, then searches on
+ * the reversed arcs in reverse finish order), both iterative.
+ * Capacities: row_ptr nv+1, col_idx ne, old_id nv.  Returns 0 or -1.
+ */
+int gg_build_csr_directed(int64_t nv, int64_t ne, const int32_t *src, const int32_t *dst,
+                          int32_t keep_scc, int64_t *row_ptr, int32_t *col_idx, int32_t *old_id,
+                          int64_t *out_n, int64_t *out_nnz) {
+    for (int64_t e = 0; e < ne; ++e)
+        if (src[e] < 0 || dst[e] < 0 || src[e] >= nv || dst[e] >= nv) return -1;
+    int64_t *deg = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < ne; ++e)
+        if (src[e] != dst[e]) deg[src[e] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) deg[v + 1] += deg[v];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv + 1));
+    memcpy(fill, deg, sizeof(int64_t) * (size_t)(nv + 1));
+    int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(deg[nv] > 0 ? deg[nv] : 1));
+    for (int64_t e = 0; e < ne; ++e)
+        if (src[e] != dst[e]) adj[fill[src[e]]++] = dst[e];
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv > 0 ? nv : 1));
+    for (int64_t v = 0; v < nv; ++v) {
+        int32_t *row = adj + deg[v];
+        int64_t len = deg[v + 1] - deg[v];
+        for (int64_t i = 1; i < len; ++i) { /* insertion sort (rows of generated digraphs are short) */
+            int32_t x = row[i]; int64_t j = i - 1;
+            while (j >= 0 && row[j] > x) { row[j + 1] = row[j]; --j; }
+            row[j + 1] = x;
+        }
+        int64_t w = 0;
+        for (int64_t i = 0; i < len; ++i)
+            if (w == 0 || row[i] != row[w - 1]) row[w++] = row[i];
+        cnt[v] = w;
+    }
+    /* reversed arcs */
+    int64_t *rdeg = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    for (int64_t v = 0; v < nv; ++v)
+        for (int64_t i = 0; i < cnt[v]; ++i) rdeg[adj[deg[v] + i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) rdeg[v + 1] += rdeg[v];
+    int64_t *rfill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv + 1));
+    memcpy(rfill, rdeg, sizeof(int64_t) * (size_t)(nv + 1));
+    int32_t *radj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(rdeg[nv] > 0 ? rdeg[nv] : 1));
+    for (int64_t v = 0; v < nv; ++v)
+        for (int64_t i = 0; i < cnt[v]; ++i) radj[rfill[adj[deg[v] + i]]++] = (int32_t)v;
+    /* pass 1: finish order */
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nv > 0 ? nv : 1));
+    int32_t *stk = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nv > 0 ? nv : 1));
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv > 0 ? nv : 1));
+    uint8_t *seen = (uint8_t *)calloc((size_t)(nv > 0 ? nv : 1), 1);
+    int64_t nord = 0;
+    for (int64_t s = 0; s < nv; ++s) {
+        if (seen[s]) continue;
+        int64_t top = 0;
+        stk[top++] = (int32_t)s; pos[s] = 0; seen[s] = 1;
+        while (top > 0) {
+            int32_t x = stk[top - 1];
+            if (pos[x] < cnt[x]) {
+                int32_t y = adj[deg[x] + pos[x]++];
+                if (!seen[y]) { seen[y] = 1; pos[y] = 0; stk[top++] = y; }
+            } else {
+                order[nord++] = x;
+                --top;
+            }
+        }
+    }
+    /* pass 2: components on the reversed arcs, in reverse finish order */
+    int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nv > 0 ? nv : 1));
+    for (int64_t v = 0; v < nv; ++v) comp[v] = -1;
+    int64_t ncomp = 0, best_size = -1;
+    int32_t best_c = -1, best_min = INT32_MAX;
+    for (int64_t i = nord - 1; i >= 0; --i) {
+        int32_t s = order[i];
+        if (comp[s] >= 0) continue;
+        int64_t h = 0, t = 0;
+        int32_t mn = s;
+        stk[t++] = s; comp[s] = (int32_t)ncomp;
+        while (h < t) {
+            int32_t x = stk[h++];
+            if (x < mn) mn = x;
+            for (int64_t q = rdeg[x]; q < rdeg[x + 1]; ++q) {
+                int32_t y = radj[q];
+                if (comp[y] < 0) { comp[y] = (int32_t)ncomp; stk[t++] = y; }
+            }
+        }
+        if (t > best_size || (t == best_size && mn < best_min)) { best_size = t; best_c = (int32_t)ncomp; best_min = mn; }
+        ++ncomp;
+    }
+    int32_t *newid = stk; /* reuse */
+    int64_t nn = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+        if (!keep_scc || comp[v] == best_c) { newid[v] = (int32_t)nn; old_id[nn] = (int32_t)v; ++nn; }
+        else newid[v] = -1;
+    }
+    int64_t nnz = 0;
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        int32_t v = old_id[i];
+        for (int64_t q = 0; q < cnt[v]; ++q) {
+            int32_t y = newid[adj[deg[v] + q]];
+            if (y >= 0) col_idx[nnz++] = y; /* ids ascend with old ids: rows stay sorted */
+        }
+        row_ptr[i + 1] = nnz;
+    }
+    *out_n = nn;
+    *out_nnz = nnz;
+    free(comp); free(seen); free(pos); free(stk); free(order); free(radj); free(rfill); free(rdeg);
+    free(cnt); free(adj); free(fill); free(deg);
+    return 0;
+}

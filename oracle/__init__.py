@@ -68,16 +68,16 @@ def _load():
         lib.or_gains.restype = ctypes.c_int
         lib.or_gains.argtypes = [I64, i32p, i32p, i32p, i32p, I64, i64p]
         lib.or_greedy.restype = ctypes.c_int
-        lib.or_greedy.argtypes = [I64, i32p, i32p, I32, i32p, i64p, ctypes.c_void_p]
+        lib.or_greedy.argtypes = [I64, i32p, i32p, I32, i32p, i64p, ctypes.c_void_p, I32]
         lib.or_greedypp.restype = ctypes.c_int
         lib.or_greedypp.argtypes = [I64, i32p, i32p, I32, I32, I32, i32p, i64p, i64p, i64p, I32, I32,
-                                    i64p]
+                                    i64p, I32]
         lib.or_pruned_stats.restype = ctypes.c_int
         lib.or_pruned_stats.argtypes = [I64, i32p, i32p, i32p, i32p, I64, i64p, i64p, i64p]
         lib.or_gains_cut.restype = ctypes.c_int
         lib.or_gains_cut.argtypes = [I64, i32p, i32p, i32p, i32p, I64, I64, I32, i64p, i32p]
-        lib.or_validate.restype = ctypes.c_int
-        lib.or_validate.argtypes = [I64, i32p, i32p]
+        lib.or_validate_graph.restype = ctypes.c_int
+        lib.or_validate_graph.argtypes = [I64, i32p, i32p, I32]
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_num_threads.argtypes = []
         _lib = lib
@@ -87,6 +87,12 @@ def _load():
 def _csr(g):
     return (int(g.n), np.ascontiguousarray(g.row_ptr, dtype=np.int32),
             np.ascontiguousarray(g.col_idx, dtype=np.int32))
+
+
+def _directed(g) -> int:
+    """1 for a directed graph (rows are out-neighbour lists; graphgen marks
+    such graphs), else 0."""
+    return 1 if getattr(g, "directed", False) else 0
 
 
 def _check(rc):
@@ -107,14 +113,14 @@ def num_threads() -> int:
 
 
 def validate(g) -> None:
-    """The input contract of Section 2 (connected, undirected, simple): raises
-    OracleError for a bad row_ptr, an id out of range, an unsorted or
-    duplicate entry, a self-loop, a missing reverse edge or a second
-    component."""
+    """The input contract of Section 2 (connected, undirected, simple; or, for
+    a graph marked directed, strongly connected): raises OracleError for a bad
+    row_ptr, an id out of range, an unsorted or duplicate entry, a self-loop,
+    a missing reverse edge (undirected) or a node that cannot be reached."""
     n, rp, ci = _csr(g)
     if rp.shape[0] != n + 1 or int(rp[n]) != ci.shape[0]:
         raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
-    _check(_load().or_validate(n, rp, ci))
+    _check(_load().or_validate_graph(n, rp, ci, _directed(g)))
 
 
 def bfs(g, src: int) -> np.ndarray:
@@ -191,7 +197,7 @@ def greedy(g, k: int, with_gains: bool = False):
     F = np.empty(k, dtype=np.int64)
     G = np.empty((max(k - 1, 1), n), dtype=np.int64) if with_gains else None
     ptr = G.ctypes.data_as(ctypes.c_void_p) if with_gains else None
-    _check(_load().or_greedy(n, rp, ci, int(k), group, F, ptr))
+    _check(_load().or_greedy(n, rp, ci, int(k), group, F, ptr, _directed(g)))
     if with_gains:
         return group, F, G[: k - 1]
     return group, F
@@ -211,7 +217,8 @@ def greedypp(g, k: int, block: int = 64, growth: int = 1):
     ev = np.zeros(k, dtype=np.int64)
     ed = np.zeros(k, dtype=np.int64)
     cuts = np.zeros(k, dtype=np.int64)
-    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed, 0, 0, cuts))
+    _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed, 0, 0, cuts,
+                               _directed(g)))
     return group, F, ev, ed
 
 
@@ -230,7 +237,7 @@ def greedypp_cut(g, k: int, block: int = 64, growth: int = 1, mode: int = 1, see
     ed = np.zeros(k, dtype=np.int64)
     cuts = np.zeros(k, dtype=np.int64)
     _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed, int(mode),
-                               int(seed), cuts))
+                               int(seed), cuts, _directed(g)))
     return group, F, ev, ed, cuts
 
 

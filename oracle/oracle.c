@@ -178,7 +178,18 @@ int or_gains(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *dS,
  * and one BFS from node 0 reaches every node.  Returns OR_OK, OR_EINVAL,
  * OR_ENOTSYM or OR_EDISCONNECTED.
  */
-int or_validate(int64_t n, const int32_t *rp, const int32_t *ci) {
+int or_validate_graph(int64_t n, const int32_t *rp, const int32_t *ci, int32_t directed);
+
+int or_validate(int64_t n, const int32_t *rp, const int32_t *ci) { return or_validate_graph(n, rp, ci, 0); }
+
+/*
+ * directed = 1: the rows are out-neighbour lists of a directed graph (the
+ * strongly connected directed graphs Section 2 also admits): the same range,
+ * order, self-loop and duplicate checks, no symmetry, and instead of one
+ * component, strong connectivity -- a BFS from node 0 over the arcs and one
+ * over the reversed arcs both reach every node.
+ */
+int or_validate_graph(int64_t n, const int32_t *rp, const int32_t *ci, int32_t directed) {
     if (n < 1 || rp[0] != 0) return OR_EINVAL;
     for (int64_t u = 0; u < n; ++u) {
         if (rp[u + 1] < rp[u]) return OR_EINVAL;
@@ -187,6 +198,24 @@ int or_validate(int64_t n, const int32_t *rp, const int32_t *ci) {
             if (v < 0 || v >= n || v == u) return OR_EINVAL;
             if (e > rp[u] && ci[e - 1] >= v) return OR_EINVAL;
         }
+    }
+    if (directed) {
+        /* reach from node 0 along the arcs, then along the reversed arcs */
+        int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int64_t r = or_bfs(n, rp, ci, 0, d, q);
+        int64_t nnz = rp[n];
+        int32_t *trp = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+        int32_t *tci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+        for (int64_t e = 0; e < nnz; ++e) trp[ci[e] + 1]++;
+        for (int64_t v = 0; v < n; ++v) trp[v + 1] += trp[v];
+        int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        memcpy(fill, trp, sizeof(int32_t) * (size_t)n);
+        for (int64_t u = 0; u < n; ++u)
+            for (int32_t e = rp[u]; e < rp[u + 1]; ++e) tci[fill[ci[e]]++] = (int32_t)u;
+        int64_t rr = or_bfs(n, trp, tci, 0, d, q);
+        free(d); free(q); free(trp); free(tci); free(fill);
+        return (r == n && rr == n) ? OR_OK : OR_EDISCONNECTED;
     }
     for (int64_t u = 0; u < n; ++u)
         for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
@@ -218,10 +247,10 @@ int or_validate(int64_t n, const int32_t *rp, const int32_t *ci) {
  * the supermodularity lemma of Section 3.2; a violation returns OR_EINVARIANT.
  */
 int or_greedy(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t *group,
-              int64_t *Fout, int64_t *gains) {
+              int64_t *Fout, int64_t *gains, int32_t directed) {
     if (k < 1 || k > n) return OR_EINVAL;
     {
-        int vrc = or_validate(n, rp, ci);
+        int vrc = or_validate_graph(n, rp, ci, directed);
         if (vrc != OR_OK) return vrc;
     }
     int64_t *Fv = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -453,11 +482,11 @@ static int64_t bfscut(int64_t n, const int32_t *rp, const int32_t *ci, int32_t v
  */
 int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t block,
                 int32_t growth, int32_t *group, int64_t *Fout, int64_t *evals, int64_t *edges,
-                int32_t cut_mode, int32_t cut_seed, int64_t *cuts) {
+                int32_t cut_mode, int32_t cut_seed, int64_t *cuts, int32_t directed) {
     if (k < 1 || k > n || block < 1 || growth < 1 || growth > 8) return OR_EINVAL;
     if (cut_mode < 0 || cut_mode > 2 || (cut_mode > 0 && cut_seed < 1)) return OR_EINVAL;
     {
-        int vrc = or_validate(n, rp, ci);
+        int vrc = or_validate_graph(n, rp, ci, directed);
         if (vrc != OR_OK) return vrc;
     }
     /* the largest batch: block grows by `growth` per batch of a round, up to 16 x block */

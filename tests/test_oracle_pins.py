@@ -485,3 +485,87 @@ def test_early_exit_cuts_the_first_round():
     _, _, ev1, ed1, cuts = oracle.greedypp_cut(g, 10, block=64, growth=2, mode=1, seed=64)
     assert cuts[1] > g.n // 4
     assert ed1[1] < ed0[1]
+
+
+# ------------------------------------------------------------ directed graphs
+# Section 2 also admits strongly connected directed graphs: d(S, w) is then
+# the length of a shortest path from S to w along the arcs.
+
+def _dcycle_F(n, S):
+    """Directed cycle: the nodes after a member up to the next one form a gap
+    of L nodes at distances 1..L."""
+    S = sorted(S)
+    F = 0
+    for a, b in zip(S, S[1:] + [S[0] + n]):
+        L = b - a - 1
+        F += L * (L + 1) // 2
+    return F
+
+
+@pytest.mark.parametrize("n,k", [(5, 3), (12, 4), (21, 6)])
+def test_directed_cycle_closed_forms(n, k):
+    g = graphgen.directed_cycle(n)
+    assert np.all(oracle.farness_all(g) == n * (n - 1) // 2)
+    grp, Fs = oracle.greedy(g, k)
+    S, F = _segment_greedy(n, k, _dcycle_F)
+    assert grp.tolist() == S and Fs.tolist() == F
+    grp_b, F_b, _, _ = oracle.greedypp(g, k, block=3, growth=2)
+    assert grp_b.tolist() == S and F_b.tolist() == F
+
+
+DIRECTED = [(6, 0.2, 1), (9, 0.15, 2), (12, 0.1, 3), (12, 0.3, 4), (30, 0.06, 5)]
+
+
+@pytest.mark.parametrize("n,p,seed", DIRECTED)
+def test_directed_against_floyd_warshall(n, p, seed):
+    """BFS along arcs, farness, gains, pruned-BFS statistics, greedy (against
+    the matrix form and, for n <= 12, the brute-force optimum) and Greedy++
+    (with and without the early exit) on random strongly connected digraphs."""
+    g = graphgen.gnp_directed(n, p, seed)
+    oracle.validate(g)
+    D = small.floyd_warshall(g)
+    assert np.all(D < small.INF)  # strongly connected
+    for v in range(g.n):
+        assert np.array_equal(oracle.bfs(g, v), D[v])
+    rng = np.random.default_rng(seed)
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    for _ in range(5):
+        S = rng.choice(g.n, size=int(rng.integers(1, g.n)), replace=False).tolist()
+        dS = D[S].min(axis=0).astype(np.int32)
+        assert np.array_equal(oracle.group_dist(g, S), dS)
+        gains = oracle.gains(g, dS, np.arange(g.n, dtype=np.int32))
+        assert gains.tolist() == [small.gain_def(D, S, v) for v in range(g.n)]
+        gg, vv, ee = oracle.pruned_stats(g, dS, np.arange(g.n, dtype=np.int32))
+        inV = D < dS[None, :]
+        assert gg.tolist() == gains.tolist()
+        assert vv.tolist() == inV.sum(axis=1).tolist()
+        assert ee.tolist() == (inV * deg[None, :]).sum(axis=1).tolist()
+    for k in range(1, min(g.n, 7) + 1):
+        grp, Fs = oracle.greedy(g, k)
+        S, F = small.greedy_matrix(D, k)
+        assert grp.tolist() == S and Fs.tolist() == F
+        if g.n <= 12 and k <= 4:
+            opt, _ = small.brute_force_opt(D, k)
+            assert opt <= int(Fs[-1])
+        grp_b, F_b, _, _ = oracle.greedypp(g, k, block=2, growth=2)
+        assert grp_b.tolist() == S and F_b.tolist() == F
+        grp_c, F_c, _, _, _ = oracle.greedypp_cut(g, k, block=2, growth=2, mode=2, seed=2)
+        assert grp_c.tolist() == S and F_c.tolist() == F
+
+
+def test_directed_validation():
+    """A directed path is not strongly connected; read as undirected, a
+    one-way arc has no reverse edge."""
+    G = graphgen.Graph
+    dpath = G("x", 3, np.array([0, 1, 2, 2], np.int32), np.array([1, 2], np.int32))
+    dpath.directed = True
+    with pytest.raises(oracle.OracleError, match="disconnected"):
+        oracle.validate(dpath)
+    with pytest.raises(oracle.OracleError):
+        oracle.greedy(dpath, 1)
+    undirected = G("x", 3, np.array([0, 1, 2, 3], np.int32), np.array([1, 2, 0], np.int32))
+    with pytest.raises(oracle.OracleError, match="symmetric"):
+        oracle.validate(undirected)
+    undirected.directed = True
+    oracle.validate(undirected)  # the directed 3-cycle
+    oracle.validate(graphgen.rmat_directed(10, 8, 3))
