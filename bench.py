@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-order comparison (training + four timed orders)")
     ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--no-early-exit", action="store_true",
+                    help="skip the early-exit comparison (first-round searches stopped by their bound)")
     ap.add_argument("--workers", type=int, default=8,
                     help="batched workload: host threads (each with its own stream and workspace)")
     ap.add_argument("--reduce-profile", metavar="PREFIX",
@@ -441,6 +443,25 @@ def main():
         learned_cmp = learned_comparison(G, g, k, args, grp, F)
         log("learned vs plain " + json.dumps(learned_cmp))
 
+    # ---- the early exit inside the first round's searches, same job
+    early = None
+    if not args.no_early_exit:
+        G.greedy_group(k, order=args.order, block=args.block, early_exit=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            ge, Fe, se = G.greedy_group(k, order=args.order, block=args.block, early_exit=1)
+        torch.cuda.synchronize()
+        assert ge.tolist() == grp.tolist() and Fe.tolist() == F.tolist(), "early exit changed the picks"
+        early = {"ms": round(1000 * (time.perf_counter() - t1) / reps, 3),
+                 "ms_round1": round(float(se["ms_round1"]), 3), "ms_later": round(float(se["ms_later"]), 3),
+                 "evals_later": int(se["evals_later"]), "cut_evals": int(se["cut_evals"]),
+                 "edges_alg": int(se["edges_alg"]), "plain_ms_round1": round(float(stats[-1]["ms_round1"]), 3),
+                 "plain_ms_later": round(float(stats[-1]["ms_later"]), 3),
+                 "plain_evals_later": int(stats[-1]["evals_later"]), "plain_edges_alg": int(edges)}
+        log("early exit " + json.dumps(early))
+
     # ---- roofline of the gain launches of the job (every round): word counts
     # and the GPU time of the launches, measured by the library with HIP
     # events on the launch stream in one more run of the same job (the events
@@ -616,6 +637,7 @@ def main():
         "evals": {"round1": int(stats[-1]["evals_round1"]), "later": int(stats[-1]["evals_later"])},
         "variants": variants or None,
         "learned_vs_plain": learned_cmp,
+        "early_exit": early,
         "load_ms": load_ms,
         "breakdown_ms": {kk: round(float(stats[-1][kk]), 3) for kk in
                          ("ms_closest", "ms_round1", "ms_later", "ms_update", "ms_mlp")},

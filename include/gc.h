@@ -55,6 +55,10 @@ typedef enum gc_status {
 
 /* gc_load_csr flags */
 #define GC_VALIDATE 0x1u /* check the CSR contract (default; strongly advised) */
+#define GC_DIRECTED 0x2u /* rows are out-neighbour lists of a strongly connected
+                            directed graph (Section 2); d(S, w) is measured along
+                            the arcs, and validation checks strong connectivity
+                            instead of symmetry */
 
 /* candidate orders for the lazy greedy loop (gc_opts.order) */
 #define GC_ORDER_PLAIN 0   /* ascending node id, the scan of the paper's while-loop */
@@ -97,6 +101,17 @@ typedef struct gc_opts {
     const void *d_bits;
     size_t bits_bytes;
     int32_t bits_levels;
+    /* early exit inside the candidates' pruned BFS (a BFScut-style bound,
+       Section 3.1, on the pruned BFS of Section 4.1), first gain round only:
+       1 = on.  The early_exit_seed candidates of largest degree (0: 1024) are
+       evaluated first, exactly; every other candidate of the round stops as
+       soon as g_l + e_l + T[l+1] cannot beat their best, where g_l is its
+       gain over the nodes claimed up to distance l, e_l the adjacency entries
+       of those at distance l, and T[j] = sum_w max(0, d(S,w) - j - 1); its
+       bound becomes its stale gain.  The picks never change; the evaluation
+       counts of later rounds do.  Pruned-BFS gains only (not with d_bits). */
+    int32_t early_exit;
+    int32_t early_exit_seed;
 } gc_opts;
 
 /* Counters filled by gc_greedy_group (all optional). */
@@ -130,6 +145,7 @@ typedef struct gc_stats {
     int64_t mlp_launches;   /* feature + MLP scoring launches (learned order) */
     int64_t bits_words;     /* bitGreedy++: 64-bit row words the bit-vector gains read */
     int64_t *h_evals_per_round; /* optional, caller-owned, k entries */
+    int64_t cut_evals;      /* evaluations stopped by the early exit (gc_opts.early_exit) */
 } gc_stats;
 
 /* ---------------------------------------------------------------- graph --- */
@@ -144,7 +160,9 @@ typedef struct gc_stats {
  *   flags      GC_VALIDATE: check the CSR on the host -- GC_EINVAL for a bad
  *              row_ptr, an id out of range, an unsorted row, a self-loop or a
  *              duplicate; GC_ENOTSYM for a missing reverse edge;
- *              GC_EDISCONNECTED if not connected.
+ *              GC_EDISCONNECTED if not connected.  GC_DIRECTED: a directed
+ *              graph (no symmetry check; GC_EDISCONNECTED unless strongly
+ *              connected); every call then follows arcs out of a row.
  *   stream     used for the copies: the CSR is copied to the host once (the
  *              degree order and the balls of nearby nodes that batch the
  *              closeness search are built there; host memory 4(n + nnz)

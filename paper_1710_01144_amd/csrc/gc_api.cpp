@@ -119,6 +119,7 @@ struct gc_graph {
     int32_t learned_pool_pct;  // GC_LEARNED_POOL_PCT: the learned order ranks the
                                // largest bounds, this many percent of a block (110..1600)
     bool balls;                // GC_BALLS (default on)
+    bool directed;             // GC_DIRECTED: rows are out-neighbour lists
     const std::vector<int32_t> &search_order() const { return balls ? by_ball : by_degree; }
 };
 
@@ -151,7 +152,7 @@ static void parallel_for(int64_t n, F f) {
 // unweighted): ranges, sorted rows, no self-loops or duplicates, symmetry,
 // one component.
 static int validate_csr(int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
-                        const std::vector<int32_t> &ci) {
+                        const std::vector<int32_t> &ci, bool directed) {
     std::atomic<int> bad{GC_OK};
     std::atomic<int64_t> where{-1};
     parallel_for(n, [&](int64_t lo, int64_t hi) {
@@ -163,7 +164,7 @@ static int validate_csr(int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
                     where = u;
                     break;
                 }
-                if (!std::binary_search(ci.begin() + rp[v], ci.begin() + rp[v + 1], (int32_t)u)) {
+                if (!directed && !std::binary_search(ci.begin() + rp[v], ci.begin() + rp[v + 1], (int32_t)u)) {
                     int exp = GC_OK;
                     bad.compare_exchange_strong(exp, GC_ENOTSYM);
                     where = u;
@@ -193,7 +194,31 @@ static int validate_csr(int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
     }
     if (t != n) return fail(GC_EDISCONNECTED, "graph has %lld of %d nodes in the component of node 0",
                             (long long)t, n);
-    (void)nnz;
+    if (directed) {
+        // strongly connected: node 0 is also reached along the reversed arcs
+        std::vector<int32_t> trp((size_t)n + 1, 0), tci((size_t)nnz);
+        for (int64_t e = 0; e < nnz; ++e) trp[(size_t)ci[e] + 1]++;
+        for (int32_t v = 0; v < n; ++v) trp[(size_t)v + 1] += trp[v];
+        std::vector<int32_t> fillp(trp.begin(), trp.end() - 1);
+        for (int32_t u = 0; u < n; ++u)
+            for (int32_t e = rp[u]; e < rp[u + 1]; ++e) tci[(size_t)fillp[ci[e]]++] = u;
+        std::fill(seen.begin(), seen.end(), 0);
+        h = 0;
+        t = 0;
+        q[t++] = 0;
+        seen[0] = 1;
+        while (h < t) {
+            int32_t x = q[h++];
+            for (int32_t e = trp[x]; e < trp[x + 1]; ++e)
+                if (!seen[tci[e]]) {
+                    seen[tci[e]] = 1;
+                    q[t++] = tci[e];
+                }
+        }
+        if (t != n)
+            return fail(GC_EDISCONNECTED, "directed graph: %lld of %d nodes reach node 0 (not strongly connected)",
+                        (long long)t, n);
+    }
     return GC_OK;
 }
 
@@ -289,8 +314,9 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
             }
         }
     }
+    g->directed = (flags & GC_DIRECTED) != 0;
     if (flags & GC_VALIDATE) {
-        int rc = validate_csr(n, nnz, rp, ci);
+        int rc = validate_csr(n, nnz, rp, ci, g->directed);
         if (rc != GC_OK) {
             delete g;
             return rc;
@@ -430,7 +456,7 @@ constexpr size_t kCtrBytes = 4096;
 struct WsLayout {
     size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
     size_t wvis, ly, lr, lb, lo, lz, lvl, act, cutprev, farout, cisplit, rinfo, dist1, order, two,
-        total;
+        tails, total;
     int32_t nslots;
     SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
@@ -514,6 +540,8 @@ WsLayout ws_layout(const gc_graph *g) {
     // and the sum of neighbour degrees of every node
     L.order = o; o += al256(n * 4);
     L.two = o; o += al256(n * 8);
+    // early exit: a histogram of d(S,.) and the bound's tail table T
+    L.tails = o; o += al256((size_t)2 * (kMaxLevels + 2) * 8);
     L.total = o;
     return L;
 }
@@ -554,6 +582,11 @@ struct Ws {
     int32_t *maxd() const { return ctr() + kMaxdSlot; }
     int64_t *words() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_WORDS; }
     int64_t *zcnt() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_TOUCHED; }
+    int64_t *cuts() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_CUTS; }
+    unsigned long long *tail_hist() const { return reinterpret_cast<unsigned long long *>(base + L.tails); }
+    int64_t *tail_T() const {
+        return reinterpret_cast<int64_t *>(base + L.tails + (size_t)(kMaxLevels + 2) * 8);
+    }
     int64_t *hdr() const { return reinterpret_cast<int64_t *>(ctr() + C_I64_BASE) + L_HDR; }
     int32_t *order() const { return reinterpret_cast<int32_t *>(base + L.order); }
     int64_t *two() const { return reinterpret_cast<int64_t *>(base + L.two); }
@@ -775,6 +808,16 @@ struct LaunchShape {
     int32_t spb = 64; // sources per batch
 };
 
+// Early exit inside the candidates' BFS (see k_gain_cut): the tail table of
+// the bound for the current d(S,.), max d(S,.), and the threshold every source
+// of the call is tested against.
+struct CutSpec {
+    const int64_t *T = nullptr;
+    int32_t maxd = 0;
+    int64_t thr = 0;
+    int32_t thr_id = -1;
+};
+
 // phase: kGainsRun launches and waits; kGainsLaunch only enqueues (one
 // launch over all candidates with host-mapped results: io->hm_done set and the
 // candidates fit one chunk; *queued tells whether it did, else it ran the
@@ -787,9 +830,11 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
               int32_t *d_vis, hipStream_t s, int32_t nlev, int64_t *h_gain = nullptr,
               int64_t *h_edges = nullptr, const HostIO *io = nullptr,
               LaunchShape *shape = nullptr, const Split *split = nullptr,
-              bool timing_started = false, int phase = kGainsRun, bool *queued = nullptr) {
+              bool timing_started = false, int phase = kGainsRun, bool *queued = nullptr,
+              const CutSpec *cut = nullptr) {
     if (queued) *queued = false;
     if (count <= 0) return GC_OK;
+    if (cut && cut->thr_id < 0) cut = nullptr;  // no threshold yet: nothing to cut against
     if (phase == kGainsLaunch && (g->wg_engine || nlev < 0 || !io || !io->hm_flag || !io->hm_done ||
                                   (g->fused_grid > 0 && g->fused_gains)))
         phase = kGainsRun;
@@ -856,6 +901,22 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             // overflow its field: edges <= nnz, gain <= n * max d(S,.)
             a.pack = d_edges && g->nnz < (1ll << kPackShift) &&
                      (int64_t)g->n * (int64_t)(nlev + 1) < (1ll << (62 - kPackShift));
+            if (cut) {
+                // the cut test reads each source's gain, reach and adjacency
+                // between levels: separate counters, per-launch scratch
+                a.pack = 0;
+                if (!a.edges) a.edges = w.aux() + off;
+                if (!a.visited) a.visited = w.aux2() + off;
+                a.active = reinterpret_cast<unsigned long long *>(w.base + w.L.act);
+                a.prev = reinterpret_cast<int64_t *>(w.base + w.L.cutprev);
+                a.far_out = reinterpret_cast<int64_t *>(w.base + w.L.farout);
+                a.cut_gain = 1;
+                a.cut_T = cut->T;
+                a.cut_maxd = cut->maxd;
+                a.cut_thr = cut->thr;
+                a.cut_id = cut->thr_id;
+                a.cut_count = reinterpret_cast<unsigned long long *>(w.cuts());
+            }
             if (mapped) {
                 a.h_gain = io->hm_gain ? io->hm_gain + off : nullptr;
                 a.h_edges = io->hm_edges ? io->hm_edges + off : nullptr;
@@ -873,7 +934,16 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                 a.dsat_out = io->dist_at_eval;
                 a.round = io->round;
             }
-            if (g->fused_grid > 0 && g->fused_gains && a.nsrc <= 1024) {
+            if (cut) {
+                // roots, then the test after every level that a deeper level can follow
+                HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
+                HIP_OK(launch_gain_cut(a, 0, s));
+                for (int32_t L = 0; L < nlev; ++L) {
+                    HIP_OK(launch_wide_levels(a, dist_bytes, L, L + 1, grid, s));
+                    if (L + 1 < nlev) HIP_OK(launch_gain_cut(a, L + 1, s));
+                }
+                HIP_OK(launch_wide_end(a, nlev, grid, s));
+            } else if (g->fused_grid > 0 && g->fused_gains && a.nsrc <= 1024) {
                 HIP_OK(launch_wide_fused(a, dist_bytes, nlev, g->fused_grid, s));
             } else {
                 HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
@@ -1108,7 +1178,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
     // level-1 bound of every node against the threshold, on the device, in search order;
     // the bounds of the survivors come back to re-test them as the best improves
     uint8_t *keep_d = reinterpret_cast<uint8_t *>(w.base + w.L.q0);
-    HIP_OK(launch_lb1_filter(w.order(), g->d_rp, w.two(), n, bestF, best, keep_d, w.aux(), s));
+    HIP_OK(launch_lb1_filter(w.order(), g->d_rp, w.two(), n, bestF, best, keep_d, w.aux(), g->directed, s));
     std::vector<uint8_t> keep((size_t)n);
     HIP_OK(hipMemcpyAsync(keep.data(), keep_d, (size_t)n, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -1181,6 +1251,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
         a.active = reinterpret_cast<unsigned long long *>(w.base + w.L.act);
         a.prev = reinterpret_cast<int64_t *>(w.base + w.L.cutprev);
         a.far_out = reinterpret_cast<int64_t *>(w.base + w.L.farout);
+        a.directed = g->directed ? 1 : 0;
         HIP_OK(launch_wide_begin(a, 2, 0, s));
         int32_t L = 0;
         bool overflow = false;
@@ -1649,9 +1720,15 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             return fail(GC_EINVAL, "prefix repeats a node id");
     }
 
+    if (o.early_exit < 0 || o.early_exit > 1 || o.early_exit_seed < 0)
+        return fail(GC_EINVAL, "early_exit must be 0 or 1 and early_exit_seed >= 0");
+    if (o.early_exit && (bits || g->wg_engine))
+        return fail(GC_EINVAL, "early exit: pruned-BFS gains on the device-wide engine only");
+
     gc_stats st{};
     if (h_stats) st.h_evals_per_round = h_stats->h_evals_per_round;
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.words()), 2 * kWordCounters, 0u, s));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.cuts()), 2, 0u, s));
     std::vector<int32_t> group;
     std::vector<int64_t> Fs;
     group.reserve(k);
@@ -1825,6 +1902,25 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     const bool verbose = getenv("GC_VERBOSE") != nullptr;
     LaunchShape shape_r1, shape_later;
     int32_t cur_round = 0, first_round_idx = (int32_t)group.size();
+    // early exit in the first gain round: its candidates of largest degree
+    // first, exactly; every other one then stops as soon as its bound cannot
+    // beat their best (see k_gain_cut)
+    const bool early = o.early_exit == 1;
+    const int32_t early_seed = o.early_exit_seed > 0 ? o.early_exit_seed : 1024;
+    CutSpec cutspec;
+    const CutSpec *cur_cut = nullptr;
+    std::vector<uint8_t> seeded;
+    int r1_phase = 0;
+    if (early) {
+        int32_t md = 0;
+        HIP_OK(launch_max_dist(d_dist, dist_bytes, n, w.maxd(), s));
+        HIP_OK(hipMemcpyAsync(&md, w.maxd(), sizeof(md), hipMemcpyDeviceToHost, s));
+        HIP_OK(launch_tail_table(d_dist, dist_bytes, n, ecc_bound, w.tail_hist(), w.tail_T(), s));
+        HIP_OK(hipStreamSynchronize(s));
+        cutspec.T = w.tail_T();
+        cutspec.maxd = md;
+        seeded.assign((size_t)n, 0);
+    }
     // evaluate a list of candidates, returning gains (and edges) on the host
     int32_t bs_round = -1, bs_levels = 0;  // bitGreedy++: round and levels of the built b^i_S rows
     auto evaluate = [&](int32_t cnt) -> int {
@@ -1878,7 +1974,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             r = run_gains(g, w, d_dist, dist_bytes, dc, cnt, w.gain(),
                           want_edges ? w.aux() : nullptr, nullptr, s,
                           nlev_now(), hg, want_edges ? he : nullptr, &io, shape,
-                          &split);
+                          &split, false, kGainsRun, nullptr, cur_cut);
         }
         if (r) return r;
         st.gain_launches += 1;
@@ -2015,6 +2111,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         for (;;) {
             int32_t cnt = 0;
             bool prelaunched = false;
+            cur_cut = nullptr;
             // the CELF and plain selections fill `sel`: the free buffer when
             // overlapping, else hc
             int32_t *const sel = overlap ? hc + (size_t)cur * n : hc;
@@ -2108,12 +2205,27 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                     keys.set(u, -1);
                     sel[cnt++] = u;
                 }
+            } else if (first_round && early && r1_phase == 0) {
+                // the seed of the early exit: candidates of largest degree
+                for (size_t i = 0; i < g->by_degree.size() && cnt < early_seed; ++i) {
+                    const int32_t u = g->by_degree[i];
+                    if (inS[u]) continue;
+                    hc[cnt++] = u;
+                    seeded[u] = 1;
+                }
+                r1_phase = 1;
             } else if (first_round) {
                 // every candidate at once, packed into batches ball by ball
+                // (with the early exit: the others, against the seed's best)
                 const int32_t *r1 = g->balls ? g->by_ball.data() : nullptr;
                 for (; pos < n && cnt < blk; ++pos) {
                     const int32_t u = r1 ? r1[pos] : pos;
-                    if (!inS[u]) hc[cnt++] = u;
+                    if (!inS[u] && !(early && seeded[u])) hc[cnt++] = u;
+                }
+                if (early) {
+                    cutspec.thr = best_gain;
+                    cutspec.thr_id = best_id;
+                    cur_cut = &cutspec;
                 }
             } else {
                 // ascending ids that can still beat the best: the tree skips
@@ -2308,6 +2420,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         st.edges_word = wc[3];
         st.edges_last = wc[4];
         st.touched_word = wc[5];
+        HIP_OK(hipMemcpyAsync(&st.cut_evals, w.cuts(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
         *h_stats = st;
     }
     return GC_OK;

@@ -28,6 +28,7 @@ enum : int {
     L_WORDS = 64,
     kWordCounters = 6,
     L_TOUCHED = 72,    // records touched by the current launch (clean-up list length)
+    L_CUTS = 73,       // sources stopped by the early exit (k_gain_cut), summed over launches
     L_HDR = 80,        // stamp of gc_workspace_init: graph-derived tables are valid
 };
 
@@ -156,6 +157,16 @@ struct WideArgs {
     // host sets it only when edges < 2^kPackShift and the gain cannot reach
     // 2^(63 - kPackShift)
     int32_t pack;
+    // early exit inside the candidates' BFS (gain launches with `active`):
+    // cut_gain selects it; the bound's tail table T (cut_maxd + 2 entries),
+    // max d(S,.), and the launch's threshold (cut_thr, cut_id)
+    int32_t cut_gain;
+    int32_t cut_maxd;
+    const int64_t *cut_T;
+    int64_t cut_thr;
+    int32_t cut_id;
+    unsigned long long *cut_count; // sources stopped, added to
+    int32_t directed;              // rows are out-neighbour lists of a directed graph
 };
 constexpr int kPackShift = 30;
 // Split every row of (rp, ci) by the distances dist (see WideArgs::rinfo);
@@ -172,12 +183,19 @@ hipError_t launch_wide_fused(const WideArgs &a, int dist_bytes, int32_t nlev, in
 // Workgroups of the fused kernel that fit on the device at once (0: no
 // cooperative launch).
 int fused_max_grid(int num_cu);
+// After level l of a gain launch with the early exit: test every live source
+// (see k_gain_cut in gc_wide.hip).
+hipError_t launch_gain_cut(const WideArgs &a, int32_t l, hipStream_t s);
+// T[j] = sum_w max(0, d(S,w) - j - 1), j = 0..maxd (T[maxd + 1] = 0);
+// hist: maxd + 2 scratch words.
+hipError_t launch_tail_table(const void *dist, int dist_bytes, int64_t n, int32_t maxd,
+                             unsigned long long *hist, int64_t *T, hipStream_t s);
 hipError_t launch_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n, int64_t *out,
                              hipStream_t s);
 // bound[i] = level-1 farness bound of node order[i]; keep[i] = 1 if it may
 // beat (best_f, best_v) (i >= 1), else 0
 hipError_t launch_lb1_filter(const int32_t *order, const int32_t *rp, const int64_t *two, int32_t n,
-                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound,
+                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound, bool directed,
                              hipStream_t s);
 // out[j] = src[idx[j]]
 hipError_t launch_gather_i64(const int64_t *src, const int32_t *idx, int32_t cnt, int64_t *out,

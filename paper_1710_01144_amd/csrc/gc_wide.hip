@@ -242,8 +242,11 @@ __device__ __forceinline__ void roots_body(const WideArgs &a, int64_t t) {
         if (a.visited) a.visited[t] = 0;
         if (a.active) {
             a.far_out[t] = -1;
-            a.prev[2 * t] = 1;                           // the root itself
-            a.prev[2 * t + 1] = a.rp[v + 1] - a.rp[v];   // its adjacency
+            // closeness: the root itself and its adjacency; gains with the
+            // early exit: nothing yet (the test after level 0 counts the root)
+            const bool base = !a.cut_gain && (uint32_t)v < (uint32_t)a.n;
+            a.prev[2 * t] = base ? 1 : 0;
+            a.prev[2 * t + 1] = base ? a.rp[v + 1] - a.rp[v] : 0;
             if (j == 0) {
                 const int64_t left = a.nsrc - (int64_t)b * a.spb;
                 const int64_t nb = left < a.spb ? left : a.spb;
@@ -701,12 +704,78 @@ __global__ void k_wide_cut(WideArgs a, int32_t L, int64_t *best, int32_t fixed) 
         return;
     }
     const int64_t rem = (int64_t)a.n - r;
-    const int64_t ef = de - dr;
+    // (undirected: one of each new node's adjacency entries leads back)
+    const int64_t ef = a.directed ? de : de - dr;
     const int64_t near = ef < rem ? ef : rem;
     const int64_t lb = sum + (int64_t)(L + 2) * near + (int64_t)(L + 3) * (rem - near);
     const int64_t bv = (int64_t)__hip_atomic_load(reinterpret_cast<unsigned long long *>(best),
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lb > bv) atomicAnd(&a.active[b], ~bit);
+}
+
+// Early exit inside the candidates' pruned BFS (gain launches with an
+// active mask): after the nodes at distance l from source v are claimed (gain
+// so far g, de the adjacency entries of the nodes claimed at distance l),
+// every node v can still claim is at distance >= l+1 with d(S,.) >= l+2 --
+// at most de of them at distance l+1, each worth 1 + (d(S,.) - l - 2), the
+// rest worth at most d(S,.) - l - 2 -- so g(v,S) <= g + de + T[l+1] with
+// T[j] = sum_w max(0, d(S,w) - j - 1) (a BFScut-style bound, Section 3.1, on
+// the pruned BFS of Section 4.1).  A source whose bound cannot beat the
+// launch's threshold (bound < thr, or bound == thr and v > thr_id) stops: its
+// bits leave the batch's active mask and its gain becomes the bound (an upper
+// bound, kept as its stale gain); far_out marks it (1).  A source that claimed
+// nothing at distance l has finished and keeps its exact gain.  The test is
+// made only while a deeper level can still claim a node (l + 1 < max d(S,.)).
+__global__ void k_gain_cut(WideArgs a, int32_t l) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= a.nsrc) return;
+    const int64_t b = t / a.spb;
+    const uint64_t bit = 1ull << (t - b * a.spb);
+    if (!(__hip_atomic_load(&a.active[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) return;
+    const int64_t r = a.visited[t];
+    const int64_t e = a.edges[t];
+    const int64_t dr = r - a.prev[2 * t];
+    const int64_t de = e - a.prev[2 * t + 1];
+    a.prev[2 * t] = r;
+    a.prev[2 * t + 1] = e;
+    if (dr == 0) {
+        atomicAnd(&a.active[b], ~bit);
+        return;
+    }
+    if (l + 1 >= a.cut_maxd) return;
+    const int64_t bound = a.gain[t] + de + a.cut_T[l + 1];
+    const int32_t v = a.src[t];
+    if (bound < a.cut_thr || (bound == a.cut_thr && v > a.cut_id)) {
+        a.gain[t] = bound;
+        a.far_out[t] = 1;
+        atomicAnd(&a.active[b], ~bit);
+        atomicAdd(a.cut_count, 1ull);
+    }
+}
+
+// hist[d] = #{w : d(S,w) = d} for d <= maxd (hist zeroed by the caller)
+template <typename DistT>
+__global__ void k_dist_hist(const DistT *dist, int64_t n, int32_t maxd, unsigned long long *hist) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = dist[i];
+        if (d <= maxd) atomicAdd(&hist[d], 1ull);
+    }
+}
+
+// T[j] = sum_{d >= j+2} (d - j - 1) hist[d] for j = 0..maxd, from suffix sums
+// of the counts and of d times the counts (one thread: maxd is at most 65534)
+__global__ void k_tail_table(const unsigned long long *hist, int32_t maxd, int64_t *T) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t cnt = 0, sum = 0;  // over d > j + 1
+    for (int32_t j = maxd; j >= 0; --j) {
+        if (j + 2 <= maxd) {
+            cnt += (int64_t)hist[j + 2];
+            sum += (int64_t)(j + 2) * (int64_t)hist[j + 2];
+        }
+        T[j] = sum - (int64_t)(j + 1) * cnt;
+    }
+    T[maxd + 1] = 0;
 }
 
 // sum of neighbour degrees, one wave per row (hub rows spread over the lanes)
@@ -796,8 +865,11 @@ __global__ __launch_bounds__(256) void k_row_split(const int32_t *rp, const int3
 // Level-1 bound of F({v}) (Section 3.1 with the BFS stopped after one level):
 // deg(v) nodes at distance 1, at most two(v) - deg(v) at distance 2 (the
 // adjacency of v's neighbours minus one back-edge each), the rest at 3 or more.
+// Directed graphs: a neighbour's row need not hold the arc back to v, so
+// nodes at distance 2 are bounded by two(v) itself.
 __global__ void k_lb1_filter(const int32_t *order, const int32_t *rp, const int64_t *two, int32_t n,
-                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound) {
+                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound,
+                             int32_t directed) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (i == 0) {
@@ -808,7 +880,7 @@ __global__ void k_lb1_filter(const int32_t *order, const int32_t *rp, const int6
     const int32_t v = order[i];
     const int64_t d = rp[v + 1] - rp[v];
     const int64_t rem = (int64_t)n - 1 - d;
-    int64_t near = two[v] - d;
+    int64_t near = directed ? two[v] : two[v] - d;
     if (near > rem) near = rem;
     if (near < 0) near = 0;
     const int64_t b = d + 2 * near + 3 * (rem - near);
@@ -835,6 +907,11 @@ __global__ void k_max_dist(const DistT *dist, int64_t n, int32_t *out) {
         m = t > m ? t : m;
     }
     if (lane_id() == 0) atomicMax(out, (int32_t)m);
+}
+
+__global__ void k_fill_u64_tail(unsigned long long *p, int64_t count) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
 }
 
 __global__ void k_set_i32(int32_t *p, int32_t v) {
@@ -933,6 +1010,28 @@ hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, bool fix
     return hipGetLastError();
 }
 
+hipError_t launch_gain_cut(const WideArgs &a, int32_t l, hipStream_t s) {
+    const int g = (int)((a.nsrc + 255) / 256);
+    hipLaunchKernelGGL(k_gain_cut, dim3(g < 1 ? 1 : g), dim3(256), 0, s, a, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_table(const void *dist, int dist_bytes, int64_t n, int32_t maxd,
+                             unsigned long long *hist, int64_t *T, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64_tail, dim3(((int64_t)maxd + 2 + 255) / 256), dim3(256), 0, s, hist,
+                       (int64_t)maxd + 2);
+    int64_t g = (n + 255) / 256;
+    const int grid = (int)(g > 2048 ? 2048 : (g < 1 ? 1 : g));
+    if (dist_bytes == 1)
+        hipLaunchKernelGGL((k_dist_hist<uint8_t>), dim3(grid), dim3(256), 0, s,
+                           reinterpret_cast<const uint8_t *>(dist), n, maxd, hist);
+    else
+        hipLaunchKernelGGL((k_dist_hist<uint16_t>), dim3(grid), dim3(256), 0, s,
+                           reinterpret_cast<const uint16_t *>(dist), n, maxd, hist);
+    hipLaunchKernelGGL(k_tail_table, dim3(1), dim3(64), 0, s, hist, maxd, T);
+    return hipGetLastError();
+}
+
 hipError_t launch_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n, int64_t *out,
                              hipStream_t s) {
     const int64_t g = ((int64_t)n * 64 + 255) / 256;
@@ -957,11 +1056,11 @@ hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, con
 }
 
 hipError_t launch_lb1_filter(const int32_t *order, const int32_t *rp, const int64_t *two, int32_t n,
-                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound,
+                             int64_t best_f, int32_t best_v, uint8_t *keep, int64_t *bound, bool directed,
                              hipStream_t s) {
     const int64_t g = ((int64_t)n + 255) / 256;
     hipLaunchKernelGGL(k_lb1_filter, dim3((unsigned)(g < 1 ? 1 : g)), dim3(256), 0, s, order, rp, two, n,
-                       best_f, best_v, keep, bound);
+                       best_f, best_v, keep, bound, (int32_t)directed);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ GC_ENOMEM = -6
 GC_EDEVICE = -7
 
 GC_VALIDATE = 0x1
+GC_DIRECTED = 0x2
 
 ORDER_PLAIN = 0
 ORDER_CELF = 1
@@ -63,7 +64,8 @@ class GcOpts(ctypes.Structure):
                 ("h_log_gain", ctypes.POINTER(ctypes.c_int64)),
                 ("h_log_feat", ctypes.POINTER(ctypes.c_float)),
                 ("h_log_count", ctypes.POINTER(ctypes.c_int64)),
-                ("d_bits", ctypes.c_void_p), ("bits_bytes", ctypes.c_size_t), ("bits_levels", ctypes.c_int32)]
+                ("d_bits", ctypes.c_void_p), ("bits_bytes", ctypes.c_size_t), ("bits_levels", ctypes.c_int32),
+                ("early_exit", ctypes.c_int32), ("early_exit_seed", ctypes.c_int32)]
 
 
 class GcTuning(ctypes.Structure):
@@ -84,7 +86,7 @@ class GcStats(ctypes.Structure):
                 ("edges_last", ctypes.c_int64), ("touched_word", ctypes.c_int64),
                 ("ms_gain_gpu", ctypes.c_double), ("mlp_launches", ctypes.c_int64),
                 ("bits_words", ctypes.c_int64),
-                ("h_evals_per_round", ctypes.POINTER(ctypes.c_int64))]
+                ("h_evals_per_round", ctypes.POINTER(ctypes.c_int64)), ("cut_evals", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "h_evals_per_round"}
@@ -204,7 +206,8 @@ class Graph:
     which are copied there).  The tensors are kept alive by this object.
     """
 
-    def __init__(self, row_ptr, col_idx, validate: bool = True, workspace: bool = True):
+    def __init__(self, row_ptr, col_idx, validate: bool = True, workspace: bool = True,
+                 directed: bool = False):
         lib = load_library()
         dev = torch.device("cuda", torch.cuda.current_device())
         if isinstance(row_ptr, np.ndarray):
@@ -218,8 +221,10 @@ class Graph:
         self.n = int(self.row_ptr.numel() - 1)
         self.nnz = int(self.col_idx.numel())
         h = ctypes.c_void_p()
-        _check(lib.gc_load_csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx),
-                               GC_VALIDATE if validate else 0, _stream(), ctypes.byref(h)))
+        self.directed = bool(directed)
+        flags = (GC_VALIDATE if validate else 0) | (GC_DIRECTED if directed else 0)
+        _check(lib.gc_load_csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), flags, _stream(),
+                               ctypes.byref(h)))
         self.handle = h
         self.ws = None
         self.ws_bytes = 0
@@ -228,6 +233,7 @@ class Graph:
 
     @classmethod
     def from_graphgen(cls, g, **kw):
+        kw.setdefault("directed", bool(getattr(g, "directed", False)))
         return cls(g.row_ptr, g.col_idx, **kw)
 
     def __del__(self):
@@ -370,9 +376,11 @@ class Graph:
 
     def greedy_group(self, k: int, order: str = "plain", block: int = 0, prefix=None,
                      mlp_params=None, log_capacity: int = 0, debug: bool = False,
-                     block_growth: int = 0, bits: bool = False):
+                     block_growth: int = 0, bits: bool = False, early_exit: int = 0,
+                     early_exit_seed: int = 0):
         """bits=True: bitGreedy++ (gains by the bit-vector sum from the rows
-        bits_prepare() stored)."""
+        bits_prepare() stored).  early_exit=1: the early exit of the first gain
+        round (see gc_opts.early_exit)."""
         lib = load_library()
         opts = GcOpts()
         if bits:
@@ -386,6 +394,8 @@ class Graph:
         opts.block = int(block)
         opts.block_growth = int(block_growth)
         opts.debug_checks = 1 if debug else 0
+        opts.early_exit = int(early_exit)
+        opts.early_exit_seed = int(early_exit_seed)
         keep = []
         if prefix is not None and len(prefix) > 0:
             arr = np.ascontiguousarray(prefix, dtype=np.int32)
