@@ -253,6 +253,26 @@ def learned_comparison(G, g, k, args, grp, F):
                      "ms_later": round(float(sv["ms_later"]), 3), "ms_first": round(
                          float(sv["ms_closest"]) + float(sv["ms_round1"]), 3),
                      "gain_launches": int(sv["gain_launches"]), "mlp_launches": int(sv["mlp_launches"])}
+    # the network ranking a wide pool (16 blocks of the largest bounds): its
+    # ranking then decides which candidates go first
+    os.environ["GC_LEARNED_POOL_PCT"] = "1600"
+    try:
+        Gw = gc.Graph.from_graphgen(g)
+    finally:
+        del os.environ["GC_LEARNED_POOL_PCT"]
+    wide = {}
+    for name, blk in [("learned", net.block), ("untrained", untrained.block)]:
+        Gw.greedy_group(k, block=args.block, order="learned", mlp_params=blk)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.learned_reps):
+            gv, Fv, sv = Gw.greedy_group(k, block=args.block, order="learned", mlp_params=blk)
+        torch.cuda.synchronize()
+        assert gv.tolist() == grp.tolist() and Fv.tolist() == F.tolist(), name
+        wide[name] = {"ms": round(1000 * (time.perf_counter() - t1) / args.learned_reps, 3),
+                      "evals_later": int(sv["evals_later"]), "gain_launches": int(sv["gain_launches"])}
+    out["wide_pool_1600pct"] = wide
+    del Gw
     return out
 
 

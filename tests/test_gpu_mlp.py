@@ -93,11 +93,14 @@ def test_node_features(gclib, device):
     assert np.allclose(F, Fr, rtol=2e-6, atol=2e-6)
 
 
-def test_learned_order_picks_and_evaluations(gclib, device):
+def test_learned_order_picks_and_evaluations(gclib, device, monkeypatch):
     """Train on gains logged from plain runs of the BA-2000 and R-MAT-16
     workloads; on held-out graphs the learned order gives the plain picks
     with fewer exact evaluations in rounds >= 2 (an untrained network still
-    gives the plain picks)."""
+    gives the plain picks).  When the network ranks a wide pool (16 blocks of
+    the largest bounds, GC_LEARNED_POOL_PCT=1600) its ranking decides which
+    candidates are evaluated first, and the trained network then needs fewer
+    evaluations than the untrained one."""
     from paper_1710_01144_amd import learned
     train_runs = [(gclib.Graph.from_graphgen(graphgen.workload("ba2000")), 10),
                   (gclib.Graph.from_graphgen(graphgen.workload("rmat16")), 10),
@@ -120,6 +123,17 @@ def test_learned_order_picks_and_evaluations(gclib, device):
         assert sl["evals_later"] < sp["evals_later"], (sl["evals_later"], sp["evals_later"])
         print("evals later: plain %d learned %d untrained %d" %
               (sp["evals_later"], sl["evals_later"], su["evals_later"]), flush=True)
+        monkeypatch.setenv("GC_LEARNED_POOL_PCT", "1600")
+        Gw = gclib.Graph.from_graphgen(g)
+        monkeypatch.delenv("GC_LEARNED_POOL_PCT")
+        _note("held-out %s k=%d, wide pool" % (g.name, k))
+        gl, Fl, slw = Gw.greedy_group(k, order="learned", mlp_params=net.block)
+        gu, Fu, suw = Gw.greedy_group(k, order="learned", mlp_params=untrained.block)
+        gc_, Fc, sc = Gw.greedy_group(k, order="celf")
+        assert gl.tolist() == gp.tolist() and gu.tolist() == gp.tolist() and gc_.tolist() == gp.tolist()
+        print("wide pool, evals later: learned %d untrained %d celf %d" %
+              (slw["evals_later"], suw["evals_later"], sc["evals_later"]), flush=True)
+        assert slw["evals_later"] < suw["evals_later"], (slw["evals_later"], suw["evals_later"])
 
 
 def test_learned_device_first_block_matches_host_ranking(gclib, device):
