@@ -81,8 +81,9 @@ def parse():
                     help="CPU baseline: repeat the oracle run until this much time is spent")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--tune", action="store_true",
-                    help="autotune the engine's launch shapes for this graph and job before timing "
-                         "(results do not depend on them; cache in $GC_TUNE_CACHE if set)")
+                    help="autotune the engine's launch shapes and the lazy loop's batch schedule "
+                         "(block, growth) for this graph and job before timing (the picks do not "
+                         "depend on them; cache in $GC_TUNE_CACHE if set)")
     ap.add_argument("--no-bitgreedy", action="store_true",
                     help="skip bitGreedy++ (bit-vector gains; graphs of <= 70k nodes with uint8 distances)")
     ap.add_argument("--no-overlap", action="store_true",
@@ -416,19 +417,23 @@ def main():
     log("workspace %.1f MiB; load %s" % (G.ws_bytes / 2**20, json.dumps(load_ms)))
     k = args.k
     tuning = None
+    growth = 0  # the library's default (2)
     if args.tune:
         from paper_1710_01144_amd import tune
         tuning = tune.autotune(G, k, order=args.order, block=args.block, reps=3)
+        sched = tune.autotune_schedule(G, k, order=args.order, reps=2)
+        tuning = dict(tuning, schedule=sched)
+        args.block, growth = sched["block"], sched["growth"]
         log("tuning " + json.dumps(tuning))
 
     # ---- timed job
     for _ in range(args.warmup):
-        G.greedy_group(k, order=args.order, block=args.block)
+        G.greedy_group(k, order=args.order, block=args.block, block_growth=growth)
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        grp, F, st = G.greedy_group(k, order=args.order, block=args.block)
+        grp, F, st = G.greedy_group(k, order=args.order, block=args.block, block_growth=growth)
         stats.append(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -487,7 +492,7 @@ def main():
     # events on the launch stream in one more run of the same job (the events
     # stay out of the wall-timed steps)
     gc.timing_enable(True)
-    _, _, st = G.greedy_group(k, order=args.order, block=args.block)
+    _, _, st = G.greedy_group(k, order=args.order, block=args.block, block_growth=growth)
     gc.timing_enable(False)
     dist_bytes = int(st["dist_bytes"])
     launches = int(st["gain_launches"])
@@ -650,6 +655,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s, k=%d, %s lazy order" % (desc, k, args.order),
                    "n": g.n, "nnz": g.nnz, "k": k, "order": args.order, "block": args.block,
+                   "block_growth": growth or 2,
                    "bitset_width": 64, "tuning": G.get_tuning(), "rocm_hip": torch.version.hip,
                    "tuned": tuning,
                    "dist_bytes": int(stats[-1]["dist_bytes"])},

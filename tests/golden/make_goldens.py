@@ -15,6 +15,7 @@ same graph.
                        from the definition) group and F
   rmat20_k100_tierB.json  R-MAT scale 20, k = 100: tier B as above
   rmat16_k50_tierA.json   R-MAT scale 16, k = 50: tier A
+  grid1024_k100_tierB.json  the perturbed 1024 x 1024 grid, k = 100: tier B
 """
 from __future__ import annotations
 
@@ -84,6 +85,16 @@ def rmat20():
     print("rmat20 tier B: %.1f s" % (time.time() - t0), flush=True)
 
 
+def grid1024():
+    g = graphgen.workload("grid1024")
+    t0 = time.time()
+    r = {"workload": "grid1024", "n": g.n, "nnz": g.nnz, "k": 100, "sha256": g.sha256(), "tier": "B",
+         "block": 64, "growth": 2}
+    r.update(_tier_b(g, 100))
+    _write("grid1024_k100_tierB.json", r)
+    print("grid1024 tier B: %.1f s" % (time.time() - t0), flush=True)
+
+
 def rmat16a():
     g = graphgen.workload("rmat16")
     t0 = time.time()
@@ -94,6 +105,6 @@ def rmat16a():
 
 
 if __name__ == "__main__":
-    todo = sys.argv[1:] or ["batchba", "rmat20", "rmat16a"]
+    todo = sys.argv[1:] or ["batchba", "rmat20", "rmat16a", "grid1024"]
     for name in todo:
-        {"batchba": batchba, "rmat20": rmat20, "rmat16a": rmat16a}[name]()
+        {"batchba": batchba, "rmat20": rmat20, "rmat16a": rmat16a, "grid1024": grid1024}[name]()

@@ -450,3 +450,18 @@ def test_repeated_runs_are_identical(gclib):
             runs.append((grp.tolist(), F.tolist(), st["evals_per_round"].tolist(),
                          tuple(int(st[k]) for k in keys)))
         assert runs[0] == runs[1] == runs[2]
+
+
+def test_schedule_autotuner_keeps_the_picks(gclib):
+    """The batch-schedule tuner times every (block, growth) of its grid on a
+    3,000-node BA graph; every schedule gives the same group (checked inside),
+    and the chosen one reproduces CPU Greedy++'s group and its evaluation
+    counts under that schedule."""
+    from paper_1710_01144_amd import tune
+    g = graphgen.ba(3000, 3, 41)
+    G = _graph(gclib, g)
+    out = tune.autotune_schedule(G, 15, schedules=[(16, 1), (64, 2), (256, 8)], reps=1)
+    grp, F, st = G.greedy_group(15, block=out["block"], block_growth=out["growth"])
+    grp_b, F_b, ev_b, _ = oracle.greedypp(g, 15, block=out["block"], growth=out["growth"])
+    assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+    assert st["evals_per_round"].tolist() == ev_b.tolist()

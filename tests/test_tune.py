@@ -20,9 +20,12 @@ class FakeGraph:
     def set_tuning(self, **kw):
         self.shape.update(kw)
 
-    def greedy_group(self, k, order="plain", block=0, mlp_params=None):
+    def greedy_group(self, k, order="plain", block=0, mlp_params=None, block_growth=0):
         self.jobs += 1
-        return None, None, {"ms_total": self.cost(self.shape)}
+        cost = self.cost(self.shape)
+        if block_growth:
+            cost += abs(block - 128) / 100.0 + abs(block_growth - 4) / 10.0
+        return [0, 1], [5, 3], {"ms_total": cost}
 
 
 def _cost(s):
@@ -55,3 +58,25 @@ def test_coordinate_descent_and_cache(tmp_path):
     # another job size is a separate entry
     g3 = FakeGraph(_cost)
     assert not tune.autotune(g3, 6, cache_path=path, reps=1)["cached"]
+
+
+def test_schedule_tuner_picks_fastest_and_caches(tmp_path):
+    path = str(tmp_path / "tune.json")
+    g = FakeGraph(_cost)
+    out = tune.autotune_schedule(g, 5, cache_path=path, reps=1)
+    assert (out["block"], out["growth"]) == (128, 4) and not out["cached"]
+    assert out["ms"] < out["ms_default"]
+    assert len(out["table"]) == len(tune.SCHEDULES)
+    g2 = FakeGraph(_cost)
+    out2 = tune.autotune_schedule(g2, 5, cache_path=path, reps=1)
+    assert out2["cached"] and g2.jobs == 0 and out2["block"] == 128
+
+
+def test_schedule_tuner_rejects_changed_picks():
+    class Flaky(FakeGraph):
+        def greedy_group(self, k, order="plain", block=0, mlp_params=None, block_growth=0):
+            self.jobs += 1
+            return [block % 3, 1], [5, 3], {"ms_total": 1.0}
+    import pytest
+    with pytest.raises(AssertionError):
+        tune.autotune_schedule(Flaky(_cost), 5, schedules=[(32, 1), (64, 1)], reps=1)
