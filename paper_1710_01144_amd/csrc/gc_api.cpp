@@ -1658,14 +1658,27 @@ struct ArgTree {
     }
 };
 
+// Failure injection for the error paths of the greedy's host allocations:
+// GC_TEST_FAIL_ALLOC=<n> makes the n-th pinned allocation of each greedy call
+// fail (1 = the first), as an exhausted pinned pool would.
+int fail_alloc_at() {
+    const char *e = getenv("GC_TEST_FAIL_ALLOC");
+    return e ? atoi(e) : 0;
+}
+
 struct PinnedBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    int *counter = nullptr;  // allocations made by this call (failure injection)
     ~PinnedBuf() {
         if (p) (void)hipHostFree(p);
     }
     hipError_t ensure(size_t b) {
         if (b <= bytes) return hipSuccess;
+        if (counter) {
+            const int at = fail_alloc_at();
+            if (at > 0 && ++*counter == at) return hipErrorOutOfMemory;
+        }
         if (p) (void)hipHostFree(p);
         p = nullptr;
         bytes = 0;
@@ -1738,7 +1751,9 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     std::vector<int32_t> last_eval((size_t)n, -1);
     std::vector<uint8_t> ds_at_eval;  // d(S,v) when v was last evaluated (features)
     // pinned host buffers the kernels read and write directly (no copy calls)
+    int alloc_count = 0;
     PinnedBuf pin_cand, pin_gain, pin_flag;
+    pin_cand.counter = pin_gain.counter = pin_flag.counter = &alloc_count;
     // (two sets: a block's bookkeeping overlaps the next block's launch)
     if (pin_cand.ensure(sizeof(int32_t) * (size_t)n * 2) != hipSuccess ||
         pin_gain.ensure(sizeof(int64_t) * (size_t)n * 4) != hipSuccess ||
@@ -1788,6 +1803,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     if (need_state && ws_bytes < w.L.total + gc_mlp_ws_bytes(n))
         return fail(GC_EWORKSPACE, "learned order / logging needs the full gc_workspace_size()");
     PinnedBuf pin_score, pin_feat, pin_pool;
+    pin_score.counter = pin_feat.counter = pin_pool.counter = &alloc_count;
     float *hscore = nullptr, *dscore = nullptr, *hfeat = nullptr, *dfeat = nullptr;
     int32_t *hpool = nullptr, *dpool = nullptr;
     if (need_state) {

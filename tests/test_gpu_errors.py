@@ -95,3 +95,31 @@ def test_closeness_search_refuses_graphs_above_its_verified_size(gclib, device):
     rc = lib.gc_greedy_group(G.handle, 1, None, ctypes.c_void_p(dummy.data_ptr()), 256,
                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), grp, fr, None)
     assert rc == -4
+
+
+@pytest.mark.gpu
+def test_workspace_too_small_and_allocation_failures(gclib, device, monkeypatch):
+    """A workspace below gc_workspace_size gives GC_EWORKSPACE before any
+    kernel runs; a failed pinned host allocation inside the greedy (injected
+    with GC_TEST_FAIL_ALLOC) gives GC_ENOMEM; the handle keeps working after
+    both."""
+    import ctypes
+    g = graphgen.ba(500, 3, 9)
+    G = gclib.Graph.from_graphgen(g)
+    lib = gclib.load_library()
+    small = torch.zeros(G.ws_bytes // 2, dtype=torch.uint8, device=device)
+    node, far = ctypes.c_int32(-1), ctypes.c_int64(-1)
+    rc = lib.gc_closest_node(G.handle, ctypes.c_void_p(small.data_ptr()), small.numel(),
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                             ctypes.byref(node), ctypes.byref(far))
+    assert rc == gclib.GC_EWORKSPACE and node.value == -1
+    assert b"workspace" in lib.gc_last_error()
+    grp_ref, F_ref, _ = G.greedy_group(5)
+    for at in (1, 2, 3):
+        monkeypatch.setenv("GC_TEST_FAIL_ALLOC", str(at))
+        with pytest.raises(gclib.GCError) as e:
+            G.greedy_group(5)
+        assert e.value.code == gclib.GC_ENOMEM
+    monkeypatch.delenv("GC_TEST_FAIL_ALLOC")
+    grp, F, _ = G.greedy_group(5)
+    assert grp.tolist() == grp_ref.tolist() and F.tolist() == F_ref.tolist()
