@@ -101,13 +101,9 @@ struct gc_graph {
     int32_t max_deg;
     int32_t num_cu;
     // tuning read once at load time so the workspace layout never changes
-    int64_t slots_target;   // GC_SLOTS
     int64_t vis_budget;     // GC_VIS_BUDGET_MB (bytes)
-    int32_t fused_grid;     // workgroups of the one-kernel small launch (0: off; GC_FUSED, GC_FUSED_WGS)
-    bool fused_gains;       // also for gain launches of <= 1024 sources (GC_FUSED_GAINS=1)
     int64_t log_entries;    // GC_LOG_ENTRIES
     int64_t touch_entries;  // GC_TOUCH_ENTRIES (0: n per batch, at most 64M)
-    bool wg_engine;         // GC_ENGINE=wg
     int32_t level_wgs_per_cu;  // GC_LEVEL_WGS (workgroups per CU of a level kernel)
     int32_t unroll;         // GC_UNROLL (4 or 8)
     int32_t min_edges;      // GC_MIN_EDGES (adjacency entries per workgroup)
@@ -345,33 +341,10 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
             return fail(GC_ENOMEM, "no memory for the ball order");
         }
     }
-    g->wg_engine = false;
-    if (const char *e = getenv("GC_ENGINE")) g->wg_engine = strcmp(e, "wg") == 0;
-    g->slots_target = (g->wg_engine ? 4LL : 1LL) * cus;
-    if (const char *e = getenv("GC_SLOTS")) {
-        long long v = strtoll(e, nullptr, 10);
-        if (v > 0) g->slots_target = v;
-    }
     g->vis_budget = (int64_t)16 << 30;
     if (const char *e = getenv("GC_VIS_BUDGET_MB")) {
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->vis_budget = (int64_t)v << 20;
-    }
-    g->fused_grid = 0;
-    {
-        // off by default: on MI355X the grid barriers of the cooperative
-        // kernel cost more than the kernel boundaries they replace
-        const char *e = getenv("GC_FUSED");
-        if (e && strcmp(e, "1") == 0) {
-            int want = cus / 2;
-            if (const char *w = getenv("GC_FUSED_WGS")) {
-                const long v = strtol(w, nullptr, 10);
-                if (v >= 1) want = (int)v;
-            }
-            g->fused_grid = std::max(0, std::min(want, fused_max_grid(cus)));
-        }
-        const char *fg = getenv("GC_FUSED_GAINS");
-        g->fused_gains = fg && strcmp(fg, "1") == 0;
     }
     g->level_wgs_per_cu = 4;
     if (const char *e = getenv("GC_LEVEL_WGS")) {
@@ -454,11 +427,9 @@ namespace {
 constexpr size_t kCtrBytes = 4096;
 
 struct WsLayout {
-    size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim, slots;
+    size_t ctr, dist16, dist8, far, cand, gain, aux, aux2, q0, q1, claim;
     size_t wvis, ly, lr, lb, lo, lz, lvl, act, cutprev, farout, cisplit, rinfo, dist1, order, two,
         tails, total;
-    int32_t nslots;
-    SlotLayout slot;
     int64_t kmax;       // batches per launch of the device-wide gain engine
     size_t vis_stride;  // words per batch
     int64_t cap;        // frontier log entries (a ring: a power of two)
@@ -472,18 +443,6 @@ constexpr int kMaxdSlot = 17;          // int32 counter slot for max d(S,.)
 
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-int32_t choose_slots(const gc_graph *g, const SlotLayout &sl) {
-    // persistent workgroups of the per-batch engine (closeness search; gains
-    // only with GC_ENGINE=wg)
-    // only the per-workgroup gain engine (GC_ENGINE=wg) uses these slots
-    if (!g->wg_engine) return 1;
-    const int64_t target = g->slots_target;
-    const size_t budget = (size_t)8 << 30;
-    int64_t cap = (int64_t)(budget / std::max<size_t>(sl.bytes, 1));
-    int64_t ns = std::min(target, std::max<int64_t>(cap, 1));
-    return (int32_t)std::max<int64_t>(ns, 1);
-}
 
 WsLayout ws_layout(const gc_graph *g) {
     WsLayout L;
@@ -500,9 +459,6 @@ WsLayout ws_layout(const gc_graph *g) {
     L.q0 = o; o += al256(n * 4);
     L.q1 = o; o += al256(n * 4);
     L.claim = o; o += al256(((n + 31) / 32) * 4);
-    L.slot = slot_layout(g->n);
-    L.nslots = choose_slots(g, L.slot);
-    L.slots = o; o += (size_t)L.nslots * L.slot.bytes;
     // device-wide engine: per-(batch, node) 32-byte records (visited word and
     // three rotating frontier words) and the frontier log
     L.vis_stride = (n + 31) & ~(size_t)31;
@@ -558,7 +514,6 @@ struct Ws {
     int64_t *gain() const { return reinterpret_cast<int64_t *>(base + L.gain); }
     int64_t *aux() const { return reinterpret_cast<int64_t *>(base + L.aux); }
     int32_t *aux2() const { return reinterpret_cast<int32_t *>(base + L.aux2); }
-    Slots slots() const { return Slots{base + L.slots, L.slot.bytes, L.nslots}; }
     int32_t *flags() const { return ctr() + kFlagSlot; }
     // learned-order region (after the main layout; see gc_mlp_ws_bytes)
     struct Mlp {
@@ -670,11 +625,6 @@ extern "C" int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes,
 
 namespace {
 
-int grid_for_batches(const Ws &w, int64_t nsrc) {
-    int64_t nb = (nsrc + kSrc - 1) / kSrc;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, w.L.nslots));
-}
-
 int bfs_grid(const gc_graph *g) {
     return std::max(1, std::min(4 * g->num_cu, (g->n + 3) / 4 + 1));
 }
@@ -718,25 +668,6 @@ int run_update(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int d
     HIP_OK(launch_bfs_finish(a, d_far, s));
     if (last) *last = h[C_BFS_LAST];
     if (claimed) *claimed = h[C_BFS_CLAIMED];
-    return GC_OK;
-}
-
-int run_gains_wg(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes,
-                 const int32_t *d_cand, int32_t count, int64_t *d_gain, int64_t *d_edges,
-                 int32_t *d_vis, hipStream_t s) {
-    EngineArgs a;
-    a.rp = g->d_rp;
-    a.ci = g->d_ci;
-    a.n = g->n;
-    a.dist = d_dist;
-    a.src = d_cand;
-    a.nsrc = count;
-    a.out_gain = d_gain;
-    a.out_edges = d_edges;
-    a.out_vis = d_vis;
-    a.ctr = w.ctr();
-    a.slots = w.slots();
-    HIP_OK(launch_gain(a, dist_bytes, grid_for_batches(w, count), s));
     return GC_OK;
 }
 
@@ -835,19 +766,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
     if (queued) *queued = false;
     if (count <= 0) return GC_OK;
     if (cut && cut->thr_id < 0) cut = nullptr;  // no threshold yet: nothing to cut against
-    if (phase == kGainsLaunch && (g->wg_engine || nlev < 0 || !io || !io->hm_flag || !io->hm_done ||
-                                  (g->fused_grid > 0 && g->fused_gains)))
-        phase = kGainsRun;
-    if (g->wg_engine) {
-        int rc = run_gains_wg(g, w, d_dist, dist_bytes, d_cand, count, d_gain, d_edges, d_vis, s);
-        if (rc) return rc;
-        if (h_gain)
-            HIP_OK(hipMemcpyAsync(h_gain, d_gain, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
-        if (h_edges && d_edges)
-            HIP_OK(hipMemcpyAsync(h_edges, d_edges, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
-        if (h_gain || h_edges) HIP_OK(hipStreamSynchronize(s));
-        return GC_OK;
-    }
+    if (phase == kGainsLaunch && (nlev < 0 || !io || !io->hm_flag || !io->hm_done)) phase = kGainsRun;
     if (nlev < 0) {
         int32_t maxd = 0;
         HIP_OK(launch_max_dist(d_dist, dist_bytes, g->n, w.maxd(), s));
@@ -943,8 +862,6 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                     if (L + 1 < nlev) HIP_OK(launch_gain_cut(a, L + 1, s));
                 }
                 HIP_OK(launch_wide_end(a, nlev, grid, s));
-            } else if (g->fused_grid > 0 && g->fused_gains && a.nsrc <= 1024) {
-                HIP_OK(launch_wide_fused(a, dist_bytes, nlev, g->fused_grid, s));
             } else {
                 HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
                 HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
@@ -1049,10 +966,6 @@ int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, 
     a.far = d_far;
     a.dist_bytes = dist_bytes;
     apply_split(a, split);
-    if (g->fused_grid > 0) {
-        HIP_OK(launch_wide_fused(a, dist_bytes, nlev, g->fused_grid, s));
-        return GC_OK;
-    }
     const int grid = wide_grid(g);
     HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
     HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
@@ -1523,7 +1436,6 @@ bool gains_layout(const gc_graph *g, size_t bytes, int64_t kwant, WsLayout *out)
     kmax = std::max<int64_t>(1, std::min<int64_t>(kmax, std::max<int64_t>(kwant, 1)));
     L.kmax = kmax;
     L.wvis = o; o += (size_t)kmax * per;
-    L.nslots = 0;
     L.total = o;
     *out = L;
     return true;
@@ -1546,7 +1458,6 @@ int gains_in_buffer(const gc_graph *g, const void *d_dist, int32_t dist_bytes, c
                     int32_t count, int64_t *d_gain, int64_t *d_edges, int32_t *d_visited, void *d_buf,
                     size_t buf_bytes, hipStream_t stream) {
     if (!g) return fail(GC_EINVAL, "graph is NULL");
-    if (g->wg_engine) return fail(GC_EINVAL, "the per-workgroup engine (GC_ENGINE=wg) needs a workspace");
     if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
     if (count < 0) return fail(GC_EINVAL, "count < 0");
     if (count > 0 && (!d_dist || !d_cand || !d_gain)) return fail(GC_EINVAL, "NULL device pointer");
@@ -1710,8 +1621,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     if (o.order < GC_ORDER_PLAIN || o.order > GC_ORDER_LEARNED) return fail(GC_EINVAL, "bad order");
     if (o.order == GC_ORDER_LEARNED && !o.d_mlp) return fail(GC_EINVAL, "learned order needs d_mlp");
     const bool bits = o.d_bits != nullptr;
-    if (bits && (o.order == GC_ORDER_LEARNED || g->wg_engine))
-        return fail(GC_EINVAL, "bit-vector gains: plain or CELF order on the device-wide engine");
+    if (bits && o.order == GC_ORDER_LEARNED)
+        return fail(GC_EINVAL, "bit-vector gains: plain or CELF order");
     if (bits && (o.bits_levels < 1 || o.bits_levels > kBitsMaxS))
         return fail(GC_EINVAL, "bits_levels out of range (gc_bits_prepare returns it)");
     if (bits && o.bits_bytes < bits_bytes(g, o.bits_levels))
@@ -1735,8 +1646,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
 
     if (o.early_exit < 0 || o.early_exit > 1 || o.early_exit_seed < 0)
         return fail(GC_EINVAL, "early_exit must be 0 or 1 and early_exit_seed >= 0");
-    if (o.early_exit && (bits || g->wg_engine))
-        return fail(GC_EINVAL, "early exit: pruned-BFS gains on the device-wide engine only");
+    if (o.early_exit && bits) return fail(GC_EINVAL, "early exit: pruned-BFS gains only");
 
     gc_stats st{};
     if (h_stats) st.h_evals_per_round = h_stats->h_evals_per_round;
@@ -1910,10 +1820,8 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     // rows split by d(S,.) of the first gain round: d(S,.) never grows, so the
     // split bounds every later round too
     Split split;
-    if (!g->wg_engine) {
-        rc = build_split(g, w, d_dist, dist_bytes, s, &split);
-        if (rc) return rc;
-    }
+    rc = build_split(g, w, d_dist, dist_bytes, s, &split);
+    if (rc) return rc;
 
     const bool verbose = getenv("GC_VERBOSE") != nullptr;
     LaunchShape shape_r1, shape_later;
@@ -1981,17 +1889,10 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
             st.gain_launches += 1;
             return GC_OK;
         }
-        if (g->wg_engine) {
-            HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
-            r = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(),
-                          want_edges ? w.aux() : nullptr, nullptr, s,
-                          nlev_now(), hg, want_edges ? he : nullptr);
-        } else {
-            r = run_gains(g, w, d_dist, dist_bytes, dc, cnt, w.gain(),
-                          want_edges ? w.aux() : nullptr, nullptr, s,
-                          nlev_now(), hg, want_edges ? he : nullptr, &io, shape,
-                          &split, false, kGainsRun, nullptr, cur_cut);
-        }
+        r = run_gains(g, w, d_dist, dist_bytes, dc, cnt, w.gain(),
+                      want_edges ? w.aux() : nullptr, nullptr, s,
+                      nlev_now(), hg, want_edges ? he : nullptr, &io, shape,
+                      &split, false, kGainsRun, nullptr, cur_cut);
         if (r) return r;
         st.gain_launches += 1;
         return GC_OK;
@@ -2107,7 +2008,7 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
         // so the host work overlaps the GPU's.  The next selection needs only
         // the best gain, which is taken first; the deferred candidates are
         // behind the plain scan's position or out of CELF's tree until then.
-        const bool overlap = !first_round && !learned && !logging && !g->wg_engine && !bits;
+        const bool overlap = !first_round && !learned && !logging && !bits;
         int dbuf = -1;        // buffer of the deferred block (-1: none)
         int32_t dcnt = 0;
         int cur = 0;          // buffer the next block goes to

@@ -11,8 +11,6 @@ constexpr int kSrc = 64;      // sources per bitset word
 
 // Workspace counters (int32 slots of the counter block).
 enum : int {
-    C_GAIN_NEXT = 0,   // next batch to take (gain / closeness engine)
-    C_GAIN_DONE = 1,   // workgroups finished (the last one resets both)
     C_BFS_CNT0 = 2,    // three rotating frontier counters of the level BFS
     C_BFS_LAST = 5,    // deepest level that claimed a node
     C_BFS_CLAIMED = 6, // nodes claimed by the current level BFS
@@ -21,7 +19,7 @@ enum : int {
 // int64 slots (index into the int64 view starting at int32 slot 8)
 enum : int {
     L_BFS_SUM = 0,     // sum of contributions of the level BFS
-    L_BEST_FAR = 1,    // best farness found by the closeness engine
+    L_BEST_FAR = 1,    // best farness found by the closeness search
     // word-level work of the device-wide engine, summed over gain launches:
     // frontier entries (all levels, root level, last level), adjacency entries
     // of expanded levels / of the last level, and (batch, node) records touched
@@ -31,36 +29,6 @@ enum : int {
     L_CUTS = 73,       // sources stopped by the early exit (k_gain_cut), summed over launches
     L_HDR = 80,        // stamp of gc_workspace_init: graph-derived tables are valid
 };
-
-struct Slots {
-    char *base;        // nslots * stride bytes
-    size_t stride;
-    int32_t nslots;
-};
-
-// Per-slot array offsets (bytes); all arrays have n entries.
-struct SlotLayout {
-    size_t vis, next, tq, uq, qv0, qv1, qm0, qm1, bytes;
-};
-SlotLayout slot_layout(int64_t n);
-
-struct EngineArgs {
-    const int32_t *rp;
-    const int32_t *ci;
-    int32_t n;
-    const void *dist;        // uint8/uint16 d(S,.) (gain mode)
-    const int32_t *src;      // sources, grouped 64 per batch
-    int32_t nsrc;
-    int64_t *out_gain;       // gain mode: g(v,S); closeness mode: F({v}) or -1 if cut
-    int64_t *out_edges;      // optional
-    int32_t *out_vis;        // optional
-    int32_t *ctr;            // workspace counter block
-    Slots slots;
-};
-
-// gain mode: dist_bytes 1 or 2.  closeness mode: dist ignored.
-hipError_t launch_gain(const EngineArgs &a, int dist_bytes, int grid, hipStream_t s);
-hipError_t launch_closeness(const EngineArgs &a, int grid, hipStream_t s);
 
 struct BfsArgs {
     const int32_t *rp;
@@ -177,12 +145,6 @@ hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, con
 // After level L: BFScut test for every live source of a closeness launch
 // (distances from an all-INF 16-bit array, so F = reached*65535 - gain).
 hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, bool fixed, hipStream_t s);
-// Whole launch (roots, up to nlev levels, clean-up, reset) as one cooperative
-// kernel, for launches of at most 1024 sources; grid <= fused_max_grid().
-hipError_t launch_wide_fused(const WideArgs &a, int dist_bytes, int32_t nlev, int grid, hipStream_t s);
-// Workgroups of the fused kernel that fit on the device at once (0: no
-// cooperative launch).
-int fused_max_grid(int num_cu);
 // After level l of a gain launch with the early exit: test every live source
 // (see k_gain_cut in gc_wide.hip).
 hipError_t launch_gain_cut(const WideArgs &a, int32_t l, hipStream_t s);

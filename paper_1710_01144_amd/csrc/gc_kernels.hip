@@ -1,46 +1,10 @@
-// HIP kernels (gfx950) for Greedy++ group-closeness maximisation.
-//
-//  * k_engine: bit-parallel multi-source BFS, one workgroup per batch of 64
-//    sources (one bit per source in a uint64 word per node).
-//      gain mode       -- pruned BFS of Section 4.1: a node y reached at
-//                         level L by source v is entered only if L < d(S,y);
-//                         it then adds d(S,y) - L to g(v,S) (the summand of
-//                         the gain sum in the proof of the Section 4.3
-//                         theorem).  Nodes failing the test are never marked,
-//                         so the prune test costs one byte read per edge.
-//      closeness mode  -- full BFS that keeps, per source, the distance sum,
-//                         the reached count and the adjacency size of the
-//                         last level, and drops a source once a lower bound
-//                         on its farness exceeds the best farness known
-//                         (BFScut of Section 3.1).
-//  * k_bfs_*: level-synchronous single-source BFS over the whole device for
-//    the d(S,.) update after a pick (pruned as in Section 4.1; full when
-//    S = {}).
-//
-// Memory model: every per-batch array lives in a per-workgroup slot that only
-// that workgroup touches during a launch, so __syncthreads() orders all its
-// accesses; cross-workgroup state is limited to device-scope atomics on the
-// counter block.
+// HIP kernels (gfx950) for Greedy++ group-closeness maximisation: the
+// level-synchronous single-source BFS of gc_update_dist (pruned as in Section
+// 4.1; full when S = {}) and small fills.  The gain, closeness and update
+// launches of the greedy run on the device-wide engine of gc_wide.hip.
 #include "gc_kernels.h"
 
 namespace gck {
-
-SlotLayout slot_layout(int64_t n) {
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    SlotLayout L;
-    size_t o = 0;
-    const size_t n8 = al((size_t)n * 8), n4 = al((size_t)n * 4);
-    L.vis = o; o += n8;
-    L.next = o; o += n8;
-    L.tq = o; o += n4;
-    L.uq = o; o += n4;
-    L.qv0 = o; o += n4;
-    L.qv1 = o; o += n4;
-    L.qm0 = o; o += n8;
-    L.qm1 = o; o += n8;
-    L.bytes = o;
-    return L;
-}
 
 namespace {
 
@@ -65,30 +29,6 @@ __device__ __forceinline__ int wave_push(bool p, int *counter) {
     return p ? base + bits_below(bal) : -1;
 }
 
-// Exclusive block scan over kWG threads; `total` receives the block sum.
-__device__ __forceinline__ int block_excl_scan(int v, int *s_wave, int &total) {
-    const int lane = lane_id();
-    const int w = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) s_wave[w] = x;
-    __syncthreads();
-    int pre = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < kWG / 64; ++i) {
-        int t = s_wave[i];
-        pre += (i < w) ? t : 0;
-        tot += t;
-    }
-    __syncthreads();
-    total = tot;
-    return pre + x - v;
-}
-
 template <typename DistT>
 struct DistInf;
 template <>
@@ -98,241 +38,6 @@ struct DistInf<uint16_t> { static constexpr uint32_t v = 0xFFFFu; };
 
 __device__ __forceinline__ int64_t *ctr64(int32_t *ctr) {
     return reinterpret_cast<int64_t *>(ctr + C_I64_BASE);
-}
-
-// MODE 0: gains (pruned by dist); MODE 1: closeness with cut.
-template <typename DistT, int MODE, bool STATS>
-__global__ __launch_bounds__(kWG) void k_engine(EngineArgs a, SlotLayout lay) {
-    __shared__ unsigned long long s_acc[kSrc];   // gain | distance sum
-    __shared__ unsigned long long s_acc2[kSrc];  // edges | adjacency of last level
-    __shared__ unsigned int s_acc3[kSrc];        // |V(v)| | reached
-    __shared__ int s_off[kWG];
-    __shared__ int s_rs[kWG];
-    __shared__ unsigned long long s_m[kWG];
-    __shared__ int s_wave[kWG / 64];
-    __shared__ int s_cntT, s_cntQ, s_cntU, s_batch;
-    __shared__ unsigned long long s_active;
-    __shared__ unsigned long long s_done;
-
-    const int tid = threadIdx.x;
-    char *slot = a.slots.base + (size_t)blockIdx.x * a.slots.stride;
-    uint64_t *vis = reinterpret_cast<uint64_t *>(slot + lay.vis);
-    unsigned long long *nxt = reinterpret_cast<unsigned long long *>(slot + lay.next);
-    int32_t *tq = reinterpret_cast<int32_t *>(slot + lay.tq);
-    int32_t *uq = reinterpret_cast<int32_t *>(slot + lay.uq);
-    int32_t *qv0 = reinterpret_cast<int32_t *>(slot + lay.qv0);
-    int32_t *qv1 = reinterpret_cast<int32_t *>(slot + lay.qv1);
-    uint64_t *qm0 = reinterpret_cast<uint64_t *>(slot + lay.qm0);
-    uint64_t *qm1 = reinterpret_cast<uint64_t *>(slot + lay.qm1);
-    const DistT *dist = reinterpret_cast<const DistT *>(a.dist);
-    const int32_t *__restrict__ rp = a.rp;
-    const int32_t *__restrict__ ci = a.ci;
-    const int nbatch = (a.nsrc + kSrc - 1) / kSrc;
-    int64_t *best_far = ctr64(a.ctr) + L_BEST_FAR;
-
-    for (;;) {
-        if (tid == 0) {
-            s_batch = atomicAdd(&a.ctr[C_GAIN_NEXT], 1);
-            s_cntT = 0;
-            s_cntQ = 0;
-            s_cntU = 0;
-            s_done = 0;
-        }
-        if (tid < kSrc) {
-            s_acc[tid] = 0;
-            s_acc2[tid] = 0;
-            s_acc3[tid] = 0;
-        }
-        __syncthreads();
-        const int b = s_batch;
-        if (b >= nbatch) break;
-        const int base = b * kSrc;
-        const int nb = min(kSrc, a.nsrc - base);
-        if (tid == 0) s_active = (nb == 64) ? ~0ull : ((1ull << nb) - 1ull);
-
-        // level 0: the roots.  In gain mode a root already in S (d = 0) is inert.
-        {
-            bool p = false;
-            int v = 0;
-            if (tid < nb) {
-                v = a.src[base + tid];
-                const bool alive = (MODE == 1) || ((uint32_t)dist[v] > 0u);
-                if (alive) {
-                    const unsigned long long old = atomicOr(&nxt[v], 1ull << tid);
-                    p = (old == 0ull);
-                }
-            }
-            const int pos = wave_push(p, &s_cntT);
-            if (p) tq[pos] = v;
-        }
-        __syncthreads();
-
-        int L = 0;
-        int cur = 0;
-        for (;;) {
-            // ---- settle the nodes first reached at distance L
-            int32_t *qv = cur ? qv1 : qv0;
-            uint64_t *qm = cur ? qm1 : qm0;
-            const int tn = s_cntT;
-            for (int i0 = 0; i0 < tn; i0 += kWG) {
-                const int i = i0 + tid;
-                const bool valid = i < tn;
-                int y = 0;
-                uint64_t nw = 0, vs = 0;
-                if (valid) {
-                    y = tq[i];
-                    nw = atomicExch(&nxt[y], 0ull);
-                    vs = vis[y];
-                    nw &= ~vs;
-                    vis[y] = vs | nw;
-                }
-                const bool pu = valid && vs == 0 && nw != 0;
-                const int pos = wave_push(pu, &s_cntU);
-                if (pu) uq[pos] = y;
-                if (valid && nw) {
-                    if (MODE == 0) {
-                        const unsigned long long c = (uint32_t)dist[y] - (uint32_t)L;
-                        const unsigned long long dg = STATS ? (unsigned long long)(rp[y + 1] - rp[y]) : 0ull;
-                        for (uint64_t m = nw; m; m &= m - 1) {
-                            const int j = __ffsll((unsigned long long)m) - 1;
-                            atomicAdd(&s_acc[j], c);
-                            if (STATS) {
-                                atomicAdd(&s_acc2[j], dg);
-                                atomicAdd(&s_acc3[j], 1u);
-                            }
-                        }
-                    } else {
-                        const unsigned long long dg =
-                            (unsigned long long)(rp[y + 1] - rp[y] - (L > 0 ? 1 : 0));
-                        for (uint64_t m = nw; m; m &= m - 1) {
-                            const int j = __ffsll((unsigned long long)m) - 1;
-                            atomicAdd(&s_acc[j], (unsigned long long)L);
-                            atomicAdd(&s_acc2[j], dg);
-                            atomicAdd(&s_acc3[j], 1u);
-                        }
-                    }
-                }
-                const bool pq = valid && nw != 0;
-                const int pos2 = wave_push(pq, &s_cntQ);
-                if (pq) {
-                    qv[pos2] = y;
-                    qm[pos2] = nw;
-                }
-            }
-            __syncthreads();
-
-            if (MODE == 1) {
-                // BFScut test per live source after completing level L:
-                // all nodes at distance <= L are known; at most ef of the
-                // remaining rem nodes are at distance L+1, the rest >= L+2.
-                if (tid < nb && ((s_active >> tid) & 1ull)) {
-                    const int64_t reached = (int64_t)s_acc3[tid];
-                    const int64_t sum = (int64_t)s_acc[tid];
-                    const int64_t ef = (int64_t)s_acc2[tid];
-                    const int64_t rem = (int64_t)a.n - reached;
-                    if (rem == 0) {
-                        a.out_gain[base + tid] = sum;
-                        atomicMin(reinterpret_cast<unsigned long long *>(best_far),
-                                  (unsigned long long)sum);
-                        atomicOr(&s_done, 1ull << tid);
-                        atomicAnd(&s_active, ~(1ull << tid));
-                    } else {
-                        const int64_t near = ef < rem ? ef : rem;
-                        const int64_t lb = sum + (int64_t)(L + 1) * near + (int64_t)(L + 2) * (rem - near);
-                        const int64_t best = (int64_t)__hip_atomic_load(
-                            reinterpret_cast<unsigned long long *>(best_far), __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-                        if (lb > best) atomicAnd(&s_active, ~(1ull << tid));
-                    }
-                }
-                if (tid < kSrc) s_acc2[tid] = 0;
-                __syncthreads();
-            }
-
-            const int qn = s_cntQ;
-            const uint64_t act = (MODE == 1) ? s_active : ~0ull;
-            __syncthreads();
-            if (tid == 0) {
-                s_cntT = 0;
-                s_cntQ = 0;
-            }
-            if (qn == 0 || act == 0ull) break;
-            __syncthreads();
-
-            // ---- expand the frontier at distance L (edge-balanced in chunks)
-            for (int c0 = 0; c0 < qn; c0 += kWG) {
-                const int i = c0 + tid;
-                int deg = 0, rs = 0;
-                uint64_t m = 0;
-                if (i < qn) {
-                    const int x = qv[i];
-                    m = qm[i] & act;
-                    if (m) {
-                        rs = rp[x];
-                        deg = rp[x + 1] - rs;
-                    }
-                }
-                int total;
-                const int off = block_excl_scan(deg, s_wave, total);
-                s_off[tid] = off;
-                s_rs[tid] = rs;
-                s_m[tid] = m;
-                __syncthreads();
-                const int cnt = min(kWG, qn - c0);
-                for (int e0 = 0; e0 < total; e0 += kWG) {
-                    const int e = e0 + tid;
-                    bool p = false;
-                    int y = 0;
-                    if (e < total) {
-                        int lo = 0, hi = cnt - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
-                        }
-                        y = ci[s_rs[lo] + (e - s_off[lo])];
-                        uint64_t mm = s_m[lo];
-                        bool ok = true;
-                        if (MODE == 0) ok = (uint32_t)(L + 1) < (uint32_t)dist[y];
-                        if (ok) {
-                            mm &= ~vis[y];
-                            if (mm) {
-                                const unsigned long long old = atomicOr(&nxt[y], (unsigned long long)mm);
-                                p = (old == 0ull);
-                            }
-                        }
-                    }
-                    const int pos = wave_push(p, &s_cntT);
-                    if (p) tq[pos] = y;
-                }
-                __syncthreads();
-            }
-            ++L;
-            cur ^= 1;
-        }
-
-        if (tid < nb) {
-            if (MODE == 0) {
-                a.out_gain[base + tid] = (int64_t)s_acc[tid];
-                if (STATS) {
-                    if (a.out_edges) a.out_edges[base + tid] = (int64_t)s_acc2[tid];
-                    if (a.out_vis) a.out_vis[base + tid] = (int32_t)s_acc3[tid];
-                }
-            } else if (!((s_done >> tid) & 1ull)) {
-                a.out_gain[base + tid] = -1;  // cut: cannot beat the best farness
-            }
-        }
-        const int un = s_cntU;
-        for (int i = tid; i < un; i += kWG) vis[uq[i]] = 0;
-        __syncthreads();
-    }
-
-    if (tid == 0) {
-        const int d = atomicAdd(&a.ctr[C_GAIN_DONE], 1);
-        if (d == (int)gridDim.x - 1) {
-            atomicExch(&a.ctr[C_GAIN_NEXT], 0);
-            atomicExch(&a.ctr[C_GAIN_DONE], 0);
-        }
-    }
 }
 
 // ------------------------------------------------------- level BFS kernels
@@ -450,25 +155,6 @@ __global__ void k_set_i64(int64_t *p, int64_t v) {
 }
 
 }  // namespace
-
-hipError_t launch_gain(const EngineArgs &a, int dist_bytes, int grid, hipStream_t s) {
-    const SlotLayout lay = slot_layout(a.n);
-    const bool stats = a.out_edges || a.out_vis;
-    if (dist_bytes == 1) {
-        if (stats) hipLaunchKernelGGL((k_engine<uint8_t, 0, true>), dim3(grid), dim3(kWG), 0, s, a, lay);
-        else hipLaunchKernelGGL((k_engine<uint8_t, 0, false>), dim3(grid), dim3(kWG), 0, s, a, lay);
-    } else {
-        if (stats) hipLaunchKernelGGL((k_engine<uint16_t, 0, true>), dim3(grid), dim3(kWG), 0, s, a, lay);
-        else hipLaunchKernelGGL((k_engine<uint16_t, 0, false>), dim3(grid), dim3(kWG), 0, s, a, lay);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_closeness(const EngineArgs &a, int grid, hipStream_t s) {
-    const SlotLayout lay = slot_layout(a.n);
-    hipLaunchKernelGGL((k_engine<uint16_t, 1, false>), dim3(grid), dim3(kWG), 0, s, a, lay);
-    return hipGetLastError();
-}
 
 hipError_t launch_bfs_init(const BfsArgs &a, int dist_bytes, int32_t root, hipStream_t s) {
     const size_t words = ((size_t)a.n + 31) / 32;

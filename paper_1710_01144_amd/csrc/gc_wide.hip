@@ -34,8 +34,6 @@
 //
 // A pruned BFS never goes deeper than max_y d(S,y) - 1, so the host launches
 // that many levels without reading anything back.
-#include <hip/hip_cooperative_groups.h>
-
 #include "gc_kernels.h"
 
 namespace gck {
@@ -647,32 +645,6 @@ __device__ __forceinline__ void reset_body(const WideArgs &a, int32_t nlev) {
 
 __global__ void k_wide_reset(WideArgs a, int32_t nlev) { reset_body(a, nlev); }
 
-// A whole small launch (at most kLdsSrc sources) in one cooperative kernel:
-// roots, the levels, the clean-up and the reset, separated by grid-wide
-// barriers.  Every workgroup passes every barrier (early exits stay inside the
-// bodies), and the loop stops after the first level that appends nothing: the
-// count is read after a barrier, so all workgroups see the same value.
-template <typename DistT, bool WRITE, int U>
-__global__ __launch_bounds__(256) void k_wide_fused(WideArgs a, int32_t nlev) {
-    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-    const int64_t span = (a.nsrc + kWG - 1) / kWG * kWG;
-    for (int64_t t = blockIdx.x * (int64_t)kWG + threadIdx.x; t < span; t += (int64_t)gridDim.x * kWG)
-        roots_body<DistT, WRITE>(a, t);
-    grid.sync();
-    int32_t run = 0;
-    while (run < nlev) {
-        level_body<DistT, WRITE, true, U>(a, run);
-        grid.sync();
-        ++run;
-        const unsigned long long pk =
-            __hip_atomic_load(&a.lvl[run].packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((pk >> kCntShift) == 0) break;
-    }
-    end_body(a);
-    grid.sync();
-    if (blockIdx.x == 0) reset_body(a, run);
-}
-
 // BFScut test (Section 3.1) after level L of a closeness launch: every node at
 // distance <= L+1 from source v is known (r of them, distance sum `sum`); of
 // the rem = n - r others at most ef (adjacency entries of the distance-(L+1)
@@ -972,36 +944,6 @@ hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_
     hipLaunchKernelGGL(k_wide_end, dim3(g), dim3(256), 0, s, a, nlev);
     hipLaunchKernelGGL(k_wide_reset, dim3(1), dim3(256), 0, s, a, nlev);
     return hipGetLastError();
-}
-
-template <typename DistT, bool WRITE>
-static const void *fused_fn() {
-    return reinterpret_cast<const void *>(&k_wide_fused<DistT, WRITE, 8>);
-}
-
-int fused_max_grid(int num_cu) {
-    static int per_cu = -1;
-    if (per_cu < 0) {
-        int coop = 0, dev = 0, m = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, fused_fn<uint8_t, false>(), kWG, 0) !=
-                hipSuccess) {
-            (void)hipGetLastError();
-            m = 0;
-        }
-        per_cu = m;
-    }
-    return per_cu * num_cu;
-}
-
-hipError_t launch_wide_fused(const WideArgs &a, int dist_bytes, int32_t nlev, int grid, hipStream_t s) {
-    WideArgs arg = a;
-    int32_t nl = nlev;
-    void *params[] = {&arg, &nl};
-    const void *f = dist_bytes == 1 ? (a.write ? fused_fn<uint8_t, true>() : fused_fn<uint8_t, false>())
-                                    : (a.write ? fused_fn<uint16_t, true>() : fused_fn<uint16_t, false>());
-    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kWG), params, 0, s);
 }
 
 hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, bool fixed, hipStream_t s) {

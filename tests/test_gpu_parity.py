@@ -219,16 +219,14 @@ def test_greedy_block_growth(gclib):
 
 
 ENGINE_ENVS = [{}, {"GC_VIS_BUDGET_MB": "1"}, {"GC_LOG_ENTRIES": "3000"}, {"GC_TOUCH_ENTRIES": "3000"},
-               {"GC_ENGINE": "wg"}, {"GC_FUSED": "1", "GC_FUSED_GAINS": "1", "GC_FUSED_WGS": "64"},
                {"GC_BALLS": "0"}]
 
 
 @pytest.mark.parametrize("env", ENGINE_ENVS,
-                         ids=["default", "chunked", "log-overflow", "touch-overflow", "wg-engine", "fused",
-                              "id-order"])
+                         ids=["default", "chunked", "log-overflow", "touch-overflow", "id-order"])
 def test_engine_configurations(gclib, device, monkeypatch, env):
     """Launch chunking, overflow retries of the frontier ring and of the
-    clean-up list, the per-workgroup engine and the source order all give the
+    clean-up list and the source order all give the
     oracle's gains and greedy picks."""
     for key, v in env.items():
         monkeypatch.setenv(key, v)
