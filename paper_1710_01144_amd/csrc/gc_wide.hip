@@ -398,12 +398,20 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
         if (tid < cnt) {
             const int64_t q = (start + i + tid) & lmask;
             const int32_t b = a.lb[q];
-            s_off[tid] = a.lo[q];
+            const int64_t off = a.lo[q];
+            s_off[tid] = off;
             s_rs[tid] = a.lr[q];
             s_b[tid] = b;
             s_rb[tid] = (size_t)b * a.vis_stride;
-            const uint64_t f = *rec(a, b, a.ly[q], fr_cur);
-            s_m[tid] = a.active ? (f & a.active[b]) : f;
+            // an entry starting at or past this workgroup's last adjacency
+            // entry is never expanded here: skip its frontier word (a random
+            // line per entry)
+            uint64_t f = 0;
+            if (off < ee) {
+                f = *rec(a, b, a.ly[q], fr_cur);
+                if (a.active) f &= a.active[b];
+            }
+            s_m[tid] = f;
         }
         if (tid == 0) s_off[cnt] = (i + cnt < N) ? a.lo[(start + i + cnt) & lmask] : E;
         __syncthreads();
@@ -491,7 +499,10 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
                         const int32_t r0 = rp[y[r]];
                         ri = make_int4(r0, rp[y[r] + 1] - r0, 0, 0);
                     }
-                    const uint64_t m = s_m[own[r]] & ~(uint64_t)(*vw);
+                    // small launches (latency-bound): claim with the atomic
+                    // alone; large ones first read the word, so that targets
+                    // every source has reached cost no atomic
+                    const uint64_t m = LDS ? s_m[own[r]] : s_m[own[r]] & ~(uint64_t)(*vw);
                     if (m) {
                         const uint64_t ov = atomicOr(vw, (unsigned long long)m);
                         tz[r] = ov == 0ull;
