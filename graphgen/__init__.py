@@ -4,7 +4,7 @@ This module produces graphs only; it contains no distance, farness or gain
 arithmetic.  Every random draw comes from SplitMix64 in counter form
 (``graphgen.c``), so a given (generator, seed) always yields the same CSR.
 
-The method's input contract is a connected, undirected, unweighted graph
+The method's basic input contract is a connected, undirected, unweighted graph
 (paper, Section 2 "Preliminaries"): every generator here returns such a graph
 as CSR int32 with rows sorted ascending, no self-loops and no duplicates.  The
 large generators keep the largest connected component and relabel it in
@@ -67,6 +67,9 @@ def _load():
         lib.gg_build_csr_directed.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, ctypes.c_int32,
                                               i64p, i32p, i32p, ctypes.POINTER(ctypes.c_int64),
                                               ctypes.POINTER(ctypes.c_int64)]
+        lib.gg_edge_weights.restype = ctypes.c_int
+        lib.gg_edge_weights.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_int32, ctypes.c_uint64,
+                                        ctypes.c_int32, np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
         lib.gg_splitmix_at.restype = ctypes.c_uint64
         lib.gg_splitmix_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         _lib = lib
@@ -75,12 +78,17 @@ def _load():
 
 @dataclass
 class Graph:
-    """Undirected CSR graph: row_ptr int32[n+1], col_idx int32[nnz] (both directions stored)."""
+    """CSR graph: row_ptr int32[n+1], col_idx int32[nnz] (undirected: both
+    directions stored; directed: out-neighbour rows).  ``weight`` (uint8[nnz],
+    every entry >= 1, the same in both rows of an undirected edge) makes it a
+    weighted graph; None means every edge has length 1."""
     name: str
     n: int
     row_ptr: np.ndarray
     col_idx: np.ndarray
     old_id: np.ndarray | None = None
+    directed: bool = False
+    weight: np.ndarray | None = None
 
     @property
     def nnz(self) -> int:
@@ -98,6 +106,9 @@ class Graph:
         h.update(np.int64(self.n).tobytes())
         h.update(np.ascontiguousarray(self.row_ptr, dtype=np.int32).tobytes())
         h.update(np.ascontiguousarray(self.col_idx, dtype=np.int32).tobytes())
+        if self.weight is not None:
+            h.update(b"w")
+            h.update(np.ascontiguousarray(self.weight, dtype=np.uint8).tobytes())
         return h.hexdigest()
 
 
@@ -303,6 +314,27 @@ def rmat_directed(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.1
     if lib.gg_rmat(scale, m, a, b, c, seed, src, dst) != 0:
         raise ValueError("bad R-MAT arguments")
     return from_arcs("rmatdir%d_ef%d_s%d" % (scale, edge_factor, seed), nv, src, dst, keep_scc=True)
+
+
+# -------------------------------------------------------- weighted graphs
+
+def with_weights(g: Graph, wmax: int, seed: int) -> Graph:
+    """The same graph with integer edge lengths drawn uniformly from
+    [1, wmax] (seeded, keyed by the endpoint pair)."""
+    w = np.zeros(g.nnz, dtype=np.uint8)
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    if _load().gg_edge_weights(g.n, rp, ci, int(wmax), seed, 1 if g.directed else 0, w) != 0:
+        raise ValueError("wmax must be in [1, 255]")
+    return Graph("%s_w%d_s%d" % (g.name, wmax, seed), g.n, rp, ci, g.old_id, g.directed, w)
+
+
+def with_weight_array(g: Graph, w) -> Graph:
+    """The same graph with the given per-arc lengths (uint8[nnz])."""
+    w = np.ascontiguousarray(w, dtype=np.uint8)
+    if w.shape != (g.nnz,):
+        raise ValueError("one weight per CSR entry")
+    return Graph(g.name + "_w", g.n, g.row_ptr, g.col_idx, g.old_id, g.directed, w)
 
 
 # --------------------------------------------------------- named workloads

@@ -400,3 +400,19 @@ int gg_build_csr_directed(int64_t nv, int64_t ne, const int32_t *src, const int3
     free(cnt); free(adj); free(fill); free(deg);
     return 0;
 }
+
+/* Integer arc weights in [1, wmax] from SplitMix64 keyed by the (unordered,
+ * unless directed) endpoint pair, so both rows of an undirected edge carry
+ * the same weight. */
+int gg_edge_weights(int64_t n, const int32_t *rp, const int32_t *ci, int32_t wmax, uint64_t seed,
+                    int32_t directed, uint8_t *w) {
+    if (wmax < 1 || wmax > 255) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t u = 0; u < n; ++u)
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int64_t a = u, b = ci[e];
+            if (!directed && b < a) { int64_t t = a; a = b; b = t; }
+            w[e] = (uint8_t)(1 + sm_at(seed, (uint64_t)a * (uint64_t)n + (uint64_t)b) % (uint64_t)wmax);
+        }
+    return 0;
+}

@@ -78,6 +78,23 @@ def _load():
         lib.or_gains_cut.argtypes = [I64, i32p, i32p, i32p, i32p, I64, I64, I32, i64p, i32p]
         lib.or_validate_graph.restype = ctypes.c_int
         lib.or_validate_graph.argtypes = [I64, i32p, i32p, I32]
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        lib.or_sssp_w.restype = I64
+        lib.or_sssp_w.argtypes = [I64, i32p, i32p, u8p, I32, i32p]
+        lib.or_validate_w.restype = ctypes.c_int
+        lib.or_validate_w.argtypes = [I64, i32p, i32p, u8p, I32]
+        lib.or_group_dist_w.restype = ctypes.c_int
+        lib.or_group_dist_w.argtypes = [I64, i32p, i32p, u8p, i32p, I32, i32p]
+        lib.or_farness_all_w.restype = ctypes.c_int
+        lib.or_farness_all_w.argtypes = [I64, i32p, i32p, u8p, i64p]
+        lib.or_gains_w.restype = ctypes.c_int
+        lib.or_gains_w.argtypes = [I64, i32p, i32p, u8p, i32p, i32p, I64, i64p]
+        lib.or_pruned_stats_w.restype = ctypes.c_int
+        lib.or_pruned_stats_w.argtypes = [I64, i32p, i32p, u8p, i32p, i32p, I64, i64p, i64p, i64p]
+        lib.or_greedy_w.restype = ctypes.c_int
+        lib.or_greedy_w.argtypes = [I64, i32p, i32p, u8p, I32, i32p, i64p, I32]
+        lib.or_greedypp_w.restype = ctypes.c_int
+        lib.or_greedypp_w.argtypes = [I64, i32p, i32p, u8p, I32, I32, I32, i32p, i64p, i64p, i64p, I32]
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_num_threads.argtypes = []
         _lib = lib
@@ -93,6 +110,17 @@ def _directed(g) -> int:
     """1 for a directed graph (rows are out-neighbour lists; graphgen marks
     such graphs), else 0."""
     return 1 if getattr(g, "directed", False) else 0
+
+
+def _weights(g):
+    """uint8[nnz] edge lengths of a weighted graph, or None (unweighted)."""
+    w = getattr(g, "weight", None)
+    if w is None:
+        return None
+    w = np.ascontiguousarray(w, dtype=np.uint8)
+    if w.shape != (int(g.col_idx.shape[0]),):
+        raise OracleError("invalid argument: one weight per CSR entry")
+    return w
 
 
 def _check(rc):
@@ -120,11 +148,29 @@ def validate(g) -> None:
     n, rp, ci = _csr(g)
     if rp.shape[0] != n + 1 or int(rp[n]) != ci.shape[0]:
         raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
-    _check(_load().or_validate_graph(n, rp, ci, _directed(g)))
+    w = _weights(g)
+    if w is None:
+        _check(_load().or_validate_graph(n, rp, ci, _directed(g)))
+    else:
+        _check(_load().or_validate_w(n, rp, ci, w, _directed(g)))
+
+
+def sssp(g, src: int) -> np.ndarray:
+    """d(src, w) for all w (-1 if unreachable): Dijkstra on a weighted graph,
+    BFS otherwise."""
+    w = _weights(g)
+    if w is None:
+        return bfs(g, src)
+    n, rp, ci = _csr(g)
+    d = np.empty(n, dtype=np.int32)
+    _load().or_sssp_w(n, rp, ci, w, int(src), d)
+    return d
 
 
 def bfs(g, src: int) -> np.ndarray:
     """d(src, w) for all w (-1 if unreachable)."""
+    if _weights(g) is not None:
+        raise OracleError("bfs() ignores weights; use sssp()")
     n, rp, ci = _csr(g)
     d = np.empty(n, dtype=np.int32)
     q = np.empty(n, dtype=np.int32)
@@ -137,12 +183,18 @@ def group_dist(g, S) -> np.ndarray:
     n, rp, ci = _csr(g)
     S = np.ascontiguousarray(S, dtype=np.int32)
     dS = np.empty(n, dtype=np.int32)
-    _check(_load().or_group_dist(n, rp, ci, S, int(S.shape[0]), dS))
+    w = _weights(g)
+    if w is None:
+        _check(_load().or_group_dist(n, rp, ci, S, int(S.shape[0]), dS))
+    else:
+        _check(_load().or_group_dist_w(n, rp, ci, w, S, int(S.shape[0]), dS))
     return dS
 
 
 def farness(g, S) -> int:
     """Integer group farness F(S) = sum_w d(S, w)."""
+    if _weights(g) is not None:
+        return int(group_dist(g, S).astype(np.int64).sum())
     n, rp, ci = _csr(g)
     S = np.ascontiguousarray(S, dtype=np.int32)
     F = int(_load().or_farness(n, rp, ci, S, int(S.shape[0])))
@@ -155,7 +207,11 @@ def farness_all(g) -> np.ndarray:
     """F({v}) for every node v."""
     n, rp, ci = _csr(g)
     F = np.empty(n, dtype=np.int64)
-    _check(_load().or_farness_all(n, rp, ci, F))
+    w = _weights(g)
+    if w is None:
+        _check(_load().or_farness_all(n, rp, ci, F))
+    else:
+        _check(_load().or_farness_all_w(n, rp, ci, w, F))
     return F
 
 
@@ -173,7 +229,9 @@ def topk_closeness(g, k: int):
 
 
 def gain(g, dS, v: int) -> int:
-    """g(v,S) = F(S) - F(S u {v}) by a full BFS from v."""
+    """g(v,S) = F(S) - F(S u {v}) by a full BFS (Dijkstra if weighted) from v."""
+    if _weights(g) is not None:
+        return int(gains(g, dS, [v])[0])
     n, rp, ci = _csr(g)
     return int(_load().or_gain(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), int(v)))
 
@@ -182,8 +240,13 @@ def gains(g, dS, cand) -> np.ndarray:
     n, rp, ci = _csr(g)
     cand = np.ascontiguousarray(cand, dtype=np.int32)
     out = np.empty(cand.shape[0], dtype=np.int64)
-    _check(_load().or_gains(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), cand,
-                            int(cand.shape[0]), out))
+    w = _weights(g)
+    if w is None:
+        _check(_load().or_gains(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), cand,
+                                int(cand.shape[0]), out))
+    else:
+        _check(_load().or_gains_w(n, rp, ci, w, np.ascontiguousarray(dS, dtype=np.int32), cand,
+                                  int(cand.shape[0]), out))
     return out
 
 
@@ -195,6 +258,12 @@ def greedy(g, k: int, with_gains: bool = False):
         raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
     group = np.empty(k, dtype=np.int32)
     F = np.empty(k, dtype=np.int64)
+    w = _weights(g)
+    if w is not None:
+        if with_gains:
+            raise OracleError("with_gains is for unweighted graphs")
+        _check(_load().or_greedy_w(n, rp, ci, w, int(k), group, F, _directed(g)))
+        return group, F
     G = np.empty((max(k - 1, 1), n), dtype=np.int64) if with_gains else None
     ptr = G.ctypes.data_as(ctypes.c_void_p) if with_gains else None
     _check(_load().or_greedy(n, rp, ci, int(k), group, F, ptr, _directed(g)))
@@ -216,6 +285,11 @@ def greedypp(g, k: int, block: int = 64, growth: int = 1):
     F = np.empty(k, dtype=np.int64)
     ev = np.zeros(k, dtype=np.int64)
     ed = np.zeros(k, dtype=np.int64)
+    w = _weights(g)
+    if w is not None:
+        _check(_load().or_greedypp_w(n, rp, ci, w, int(k), int(block), int(growth), group, F, ev, ed,
+                                     _directed(g)))
+        return group, F, ev, ed
     cuts = np.zeros(k, dtype=np.int64)
     _check(_load().or_greedypp(n, rp, ci, int(k), int(block), int(growth), group, F, ev, ed, 0, 0, cuts,
                                _directed(g)))
@@ -228,6 +302,8 @@ def greedypp_cut(g, k: int, block: int = 64, growth: int = 1, mode: int = 1, see
     first round (after the `seed` candidates of largest degree, evaluated
     exactly), mode 2 in every round.  Returns (group, F, evals per round,
     edges per round, cut candidates per round)."""
+    if _weights(g) is not None:
+        raise OracleError("the early exit is for unweighted graphs")
     n, rp, ci = _csr(g)
     if rp.shape[0] != n + 1 or int(rp[n]) != ci.shape[0]:
         raise OracleError("invalid argument or malformed CSR (row_ptr length or nnz)")
@@ -245,6 +321,8 @@ def gains_cut(g, dS, cand, thr: int, thr_id: int):
     """The early-exit pruned BFS of tier B against one threshold: (value,
     cut) per candidate -- the exact gain (cut 0) or the bound it stopped at
     (cut 1)."""
+    if _weights(g) is not None:
+        raise OracleError("the early exit is for unweighted graphs")
     n, rp, ci = _csr(g)
     cand = np.ascontiguousarray(cand, dtype=np.int32)
     out = np.empty(cand.shape[0], dtype=np.int64)
@@ -262,6 +340,11 @@ def pruned_stats(g, dS, cand):
     gg = np.empty(c, dtype=np.int64)
     vv = np.empty(c, dtype=np.int64)
     ee = np.empty(c, dtype=np.int64)
-    _check(_load().or_pruned_stats(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), cand, c,
-                                   gg, vv, ee))
+    w = _weights(g)
+    if w is None:
+        _check(_load().or_pruned_stats(n, rp, ci, np.ascontiguousarray(dS, dtype=np.int32), cand, c,
+                                       gg, vv, ee))
+    else:
+        _check(_load().or_pruned_stats_w(n, rp, ci, w, np.ascontiguousarray(dS, dtype=np.int32), cand,
+                                         c, gg, vv, ee))
     return gg, vv, ee

@@ -614,7 +614,7 @@ int or_greedypp(int64_t n, const int32_t *rp, const int32_t *ci, int32_t k, int3
             if (nb == 0) break;
             const int64_t thr = bgain;
             const int32_t thr_id = use_cut ? bid : -1;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (nb > 1)
             for (int32_t j = 0; j < nb; ++j) {
                 int t = 0;
 #ifdef _OPENMP
@@ -739,4 +739,438 @@ int or_num_threads(void) {
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------- weighted graphs --- */
+/*
+ * Section 2 names SSSP on weighted graphs as the distance computation in
+ * general (BFS is its unweighted special case); Section 4.1's pruning is
+ * stated for SSSP.  Here every arc e of the CSR carries an integer weight
+ * w[e] >= 1 (uint8; an undirected edge has the same weight in both rows), and
+ * d(u, v) is the least total weight of a path.  Everything below is the
+ * textbook form: Dijkstra's algorithm with a binary heap of (distance, node)
+ * pairs and lazy deletion.
+ */
+
+typedef struct { int64_t d; int32_t v; } or_hent;
+
+static void heap_push(or_hent *h, int64_t *len, int64_t d, int32_t v) {
+    int64_t i = (*len)++;
+    h[i].d = d; h[i].v = v;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].d < h[i].d || (h[p].d == h[i].d && h[p].v <= h[i].v)) break;
+        or_hent t = h[p]; h[p] = h[i]; h[i] = t; i = p;
+    }
+}
+
+static or_hent heap_pop(or_hent *h, int64_t *len) {
+    or_hent top = h[0];
+    h[0] = h[--(*len)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *len && (h[l].d < h[m].d || (h[l].d == h[m].d && h[l].v < h[m].v))) m = l;
+        if (r < *len && (h[r].d < h[m].d || (h[r].d == h[m].d && h[r].v < h[m].v))) m = r;
+        if (m == i) break;
+        or_hent t = h[m]; h[m] = h[i]; h[i] = t; i = m;
+    }
+    return top;
+}
+
+/* Dijkstra from src: dist[w] = d(src, w) or -1 if unreachable; returns #reached.
+ * heap: capacity nnz + 1 entries. */
+static int64_t sssp_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, int32_t src,
+                      int32_t *dist, or_hent *heap) {
+    for (int64_t i = 0; i < n; ++i) dist[i] = -1;
+    int64_t len = 0, reached = 0;
+    /* dist[w]: -1 unseen, -(t + 2) while w waits in the heap with tentative
+     * distance t, d(src, w) once settled */
+    dist[src] = -2;
+    heap_push(heap, &len, 0, src);
+    while (len > 0) {
+        or_hent t = heap_pop(heap, &len);
+        if (dist[t.v] >= 0) continue;             /* already settled */
+        if (-(int64_t)dist[t.v] - 2 != t.d) continue; /* a stale entry */
+        dist[t.v] = (int32_t)t.d;
+        ++reached;
+        for (int32_t e = rp[t.v]; e < rp[t.v + 1]; ++e) {
+            int32_t y = ci[e];
+            if (dist[y] >= 0) continue;
+            int64_t nd = t.d + w[e];
+            if (dist[y] == -1 || nd < -(int64_t)dist[y] - 2) {
+                dist[y] = (int32_t)(-(nd + 2));
+                heap_push(heap, &len, nd, y);
+            }
+        }
+    }
+    return reached;
+}
+
+int64_t or_sssp_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, int32_t src,
+                  int32_t *dist) {
+    or_hent *heap = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+    int64_t r = sssp_w(n, rp, ci, w, src, dist, heap);
+    free(heap);
+    return r;
+}
+
+/* structure (as or_validate_graph), every weight >= 1, and for undirected
+ * graphs the same weight in both rows of an edge */
+int or_validate_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, int32_t directed) {
+    int rc = or_validate_graph(n, rp, ci, directed);
+    if (rc != OR_OK) return rc;
+    for (int64_t u = 0; u < n; ++u)
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            if (w[e] < 1) return OR_EINVAL;
+            if (directed) continue;
+            int32_t v = ci[e], lo = rp[v], hi = rp[v + 1];
+            while (lo < hi) {
+                int32_t mid = lo + (hi - lo) / 2;
+                if (ci[mid] < u) lo = mid + 1; else hi = mid;
+            }
+            if (w[lo] != w[e]) return OR_ENOTSYM;
+        }
+    return OR_OK;
+}
+
+int or_group_dist_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, const int32_t *S,
+                    int32_t ns, int32_t *dS) {
+    if (ns < 1) return OR_EINVAL;
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    or_hent *heap = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+    int rc = OR_OK;
+    for (int32_t i = 0; i < ns && rc == OR_OK; ++i) {
+        if (S[i] < 0 || S[i] >= n) { rc = OR_EINVAL; break; }
+        if (sssp_w(n, rp, ci, w, S[i], d, heap) != n) { rc = OR_EDISCONNECTED; break; }
+        for (int64_t v = 0; v < n; ++v)
+            if (i == 0 || d[v] < dS[v]) dS[v] = d[v];
+    }
+    free(d); free(heap);
+    return rc;
+}
+
+int or_farness_all_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, int64_t *F) {
+    int rc = OR_OK;
+#pragma omp parallel
+    {
+        int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        or_hent *heap = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t v = 0; v < n; ++v) {
+            int64_t r = sssp_w(n, rp, ci, w, (int32_t)v, d, heap);
+            int64_t s = 0;
+            for (int64_t u = 0; u < n; ++u) s += d[u];
+            F[v] = s;
+            if (r != n) {
+#pragma omp atomic write
+                rc = OR_EDISCONNECTED;
+            }
+        }
+        free(d); free(heap);
+    }
+    return rc;
+}
+
+/* g(v,S) = sum_u (dS[u] - min(dS[u], d(v,u))) with a full Dijkstra from v */
+int or_gains_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, const int32_t *dS,
+               const int32_t *cand, int64_t count, int64_t *gain) {
+#pragma omp parallel
+    {
+        int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        or_hent *heap = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < count; ++i) {
+            sssp_w(n, rp, ci, w, cand[i], d, heap);
+            int64_t g = 0;
+            for (int64_t u = 0; u < n; ++u) g += dS[u] - (d[u] < dS[u] ? d[u] : dS[u]);
+            gain[i] = g;
+        }
+        free(d); free(heap);
+    }
+    return OR_OK;
+}
+
+/*
+ * Pruned Dijkstra from u (Section 4.1 for SSSP): a node reached with a
+ * distance that is not below its d_S is not entered, and nothing behind it
+ * is.  Returns g(u,S) = sum over settled w of (dS[w] - d(u,w)); *edges and
+ * *visited as in pruned_gain.  With `write`, dS[w] is lowered to d(u,w) for
+ * every settled w (the d(S,.) update after a pick).  tent: n entries, all
+ * -1 on entry and on return.
+ */
+static int64_t pruned_gain_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w,
+                             int32_t *dS, int32_t u, int32_t *tent, int32_t *done, or_hent *heap,
+                             int32_t *touched, int write, int64_t *edges, int64_t *visited) {
+    (void)n;
+    int64_t g = 0, e_cnt = 0, v_cnt = 0, len = 0, nt = 0;
+    *edges = 0; *visited = 0;
+    if (!(0 < dS[u])) return 0;
+    tent[u] = 0; touched[nt++] = u;
+    heap_push(heap, &len, 0, u);
+    while (len > 0) {
+        or_hent t = heap_pop(heap, &len);
+        if (done[t.v] || tent[t.v] != t.d) continue;
+        done[t.v] = 1;
+        g += dS[t.v] - t.d;
+        v_cnt += 1;
+        e_cnt += rp[t.v + 1] - rp[t.v];
+        for (int32_t e = rp[t.v]; e < rp[t.v + 1]; ++e) {
+            int32_t y = ci[e];
+            int64_t nd = t.d + w[e];
+            if (done[y] || nd >= dS[y]) continue;  /* pruned: S is at least as close */
+            if (tent[y] < 0 || nd < tent[y]) {
+                if (tent[y] < 0) touched[nt++] = y;
+                tent[y] = (int32_t)nd;
+                heap_push(heap, &len, nd, y);
+            }
+        }
+    }
+    for (int64_t i = 0; i < nt; ++i) {
+        int32_t y = touched[i];
+        if (write && done[y]) dS[y] = tent[y];
+        tent[y] = -1; done[y] = 0;
+    }
+    *edges = e_cnt; *visited = v_cnt;
+    return g;
+}
+
+int or_pruned_stats_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, const int32_t *dS,
+                      const int32_t *cand, int64_t count, int64_t *gain, int64_t *visited, int64_t *edges) {
+#pragma omp parallel
+    {
+        int32_t *tent = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *done = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        or_hent *heap = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+        for (int64_t i = 0; i < n; ++i) tent[i] = -1;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < count; ++i) {
+            int64_t e, v;
+            gain[i] = pruned_gain_w(n, rp, ci, w, (int32_t *)dS, cand[i], tent, done, heap, touched, 0, &e, &v);
+            if (visited) visited[i] = v;
+            if (edges) edges[i] = e;
+        }
+        free(tent); free(done); free(touched); free(heap);
+    }
+    return OR_OK;
+}
+
+/*
+ * Tier A on a weighted graph: the plain greedy of Section 3.2 with Dijkstra
+ * for every SSSP, ties to the smallest id, the same invariants as or_greedy.
+ */
+int or_greedy_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, int32_t k,
+                int32_t *group, int64_t *Fout, int32_t directed) {
+    if (k < 1 || k > n) return OR_EINVAL;
+    int vrc = or_validate_w(n, rp, ci, w, directed);
+    if (vrc != OR_OK) return vrc;
+    int64_t *Fv = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *dS = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *dsnew = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t *inS = (uint8_t *)calloc((size_t)n, 1);
+    or_hent *heap = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+    int rc = or_farness_all_w(n, rp, ci, w, Fv);
+    if (rc == OR_OK) {
+        int32_t s = 0;
+        for (int64_t v = 1; v < n; ++v)
+            if (Fv[v] < Fv[s]) s = (int32_t)v;
+        group[0] = s;
+        inS[s] = 1;
+        sssp_w(n, rp, ci, w, s, dS, heap);
+        int64_t F = Fv[s];
+        Fout[0] = F;
+        for (int64_t v = 0; v < n; ++v) prev[v] = INT64_MAX;
+        for (int32_t i = 1; i < k && rc == OR_OK; ++i) {
+            int bad = 0;
+#pragma omp parallel
+            {
+                int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+                or_hent *hp = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+#pragma omp for schedule(dynamic, 4)
+                for (int64_t v = 0; v < n; ++v) {
+                    if (inS[v]) { Fv[v] = INT64_MAX; continue; }
+                    sssp_w(n, rp, ci, w, (int32_t)v, d, hp);
+                    int64_t t = 0;
+                    for (int64_t u = 0; u < n; ++u) t += (d[u] < dS[u] ? d[u] : dS[u]);
+                    Fv[v] = t;
+                }
+                free(d); free(hp);
+            }
+            int32_t best = -1;
+            for (int64_t v = 0; v < n; ++v) {
+                if (inS[v]) continue;
+                int64_t g = F - Fv[v];
+                if (g > prev[v]) bad = 1;             /* supermodularity */
+                if (g < dS[v] || dS[v] < 1) bad = 1;  /* v itself drops to 0 */
+                prev[v] = g;
+                if (best < 0 || Fv[v] < Fv[best]) best = (int32_t)v;
+            }
+            sssp_w(n, rp, ci, w, best, dsnew, heap);
+            int64_t sum = 0;
+            for (int64_t u = 0; u < n; ++u) {
+                int32_t m = dsnew[u] < dS[u] ? dsnew[u] : dS[u];
+                if (m > dS[u]) bad = 1;
+                dS[u] = m;
+                sum += m;
+            }
+            if (sum != Fv[best] || !(Fv[best] < F)) bad = 1;
+            F = Fv[best];
+            group[i] = best;
+            inS[best] = 1;
+            Fout[i] = F;
+            if (bad) rc = OR_EINVARIANT;
+        }
+    }
+    free(Fv); free(prev); free(dS); free(dsnew); free(inS); free(heap);
+    return rc;
+}
+
+/*
+ * Tier B on a weighted graph: the first node by the closeness search in
+ * decreasing degree order, each Dijkstra stopped, when the next node to
+ * settle is at distance D, once sum + D * (unsettled) cannot beat the best
+ * (every unsettled node is at D or more); then
+ * the lazy loop of or_greedypp with pruned Dijkstra gains and the pruned
+ * update.  Same batch schedule (block, growth) and evaluation counts.
+ */
+int or_greedypp_w(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *w, int32_t k,
+                  int32_t block, int32_t growth, int32_t *group, int64_t *Fout, int64_t *evals,
+                  int64_t *edges, int32_t directed) {
+    if (k < 1 || k > n || block < 1 || growth < 1 || growth > 8) return OR_EINVAL;
+    int vrc = or_validate_w(n, rp, ci, w, directed);
+    if (vrc != OR_OK) return vrc;
+    int64_t maxb = growth > 1 ? 16 * (int64_t)block : block;
+    if (maxb > n) maxb = n;
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = omp_get_max_threads();
+#endif
+    int32_t **tent = (int32_t **)malloc(sizeof(void *) * (size_t)nthr);
+    int32_t **done = (int32_t **)malloc(sizeof(void *) * (size_t)nthr);
+    int32_t **tch = (int32_t **)malloc(sizeof(void *) * (size_t)nthr);
+    or_hent **heaps = (or_hent **)malloc(sizeof(void *) * (size_t)nthr);
+    for (int t = 0; t < nthr; ++t) {
+        tent[t] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        for (int64_t i = 0; i < n; ++i) tent[t][i] = -1;
+        done[t] = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        tch[t] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        heaps[t] = (or_hent *)malloc(sizeof(or_hent) * (size_t)(rp[n] + 2));
+    }
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *dS = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *ub = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *batch = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxb);
+    int64_t *bg = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxb);
+    int64_t *be = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxb);
+    int rc = OR_OK;
+    {
+        /* decreasing degree, ties ascending id (stable counting sort) */
+        int32_t maxdeg = 0;
+        for (int64_t v = 0; v < n; ++v) if (rp[v + 1] - rp[v] > maxdeg) maxdeg = rp[v + 1] - rp[v];
+        int64_t *cnt = (int64_t *)calloc((size_t)maxdeg + 2, sizeof(int64_t));
+        for (int64_t v = 0; v < n; ++v) cnt[maxdeg - (rp[v + 1] - rp[v]) + 1]++;
+        for (int32_t x = 0; x <= maxdeg; ++x) cnt[x + 1] += cnt[x];
+        for (int64_t v = 0; v < n; ++v) order[cnt[maxdeg - (rp[v + 1] - rp[v])]++] = (int32_t)v;
+        free(cnt);
+    }
+    /* first node: Dijkstra with the distance-group cut, in degree order */
+    int64_t bestF = -1;
+    int32_t bestId = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t v = order[i];
+        int32_t *tv = tent[0], *dn = done[0], *tc = tch[0];
+        or_hent *hp = heaps[0];
+        int64_t len = 0, nt = 0, settled = 0, sum = 0, cur = -1;
+        int cut = 0;
+        tv[v] = 0; tc[nt++] = v;
+        heap_push(hp, &len, 0, v);
+        while (len > 0) {
+            or_hent t = heap_pop(hp, &len);
+            if (dn[t.v] || tv[t.v] != t.d) continue;
+            if (t.d > cur) {
+                /* every node closer than t.d is settled; Dijkstra pops in
+                 * nondecreasing order, so every other node is at t.d or more */
+                if (cur >= 0 && bestId >= 0) {
+                    int64_t lb = sum + t.d * (n - settled);
+                    if (lb > bestF || (lb == bestF && v > bestId)) { cut = 1; break; }
+                }
+                cur = t.d;
+            }
+            dn[t.v] = 1; settled += 1; sum += t.d;
+            for (int32_t e = rp[t.v]; e < rp[t.v + 1]; ++e) {
+                int32_t y = ci[e];
+                int64_t nd = t.d + w[e];
+                if (dn[y]) continue;
+                if (tv[y] < 0 || nd < tv[y]) {
+                    if (tv[y] < 0) tc[nt++] = y;
+                    tv[y] = (int32_t)nd;
+                    heap_push(hp, &len, nd, y);
+                }
+            }
+        }
+        for (int64_t j = 0; j < nt; ++j) { tv[tc[j]] = -1; dn[tc[j]] = 0; }
+        if (cut) continue;
+        if (settled != n) { rc = OR_EDISCONNECTED; goto done; }
+        if (bestId < 0 || sum < bestF || (sum == bestF && v < bestId)) { bestF = sum; bestId = v; }
+    }
+    group[0] = bestId;
+    Fout[0] = bestF;
+    sssp_w(n, rp, ci, w, bestId, dS, heaps[0]);
+    for (int64_t v = 0; v < n; ++v) ub[v] = INT64_MAX;
+    if (evals) evals[0] = 0;
+    if (edges) edges[0] = 0;
+    {
+        int64_t F = bestF;
+        for (int32_t r = 1; r < k; ++r) {
+            int64_t bgain = -1;
+            int32_t bid = -1;
+            int64_t pos = 0, nev = 0, ned = 0;
+            int64_t cur = block < maxb ? block : maxb;
+            for (;;) {
+                int32_t nb = 0;
+                while (pos < n && nb < cur) {
+                    int32_t u = (int32_t)pos++;
+                    if (dS[u] == 0) continue;
+                    if (bid >= 0 && (ub[u] < bgain || (ub[u] == bgain && u > bid))) continue;
+                    batch[nb++] = u;
+                }
+                if (nb == 0) break;
+#pragma omp parallel for schedule(dynamic, 1) if (nb > 1)
+                for (int32_t j = 0; j < nb; ++j) {
+                    int t = 0;
+#ifdef _OPENMP
+                    t = omp_get_thread_num();
+#endif
+                    int64_t vis;
+                    bg[j] = pruned_gain_w(n, rp, ci, w, dS, batch[j], tent[t], done[t], heaps[t], tch[t], 0,
+                                          &be[j], &vis);
+                }
+                for (int32_t j = 0; j < nb; ++j) {
+                    int32_t u = batch[j];
+                    ub[u] = bg[j];
+                    ned += be[j];
+                    if (bid < 0 || bg[j] > bgain || (bg[j] == bgain && u < bid)) { bgain = bg[j]; bid = u; }
+                }
+                nev += nb;
+                if (r >= 2 && cur * growth <= maxb) cur *= growth;
+                else if (r >= 2) cur = maxb;
+            }
+            if (evals) evals[r] = nev;
+            if (edges) edges[r] = ned;
+            group[r] = bid;
+            {
+                int64_t e, v;
+                pruned_gain_w(n, rp, ci, w, dS, bid, tent[0], done[0], heaps[0], tch[0], 1, &e, &v);
+            }
+            F -= bgain;
+            Fout[r] = F;
+        }
+    }
+done:
+    for (int t = 0; t < nthr; ++t) { free(tent[t]); free(done[t]); free(tch[t]); free(heaps[t]); }
+    free(tent); free(done); free(tch); free(heaps);
+    free(order); free(dS); free(ub); free(batch); free(bg); free(be);
+    return rc;
 }

@@ -30,11 +30,14 @@ def adjacency(g) -> np.ndarray:
 
 
 def floyd_warshall(g) -> np.ndarray:
-    """All-pairs shortest-path lengths (int64, INF if unreachable)."""
-    A = adjacency(g)
+    """All-pairs shortest-path lengths (int64, INF if unreachable); edge
+    lengths from ``g.weight`` when the graph has them, else 1."""
     n = g.n
     D = np.full((n, n), INF, dtype=np.int64)
-    D[A] = 1
+    w = getattr(g, "weight", None)
+    for u in range(n):
+        for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+            D[u, int(g.col_idx[e])] = 1 if w is None else int(w[e])
     np.fill_diagonal(D, 0)
     for m in range(n):
         D = np.minimum(D, D[:, m:m + 1] + D[m:m + 1, :])

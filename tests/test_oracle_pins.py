@@ -569,3 +569,157 @@ def test_directed_validation():
     undirected.directed = True
     oracle.validate(undirected)  # the directed 3-cycle
     oracle.validate(graphgen.rmat_directed(10, 8, 3))
+
+
+# ------------------------------------------------------------ weighted graphs
+# Section 2 defines distances through SSSP, of which BFS is the unit-length
+# case; the oracle's weighted path is Dijkstra with a binary heap.
+
+def _star_weighted():
+    """Star with centre 0 and leaves 1..4; edge 0-1 has length 10, the rest 1."""
+    g = graphgen.star(5)
+    w = np.ones(g.nnz, dtype=np.uint8)
+    for u in range(g.n):
+        for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+            if {u, int(g.col_idx[e])} == {0, 1}:
+                w[e] = 10
+    return graphgen.with_weight_array(g, w)
+
+
+def test_weighted_star_by_hand():
+    """Worked by hand: F({0}) = 10+1+1+1 = 13, F({1}) = 10+3*11 = 43,
+    F({2}) = 1+11+2+2 = 16 (and so for leaves 3, 4); from {0}, leaf 1 gains
+    10 and every other leaf 1, so the group grows 0, 1, 2, 3, 4 with
+    F = 13, 3, 2, 1, 0."""
+    g = _star_weighted()
+    oracle.validate(g)
+    assert oracle.sssp(g, 0).tolist() == [0, 10, 1, 1, 1]
+    assert oracle.sssp(g, 2).tolist() == [1, 11, 0, 2, 2]
+    assert oracle.farness_all(g).tolist() == [13, 43, 16, 16, 16]
+    for tier in (lambda k: oracle.greedy(g, k), lambda k: oracle.greedypp(g, k, block=1)[:2]):
+        grp, F = tier(5)
+        assert grp.tolist() == [0, 1, 2, 3, 4]
+        assert F.tolist() == [13, 3, 2, 1, 0]
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (7, 2), (30, 3)])
+def test_weighted_path_prefix_sums(n, seed):
+    """On a path, d(u, v) is the difference of prefix sums of the lengths."""
+    g = graphgen.with_weights(graphgen.path(n), 9, seed)
+    lens = [int(g.weight[int(g.row_ptr[i]) + (1 if i > 0 else 0)]) for i in range(n - 1)]
+    pre = np.concatenate([[0], np.cumsum(lens)])
+    for u in range(n):
+        assert oracle.sssp(g, u).tolist() == np.abs(pre - pre[u]).tolist()
+
+
+@pytest.mark.parametrize("mk", [lambda: graphgen.ba(300, 3, 5), lambda: graphgen.grid(12, 14, 3),
+                                lambda: graphgen.rmat_directed(8, 8, 4)])
+@pytest.mark.parametrize("c", [1, 3, 255])
+def test_weighted_uniform_lengths_scale(mk, c):
+    """Every edge of length c multiplies every distance by c: the greedy
+    picks the same group and every F is c times the unweighted one."""
+    g = mk()
+    gw = graphgen.with_weight_array(g, np.full(g.nnz, c, np.uint8))
+    for v in (0, g.n // 2, g.n - 1):
+        assert np.array_equal(oracle.sssp(gw, v), c * oracle.bfs(g, v))
+    grp, F = oracle.greedy(g, 6)
+    grp_w, F_w = oracle.greedy(gw, 6)
+    assert grp_w.tolist() == grp.tolist() and F_w.tolist() == (c * F).tolist()
+    grp_b, F_b, ev, _ = oracle.greedypp(gw, 6, block=4, growth=2)
+    assert grp_b.tolist() == grp.tolist() and F_b.tolist() == (c * F).tolist()
+
+
+WTINY = [(n, p, s, wmax) for (n, p, s), wmax in zip(TINY, [2, 3, 5, 9, 17, 40, 100, 255, 7])]
+
+
+@pytest.mark.parametrize("n,p,seed,wmax", WTINY)
+def test_weighted_against_floyd_warshall(n, p, seed, wmax):
+    """SSSP, group distances, farness, gains, pruned-search statistics, the
+    greedy (against the matrix form and, for small k, the brute-force
+    optimum) and Greedy++ on tiny weighted graphs."""
+    g = graphgen.with_weights(graphgen.gnp_connected(n, p, seed), wmax, seed + 50)
+    oracle.validate(g)
+    D = small.floyd_warshall(g)
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    for v in range(n):
+        assert np.array_equal(oracle.sssp(g, v), D[v])
+    assert oracle.farness_all(g).tolist() == D.sum(axis=1).tolist()
+    rng = np.random.default_rng(seed)
+    for _ in range(6):
+        S = rng.choice(n, size=int(rng.integers(1, n)), replace=False).tolist()
+        dS = D[S].min(axis=0).astype(np.int32)
+        assert np.array_equal(oracle.group_dist(g, S), dS)
+        assert oracle.farness(g, S) == small.farness(D, S)
+        cand = np.arange(n, dtype=np.int32)
+        gains = oracle.gains(g, dS, cand)
+        assert gains.tolist() == [small.gain_def(D, S, v) for v in range(n)]
+        gg, vv, ee = oracle.pruned_stats(g, dS, cand)
+        inV = D < dS[None, :]
+        assert gg.tolist() == gains.tolist()
+        assert vv.tolist() == inV.sum(axis=1).tolist()
+        assert ee.tolist() == (inV * deg[None, :]).sum(axis=1).tolist()
+    for k in range(1, n + 1):
+        grp, Fs = oracle.greedy(g, k)
+        S, F = small.greedy_matrix(D, k)
+        assert grp.tolist() == S and Fs.tolist() == F
+        if k <= 4:
+            opt, _ = small.brute_force_opt(D, k)
+            assert opt <= int(Fs[-1])
+            if k == 1:
+                assert opt == int(Fs[0])
+        for block, growth in ((1, 1), (3, 2)):
+            grp_b, F_b, _, _ = oracle.greedypp(g, k, block=block, growth=growth)
+            assert grp_b.tolist() == S and F_b.tolist() == F
+
+
+@pytest.mark.parametrize("n,p,seed", DIRECTED)
+def test_weighted_directed_against_floyd_warshall(n, p, seed):
+    g = graphgen.with_weights(graphgen.gnp_directed(n, p, seed), 20, seed)
+    oracle.validate(g)
+    D = small.floyd_warshall(g)
+    for v in range(g.n):
+        assert np.array_equal(oracle.sssp(g, v), D[v])
+    for k in range(1, min(g.n, 6) + 1):
+        grp, Fs = oracle.greedy(g, k)
+        S, F = small.greedy_matrix(D, k)
+        assert grp.tolist() == S and Fs.tolist() == F
+        grp_b, F_b, _, _ = oracle.greedypp(g, k, block=2, growth=2)
+        assert grp_b.tolist() == S and F_b.tolist() == F
+
+
+@pytest.mark.parametrize("mk", [lambda: graphgen.ba(700, 4, 1), lambda: graphgen.rmat(10, 8, 9),
+                                lambda: graphgen.grid(24, 30, 2)])
+@pytest.mark.parametrize("wmax", [4, 255])
+def test_weighted_tier_b_equals_tier_a(mk, wmax):
+    g = graphgen.with_weights(mk(), wmax, 17)
+    grp, F = oracle.greedy(g, 6)
+    for block, growth in ((1, 1), (64, 2)):
+        grp_b, F_b, ev, ed = oracle.greedypp(g, 6, block=block, growth=growth)
+        assert grp_b.tolist() == grp.tolist() and F_b.tolist() == F.tolist()
+        assert ev[0] == 0 and np.all(ev[1:] >= 1)
+    # the pruned update matches group distances from scratch
+    dS = oracle.group_dist(g, grp)
+    assert int(dS.astype(np.int64).sum()) == int(F[-1])
+
+
+def test_weighted_validation():
+    g = _star_weighted()
+    bad = g.weight.copy()
+    bad[0] = 0
+    with pytest.raises(oracle.OracleError, match="malformed|invalid"):
+        oracle.validate(graphgen.with_weight_array(g, bad))
+    asym = g.weight.copy()
+    asym[0] = 7  # row 0's edge to 1 keeps 10 in row 1
+    with pytest.raises(oracle.OracleError, match="symmetric"):
+        oracle.validate(graphgen.with_weight_array(g, asym))
+    with pytest.raises(oracle.OracleError):
+        oracle.greedy(graphgen.with_weight_array(g, asym), 2)
+    with pytest.raises(oracle.OracleError, match="weight"):
+        oracle.greedy(graphgen.Graph("x", g.n, g.row_ptr, g.col_idx, weight=g.weight[:-1]), 2)
+    d = graphgen.with_weights(graphgen.directed_cycle(5), 9, 1)
+    d.weight[0] = 3
+    oracle.validate(d)  # a directed arc's length need not match any other
+    with pytest.raises(oracle.OracleError):
+        oracle.bfs(g, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.greedypp_cut(g, 2)
