@@ -341,7 +341,7 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
             return fail(GC_ENOMEM, "no memory for the ball order");
         }
     }
-    g->vis_budget = (int64_t)16 << 30;
+    g->vis_budget = (int64_t)64 << 30;
     if (const char *e = getenv("GC_VIS_BUDGET_MB")) {
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->vis_budget = (int64_t)v << 20;
