@@ -13,6 +13,12 @@
  * gains of earlier rounds are upper bounds that let the greedy loop skip
  * candidates (Section 4.2, valid by the supermodularity lemma of Section 3.2).
  *
+ * Weighted graphs (gc_load_csr_weighted): every edge has an integer length
+ * 1..255 and d is the SSSP distance (Section 2 names SSSP in general, BFS
+ * being the unit-length case); the pruning of Section 4.1 and the lazy loop of
+ * Section 4.2 hold unchanged.  Each candidate's search runs inside one
+ * workgroup as a bucketed label-correcting search (delta-stepping).
+ *
  * Conventions for every function
  *  - Return value: GC_OK (0) or a negative gc_status.  On error no output is
  *    written; gc_last_error() gives a message (thread-local).
@@ -26,7 +32,8 @@
  *  - Work is enqueued on `stream`.  Calls with h_* outputs synchronise the
  *    stream before returning; calls with only d_* outputs are asynchronous.
  *  - Distances d(S, .) are stored as uint8 (dist_bytes = 1, INF = 255) or
- *    uint16 (dist_bytes = 2, INF = 65535).  A distance array that is INF
+ *    uint16 (dist_bytes = 2, INF = 65535); on a weighted graph as int32
+ *    (dist_bytes = 4, INF = 2^31 - 1).  A distance array that is INF
  *    everywhere stands for S = {} .
  *  - Node ids are int32 in [0, n); ties between equal gains or equal farness
  *    always go to the smallest node id.
@@ -174,6 +181,30 @@ typedef struct gc_stats {
  */
 int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                 uint32_t flags, hipStream_t stream, gc_graph **out);
+
+/*
+ * gc_load_csr_weighted -- as gc_load_csr, for a graph whose edges have
+ * integer lengths (Section 2: distances are SSSP distances).
+ *   d_weight   device uint8[nnz]: the length of the edge of each CSR entry,
+ *              1..255; for an undirected graph both entries of an edge hold
+ *              the same length.  Borrowed like the CSR arrays.
+ *   n          1 <= n < 2^23 (GC_ERANGE otherwise), so that every distance,
+ *              at most 255 (n - 1), fits int32
+ *   flags      as for gc_load_csr; GC_VALIDATE also checks the lengths:
+ *              GC_EINVAL for a length 0, GC_ENOTSYM for an undirected edge
+ *              whose two entries differ
+ * The lengths are copied to the host once (nnz bytes).  On the handle:
+ * gc_closest_node, gc_topk_closeness, gc_update_dist and gc_marginal_gains
+ * take int32 distances (dist_bytes = 4); gc_greedy_group takes the plain or
+ * CELF order without bit vectors, early exit or evaluation log; the
+ * bit-vector calls, gc_marginal_gains_noalloc, gc_gain_words and
+ * gc_node_features give GC_EINVAL.  GC_WDELTA and GC_WDELTA_CLOSE (the
+ * bucket widths of the gain and closeness searches, default twice and half
+ * the largest length) and GC_WSLOTS (searches in flight, default 8 per
+ * compute unit within the record budget GC_VIS_BUDGET_MB) are read here.
+ */
+int gc_load_csr_weighted(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                         const uint8_t *d_weight, uint32_t flags, hipStream_t stream, gc_graph **out);
 void gc_free_graph(gc_graph *g);
 int32_t gc_graph_n(const gc_graph *g);
 int64_t gc_graph_nnz(const gc_graph *g);
@@ -236,7 +267,10 @@ int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_
  * Synchronises the stream.  GC_ERANGE for graphs with more than 2^20 nodes
  * or 2^25 adjacency entries (the largest class this search has been run
  * on; the same limit holds for gc_topk_closeness and for gc_greedy_group
- * without a prefix).
+ * without a prefix).  Weighted graphs: one search per node in decreasing
+ * degree order (the first alone), each stopped once the nodes it has settled
+ * below theta and theta for every other node add up to more than the best
+ * farness found; GC_EDISCONNECTED if a finished search missed a node.
  */
 int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream,
                     int32_t *h_node, int64_t *h_farness);
@@ -291,7 +325,7 @@ int gc_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t l
  * entry unchanged (Section 4.1).
  *   d_dist      device uint8/uint16[n], in/out: d(S,.) -> d(S u {node},.);
  *               all-INF means S = {} (then a full BFS is run)
- *   dist_bytes  1 or 2 (GC_EINVAL otherwise)
+ *   dist_bytes  1 or 2 (GC_EINVAL otherwise); 4 on a weighted graph
  *   d_farness   device int64, in/out: F(S) -> F(S u {node}); its input is
  *               ignored when S = {}
  * Synchronises the stream every few levels (the depth is found as it goes).
@@ -308,7 +342,8 @@ int gc_update_dist(const gc_graph *g, int32_t node, void *d_dist, int32_t dist_b
  * Section 4.3).  Candidates are processed in groups of bitset_width sources
  * that share one bit-parallel BFS frontier.  A candidate already in S gets 0.
  * Requires S != {} (d_dist finite everywhere).
- *   d_dist      device uint8/uint16[n] = d(S,.)
+ *   d_dist      device uint8/uint16[n] = d(S,.) (int32[n], dist_bytes = 4,
+ *               on a weighted graph: one search per candidate, asynchronous)
  *   d_cand      device int32[count], ids in [0,n) (duplicates allowed)
  *   d_gain      device int64[count] out
  *   d_edges     device int64[count] out or NULL: sum_{w in V(v)} deg(w)
@@ -371,7 +406,9 @@ int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_bytes, hipStrea
  *   h_group     host out int32[k]: picks in order
  *   h_farness   host out int64[k]: F(S_1), ..., F(S_k)
  *   h_stats     host out or NULL
- * Synchronises the stream.
+ * Synchronises the stream.  Weighted graphs: plain or CELF order only (no
+ * d_bits, early exit, learned order or log: GC_EINVAL); the first gain round
+ * evaluates every node in one launch; stats.dist_bytes = 4, ecc_s1 = 0.
  */
 int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts, void *d_ws,
                     size_t ws_bytes, hipStream_t stream, int32_t *h_group, int64_t *h_farness,

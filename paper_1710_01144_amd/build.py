@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 SOURCES = ["gc_kernels.hip", "gc_wide.hip", "gc_mlp.hip", "gc_bits.hip", "gc_noalloc.hip",
-           "gc_api.cpp"]
+           "gc_weighted.hip", "gc_api.cpp"]
 
 
 def _compile(src: str) -> str:
@@ -44,7 +44,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp%d" % os.getpid()
-    subprocess.check_call([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs +
+    # --no-undefined: a symbol no object defines fails here, not at load time
+    subprocess.check_call([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Wl,--no-undefined"] + objs +
                           ["-o", tmp])
     os.replace(tmp, OUT)
     if verbose:

@@ -20,6 +20,7 @@
 #include "gc_mlp.h"
 #include "gc_bits.h"
 #include "gc_internal.h"
+#include "gc_weighted.h"
 
 using namespace gck;
 
@@ -116,11 +117,28 @@ struct gc_graph {
                                // largest bounds, this many percent of a block (110..1600)
     bool balls;                // GC_BALLS (default on)
     bool directed;             // GC_DIRECTED: rows are out-neighbour lists
+    // weighted graphs (gc_load_csr_weighted): the caller's uint8 lengths, the
+    // largest one, the bucket widths of the gain and closeness searches
+    // (GC_WDELTA, GC_WDELTA_CLOSE) and the number of search slots (GC_WSLOTS)
+    bool weighted = false;
+    const uint8_t *d_w = nullptr;
+    int32_t wmax = 0;
+    int32_t wdelta_gain = 0;
+    int32_t wdelta_close = 0;
+    int32_t wslots = 0;
     const std::vector<int32_t> &search_order() const { return balls ? by_ball : by_degree; }
 };
 
 extern "C" int32_t gc_graph_n(const gc_graph *g) { return g ? g->n : -1; }
 extern "C" int64_t gc_graph_nnz(const gc_graph *g) { return g ? g->nnz : -1; }
+
+// weighted graphs: every distance, at most 255 (n - 1), fits int32
+constexpr int32_t kWeightedMaxN = 1 << 23;
+
+// GC_EINVAL for a weighted graph in a call that only the unweighted engine has
+static int unweighted_only(const gc_graph *g, const char *what) {
+    return g && g->weighted ? fail(GC_EINVAL, "%s: unweighted graphs only", what) : GC_OK;
+}
 
 static int hw_threads() {
     unsigned t = std::thread::hardware_concurrency();
@@ -250,19 +268,38 @@ static void ball_order(int32_t n, const std::vector<int32_t> &rp, const std::vec
     for (int32_t i = 0; i < n; ++i) rank[(size_t)out[i]] = i;
 }
 
-extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
-                           const int32_t *d_col_idx, uint32_t flags, hipStream_t stream,
-                           gc_graph **out) {
+// every length >= 1 and, undirected, both rows of an edge with the same length
+static int validate_weights(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                            const std::vector<uint8_t> &w, bool directed) {
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            if (w[(size_t)e] == 0) return fail(GC_EINVAL, "row %d: an edge of length 0", u);
+            if (directed) continue;
+            const int32_t v = ci[(size_t)e];
+            const auto it = std::lower_bound(ci.begin() + rp[v], ci.begin() + rp[v + 1], u);
+            if (w[(size_t)(it - ci.begin())] != w[(size_t)e])
+                return fail(GC_ENOTSYM, "edge %d-%d has different lengths in its two rows", u, v);
+        }
+    return GC_OK;
+}
+
+static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                      bool weighted, const uint8_t *d_weight, uint32_t flags, hipStream_t stream,
+                      gc_graph **out) {
     if (!out) return fail(GC_EINVAL, "out is NULL");
     if (n < 1) return fail(GC_EINVAL, "n must be >= 1 (got %d)", n);
     if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(GC_EINVAL, "nnz out of range");
     if (!d_row_ptr || (nnz > 0 && !d_col_idx)) return fail(GC_EINVAL, "NULL CSR array");
+    if (weighted && n >= kWeightedMaxN)
+        return fail(GC_ERANGE, "weighted graphs: n must be below 2^23 (distances stay below 2^31)");
     gc_graph *g = new (std::nothrow) gc_graph();
     if (!g) return fail(GC_ENOMEM, "no memory for the handle");
     g->n = n;
     g->nnz = nnz;
     g->d_rp = d_row_ptr;
     g->d_ci = d_col_idx;
+    g->weighted = weighted;
+    g->d_w = d_weight;
     try {
         g->h_rp.resize((size_t)n + 1);
     } catch (...) {
@@ -290,8 +327,8 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         md = std::max(md, rp[u + 1] - rp[u]);
     }
     g->max_deg = md;
-    g->balls = true;
-    if (const char *e = getenv("GC_BALLS")) g->balls = strcmp(e, "0") != 0;
+    g->balls = !weighted;  // the balls batch the bit-parallel searches only
+    if (const char *e = getenv("GC_BALLS")) g->balls = g->balls && strcmp(e, "0") != 0;
     std::vector<int32_t> ci;
     if ((flags & GC_VALIDATE) || g->balls) {
         try {
@@ -317,6 +354,33 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
             delete g;
             return rc;
         }
+    }
+    if (weighted) {
+        std::vector<uint8_t> hw;
+        try {
+            hw.resize((size_t)nnz);
+        } catch (...) {
+            delete g;
+            return fail(GC_ENOMEM, "no memory for the length copy");
+        }
+        if (nnz > 0) {
+            e = hipMemcpyAsync(hw.data(), d_weight, (size_t)nnz, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) {
+                delete g;
+                return fail(GC_EDEVICE, "copying the lengths: %s", hipGetErrorString(e));
+            }
+        }
+        if (flags & GC_VALIDATE) {
+            int rc = validate_weights(n, rp, ci, hw, g->directed);
+            if (rc != GC_OK) {
+                delete g;
+                return rc;
+            }
+        }
+        int32_t wmax = 1;
+        for (uint8_t x : hw) wmax = std::max<int32_t>(wmax, x);
+        g->wmax = wmax;
     }
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -384,8 +448,43 @@ extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->touch_entries = v;
     }
+    if (weighted) {
+        // bucket widths: the gain searches are short and pay per phase, so one
+        // phase spans twice the longest edge; the closeness search checks its
+        // bound once per phase, so its phases are a quarter of that
+        g->wdelta_gain = std::min(2 * g->wmax, 65535);
+        g->wdelta_close = std::max(1, g->wmax / 2);
+        if (const char *e = getenv("GC_WDELTA")) {
+            const long v = strtol(e, nullptr, 10);
+            if (v >= 1 && v <= 65535) g->wdelta_gain = (int32_t)v;
+        }
+        if (const char *e = getenv("GC_WDELTA_CLOSE")) {
+            const long v = strtol(e, nullptr, 10);
+            if (v >= 1 && v <= 65535) g->wdelta_close = (int32_t)v;
+        }
+        // one slot per resident workgroup of 256 threads (8 per CU), within the record budget
+        const int64_t per_slot = (int64_t)kWSlotBytesPerNode * n;
+        int64_t slots = std::min<int64_t>(8LL * g->num_cu, std::max<int64_t>(1, g->vis_budget / per_slot));
+        if (const char *e = getenv("GC_WSLOTS")) {
+            const long long v = strtoll(e, nullptr, 10);
+            if (v >= 1 && v <= 65536) slots = v;
+        }
+        g->wslots = (int32_t)slots;
+    }
     *out = g;
     return GC_OK;
+}
+
+extern "C" int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                           uint32_t flags, hipStream_t stream, gc_graph **out) {
+    return load_graph(n, nnz, d_row_ptr, d_col_idx, false, nullptr, flags, stream, out);
+}
+
+extern "C" int gc_load_csr_weighted(int32_t n, int64_t nnz, const int32_t *d_row_ptr,
+                                    const int32_t *d_col_idx, const uint8_t *d_weight, uint32_t flags,
+                                    hipStream_t stream, gc_graph **out) {
+    if (!d_weight && nnz > 0) return fail(GC_EINVAL, "NULL length array");
+    return load_graph(n, nnz, d_row_ptr, d_col_idx, true, d_weight, flags, stream, out);
 }
 
 extern "C" void gc_free_graph(gc_graph *g) { delete g; }
@@ -576,12 +675,176 @@ int get_ws(const gc_graph *g, void *d_ws, size_t ws_bytes, Ws *w) {
     return GC_OK;
 }
 
+// ---- weighted graphs: workspace of the per-workgroup searches
+// counter block (256 bytes): work counter, flags, best farness, argmin
+// result, sum, one node id, F(S); then d(S,.) (int32), per-candidate outputs,
+// the candidate list, and the slots (records, then work lists)
+struct WLayout {
+    size_t ctr, dist, out, edges, vis, cand, rec, lists, total;
+};
+
+WLayout wlayout(const gc_graph *g) {
+    WLayout L{};
+    const size_t n = (size_t)g->n, slots = (size_t)g->wslots;
+    size_t o = 0;
+    L.ctr = o; o += 256;
+    L.dist = o; o += al256(n * 4);
+    L.out = o; o += al256(n * 8);
+    L.edges = o; o += al256(n * 8);
+    L.vis = o; o += al256(n * 4);
+    L.cand = o; o += al256(n * 4);
+    L.rec = o; o += al256(slots * n * sizeof(WRec));
+    L.lists = o; o += al256(slots * n * kWLists * 4);
+    L.total = o;
+    return L;
+}
+
+struct WWs {
+    WLayout L;
+    char *base;
+    uint32_t *next() const { return reinterpret_cast<uint32_t *>(base + L.ctr); }
+    int32_t *flags() const { return reinterpret_cast<int32_t *>(base + L.ctr + 4); }
+    unsigned long long *best() const { return reinterpret_cast<unsigned long long *>(base + L.ctr + 8); }
+    int64_t *res() const { return reinterpret_cast<int64_t *>(base + L.ctr + 16); }
+    unsigned long long *sum() const { return reinterpret_cast<unsigned long long *>(base + L.ctr + 32); }
+    int32_t *one() const { return reinterpret_cast<int32_t *>(base + L.ctr + 40); }
+    int64_t *far() const { return reinterpret_cast<int64_t *>(base + L.ctr + 48); }
+    int32_t *dist() const { return reinterpret_cast<int32_t *>(base + L.dist); }
+    int64_t *out() const { return reinterpret_cast<int64_t *>(base + L.out); }
+    int64_t *edges() const { return reinterpret_cast<int64_t *>(base + L.edges); }
+    int32_t *vis() const { return reinterpret_cast<int32_t *>(base + L.vis); }
+    int32_t *cand() const { return reinterpret_cast<int32_t *>(base + L.cand); }
+    WRec *rec() const { return reinterpret_cast<WRec *>(base + L.rec); }
+    int32_t *lists() const { return reinterpret_cast<int32_t *>(base + L.lists); }
+};
+
+int get_wws(const gc_graph *g, void *d_ws, size_t ws_bytes, WWs *w) {
+    if (!g) return fail(GC_EINVAL, "graph is NULL");
+    w->L = wlayout(g);
+    if (!d_ws) return fail(GC_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(GC_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < w->L.total)
+        return fail(GC_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w->L.total);
+    w->base = reinterpret_cast<char *>(d_ws);
+    return GC_OK;
+}
+
+// ---------------------------------------------------------- weighted graphs
+//
+// The same operations on a graph with integer edge lengths: every search is
+// one workgroup's bucketed search (gc_weighted.hip) and d(S,.) is int32.
+
+int wlaunch(const gc_graph *g, const WWs &w, int32_t mode, int32_t *dS, const int32_t *cand, int32_t count,
+            int64_t *out, int64_t *edges, int32_t *vis, int64_t thr, unsigned long long *best, bool one,
+            hipStream_t s) {
+    if (count <= 0) return GC_OK;
+    HIP_OK(launch_fill_u32(w.next(), 1, 0u, s));
+    WArgs a{};
+    a.rp = g->d_rp;
+    a.ci = g->d_ci;
+    a.w = g->d_w;
+    a.n = g->n;
+    a.mode = mode;
+    a.dS = dS;
+    a.cand = cand;
+    a.count = count;
+    a.next = w.next();
+    a.out = out;
+    a.edges = edges;
+    a.visited = vis;
+    a.rec = w.rec();
+    a.lists = w.lists();
+    a.delta = mode == W_CLOSE ? g->wdelta_close : g->wdelta_gain;
+    a.thr = thr;
+    a.best = best;
+    a.flags = w.flags();
+    HIP_OK(one ? launch_wsearch_one(a, s) : launch_wsearch(a, g->wslots, s));
+    return GC_OK;
+}
+
+// The k nodes of least F({v}) (Section 3.1 with k >= 1), in increasing
+// (F, id) order.  Candidates go in decreasing degree order; the first one is
+// searched alone so that its farness is the cut threshold of all the others.
+// k = 1: one launch over the rest, each search cut against the best farness
+// any search has finished with (a device atomic).  k > 1: launches of a few
+// candidates per slot, each cut against the k-th best farness of the
+// launches before.  A cut search's farness exceeds the threshold, so it is
+// not among the k.
+int run_wclosest(const gc_graph *g, const WWs &w, hipStream_t s, int32_t k,
+                 std::vector<std::pair<int64_t, int32_t>> *top) {
+    const int32_t n = g->n;
+    HIP_OK(hipMemcpyAsync(w.cand(), g->by_degree.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
+    // (the kernel compares the best as a signed value: start at INT64_MAX)
+    HIP_OK(launch_set_i64(reinterpret_cast<int64_t *>(w.best()), std::numeric_limits<int64_t>::max(), s));
+    unsigned long long *best = k == 1 ? w.best() : nullptr;
+    int rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand(), 1, w.out(), nullptr, nullptr,
+                     std::numeric_limits<int64_t>::max(), best, true, s);
+    if (rc) return rc;
+    top->clear();
+    int32_t flag = 0;
+    if (k == 1) {
+        rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand() + 1, n - 1, w.out() + 1, nullptr, nullptr,
+                     std::numeric_limits<int64_t>::max(), best, false, s);
+        if (rc) return rc;
+        HIP_OK(launch_wargmin(w.out(), w.cand(), n, w.res(), s));
+        int64_t res[2] = {-1, -1};
+        HIP_OK(hipMemcpyAsync(res, w.res(), sizeof(res), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (flag || res[1] < 0) return fail(GC_EDISCONNECTED, "a closeness search did not reach every node");
+        top->emplace_back(res[0], (int32_t)res[1]);
+        return GC_OK;
+    }
+    const int32_t chunk = std::max<int32_t>(1, 4 * g->wslots);
+    std::vector<int64_t> hout((size_t)std::min<int32_t>(chunk, n));
+    for (int32_t start = 0; start < n;) {
+        const int32_t cnt = start == 0 ? 1 : std::min<int32_t>(chunk, n - start);
+        if (start > 0) {
+            const int64_t thr = (int32_t)top->size() < k ? std::numeric_limits<int64_t>::max()
+                                                         : (*top)[(size_t)k - 1].first;
+            rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand() + start, cnt, w.out() + start, nullptr, nullptr, thr,
+                         nullptr, false, s);
+            if (rc) return rc;
+        }
+        HIP_OK(hipMemcpyAsync(hout.data(), w.out() + start, sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost,
+                              s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (int32_t j = 0; j < cnt; ++j)
+            if (hout[(size_t)j] >= 0) top->emplace_back(hout[(size_t)j], g->by_degree[(size_t)start + j]);
+        std::sort(top->begin(), top->end());
+        if ((int32_t)top->size() > k) top->resize((size_t)k);
+        start += cnt;
+    }
+    HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (flag || (int32_t)top->size() < k) return fail(GC_EDISCONNECTED, "a closeness search did not reach every node");
+    return GC_OK;
+}
+
+// add `node` to S: d(S,.) <- min(d(S,.), d(node,.)) by the pruned search,
+// and F(S) in *d_far (S = {}: the sum of the new distances; else minus the
+// gain, which the search leaves in w.res()[0])
+int run_wupdate(const gc_graph *g, const WWs &w, int32_t node, int32_t *dS, int64_t *d_far, bool s_empty,
+                hipStream_t s) {
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.one()), 1, (uint32_t)node, s));
+    int rc = wlaunch(g, w, W_WRITE, dS, w.one(), 1, w.res(), nullptr, nullptr, 0, nullptr, true, s);
+    if (rc) return rc;
+    if (s_empty) HIP_OK(launch_wsum(dS, g->n, reinterpret_cast<unsigned long long *>(d_far), s));
+    else HIP_OK(launch_wsub(d_far, w.res(), s));
+    return GC_OK;
+}
+
 }  // namespace
 
 extern "C" int gc_workspace_size(const gc_graph *g, int32_t bitset_width, size_t *bytes) {
     if (!g || !bytes) return fail(GC_EINVAL, "NULL argument");
     if (bitset_width != 0 && bitset_width != 64)
         return fail(GC_EINVAL, "bitset_width must be 64 or 0");
+    if (g->weighted) {
+        *bytes = wlayout(g).total;
+        return GC_OK;
+    }
     WsLayout L = ws_layout(g);
     *bytes = L.total + gc_mlp_ws_bytes(g->n);
     return GC_OK;
@@ -614,6 +877,14 @@ int ensure_graph_tables(const gc_graph *g, const Ws &w, hipStream_t s) {
 }  // namespace
 
 extern "C" int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (g && g->weighted) {
+        // every record of every slot starts at zero (untouched)
+        WWs ww;
+        int rc = get_wws(g, d_ws, ws_bytes, &ww);
+        if (rc) return rc;
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(ww.base), ww.L.total / 4, 0u, stream));
+        return GC_OK;
+    }
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
     if (rc) return rc;
@@ -1241,6 +1512,18 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
 extern "C" int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t stream,
                                int32_t *h_node, int64_t *h_farness) {
     if (!g) return fail(GC_EINVAL, "graph is NULL");
+    if (g->weighted) {
+        WWs ww;
+        int rc = get_wws(g, d_ws, ws_bytes, &ww);
+        if (rc) return rc;
+        if (!h_node || !h_farness) return fail(GC_EINVAL, "NULL output");
+        std::vector<std::pair<int64_t, int32_t>> top;
+        rc = run_wclosest(g, ww, stream, 1, &top);
+        if (rc) return rc;
+        *h_node = top[0].second;
+        *h_farness = top[0].first;
+        return GC_OK;
+    }
     if (int rc0 = search_size_ok(g)) return rc0;
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
@@ -1258,6 +1541,21 @@ extern "C" int gc_closest_node(const gc_graph *g, void *d_ws, size_t ws_bytes, h
 extern "C" int gc_topk_closeness(const gc_graph *g, int32_t k, void *d_ws, size_t ws_bytes,
                                  hipStream_t stream, int32_t *h_nodes, int64_t *h_farness) {
     if (!g) return fail(GC_EINVAL, "graph is NULL");
+    if (g->weighted) {
+        WWs ww;
+        int rc = get_wws(g, d_ws, ws_bytes, &ww);
+        if (rc) return rc;
+        if (!h_nodes || !h_farness) return fail(GC_EINVAL, "NULL output");
+        if (k < 1 || k > g->n) return fail(GC_EINVAL, "k = %d out of range 1..%d", k, g->n);
+        std::vector<std::pair<int64_t, int32_t>> top;
+        rc = run_wclosest(g, ww, stream, k, &top);
+        if (rc) return rc;
+        for (int32_t i = 0; i < k; ++i) {
+            h_nodes[i] = top[(size_t)i].second;
+            h_farness[i] = top[(size_t)i].first;
+        }
+        return GC_OK;
+    }
     if (int rc0 = search_size_ok(g)) return rc0;
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
@@ -1298,6 +1596,7 @@ extern "C" int gc_bits_size(const gc_graph *g, int32_t levels, size_t *bytes) {
 extern "C" int gc_bits_prepare(const gc_graph *g, void *d_bits, size_t bytes, hipStream_t s,
                                int32_t *h_levels) {
     if (!g || !d_bits || !h_levels) return fail(GC_EINVAL, "NULL argument");
+    if (int rc0 = unweighted_only(g, "gc_bits_prepare")) return rc0;
     const size_t lb = bits_level_bytes(g);
     const size_t fixed = (size_t)kBitsMaxS * (size_t)bits_words(g) * 8 + 256;
     if (bytes < fixed + 2 * lb) return fail(GC_EWORKSPACE, "bits buffer too small for two levels");
@@ -1361,6 +1660,7 @@ unsigned long long *bits_words_counter(const gc_graph *g, const void *d_bits, si
 extern "C" int gc_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes, int32_t levels,
                              const void *d_dist, int32_t dist_bytes, const int32_t *d_cand, int64_t count,
                              int64_t *d_gain, hipStream_t stream) {
+    if (int rc0 = unweighted_only(g, "gc_bits_gains")) return rc0;
     if (!g || !d_bits || !d_dist || (count > 0 && (!d_cand || !d_gain))) return fail(GC_EINVAL, "NULL argument");
     if (dist_bytes != 1) return fail(GC_EINVAL, "the bit-vector gains take uint8 distances");
     if (levels < 1 || levels > kBitsMaxS) return fail(GC_EINVAL, "levels out of range");
@@ -1371,6 +1671,20 @@ extern "C" int gc_bits_gains(const gc_graph *g, const void *d_bits, size_t bytes
 
 extern "C" int gc_update_dist(const gc_graph *g, int32_t node, void *d_dist, int32_t dist_bytes,
                               void *d_ws, size_t ws_bytes, hipStream_t stream, int64_t *d_farness) {
+    if (g && g->weighted) {
+        WWs ww;
+        int rc = get_wws(g, d_ws, ws_bytes, &ww);
+        if (rc) return rc;
+        if (node < 0 || node >= g->n) return fail(GC_EINVAL, "node %d out of range", node);
+        if (dist_bytes != 4) return fail(GC_EINVAL, "weighted graphs: dist_bytes must be 4");
+        if (!d_dist || !d_farness) return fail(GC_EINVAL, "NULL device pointer");
+        int32_t dn = 0;
+        HIP_OK(hipMemcpyAsync(&dn, reinterpret_cast<int32_t *>(d_dist) + node, sizeof(dn), hipMemcpyDeviceToHost,
+                              stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        // on a connected graph d(S, node) is finite unless S = {}
+        return run_wupdate(g, ww, node, reinterpret_cast<int32_t *>(d_dist), d_farness, dn == INT32_MAX, stream);
+    }
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
     if (rc) return rc;
@@ -1384,6 +1698,26 @@ extern "C" int gc_marginal_gains(const gc_graph *g, const void *d_dist, int32_t 
                                  const int32_t *d_cand, int32_t count, int64_t *d_gain,
                                  int64_t *d_edges, int32_t *d_visited, void *d_ws, size_t ws_bytes,
                                  hipStream_t stream) {
+    if (g && g->weighted) {
+        WWs ww;
+        int rc = get_wws(g, d_ws, ws_bytes, &ww);
+        if (rc) return rc;
+        if (dist_bytes != 4) return fail(GC_EINVAL, "weighted graphs: dist_bytes must be 4");
+        if (count < 0) return fail(GC_EINVAL, "count < 0");
+        if (count > 0 && (!d_dist || !d_cand || !d_gain)) return fail(GC_EINVAL, "NULL device pointer");
+        if (count == 0) return GC_OK;
+        if (g_timing) HIP_OK(hipEventRecord(g_ev0, stream));
+        // W_GAIN only reads d(S,.)
+        rc = wlaunch(g, ww, W_GAIN, const_cast<int32_t *>(reinterpret_cast<const int32_t *>(d_dist)), d_cand, count,
+                     d_gain, d_edges, d_visited, 0, nullptr, false, stream);
+        if (rc) return rc;
+        if (g_timing) {
+            HIP_OK(hipEventRecord(g_ev1, stream));
+            HIP_OK(hipEventSynchronize(g_ev1));
+            HIP_OK(hipEventElapsedTime(&g_timing_ms, g_ev0, g_ev1));
+        }
+        return GC_OK;
+    }
     Ws w;
     int rc = get_ws(g, d_ws, ws_bytes, &w);
     if (rc) return rc;
@@ -1457,6 +1791,7 @@ size_t gains_buffer_min_bytes(const gc_graph *g) {
 int gains_in_buffer(const gc_graph *g, const void *d_dist, int32_t dist_bytes, const int32_t *d_cand,
                     int32_t count, int64_t *d_gain, int64_t *d_edges, int32_t *d_visited, void *d_buf,
                     size_t buf_bytes, hipStream_t stream) {
+    if (int rc0 = unweighted_only(g, "gc_marginal_gains_noalloc")) return rc0;
     if (!g) return fail(GC_EINVAL, "graph is NULL");
     if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
     if (count < 0) return fail(GC_EINVAL, "count < 0");
@@ -1488,6 +1823,7 @@ int gains_in_buffer(const gc_graph *g, const void *d_dist, int32_t dist_bytes, c
 
 extern "C" int gc_gain_words(const gc_graph *g, const void *d_ws, size_t ws_bytes, hipStream_t stream,
                              int64_t *h_words) {
+    if (int rc0 = unweighted_only(g, "gc_gain_words")) return rc0;
     Ws w;
     int rc = get_ws(g, const_cast<void *>(d_ws), ws_bytes, &w);
     if (rc) return rc;
@@ -1599,6 +1935,233 @@ struct PinnedBuf {
     }
 };
 
+// Greedy++ on a weighted graph: the first pick by the closeness search, the
+// first gain round over every other node in one launch, then the lazy loop
+// of Section 4.2 (stale gains bound the new ones by supermodularity) in
+// ascending-id or CELF order, batches growing as in the unweighted loop.
+int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, size_t ws_bytes, hipStream_t s,
+                    int32_t *h_group, int64_t *h_farness, gc_stats *h_stats) {
+    const double t_start = now_ms();
+    WWs w;
+    int rc = get_wws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    const int32_t n = g->n;
+    if (k < 1 || k > n) return fail(GC_EINVAL, "k = %d outside [1, n = %d]", k, n);
+    if (!h_group || !h_farness) return fail(GC_EINVAL, "NULL output");
+    if (o.order != GC_ORDER_PLAIN && o.order != GC_ORDER_CELF)
+        return fail(GC_EINVAL, "weighted graphs: plain or CELF order");
+    if (o.d_bits || o.early_exit || o.log_capacity > 0)
+        return fail(GC_EINVAL, "weighted graphs: no bit-vector gains, early exit or evaluation log");
+    if (o.bitset_width != 0 && o.bitset_width != 64) return fail(GC_EINVAL, "bitset_width must be 64");
+    if (o.block < 0) return fail(GC_EINVAL, "block < 0");
+    if (o.block_growth < 0 || o.block_growth > 8) return fail(GC_EINVAL, "block_growth outside [0, 8]");
+    if (o.nprefix < 0 || o.nprefix > k || (o.nprefix > 0 && !o.h_prefix)) return fail(GC_EINVAL, "bad prefix");
+    for (int32_t i = 0; i < o.nprefix; ++i)
+        if (o.h_prefix[i] < 0 || o.h_prefix[i] >= n) return fail(GC_EINVAL, "prefix id out of range");
+    if (o.nprefix > 1) {
+        std::vector<int32_t> ids(o.h_prefix, o.h_prefix + o.nprefix);
+        std::sort(ids.begin(), ids.end());
+        if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+            return fail(GC_EINVAL, "prefix repeats a node id");
+    }
+    const int32_t block = o.block > 0 ? o.block : kSrc;
+    const int32_t growth = o.block_growth > 0 ? o.block_growth : 2;
+    const int64_t maxb = std::min<int64_t>(16LL * block, n);
+    gc_stats st{};
+    if (h_stats) st.h_evals_per_round = h_stats->h_evals_per_round;
+    if (st.h_evals_per_round)
+        for (int32_t i = 0; i < k; ++i) st.h_evals_per_round[i] = 0;
+    st.dist_bytes = 4;
+    int alloc_count = 0;
+    PinnedBuf pin_cand, pin_out;
+    pin_cand.counter = pin_out.counter = &alloc_count;
+    if (pin_cand.ensure(sizeof(int32_t) * (size_t)n * 2) != hipSuccess ||
+        pin_out.ensure(sizeof(int64_t) * (size_t)n * 2 + 64) != hipSuccess)
+        return fail(GC_ENOMEM, "pinned host buffers");
+    int32_t *hc = reinterpret_cast<int32_t *>(pin_cand.p);
+    int32_t *hv = hc + n;
+    int64_t *hg = reinterpret_cast<int64_t *>(pin_out.p);
+    int64_t *he = hg + n;
+    int64_t *hsmall = he + n;  // gain and F of an update
+
+    // ---- s_1 and d(S,.) of S = {s_1}
+    double t0 = now_ms();
+    int32_t s1;
+    if (o.nprefix > 0) {
+        s1 = o.h_prefix[0];
+    } else {
+        std::vector<std::pair<int64_t, int32_t>> top;
+        rc = run_wclosest(g, w, s, 1, &top);
+        if (rc) return rc;
+        s1 = top[0].second;
+        st.closest_sources = n;
+    }
+    st.ms_closest = now_ms() - t0;
+    t0 = now_ms();
+    int32_t *dS = w.dist();
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(dS), (size_t)n, 0x7FFFFFFFu, s));
+    rc = run_wupdate(g, w, s1, dS, w.far(), true, s);
+    if (rc) return rc;
+    HIP_OK(hipMemcpyAsync(hsmall + 1, w.far(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    int64_t F = hsmall[1];
+    std::vector<int32_t> group;
+    std::vector<int64_t> Fs;
+    std::vector<uint8_t> inS((size_t)n, 0);
+    group.push_back(s1);
+    Fs.push_back(F);
+    inS[(size_t)s1] = 1;
+    for (int32_t i = 1; i < o.nprefix; ++i) {
+        const int32_t v = o.h_prefix[i];
+        rc = run_wupdate(g, w, v, dS, w.far(), false, s);
+        if (rc) return rc;
+        HIP_OK(hipMemcpyAsync(hsmall + 1, w.far(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        F = hsmall[1];
+        group.push_back(v);
+        Fs.push_back(F);
+        inS[(size_t)v] = 1;
+    }
+    st.ms_update += now_ms() - t0;
+
+    auto evaluate = [&](int32_t cnt) -> int {
+        HIP_OK(hipMemcpyAsync(w.cand(), hc, sizeof(int32_t) * (size_t)cnt, hipMemcpyHostToDevice, s));
+        if (g_timing) HIP_OK(hipEventRecord(g_ev0, s));
+        int r = wlaunch(g, w, W_GAIN, dS, w.cand(), cnt, w.out(), w.edges(), w.vis(), 0, nullptr, false, s);
+        if (r) return r;
+        if (g_timing) HIP_OK(hipEventRecord(g_ev1, s));
+        HIP_OK(hipMemcpyAsync(hg, w.out(), sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(he, w.edges(), sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(hv, w.vis(), sizeof(int32_t) * (size_t)cnt, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (g_timing) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, g_ev0, g_ev1));
+            st.ms_gain_gpu += ms;
+            g_timing_ms = ms;
+        }
+        for (int32_t j = 0; j < cnt; ++j) {
+            st.edges_alg += he[j];
+            st.visited += hv[j];
+        }
+        st.gain_launches += 1;
+        return GC_OK;
+    };
+
+    std::vector<int64_t> ub((size_t)n, std::numeric_limits<int64_t>::max());
+    const bool celf = o.order == GC_ORDER_CELF;
+    MaxTree tree;
+    ArgTree keys;
+    const int32_t first_gain_round = (int32_t)group.size();
+    for (int32_t r = first_gain_round; r < k; ++r) {
+        const double tr = now_ms();
+        int64_t bgain = -1;
+        int32_t bid = -1;
+        int64_t nev = 0;
+        if (r == first_gain_round) {
+            // every stale gain is +inf: all candidates in one launch, ascending id
+            int32_t cnt = 0;
+            for (int32_t v = 0; v < n; ++v)
+                if (!inS[(size_t)v]) hc[cnt++] = v;
+            rc = evaluate(cnt);
+            if (rc) return rc;
+            for (int32_t j = 0; j < cnt; ++j) {
+                ub[(size_t)hc[j]] = hg[j];
+                if (hg[j] > bgain) {
+                    bgain = hg[j];
+                    bid = hc[j];
+                }
+            }
+            nev = cnt;
+            if (celf) keys.build(ub, inS, -1);
+            else tree.build(ub, inS);
+        } else {
+            int64_t cur = std::min<int64_t>(block, maxb);
+            int32_t pos = 0;
+            for (;;) {
+                int32_t cnt = 0;
+                if (celf) {
+                    // largest (stale gain, -id) first, while it can still win
+                    while (cnt < cur) {
+                        const int32_t v = keys.top();
+                        if (v < 0) break;
+                        const int64_t u = ub[(size_t)v];
+                        // stop unless (u, -v) beats (bgain, -bid); the best itself,
+                        // back in the tree with its exact gain, does not
+                        if (bid >= 0 && (u < bgain || (u == bgain && v >= bid))) break;
+                        hc[cnt++] = v;
+                        keys.set(v, -1);
+                    }
+                } else {
+                    // ascending id: every id left is above bid, so it must beat bgain
+                    while (cnt < cur) {
+                        const int32_t v = tree.first_at_least(pos, bid < 0 ? 0 : bgain + 1);
+                        if (v < 0) break;
+                        hc[cnt++] = v;
+                        pos = v + 1;
+                    }
+                }
+                if (cnt == 0) break;
+                rc = evaluate(cnt);
+                if (rc) return rc;
+                for (int32_t j = 0; j < cnt; ++j) {
+                    const int32_t v = hc[j];
+                    if (hg[j] > ub[(size_t)v]) return fail(GC_EDEVICE, "gain of node %d grew (supermodularity)", v);
+                    ub[(size_t)v] = hg[j];
+                    if (celf) keys.set(v, hg[j]);
+                    else tree.set(v, hg[j]);
+                    if (hg[j] > bgain || (hg[j] == bgain && v < bid)) {
+                        bgain = hg[j];
+                        bid = v;
+                    }
+                }
+                nev += cnt;
+                // a candidate is evaluated at most once per round
+                if (nev > n) return fail(GC_EDEVICE, "round %d evaluated more than n candidates", r);
+                cur = std::min<int64_t>(cur * growth, maxb);
+            }
+        }
+        if (bid < 0) return fail(GC_EDEVICE, "no candidate left in round %d", r);
+        const double tu = now_ms();
+        if (r == first_gain_round) st.ms_round1 += tu - tr;
+        else st.ms_later += tu - tr;
+        rc = run_wupdate(g, w, bid, dS, w.far(), false, s);
+        if (rc) return rc;
+        HIP_OK(hipMemcpyAsync(hsmall, w.res(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(hsmall + 1, w.far(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (hsmall[0] != bgain || hsmall[1] != F - bgain)
+            return fail(GC_EDEVICE, "update of node %d: gain %lld, expected %lld", bid, (long long)hsmall[0],
+                        (long long)bgain);
+        F -= bgain;
+        if (o.debug_checks) {
+            unsigned long long sum = 0;
+            HIP_OK(launch_wsum(dS, n, w.sum(), s));
+            HIP_OK(hipMemcpyAsync(&sum, w.sum(), sizeof(sum), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            if ((int64_t)sum != F) return fail(GC_EDEVICE, "F(S) = %lld but d(S,.) sums to %llu", (long long)F, sum);
+        }
+        st.ms_update += now_ms() - tu;
+        group.push_back(bid);
+        Fs.push_back(F);
+        inS[(size_t)bid] = 1;
+        ub[(size_t)bid] = -1;
+        if (celf) keys.set(bid, -1);
+        else tree.set(bid, -1);
+        st.evals_total += nev;
+        if (r == first_gain_round) st.evals_round1 += nev;
+        else st.evals_later += nev;
+        if (st.h_evals_per_round) st.h_evals_per_round[r] = nev;
+    }
+    for (int32_t i = 0; i < k; ++i) {
+        h_group[i] = group[(size_t)i];
+        h_farness[i] = Fs[(size_t)i];
+    }
+    st.ms_total = now_ms() - t_start;
+    if (h_stats) *h_stats = st;
+    return GC_OK;
+}
+
 }  // namespace
 
 extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts, void *d_ws,
@@ -1606,6 +2169,11 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                                int64_t *h_farness, gc_stats *h_stats) {
     const double t_start = now_ms();
     if (!g) return fail(GC_EINVAL, "graph is NULL");
+    if (g->weighted) {
+        gc_opts o{};
+        if (opts) o = *opts;
+        return greedy_weighted(g, k, o, d_ws, ws_bytes, s, h_group, h_farness, h_stats);
+    }
     // without a prefix the first pick comes from the closeness search
     if (!opts || opts->nprefix == 0)
         if (int rc0 = search_size_ok(g)) return rc0;
@@ -2455,6 +3023,7 @@ extern "C" int gc_node_features(const gc_graph *g, const void *d_dist, int32_t d
                                 const int32_t *d_last_eval, const uint16_t *d_dist_at_eval,
                                 int32_t round, int32_t k, int32_t ecc1, float *d_feat,
                                 hipStream_t stream) {
+    if (int rc0 = unweighted_only(g, "gc_node_features")) return rc0;
     if (!g) return fail(GC_EINVAL, "graph is NULL");
     if (dist_bytes != 1 && dist_bytes != 2) return fail(GC_EINVAL, "dist_bytes must be 1 or 2");
     if (count < 0) return fail(GC_EINVAL, "count < 0");

@@ -40,7 +40,7 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
             "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many",
             "gc_topk_closeness", "gc_get_tuning", "gc_set_tuning", "gc_bits_size", "gc_bits_prepare",
-            "gc_bits_gains", "gc_marginal_gains_noalloc"]
+            "gc_bits_gains", "gc_marginal_gains_noalloc", "gc_load_csr_weighted"]
 TUNING_FIELDS = ("unroll", "unroll_small", "min_edges", "min_edges_small", "level_wgs_per_cu")
 MLP_PARAMS = 4801
 MLP_IN = 8
@@ -107,6 +107,8 @@ def load_library():
     vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     lib.gc_load_csr.restype = ctypes.c_int
     lib.gc_load_csr.argtypes = [i32, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    lib.gc_load_csr_weighted.restype = ctypes.c_int
+    lib.gc_load_csr_weighted.argtypes = [i32, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
     lib.gc_free_graph.restype = None
     lib.gc_free_graph.argtypes = [vp]
     lib.gc_graph_n.restype = i32
@@ -203,11 +205,13 @@ class Graph:
     """A device CSR graph plus its library handle and workspace.
 
     row_ptr, col_idx: int32 tensors on the current HIP device (or numpy arrays,
-    which are copied there).  The tensors are kept alive by this object.
+    which are copied there).  weight: None, or uint8 edge lengths (one per
+    CSR entry) for a weighted graph, whose distances are int32
+    (dist_bytes = 4).  The tensors are kept alive by this object.
     """
 
     def __init__(self, row_ptr, col_idx, validate: bool = True, workspace: bool = True,
-                 directed: bool = False):
+                 directed: bool = False, weight=None):
         lib = load_library()
         dev = torch.device("cuda", torch.cuda.current_device())
         if isinstance(row_ptr, np.ndarray):
@@ -223,8 +227,18 @@ class Graph:
         h = ctypes.c_void_p()
         self.directed = bool(directed)
         flags = (GC_VALIDATE if validate else 0) | (GC_DIRECTED if directed else 0)
-        _check(lib.gc_load_csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), flags, _stream(),
-                               ctypes.byref(h)))
+        self.weight = None
+        if weight is not None:
+            if isinstance(weight, np.ndarray):
+                weight = torch.from_numpy(np.ascontiguousarray(weight, dtype=np.uint8))
+            if weight.numel() != self.nnz:
+                raise ValueError("one length per CSR entry (%d), got %d" % (self.nnz, weight.numel()))
+            self.weight = weight.to(dev, dtype=torch.uint8).contiguous()
+            _check(lib.gc_load_csr_weighted(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx),
+                                            _ptr(self.weight), flags, _stream(), ctypes.byref(h)))
+        else:
+            _check(lib.gc_load_csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), flags, _stream(),
+                                   ctypes.byref(h)))
         self.handle = h
         self.ws = None
         self.ws_bytes = 0
@@ -234,7 +248,12 @@ class Graph:
     @classmethod
     def from_graphgen(cls, g, **kw):
         kw.setdefault("directed", bool(getattr(g, "directed", False)))
+        kw.setdefault("weight", getattr(g, "weight", None))
         return cls(g.row_ptr, g.col_idx, **kw)
+
+    @property
+    def weighted(self) -> bool:
+        return self.weight is not None
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -282,7 +301,10 @@ class Graph:
         return nodes, far
 
     def new_dist(self, dist_bytes: int = 1):
-        """A d(S,.) buffer for S = {} (all INF), padded to whole 4-byte words."""
+        """A d(S,.) buffer for S = {} (all INF), padded to whole 4-byte words
+        (dist_bytes 4: int32 with INF = 2^31 - 1, for weighted graphs)."""
+        if dist_bytes == 4:
+            return torch.full((self.n,), 2**31 - 1, dtype=torch.int32, device=self.row_ptr.device)
         dt = torch.uint8 if dist_bytes == 1 else torch.int16
         nwords = (self.n * dist_bytes + 3) // 4
         buf = torch.full((nwords * 4 // dist_bytes,), -1, dtype=dt, device=self.row_ptr.device)
