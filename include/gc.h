@@ -198,10 +198,14 @@ int gc_load_csr(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t 
  * take int32 distances (dist_bytes = 4); gc_greedy_group takes the plain or
  * CELF order without bit vectors, early exit or evaluation log; the
  * bit-vector calls, gc_marginal_gains_noalloc, gc_gain_words and
- * gc_node_features give GC_EINVAL.  GC_WDELTA and GC_WDELTA_CLOSE (the
- * bucket widths of the gain and closeness searches, default twice and half
- * the largest length) and GC_WSLOTS (searches in flight, default 8 per
- * compute unit within the record budget GC_VIS_BUDGET_MB) are read here.
+ * gc_node_features give GC_EINVAL.  Read here: GC_WDELTA and
+ * GC_WDELTA_CLOSE (the bucket widths of the gain and closeness searches;
+ * defaults twice the largest length, and a sixteenth of the mean distance
+ * from the first node the closeness search takes), GC_WSLOTS (gain searches
+ * in flight, default 8 per compute unit within the record budget
+ * GC_VIS_BUDGET_MB), GC_WCLOSE_SLOTS and GC_WCLOSE_THREADS (closeness
+ * searches in flight and their workgroup size, default 256 and 1024).  None
+ * changes a result.
  */
 int gc_load_csr_weighted(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                          const uint8_t *d_weight, uint32_t flags, hipStream_t stream, gc_graph **out);

@@ -126,6 +126,9 @@ struct gc_graph {
     int32_t wdelta_gain = 0;
     int32_t wdelta_close = 0;
     int32_t wslots = 0;
+    int32_t wclose_threads = 1024; // GC_WCLOSE_THREADS: workgroup of a closeness search (256 or 1024)
+    int32_t wclose_slots = 256;    // GC_WCLOSE_SLOTS: closeness searches in flight (<= wslots)
+    bool wdelta_close_env = false; // GC_WDELTA_CLOSE given (else from the first search's mean distance)
     const std::vector<int32_t> &search_order() const { return balls ? by_ball : by_degree; }
 };
 
@@ -451,7 +454,8 @@ static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const in
     if (weighted) {
         // bucket widths: the gain searches are short and pay per phase, so one
         // phase spans twice the longest edge; the closeness search checks its
-        // bound once per phase, so its phases are a quarter of that
+        // bound once per phase, so its width comes from the first search's
+        // mean distance (this value only when GC_WDELTA_CLOSE sets it)
         g->wdelta_gain = std::min(2 * g->wmax, 65535);
         g->wdelta_close = std::max(1, g->wmax / 2);
         if (const char *e = getenv("GC_WDELTA")) {
@@ -460,7 +464,10 @@ static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const in
         }
         if (const char *e = getenv("GC_WDELTA_CLOSE")) {
             const long v = strtol(e, nullptr, 10);
-            if (v >= 1 && v <= 65535) g->wdelta_close = (int32_t)v;
+            if (v >= 1 && v <= 65535) {
+                g->wdelta_close = (int32_t)v;
+                g->wdelta_close_env = true;
+            }
         }
         // one slot per resident workgroup of 256 threads (8 per CU), within the record budget
         const int64_t per_slot = (int64_t)kWSlotBytesPerNode * n;
@@ -470,6 +477,15 @@ static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const in
             if (v >= 1 && v <= 65536) slots = v;
         }
         g->wslots = (int32_t)slots;
+        if (const char *e = getenv("GC_WCLOSE_THREADS")) g->wclose_threads = strtol(e, nullptr, 10) == 256 ? 256 : 1024;
+        // the closeness searches are full SSSPs: fewer, wider workgroups keep
+        // their records (16 bytes per node each) closer to the caches
+        g->wclose_slots = 256;
+        if (const char *e = getenv("GC_WCLOSE_SLOTS")) {
+            const long long v = strtoll(e, nullptr, 10);
+            if (v >= 1 && v <= 65536) g->wclose_slots = (int32_t)v;
+        }
+        g->wclose_slots = std::min(g->wclose_slots, g->wslots);
     }
     *out = g;
     return GC_OK;
@@ -680,7 +696,8 @@ int get_ws(const gc_graph *g, void *d_ws, size_t ws_bytes, Ws *w) {
 // result, sum, one node id, F(S); then d(S,.) (int32), per-candidate outputs,
 // the candidate list, and the slots (records, then work lists)
 struct WLayout {
-    size_t ctr, dist, out, edges, vis, cand, rec, lists, total;
+    size_t ctr, dist, out, edges, vis, cand, d0, t0, hist, rec, lists, total;
+    int64_t t0_cap;  // entries of the closeness bound's tail table
 };
 
 WLayout wlayout(const gc_graph *g) {
@@ -693,6 +710,12 @@ WLayout wlayout(const gc_graph *g) {
     L.edges = o; o += al256(n * 8);
     L.vis = o; o += al256(n * 4);
     L.cand = o; o += al256(n * 4);
+    // the landmark distances of the closeness search and their tail sums,
+    // for distances up to min(255 (n - 1), 2^22)
+    L.t0_cap = std::min<int64_t>(255LL * (int64_t)(n - 1) + 2, (int64_t)1 << 22);
+    L.d0 = o; o += al256(n * 4);
+    L.t0 = o; o += al256((size_t)L.t0_cap * 8);
+    L.hist = o; o += al256((size_t)L.t0_cap * 4);
     L.rec = o; o += al256(slots * n * sizeof(WRec));
     L.lists = o; o += al256(slots * n * kWLists * 4);
     L.total = o;
@@ -714,6 +737,10 @@ struct WWs {
     int64_t *edges() const { return reinterpret_cast<int64_t *>(base + L.edges); }
     int32_t *vis() const { return reinterpret_cast<int32_t *>(base + L.vis); }
     int32_t *cand() const { return reinterpret_cast<int32_t *>(base + L.cand); }
+    int32_t *d0() const { return reinterpret_cast<int32_t *>(base + L.d0); }
+    int64_t *t0() const { return reinterpret_cast<int64_t *>(base + L.t0); }
+    uint32_t *hist() const { return reinterpret_cast<uint32_t *>(base + L.hist); }
+    int32_t *maxd0() const { return reinterpret_cast<int32_t *>(base + L.ctr + 56); }
     WRec *rec() const { return reinterpret_cast<WRec *>(base + L.rec); }
     int32_t *lists() const { return reinterpret_cast<int32_t *>(base + L.lists); }
 };
@@ -734,9 +761,16 @@ int get_wws(const gc_graph *g, void *d_ws, size_t ws_bytes, WWs *w) {
 // The same operations on a graph with integer edge lengths: every search is
 // one workgroup's bucketed search (gc_weighted.hip) and d(S,.) is int32.
 
+struct WClose {
+    int32_t delta = 0;          // bucket width (0: the graph's default)
+    const int32_t *d0 = nullptr;
+    const int64_t *t0 = nullptr;
+    int32_t t0_len = 0;
+};
+
 int wlaunch(const gc_graph *g, const WWs &w, int32_t mode, int32_t *dS, const int32_t *cand, int32_t count,
             int64_t *out, int64_t *edges, int32_t *vis, int64_t thr, unsigned long long *best, bool one,
-            hipStream_t s) {
+            hipStream_t s, const WClose *wc = nullptr) {
     if (count <= 0) return GC_OK;
     HIP_OK(launch_fill_u32(w.next(), 1, 0u, s));
     WArgs a{};
@@ -758,36 +792,87 @@ int wlaunch(const gc_graph *g, const WWs &w, int32_t mode, int32_t *dS, const in
     a.thr = thr;
     a.best = best;
     a.flags = w.flags();
-    HIP_OK(one ? launch_wsearch_one(a, s) : launch_wsearch(a, g->wslots, s));
+    if (wc) {
+        if (wc->delta > 0) a.delta = wc->delta;
+        a.d0 = wc->d0;
+        a.t0 = wc->t0;
+        a.t0_len = wc->t0_len;
+    }
+    HIP_OK(one ? launch_wsearch_one(a, s)
+               : mode == W_CLOSE ? launch_wsearch(a, g->wclose_slots, g->wclose_threads, s)
+                                 : launch_wsearch(a, g->wslots, 256, s));
     return GC_OK;
 }
 
 // The k nodes of least F({v}) (Section 3.1 with k >= 1), in increasing
-// (F, id) order.  Candidates go in decreasing degree order; the first one is
-// searched alone so that its farness is the cut threshold of all the others.
-// k = 1: one launch over the rest, each search cut against the best farness
-// any search has finished with (a device atomic).  k > 1: launches of a few
-// candidates per slot, each cut against the k-th best farness of the
-// launches before.  A cut search's farness exceeds the threshold, so it is
-// not among the k.
+// (F, id) order.  Candidates go in decreasing degree order.  The first one,
+// v0, is a full search that writes d0 = d(v0,.): its farness is the first
+// cut threshold, d0 the landmark of the cut bound (with the tail table T0
+// built from a histogram of d0), and its mean distance sets the bucket width
+// (a sixteenth of it, so the bound is tested many times before the search
+// passes the mean).  k = 1: one launch over the rest, each search cut against
+// the best farness any search has finished with (a device atomic).  k > 1:
+// launches of a few candidates per slot, each cut against the k-th best
+// farness of the launches before.  A cut search's farness exceeds the
+// threshold, so it is not among the k.
 int run_wclosest(const gc_graph *g, const WWs &w, hipStream_t s, int32_t k,
-                 std::vector<std::pair<int64_t, int32_t>> *top) {
+                 std::vector<std::pair<int64_t, int32_t>> *top, int64_t *sources = nullptr) {
     const int32_t n = g->n;
     HIP_OK(hipMemcpyAsync(w.cand(), g->by_degree.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
-    // (the kernel compares the best as a signed value: start at INT64_MAX)
-    HIP_OK(launch_set_i64(reinterpret_cast<int64_t *>(w.best()), std::numeric_limits<int64_t>::max(), s));
-    unsigned long long *best = k == 1 ? w.best() : nullptr;
-    int rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand(), 1, w.out(), nullptr, nullptr,
-                     std::numeric_limits<int64_t>::max(), best, true, s);
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.d0()), (size_t)n, 0x7FFFFFFFu, s));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.maxd0()), 1, 0u, s));
+    int rc = wlaunch(g, w, W_WRITE, w.d0(), w.cand(), 1, w.res(), nullptr, nullptr, 0, nullptr, true, s);
     if (rc) return rc;
+    HIP_OK(launch_wsum(w.d0(), n, w.best(), s));
+    HIP_OK(launch_wmax(w.d0(), n, w.maxd0(), s));
+    int64_t F0 = 0;
+    int32_t maxd0 = 0;
+    HIP_OK(hipMemcpyAsync(&F0, w.best(), sizeof(F0), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(&maxd0, w.maxd0(), sizeof(maxd0), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (maxd0 == INT32_MAX) return fail(GC_EDISCONNECTED, "node %d does not reach every node", g->by_degree[0]);
+    HIP_OK(launch_set_i64(w.out(), F0, s));
+    WClose wc;
+    wc.delta = g->wdelta_close_env ? g->wdelta_close
+                                   : (int32_t)std::min<int64_t>(65535, std::max<int64_t>(1, F0 / std::max(1, n - 1) / 16));
+    wc.d0 = w.d0();
+    if ((int64_t)maxd0 + 2 <= w.L.t0_cap) {
+        // T0[M] = sum_w max(0, d0(w) - M) = T0[M + 1] + #{w : d0(w) > M}
+        const int32_t len = maxd0 + 2;
+        std::vector<uint32_t> h((size_t)len);
+        std::vector<int64_t> t((size_t)len, 0);
+        HIP_OK(launch_fill_u32(w.hist(), (size_t)len, 0u, s));
+        HIP_OK(launch_whist(w.d0(), n, w.hist(), s));
+        HIP_OK(hipMemcpyAsync(h.data(), w.hist(), sizeof(uint32_t) * (size_t)len, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        int64_t above = 0;  // #{w : d0(w) > M}
+        for (int32_t M = len - 2; M >= 0; --M) {
+            above += h[(size_t)M + 1];
+            t[(size_t)M] = t[(size_t)M + 1] + above;
+        }
+        HIP_OK(hipMemcpyAsync(w.t0(), t.data(), sizeof(int64_t) * (size_t)len, hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));  // t lives on this stack frame
+        wc.t0 = w.t0();
+        wc.t0_len = len;
+    }
     top->clear();
     int32_t flag = 0;
     if (k == 1) {
-        rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand() + 1, n - 1, w.out() + 1, nullptr, nullptr,
-                     std::numeric_limits<int64_t>::max(), best, false, s);
+        // On an undirected graph a node v whose only neighbour is h (edge of
+        // length e) reaches every other node through h, so F({v}) =
+        // F({h}) + (n - 2) e > F({h}) for n >= 3: it cannot be the closest.
+        // The degree order puts such nodes last.
+        int32_t cnt = n;
+        if (!g->directed && n >= 3)
+            while (cnt > 1 && g->h_rp[(size_t)g->by_degree[(size_t)cnt - 1] + 1] -
+                                      g->h_rp[(size_t)g->by_degree[(size_t)cnt - 1]] == 1)
+                --cnt;
+        rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand() + 1, cnt - 1, w.out() + 1, nullptr, nullptr,
+                     std::numeric_limits<int64_t>::max(), w.best(), false, s, &wc);
         if (rc) return rc;
-        HIP_OK(launch_wargmin(w.out(), w.cand(), n, w.res(), s));
+        HIP_OK(launch_wargmin(w.out(), w.cand(), cnt, w.res(), s));
+        if (sources) *sources = cnt;
         int64_t res[2] = {-1, -1};
         HIP_OK(hipMemcpyAsync(res, w.res(), sizeof(res), hipMemcpyDeviceToHost, s));
         HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
@@ -796,17 +881,16 @@ int run_wclosest(const gc_graph *g, const WWs &w, hipStream_t s, int32_t k,
         top->emplace_back(res[0], (int32_t)res[1]);
         return GC_OK;
     }
+    top->emplace_back(F0, g->by_degree[0]);
     const int32_t chunk = std::max<int32_t>(1, 4 * g->wslots);
     std::vector<int64_t> hout((size_t)std::min<int32_t>(chunk, n));
-    for (int32_t start = 0; start < n;) {
-        const int32_t cnt = start == 0 ? 1 : std::min<int32_t>(chunk, n - start);
-        if (start > 0) {
-            const int64_t thr = (int32_t)top->size() < k ? std::numeric_limits<int64_t>::max()
-                                                         : (*top)[(size_t)k - 1].first;
-            rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand() + start, cnt, w.out() + start, nullptr, nullptr, thr,
-                         nullptr, false, s);
-            if (rc) return rc;
-        }
+    for (int32_t start = 1; start < n;) {
+        const int32_t cnt = std::min<int32_t>(chunk, n - start);
+        const int64_t thr = (int32_t)top->size() < k ? std::numeric_limits<int64_t>::max()
+                                                     : (*top)[(size_t)k - 1].first;
+        rc = wlaunch(g, w, W_CLOSE, nullptr, w.cand() + start, cnt, w.out() + start, nullptr, nullptr, thr,
+                     nullptr, false, s, &wc);
+        if (rc) return rc;
         HIP_OK(hipMemcpyAsync(hout.data(), w.out() + start, sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost,
                               s));
         HIP_OK(hipStreamSynchronize(s));
@@ -819,6 +903,7 @@ int run_wclosest(const gc_graph *g, const WWs &w, hipStream_t s, int32_t k,
     HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (flag || (int32_t)top->size() < k) return fail(GC_EDISCONNECTED, "a closeness search did not reach every node");
+    if (sources) *sources = n;
     return GC_OK;
 }
 
@@ -1991,10 +2076,9 @@ int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, 
         s1 = o.h_prefix[0];
     } else {
         std::vector<std::pair<int64_t, int32_t>> top;
-        rc = run_wclosest(g, w, s, 1, &top);
+        rc = run_wclosest(g, w, s, 1, &top, &st.closest_sources);
         if (rc) return rc;
         s1 = top[0].second;
-        st.closest_sources = n;
     }
     st.ms_closest = now_ms() - t0;
     t0 = now_ms();

@@ -55,12 +55,16 @@ struct WArgs {
     int32_t delta;          // bucket width
     int64_t thr;            // W_CLOSE: cut once the bound exceeds min(thr, *best)
     unsigned long long *best;  // W_CLOSE: best F so far (atomicMin), or nullptr
+    const int32_t *d0;      // W_CLOSE: distances from a landmark node, or nullptr
+    const int64_t *t0;      // W_CLOSE: t0[M] = sum_w max(0, d0(w) - M), M < t0_len
+    int32_t t0_len;         //          (t0[t0_len - 1] = 0), or nullptr
     int32_t *flags;         // bit 0: a closeness search did not reach every node
 };
 
-// count candidates over `slots` slots (at most `slots` workgroups of 256
-// threads, each taking candidates from the work counter until none is left)
-hipError_t launch_wsearch(const WArgs &a, int32_t slots, hipStream_t s);
+// count candidates over `slots` slots (at most `slots` workgroups of
+// `threads` threads, 256 or 1024, each taking candidates from the work
+// counter until none is left)
+hipError_t launch_wsearch(const WArgs &a, int32_t slots, int32_t threads, hipStream_t s);
 // one candidate on slot 0, with a workgroup of 1024 threads (updates, the
 // first source of the closeness search)
 hipError_t launch_wsearch_one(const WArgs &a, hipStream_t s);
@@ -71,5 +75,9 @@ hipError_t launch_wargmin(const int64_t *out, const int32_t *cand, int32_t count
 hipError_t launch_wsum(const int32_t *d, int32_t n, unsigned long long *sum, hipStream_t s);
 // *far -= *gain
 hipError_t launch_wsub(int64_t *far, const int64_t *gain, hipStream_t s);
+// *mx = max of d[0..n) (d >= 0); *mx must be 0 on entry
+hipError_t launch_wmax(const int32_t *d, int32_t n, int32_t *mx, hipStream_t s);
+// hist[d[i]] += 1 for every i (hist zeroed by the caller, entries > max(d))
+hipError_t launch_whist(const int32_t *d, int32_t n, uint32_t *hist, hipStream_t s);
 
 }  // namespace gck

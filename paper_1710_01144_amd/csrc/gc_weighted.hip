@@ -27,7 +27,12 @@
 //   W_CLOSE  full SSSP for the closeness search of Section 3.1: after each
 //            phase, sum(settled) + theta * (n - settled) bounds F({u}) from
 //            below, and the search stops once the bound exceeds the best
-//            farness known (the weighted form of the BFScut bound).
+//            farness known (the weighted form of the BFScut bound).  With the
+//            distances d0 from one landmark node, a node w the search has not
+//            touched lies at least theta + d0(w) - M from u, M the largest d0
+//            over the touched nodes (the triangle inequality through the
+//            first touched node on a shortest path), which adds
+//            T0[M] = sum_w max(0, d0(w) - M) to the bound.
 #include "gc_weighted.h"
 
 #include <stdint.h>
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
     __shared__ int32_t s_off[BS + 1];
     __shared__ int32_t s_wave[BS / 64];
     __shared__ int64_t s_red[BS / 64];
-    __shared__ int32_t s_ci, s_ncur, s_nnext, s_nfar, s_nfar2, s_ntouch, s_nset, s_minfar, s_cut;
+    __shared__ int32_t s_ci, s_ncur, s_nnext, s_nfar, s_nfar2, s_ntouch, s_nset, s_minfar, s_cut, s_maxd0;
 
     const int tid = threadIdx.x;
     const int32_t n = a.n;
@@ -126,6 +131,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
             s_nfar = 0;
             s_nset = 0;
             s_cut = 0;
+            s_maxd0 = a.d0 ? a.d0[u] : 0;
         }
         int32_t theta = a.delta;
         uint32_t it = 1, ph = 1;
@@ -180,6 +186,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
                         if (old == 0u) {
                             const int32_t t = atomicAdd(&s_ntouch, 1);
                             touch[t] = y;
+                            if (close && a.d0) atomicMax(&s_maxd0, a.d0[y]);
                         }
                         if (nd < theta) {
                             if (atomicExch(&rec[y].mark, it) != it) {
@@ -215,7 +222,12 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
                                                                          __HIP_MEMORY_SCOPE_AGENT);
                             lim = b < lim ? b : lim;
                         }
-                        if (set_sum + (int64_t)theta * (int64_t)(n - set_cnt) > lim) s_cut = 1;
+                        // every node not settled is at theta or more; one that is
+                        // not even touched is reached through a touched node y, so
+                        // it is also at theta + d0(w) - d0(y) >= theta + d0(w) - maxd0
+                        int64_t lb = set_sum + (int64_t)theta * (int64_t)(n - set_cnt);
+                        if (a.t0) lb += a.t0[s_maxd0 < a.t0_len ? s_maxd0 : a.t0_len - 1];
+                        if (lb > lim) s_cut = 1;
                     }
                 }
                 __syncthreads();
@@ -352,12 +364,30 @@ __global__ void k_wzero64(unsigned long long *p) { *p = 0ull; }
 
 __global__ void k_wsub(int64_t *far, const int64_t *gain) { *far -= *gain; }
 
+__global__ __launch_bounds__(256) void k_wmax(const int32_t *d, int32_t n, int32_t *mx) {
+    int32_t v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        v = d[i] > v ? d[i] : v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t y = __shfl_down(v, o, 64);
+        v = y > v ? y : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+}
+
+__global__ __launch_bounds__(256) void k_whist(const int32_t *d, int32_t n, uint32_t *hist) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        atomicAdd(&hist[d[i]], 1u);
+}
+
 }  // namespace
 
-hipError_t launch_wsearch(const WArgs &a, int32_t slots, hipStream_t s) {
+hipError_t launch_wsearch(const WArgs &a, int32_t slots, int32_t threads, hipStream_t s) {
     if (a.count <= 0) return hipSuccess;
     const int32_t grid = slots < a.count ? slots : a.count;
-    hipLaunchKernelGGL(k_wsearch<256>, dim3(grid), dim3(256), 0, s, a);
+    if (threads == 1024) hipLaunchKernelGGL(k_wsearch<1024>, dim3(grid), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL(k_wsearch<256>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -381,6 +411,18 @@ hipError_t launch_wsum(const int32_t *d, int32_t n, unsigned long long *sum, hip
 
 hipError_t launch_wsub(int64_t *far, const int64_t *gain, hipStream_t s) {
     hipLaunchKernelGGL(k_wsub, dim3(1), dim3(1), 0, s, far, gain);
+    return hipGetLastError();
+}
+
+hipError_t launch_wmax(const int32_t *d, int32_t n, int32_t *mx, hipStream_t s) {
+    const int32_t grid = (int32_t)std::min<int64_t>(1024, ((int64_t)n + 255) / 256);
+    hipLaunchKernelGGL(k_wmax, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, d, n, mx);
+    return hipGetLastError();
+}
+
+hipError_t launch_whist(const int32_t *d, int32_t n, uint32_t *hist, hipStream_t s) {
+    const int32_t grid = (int32_t)std::min<int64_t>(1024, ((int64_t)n + 255) / 256);
+    hipLaunchKernelGGL(k_whist, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, d, n, hist);
     return hipGetLastError();
 }
 

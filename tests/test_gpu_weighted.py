@@ -129,7 +129,8 @@ def test_weighted_medium(gclib, device, mk, wmax):
 
 
 ENVS = [{"GC_WSLOTS": "1"}, {"GC_WSLOTS": "3"}, {"GC_WDELTA": "1"}, {"GC_WDELTA": "5000"},
-        {"GC_WDELTA_CLOSE": "1"}, {"GC_WDELTA_CLOSE": "4000"}, {"GC_VIS_BUDGET_MB": "1"}]
+        {"GC_WDELTA_CLOSE": "1"}, {"GC_WDELTA_CLOSE": "4000"}, {"GC_VIS_BUDGET_MB": "1"},
+        {"GC_WCLOSE_THREADS": "256"}, {"GC_WCLOSE_SLOTS": "1"}, {"GC_WCLOSE_SLOTS": "5", "GC_WSLOTS": "2"}]
 
 
 @pytest.mark.parametrize("env", ENVS, ids=lambda e: ",".join("%s=%s" % kv for kv in e.items()))
