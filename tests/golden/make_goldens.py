@@ -1,6 +1,6 @@
 """Writes the stored expected values of the large-workload GPU tests.
 
-    python tests/golden/make_goldens.py [batchba] [rmat20] [rmat16a]
+    python tests/golden/make_goldens.py [batchba] [rmat20] [rmat16a] [grid1024] [rmat16w] [grid256w]
 
 Only the CPU oracle (oracle/) and the seeded generators (graphgen/) are
 called; nothing here touches the GPU library.  Each record carries the sha256
@@ -16,6 +16,10 @@ same graph.
   rmat20_k100_tierB.json  R-MAT scale 20, k = 100: tier B as above
   rmat16_k50_tierA.json   R-MAT scale 16, k = 50: tier A
   grid1024_k100_tierB.json  the perturbed 1024 x 1024 grid, k = 100: tier B
+  rmat16w_k50_tierB.json    R-MAT scale 16 with edge lengths 1..255 (seed 21),
+                            k = 50: tier B on Dijkstra (weighted oracle)
+  grid256w_k50_tierB.json   the perturbed 256 x 256 grid with lengths 1..255
+                            (seed 21), k = 50: tier B on Dijkstra
 """
 from __future__ import annotations
 
@@ -104,7 +108,27 @@ def rmat16a():
     print("rmat16 tier A: %.1f s" % (time.time() - t0), flush=True)
 
 
+def _weighted(workload, k, fname):
+    g = graphgen.with_weights(graphgen.workload(workload), 255, 21)
+    t0 = time.time()
+    r = {"workload": workload + ", lengths 1..255 seed 21", "n": g.n, "nnz": g.nnz, "k": k,
+         "sha256": g.sha256(), "tier": "B", "block": 64, "growth": 2}
+    r.update(_tier_b(g, k))
+    r["oracle_s"] = round(time.time() - t0, 1)
+    _write(fname, r)
+    print("%s tier B: %.1f s" % (fname, time.time() - t0), flush=True)
+
+
+def rmat16w():
+    _weighted("rmat16", 50, "rmat16w_k50_tierB.json")
+
+
+def grid256w():
+    _weighted("grid256", 50, "grid256w_k50_tierB.json")
+
+
 if __name__ == "__main__":
-    todo = sys.argv[1:] or ["batchba", "rmat20", "rmat16a", "grid1024"]
+    todo = sys.argv[1:] or ["batchba", "rmat20", "rmat16a", "grid1024", "rmat16w", "grid256w"]
     for name in todo:
-        {"batchba": batchba, "rmat20": rmat20, "rmat16a": rmat16a, "grid1024": grid1024}[name]()
+        {"batchba": batchba, "rmat20": rmat20, "rmat16a": rmat16a, "grid1024": grid1024,
+         "rmat16w": rmat16w, "grid256w": grid256w}[name]()
