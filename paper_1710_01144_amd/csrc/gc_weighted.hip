@@ -136,7 +136,11 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
         int32_t theta = a.delta;
         uint32_t it = 1, ph = 1;
         int64_t set_sum = 0, set_cnt = 0;  // closeness: settled nodes (uniform)
-        __threadfence();  // the source's record is in the L2 before any atomic on it
+        // the source's record is written before any atomic on it; a slot is
+        // private to its workgroup within a launch, so a workgroup-scope fence
+        // is enough (a device-scope one would write back the L2 of the chip's
+        // dies on every search)
+        __threadfence_block();
         __syncthreads();
         for (;;) {
             // ---- rounds over the near list until nothing below theta changes
@@ -312,7 +316,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
             if (a.edges) a.edges[ci] = esum;
             if (a.visited) a.visited[ci] = nt;
         }
-        __threadfence();  // the zeroed records are in the L2 before the next search's atomics
+        __threadfence_block();  // the zeroed records are written before the next search's atomics
         __syncthreads();
     }
 }

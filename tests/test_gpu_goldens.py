@@ -83,3 +83,35 @@ def test_rmat16_k50_against_stored_tier_a(gclib):
         _note("rmat16 k=50 %s vs tier A" % order)
         grp, F, _ = G.greedy_group(50, order=order, block=64)
         assert grp.tolist() == gold["group"] and F.tolist() == gold["F"], order
+
+
+@pytest.mark.parametrize("name,workload,k", [("rmat16w_k50_tierB.json", "rmat16", 50),
+                                             ("grid256w_k50_tierB.json", "grid256", 50)])
+def test_weighted_against_stored_tier_b(gclib, name, workload, k):
+    """Weighted R-MAT scale 16 and 256 x 256 grid (lengths 1..255, seed 21),
+    k = 50: plain and CELF groups, F and (plain) the evaluations of every
+    round equal the stored tier-B run on Dijkstra."""
+    gold = _gold(name)
+    g = graphgen.with_weights(graphgen.workload(workload), 255, 21)
+    assert g.sha256() == gold["sha256"]
+    G = gclib.Graph.from_graphgen(g)
+    for order in ("plain", "celf"):
+        _note("%s weighted k=%d %s" % (workload, k, order))
+        grp, F, st = G.greedy_group(k, order=order, block=64)
+        assert grp.tolist() == gold["group"] and F.tolist() == gold["F"], order
+        if order == "plain":
+            assert st["evals_per_round"].tolist() == gold["evals"]
+
+
+def test_grid1024_k100_against_stored_tier_b(gclib):
+    """The perturbed 1024 x 1024 grid, k = 100 (a job of about 70 s): the
+    plain group, F and the evaluations of every round equal the stored
+    tier-B run."""
+    gold = _gold("grid1024_k100_tierB.json")
+    g = graphgen.workload("grid1024")
+    assert g.sha256() == gold["sha256"]
+    G = gclib.Graph.from_graphgen(g)
+    _note("grid1024 k=100 plain")
+    grp, F, st = G.greedy_group(100, order="plain", block=64)
+    assert grp.tolist() == gold["group"] and F.tolist() == gold["F"]
+    assert st["evals_per_round"].tolist() == gold["evals"]
