@@ -37,6 +37,15 @@
  *    everywhere stands for S = {} .
  *  - Node ids are int32 in [0, n); ties between equal gains or equal farness
  *    always go to the smallest node id.
+ *  - Watchdogs, read by gc_load_csr / gc_load_csr_weighted from the
+ *    environment (default: none): GC_LEVEL_CAP=L makes a call whose BFS needs
+ *    more than L levels fail with GC_EDEVICE; GC_ROUND_CAP=R abandons a
+ *    weighted search after R near-list rounds, and gc_closest_node,
+ *    gc_topk_closeness and gc_greedy_group then fail with GC_EDEVICE (the
+ *    asynchronous weighted calls cannot report it; their outputs are then
+ *    undefined).  Every kernel still ends normally; after GC_EDEVICE the
+ *    distance array and F of the call are undefined and the workspace must be
+ *    prepared again with gc_workspace_init.
  */
 #ifndef GC_H
 #define GC_H

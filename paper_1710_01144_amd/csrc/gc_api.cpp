@@ -120,6 +120,11 @@ struct gc_graph {
     // weighted graphs (gc_load_csr_weighted): the caller's uint8 lengths, the
     // largest one, the bucket widths of the gain and closeness searches
     // (GC_WDELTA, GC_WDELTA_CLOSE) and the number of search slots (GC_WSLOTS)
+    // watchdogs (GC_LEVEL_CAP, GC_ROUND_CAP; 0 = none): a BFS that needs more
+    // levels, or a weighted search more near-list rounds, fails the call
+    // with GC_EDEVICE instead of running on
+    int32_t level_cap = 0;
+    uint32_t wround_cap = 0;
     bool weighted = false;
     const uint8_t *d_w = nullptr;
     int32_t wmax = 0;
@@ -137,6 +142,14 @@ extern "C" int64_t gc_graph_nnz(const gc_graph *g) { return g ? g->nnz : -1; }
 
 // weighted graphs: every distance, at most 255 (n - 1), fits int32
 constexpr int32_t kWeightedMaxN = 1 << 23;
+
+// the level watchdog: GC_EDEVICE once a BFS has reached `levels` levels
+// beyond the cap (the call's device state is then undefined)
+static int level_cap_check(const gc_graph *g, int64_t levels) {
+    if (g->level_cap > 0 && levels > g->level_cap)
+        return fail(GC_EDEVICE, "a BFS passed the level cap (GC_LEVEL_CAP = %d)", g->level_cap);
+    return GC_OK;
+}
 
 // GC_EINVAL for a weighted graph in a call that only the unweighted engine has
 static int unweighted_only(const gc_graph *g, const char *what) {
@@ -445,6 +458,14 @@ static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const in
     if (const char *e = getenv("GC_LOG_ENTRIES")) {
         long long v = strtoll(e, nullptr, 10);
         if (v > 0) g->log_entries = v;
+    }
+    if (const char *e = getenv("GC_LEVEL_CAP")) {
+        const long v = strtol(e, nullptr, 10);
+        if (v >= 1) g->level_cap = (int32_t)std::min<long>(v, INT32_MAX);
+    }
+    if (const char *e = getenv("GC_ROUND_CAP")) {
+        const long long v = strtoll(e, nullptr, 10);
+        if (v >= 1) g->wround_cap = (uint32_t)std::min<long long>(v, UINT32_MAX);
     }
     g->touch_entries = 0;
     if (const char *e = getenv("GC_TOUCH_ENTRIES")) {
@@ -792,6 +813,7 @@ int wlaunch(const gc_graph *g, const WWs &w, int32_t mode, int32_t *dS, const in
     a.thr = thr;
     a.best = best;
     a.flags = w.flags();
+    a.max_rounds = g->wround_cap;
     if (wc) {
         if (wc->delta > 0) a.delta = wc->delta;
         a.d0 = wc->d0;
@@ -830,7 +852,10 @@ int run_wclosest(const gc_graph *g, const WWs &w, hipStream_t s, int32_t k,
     int32_t maxd0 = 0;
     HIP_OK(hipMemcpyAsync(&F0, w.best(), sizeof(F0), hipMemcpyDeviceToHost, s));
     HIP_OK(hipMemcpyAsync(&maxd0, w.maxd0(), sizeof(maxd0), hipMemcpyDeviceToHost, s));
+    int32_t flag0 = 0;
+    HIP_OK(hipMemcpyAsync(&flag0, w.flags(), sizeof(flag0), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    if (flag0 & 2) return fail(GC_EDEVICE, "a search passed the round cap (GC_ROUND_CAP = %u)", g->wround_cap);
     if (maxd0 == INT32_MAX) return fail(GC_EDISCONNECTED, "node %d does not reach every node", g->by_degree[0]);
     HIP_OK(launch_set_i64(w.out(), F0, s));
     WClose wc;
@@ -877,6 +902,7 @@ int run_wclosest(const gc_graph *g, const WWs &w, hipStream_t s, int32_t k,
         HIP_OK(hipMemcpyAsync(res, w.res(), sizeof(res), hipMemcpyDeviceToHost, s));
         HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
+        if (flag & 2) return fail(GC_EDEVICE, "a search passed the round cap (GC_ROUND_CAP = %u)", g->wround_cap);
         if (flag || res[1] < 0) return fail(GC_EDISCONNECTED, "a closeness search did not reach every node");
         top->emplace_back(res[0], (int32_t)res[1]);
         return GC_OK;
@@ -902,6 +928,7 @@ int run_wclosest(const gc_graph *g, const WWs &w, hipStream_t s, int32_t k,
     }
     HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    if (flag & 2) return fail(GC_EDEVICE, "a search passed the round cap (GC_ROUND_CAP = %u)", g->wround_cap);
     if (flag || (int32_t)top->size() < k) return fail(GC_EDISCONNECTED, "a closeness search did not reach every node");
     if (sources) *sources = n;
     return GC_OK;
@@ -1006,6 +1033,7 @@ int run_update(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int d
     HIP_OK(launch_bfs_init(a, dist_bytes, root, s));
     const int grid = bfs_grid(g);
     if (nlev >= 0) {
+        if (int rc = level_cap_check(g, nlev)) return rc;
         for (int32_t L = 0; L < nlev; ++L) HIP_OK(launch_bfs_level(a, dist_bytes, L, grid, s));
         HIP_OK(launch_bfs_finish(a, d_far, s));
         return GC_OK;
@@ -1019,6 +1047,7 @@ int run_update(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int d
         HIP_OK(hipMemcpyAsync(h, w.ctr(), sizeof(h), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         if (h[C_BFS_CNT0 + level % 3] == 0) break;
+        if (int rc = level_cap_check(g, level)) return rc;
         chunk = std::min(chunk * 2, 64);
     }
     HIP_OK(launch_bfs_finish(a, d_far, s));
@@ -1131,6 +1160,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
         nlev = std::max(maxd - 1, 0);
     }
     nlev = std::min(nlev, kMaxLevels - 1);
+    if (int rc = level_cap_check(g, nlev)) return rc;
     const bool mapped = io && io->hm_flag;
     const int grid = wide_grid(g);
     const bool timed = io && io->ev0 && io->gpu_ms;
@@ -1305,6 +1335,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
 int run_update_wide(const gc_graph *g, const Ws &w, int32_t root, void *d_dist, int dist_bytes,
                     int64_t *d_far, hipStream_t s, int32_t nlev, const Split *split = nullptr) {
     nlev = std::min(std::max(nlev, 0), kMaxLevels - 1);
+    if (int rc = level_cap_check(g, nlev)) return rc;
     WideArgs a = w.wide();
     a.unroll = g->unroll_small;  // one source: a small launch
     a.min_edges = g->min_edges;
@@ -1368,6 +1399,7 @@ int run_full_bfs(const gc_graph *g, const Ws &w, int32_t root, uint16_t *dist16,
                               hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         if ((rec.packed >> kCntShift) == 0 || L >= kMaxLevels - 1) break;
+        if (int rc = level_cap_check(g, L)) return rc;
     }
     HIP_OK(launch_wide_end(a, L, grid, s));
     int32_t maxd = 0;
@@ -1544,6 +1576,7 @@ int run_closest(const gc_graph *g, const Ws &w, hipStream_t s, int32_t *node, in
                 break;
             }
             if ((rec.packed >> kCntShift) == 0 || L >= kMaxLevels - 1) break;
+            if (int rc = level_cap_check(g, L)) return rc;
         }
         if (overflow) {
             // too many frontier entries: clear and redo this chunk with fewer sources
@@ -2057,6 +2090,7 @@ int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, 
     if (st.h_evals_per_round)
         for (int32_t i = 0; i < k; ++i) st.h_evals_per_round[i] = 0;
     st.dist_bytes = 4;
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
     int alloc_count = 0;
     PinnedBuf pin_cand, pin_out;
     pin_cand.counter = pin_out.counter = &alloc_count;
@@ -2067,7 +2101,12 @@ int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, 
     int32_t *hv = hc + n;
     int64_t *hg = reinterpret_cast<int64_t *>(pin_out.p);
     int64_t *he = hg + n;
-    int64_t *hsmall = he + n;  // gain and F of an update
+    int64_t *hsmall = he + n;  // gain and F of an update, then the flags word
+    int32_t *hflag = reinterpret_cast<int32_t *>(hsmall + 2);
+    auto watchdog = [&]() -> int {
+        return (*hflag & 2) ? fail(GC_EDEVICE, "a search passed the round cap (GC_ROUND_CAP = %u)", g->wround_cap)
+                            : GC_OK;
+    };
 
     // ---- s_1 and d(S,.) of S = {s_1}
     double t0 = now_ms();
@@ -2087,7 +2126,9 @@ int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, 
     rc = run_wupdate(g, w, s1, dS, w.far(), true, s);
     if (rc) return rc;
     HIP_OK(hipMemcpyAsync(hsmall + 1, w.far(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(hflag, w.flags(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    if (int r0 = watchdog()) return r0;
     int64_t F = hsmall[1];
     std::vector<int32_t> group;
     std::vector<int64_t> Fs;
@@ -2100,7 +2141,9 @@ int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, 
         rc = run_wupdate(g, w, v, dS, w.far(), false, s);
         if (rc) return rc;
         HIP_OK(hipMemcpyAsync(hsmall + 1, w.far(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(hflag, w.flags(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
+        if (int r0 = watchdog()) return r0;
         F = hsmall[1];
         group.push_back(v);
         Fs.push_back(F);
@@ -2117,7 +2160,9 @@ int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, 
         HIP_OK(hipMemcpyAsync(hg, w.out(), sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost, s));
         HIP_OK(hipMemcpyAsync(he, w.edges(), sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost, s));
         HIP_OK(hipMemcpyAsync(hv, w.vis(), sizeof(int32_t) * (size_t)cnt, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(hflag, w.flags(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
+        if (int r0 = watchdog()) return r0;
         if (g_timing) {
             float ms = 0.f;
             HIP_OK(hipEventElapsedTime(&ms, g_ev0, g_ev1));
@@ -2213,7 +2258,9 @@ int greedy_weighted(const gc_graph *g, int32_t k, const gc_opts &o, void *d_ws, 
         if (rc) return rc;
         HIP_OK(hipMemcpyAsync(hsmall, w.res(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIP_OK(hipMemcpyAsync(hsmall + 1, w.far(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(hflag, w.flags(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
+        if (int r0 = watchdog()) return r0;
         if (hsmall[0] != bgain || hsmall[1] != F - bgain)
             return fail(GC_EDEVICE, "update of node %d: gain %lld, expected %lld", bid, (long long)hsmall[0],
                         (long long)bgain);

@@ -58,7 +58,9 @@ struct WArgs {
     const int32_t *d0;      // W_CLOSE: distances from a landmark node, or nullptr
     const int64_t *t0;      // W_CLOSE: t0[M] = sum_w max(0, d0(w) - M), M < t0_len
     int32_t t0_len;         //          (t0[t0_len - 1] = 0), or nullptr
-    int32_t *flags;         // bit 0: a closeness search did not reach every node
+    int32_t *flags;         // bit 0: a closeness search did not reach every node;
+                            // bit 1: a search passed max_rounds (and was abandoned)
+    uint32_t max_rounds;    // watchdog: near-list rounds per search (0: no limit)
 };
 
 // count candidates over `slots` slots (at most `slots` workgroups of

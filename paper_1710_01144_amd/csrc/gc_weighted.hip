@@ -147,6 +147,16 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
             for (;;) {
                 const int32_t ncur = s_ncur;
                 if (ncur == 0) break;
+                if (a.max_rounds && it > a.max_rounds) {
+                    // watchdog: give the search up (it is counted as cut) and
+                    // let the host report it
+                    if (tid == 0) {
+                        s_cut = 1;
+                        atomicOr(a.flags, 2);
+                    }
+                    __syncthreads();
+                    break;
+                }
                 ++it;
                 __syncthreads();  // every thread has read s_ncur
                 if (tid == 0) s_nnext = 0;

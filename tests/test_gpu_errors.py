@@ -123,3 +123,48 @@ def test_workspace_too_small_and_allocation_failures(gclib, device, monkeypatch)
     monkeypatch.delenv("GC_TEST_FAIL_ALLOC")
     grp, F, _ = G.greedy_group(5)
     assert grp.tolist() == grp_ref.tolist() and F.tolist() == F_ref.tolist()
+
+
+def test_level_watchdog(gclib, device, monkeypatch):
+    """GC_LEVEL_CAP: a BFS that needs more levels fails the call with
+    GC_EDEVICE (the kernels already launched end normally); graphs whose
+    searches stay under the cap are not affected."""
+    monkeypatch.setenv("GC_LEVEL_CAP", "10")
+    P = gclib.Graph.from_graphgen(graphgen.path(300))
+    for call in (P.closest_node, lambda: P.greedy_group(3, prefix=[150])):
+        with pytest.raises(gclib.GCError) as ei:
+            call()
+        assert ei.value.code == gclib.GC_EDEVICE and "level cap" in str(ei.value)
+        P.alloc_workspace()  # a failed call leaves the workspace to be prepared again
+    far_t = torch.zeros(1, dtype=torch.int64, device=device)
+    dist = P.new_dist(2)
+    with pytest.raises(gclib.GCError) as ei:
+        P.update_dist(0, dist, 2, far_t)
+    assert ei.value.code == gclib.GC_EDEVICE
+    g = graphgen.ba(2000, 4, 1)
+    G = gclib.Graph.from_graphgen(g)
+    grp, F, _ = G.greedy_group(10)
+    monkeypatch.delenv("GC_LEVEL_CAP")
+    G2 = gclib.Graph.from_graphgen(g)
+    grp2, F2, _ = G2.greedy_group(10)
+    assert grp.tolist() == grp2.tolist() and F.tolist() == F2.tolist()
+    P2 = gclib.Graph.from_graphgen(graphgen.path(300))
+    assert P2.closest_node() == (149, 2 * sum(range(1, 150)) + 150)
+
+
+def test_round_watchdog_weighted(gclib, device, monkeypatch):
+    """GC_ROUND_CAP: a weighted search that needs more near-list rounds is
+    abandoned and the synchronising calls report GC_EDEVICE."""
+    g = graphgen.with_weights(graphgen.path(200), 9, 3)
+    monkeypatch.setenv("GC_ROUND_CAP", "3")
+    P = gclib.Graph.from_graphgen(g)
+    for call in (P.closest_node, lambda: P.topk_closeness(3), lambda: P.greedy_group(3)):
+        with pytest.raises(gclib.GCError) as ei:
+            call()
+        assert ei.value.code == gclib.GC_EDEVICE and "round cap" in str(ei.value)
+        P.alloc_workspace()
+    monkeypatch.setenv("GC_ROUND_CAP", "100000")
+    P2 = gclib.Graph.from_graphgen(g)
+    monkeypatch.delenv("GC_ROUND_CAP")
+    P3 = gclib.Graph.from_graphgen(g)
+    assert P2.greedy_group(4)[0].tolist() == P3.greedy_group(4)[0].tolist()
