@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-order comparison (training + four timed orders)")
     ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--only-weighted", action="store_true",
+                    help="run only the weighted-graph leg (one JSON object)")
+    ap.add_argument("--no-weighted", action="store_true",
+                    help="skip the weighted-graph leg (R-MAT scale 16 with edge lengths 1..255, k=50)")
     ap.add_argument("--no-early-exit", action="store_true",
                     help="skip the early-exit comparison (first-round searches stopped by their bound)")
     ap.add_argument("--workers", type=int, default=8,
@@ -215,6 +219,86 @@ def run_batched(args):
         "evals": evals, "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def weighted_leg(args):
+    """Weighted graphs: R-MAT scale 16 with edge lengths 1..255 (seed 21),
+    k = 50, plain and CELF (two jobs each); the first gain round's searches
+    event-timed against their algorithmic bytes (per settled node its row
+    pointers, 8 bytes, and per adjacency entry its column, length and
+    d(S,.), 9 bytes); and, unless --no-cpu-baseline, the oracle's pruned
+    Dijkstra over the same round's candidates, checked against the GPU's
+    gains."""
+    import torch
+    import graphgen
+    from paper_1710_01144_amd import gc
+    g = graphgen.with_weights(graphgen.workload("rmat16"), 255, 21)
+    G = gc.Graph.from_graphgen(g)
+    k = 50
+    dev = G.row_ptr.device
+    jobs = {}
+    grp = None
+    for order in ("plain", "celf"):
+        ms = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            grp_o, F_o, st = G.greedy_group(k, order=order)
+            torch.cuda.synchronize()
+            ms.append(1000 * (time.perf_counter() - t1))
+        if grp is None:
+            grp, F = grp_o, F_o
+        assert grp_o.tolist() == grp.tolist() and F_o.tolist() == F.tolist(), "orders disagree"
+        jobs[order] = {"ms": round(min(ms), 3), "evals_later": int(st["evals_later"]),
+                       "gain_launches": int(st["gain_launches"]),
+                       "breakdown_ms": {kk: round(float(st[kk]), 3) for kk in
+                                        ("ms_closest", "ms_round1", "ms_later", "ms_update")},
+                       "closest_sources": int(st["closest_sources"])}
+    # the first gain round alone: S = {s1}, every other node a candidate
+    s1 = int(grp[0])
+    dist = G.new_dist(4)
+    far = torch.zeros(1, dtype=torch.int64, device=dev)
+    G.update_dist(s1, dist, 4, far)
+    cand = torch.tensor([v for v in range(g.n) if v != s1], dtype=torch.int32, device=dev)
+    gc.timing_enable(True)
+    best = None
+    for _ in range(3):
+        gain, edges, vis = G.marginal_gains(dist, 4, cand, stats=True)
+        torch.cuda.synchronize()
+        ms = gc.timing_last_ms()
+        best = ms if best is None else min(best, ms)
+    gc.timing_enable(False)
+    E = int(edges.sum().item())
+    V = int(vis.sum().item())
+    alg = 8 * V + 9 * E
+    gbs = alg / (best / 1000.0) / 1e9
+    out = {"workload": "R-MAT scale 16, edge factor 16, largest component, edge lengths 1..255 (seed 21)",
+           "n": g.n, "nnz": g.nnz, "k": k, "F_last": int(F[-1]), "jobs": jobs,
+           "first_gain_round": {"candidates": int(cand.numel()), "ms": round(best, 4), "visited": V,
+                                "edges_alg": E, "gteps_alg": round(E / best / 1e6, 2),
+                                "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                                             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                                             "alg_bytes": alg, "traffic": None,
+                                             "kernel": "k_wsearch<256> (gain mode)"}},
+           "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        import oracle
+        dS = dist[: g.n].cpu().numpy()
+        cnp = cand.cpu().numpy()
+        reps, t_cpu = 0, 0.0
+        while t_cpu < min(args.cpu_seconds, 5.0) and reps < 50:
+            t1 = time.perf_counter()
+            gg, vv, ee = oracle.pruned_stats(g, dS, cnp)
+            t_cpu += time.perf_counter() - t1
+            reps += 1
+        assert gg.tolist() == gain.cpu().numpy().tolist(), "oracle gains disagree"
+        assert int(ee.sum()) == E and int(vv.sum()) == V, "oracle counts disagree"
+        out["cpu_baseline"] = {"value": round(E * reps / t_cpu / 1e9, 4), "unit": "GTEPS",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "the first gain round (every candidate's pruned Dijkstra, "
+                                         "%d run(s), %.3f s each)" % (reps, t_cpu / reps)}
+    log("weighted %s" % json.dumps(out))
+    return out
 
 
 def learned_comparison(G, g, k, args, grp, F):
@@ -390,6 +474,9 @@ def main():
     import torch
     import graphgen
     from paper_1710_01144_amd import gc
+    if args.only_weighted:
+        print(json.dumps({"weighted": weighted_leg(args)}), flush=True)
+        return
 
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
@@ -603,6 +690,11 @@ def main():
                    "topk_closeness_ms": round(topk_ms, 3)}
         log("overlap %s" % json.dumps(overlap))
 
+    # ---- weighted graphs (edge lengths; per-workgroup bucketed searches)
+    weighted = None
+    if not args.no_weighted:
+        weighted = weighted_leg(args)
+
     # ---- a plain copy of known size: measured bandwidth and counter scale
     copy_gbs = None
     if args.calib_bytes > 0:
@@ -680,6 +772,7 @@ def main():
                              "gteps_word": round(Ew / kern_ms / 1e6, 2)},
         "bitgreedy": bitg,
         "overlap": overlap,
+        "weighted": weighted,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
