@@ -451,6 +451,35 @@ int gc_greedy_many(int32_t count, const gc_graph *const *graphs, const int32_t *
                    const hipStream_t *streams, int32_t *h_group, int64_t *h_farness,
                    gc_stats *h_stats);
 
+/*
+ * gc_greedy_batch -- the jobs of gc_greedy_many (same arguments and the same
+ * picks, farness and evaluation counts) with their later rounds run in
+ * lockstep.  Phase 1, on the nworkers host threads as in gc_greedy_many:
+ * each job's first pick, its first gain round (every candidate) and its
+ * second pick.  Phase 2, on streams[0]: every job's later rounds at once --
+ * each step, every job still selecting takes its next batch of candidates
+ * by the lazy rule of Section 4.2 and one gain call over the disjoint union
+ * of all the graphs evaluates them all; the jobs whose round ended get their
+ * d(S,.) update in one call.  A batch of 64 sources holds one job's
+ * candidates and gets records for that job's nodes only.
+ *   d_union, union_bytes  device buffer of at least gc_batch_union_size bytes
+ *               (256-byte aligned; the union CSR, its d(S,.) and the engine's
+ *               scratch), prepared by the call itself
+ *   opts        NULL or plain/CELF order with block and block_growth (no
+ *               prefix, log, learned order, bit vectors or early exit)
+ *   graphs      unweighted (GC_EINVAL otherwise); the union must have fewer
+ *               than 2^31 nodes and adjacency entries (GC_ERANGE)
+ *   h_stats     per job: evaluations, E_alg, launches and its phase-1 times;
+ *               ms_later is the whole phase 2 and ms_total the whole call
+ * Synchronises every stream.  On error the lowest-numbered failed job's
+ * error (phase 1) or the call's error (phase 2) is returned.
+ */
+int gc_batch_union_size(int32_t count, const gc_graph *const *graphs, int32_t block, size_t *bytes);
+int gc_greedy_batch(int32_t count, const gc_graph *const *graphs, const int32_t *k, const gc_opts *opts,
+                    int32_t nworkers, void *const *d_ws, const size_t *ws_bytes, const hipStream_t *streams,
+                    void *d_union, size_t union_bytes, int32_t *h_group, int64_t *h_farness,
+                    gc_stats *h_stats);
+
 /* --------------------------------------------- candidate-ordering MLP --- */
 /*
  * Not part of the paper's method: a small network that predicts marginal

@@ -1978,6 +1978,22 @@ struct MaxTree {
     }
     // leftmost id >= lo with value >= x, or -1
     int32_t first_at_least(int32_t lo, int64_t x) const { return first(1, 0, leaves, lo, x); }
+    // the leftmost ids >= lo with value >= x, at most `want` of them, in one
+    // walk of the tree (subtrees left of lo or below x are skipped)
+    void collect(int32_t lo, int64_t x, int64_t want, std::vector<int32_t> &out) const {
+        if (want > 0) collect_at(1, 0, leaves, lo, x, want, out);
+    }
+    void collect_at(size_t node, int32_t nl, int32_t nr, int32_t lo, int64_t x, int64_t want,
+                    std::vector<int32_t> &out) const {
+        if (nr <= lo || t[node] < x || (int64_t)out.size() >= want) return;
+        if (nr - nl == 1) {
+            out.push_back(nl);
+            return;
+        }
+        const int32_t mid = nl + (nr - nl) / 2;
+        collect_at(2 * node, nl, mid, lo, x, want, out);
+        collect_at(2 * node + 1, mid, nr, lo, x, want, out);
+    }
     int32_t first(size_t node, int32_t nl, int32_t nr, int32_t lo, int64_t x) const {
         if (nr <= lo || t[node] < x) return -1;
         if (nr - nl == 1) return nl;
@@ -3146,6 +3162,716 @@ extern "C" int gc_greedy_many(int32_t count, const gc_graph *const *graphs, cons
     }
     for (int32_t i = 0; i < count; ++i)
         if (rc[(size_t)i] != GC_OK) return fail(rc[(size_t)i], "job %d: %s", i, msg[(size_t)i].c_str());
+    return GC_OK;
+}
+
+// ------------------------------------------------------------ batched jobs
+//
+// gc_greedy_batch: many independent jobs, their later rounds in lockstep.
+// Phase 1 runs each job's first pick, first gain round (every candidate, one
+// call) and second pick on the worker threads, as gc_greedy_many would, and
+// leaves the job's d(S,.) in one array over the disjoint union of all the
+// graphs and its first-round gains on the host.  Phase 2 then advances every
+// job through its later rounds at once: in each step every job still
+// selecting contributes its next batch of candidates (the same lazy rule and
+// batch schedule as gc_greedy_group, so picks and evaluation counts are the
+// same), and one gain call over the union evaluates all of them; the jobs
+// whose round ended get their d(S,.) update in one write-mode call.  A batch
+// holds sources of one job only and gets records for that job's nodes only
+// (WideArgs::bbase), so a step's records scale with the jobs' sizes, not
+// with the union's.
+
+namespace {
+
+struct BatchJob {
+    const gc_graph *g = nullptr;
+    int32_t k = 0;
+    int32_t nb = 0;   // first node of the job in the union
+    int64_t eb = 0;   // first adjacency entry of the job in the union
+    int32_t ecc = 0;  // eccentricity of the first pick
+    std::vector<int32_t> group;
+    std::vector<int64_t> F;
+    std::vector<int64_t> ub;     // stale gains (local ids); -1 for members of S
+    std::vector<uint8_t> inS;
+    std::vector<int64_t> evals;  // per round
+    gc_stats st{};
+    int rc = GC_OK;
+    std::string msg;
+    // phase 2
+    MaxTree tree;
+    ArgTree keys;
+    bool in_round = false;
+    int32_t pos = 0, bid = -1;
+    int64_t bgain = -1, cur = 0, nev = 0;
+    std::vector<int32_t> batch;  // local ids of the current step's batch
+};
+
+// union record budget: a step gives each job at most 16 blocks of candidates
+int64_t batch_union_kmax(int32_t block) { return 16LL * std::max(block, 1) / 64 + 2; }
+
+void batch_union_graph(const gc_graph *const *graphs, int32_t count, int32_t block, gc_graph *gu) {
+    int64_t N = 0, NNZ = 0;
+    int32_t md = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        N += graphs[i]->n;
+        NNZ += graphs[i]->nnz;
+        md = std::max(md, graphs[i]->max_deg);
+    }
+    const gc_graph *g0 = graphs[0];
+    gu->n = (int32_t)N;
+    gu->nnz = NNZ;
+    gu->max_deg = md;
+    gu->num_cu = g0->num_cu;
+    gu->level_wgs_per_cu = g0->level_wgs_per_cu;
+    gu->unroll = g0->unroll;
+    gu->min_edges = g0->min_edges;
+    gu->unroll_small = g0->unroll_small;
+    gu->min_edges_small = g0->min_edges_small;
+    gu->learned_pool_pct = g0->learned_pool_pct;
+    gu->balls = false;
+    gu->directed = false;
+    gu->level_cap = g0->level_cap;
+    const int64_t stride = (N + 31) & ~(int64_t)31;
+    gu->vis_budget = batch_union_kmax(block) * stride * 32;
+    gu->log_entries = std::min<int64_t>((int64_t)256 << 20, std::max<int64_t>((int64_t)8 << 20, 16LL * N));
+    gu->touch_entries = 0;
+}
+
+struct BatchUnionLayout {
+    WsLayout L;
+    size_t rp, ci, bbase, src, gout, total;
+    int64_t max_batches;
+};
+
+BatchUnionLayout batch_union_layout(const gc_graph *gu, int32_t count) {
+    BatchUnionLayout U;
+    U.L = ws_layout(gu);
+    size_t o = al256(U.L.total);
+    U.rp = o; o += al256(((size_t)gu->n + 1) * 4);
+    U.ci = o; o += al256((size_t)gu->nnz * 4 + 4);
+    // a step's batches: at most one partial batch per job beyond n / 64
+    U.max_batches = (int64_t)gu->n / 64 + 2LL * count + 64;
+    U.bbase = o; o += al256((size_t)U.max_batches * 8);
+    // sources of a launch (whole batches of 64, padded) and their gains and
+    // adjacency counts: up to 64 per batch, which may exceed the node count
+    U.src = o; o += al256((size_t)U.max_batches * 64 * 4);
+    U.gout = o; o += al256((size_t)U.max_batches * 64 * 16);
+    U.total = o;
+    return U;
+}
+
+// Phase 1 of one job on a worker: s1, d(s1,.), every first-round gain, s2 and
+// the update; d(S,.) goes to the union's uint16 array at the job's offset.
+int batch_phase1(BatchJob &J, void *d_ws, size_t ws_bytes, hipStream_t s, uint16_t *u_dist16) {
+    const gc_graph *g = J.g;
+    const int32_t n = g->n;
+    int rc = gc_workspace_init(g, d_ws, ws_bytes, s);
+    if (rc) return rc;
+    Ws w;
+    rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    const double t0 = now_ms();
+    int32_t s1 = -1, v0 = -1, ecc_v0 = 0;
+    int64_t F1 = 0;
+    rc = run_closest(g, w, s, &s1, &F1, &J.st.closest_sources, &ecc_v0, &v0);
+    if (rc) return rc;
+    J.st.ms_closest = now_ms() - t0;
+    const double t1 = now_ms();
+    int32_t ecc = 0;
+    if (s1 == v0) {
+        ecc = ecc_v0;  // the closeness search left d(v0,.) in dist16
+    } else {
+        rc = run_full_bfs(g, w, s1, w.dist16(), w.far(), s, &ecc);
+        if (rc) return rc;
+    }
+    if (ecc >= 65535) return fail(GC_ERANGE, "eccentricity of node %d exceeds 65534", s1);
+    HIP_OK(hipMemcpyAsync(&F1, w.far(), sizeof(F1), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    J.ecc = ecc;
+    J.group.assign(1, s1);
+    J.F.assign(1, F1);
+    J.inS.assign((size_t)n, 0);
+    J.inS[(size_t)s1] = 1;
+    J.ub.assign((size_t)n, std::numeric_limits<int64_t>::max());
+    J.ub[(size_t)s1] = -1;
+    J.evals.assign((size_t)J.k, 0);
+    J.st.ecc_s1 = ecc;
+    J.st.ms_update += now_ms() - t1;
+    if (J.k >= 2) {
+        const double t2 = now_ms();
+        void *d_dist = w.dist16();
+        int dist_bytes = 2;
+        if (ecc <= 254) {
+            HIP_OK(launch_u16_to_u8(w.dist16(), w.dist8(), n, s));
+            d_dist = w.dist8();
+            dist_bytes = 1;
+        }
+        Split split;
+        rc = build_split(g, w, d_dist, dist_bytes, s, &split);
+        if (rc) return rc;
+        // every other node, batched ball by ball as in gc_greedy_group's first round
+        std::vector<int32_t> cand;
+        cand.reserve((size_t)n);
+        const auto &ord = g->balls ? g->by_ball : g->by_degree;
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t u = g->balls ? ord[(size_t)i] : i;
+            if (u != s1) cand.push_back(u);
+        }
+        const int32_t cnt = (int32_t)cand.size();
+        std::vector<int64_t> hg((size_t)cnt), he((size_t)cnt);
+        if (cnt > 0) {
+            HIP_OK(hipMemcpyAsync(w.cand(), cand.data(), sizeof(int32_t) * (size_t)cnt, hipMemcpyHostToDevice, s));
+            rc = run_gains(g, w, d_dist, dist_bytes, w.cand(), cnt, w.gain(), w.aux(), nullptr, s,
+                           std::max(ecc - 1, 0), hg.data(), he.data(), nullptr, nullptr, &split);
+            if (rc) return rc;
+        }
+        int64_t bgain = -1;
+        int32_t bid = -1;
+        for (int32_t j = 0; j < cnt; ++j) {
+            const int32_t u = cand[(size_t)j];
+            J.ub[(size_t)u] = hg[(size_t)j];
+            J.st.edges_alg += he[(size_t)j];
+            if (hg[(size_t)j] > bgain || (hg[(size_t)j] == bgain && u < bid)) {
+                bgain = hg[(size_t)j];
+                bid = u;
+            }
+        }
+        J.st.evals_round1 = cnt;
+        J.evals[1] = cnt;
+        J.st.gain_launches += 1;
+        J.st.ms_round1 = now_ms() - t2;
+        if (bid < 0) return fail(GC_EDEVICE, "no candidate in the first gain round");
+        const double t3 = now_ms();
+        rc = run_update_wide(g, w, bid, d_dist, dist_bytes, w.far(), s, std::max(ecc - 1, 0), &split);
+        if (rc) return rc;
+        int64_t F2 = 0;
+        HIP_OK(hipMemcpyAsync(&F2, w.far(), sizeof(F2), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (F2 != F1 - bgain)
+            return fail(GC_EDEVICE, "update of node %d: F %lld, expected %lld", bid, (long long)F2,
+                        (long long)(F1 - bgain));
+        J.group.push_back(bid);
+        J.F.push_back(F2);
+        J.inS[(size_t)bid] = 1;
+        J.ub[(size_t)bid] = -1;
+        if (dist_bytes == 1) HIP_OK(launch_u8_to_u16(w.dist8(), u_dist16 + J.nb, n, s));
+        else HIP_OK(hipMemcpyAsync(u_dist16 + J.nb, w.dist16(), sizeof(uint16_t) * (size_t)n,
+                                   hipMemcpyDeviceToDevice, s));
+        J.st.ms_update += now_ms() - t3;
+    } else {
+        HIP_OK(hipMemcpyAsync(u_dist16 + J.nb, w.dist16(), sizeof(uint16_t) * (size_t)n, hipMemcpyDeviceToDevice,
+                              s));
+    }
+    // the worker's workspace is prepared again for its next job: wait for the copy
+    HIP_OK(hipStreamSynchronize(s));
+    return GC_OK;
+}
+
+// One gain (or, write = true, update) call over the union: `lists` holds, per
+// job taking part, its sources as union ids; gains (and edges) come back in
+// the same order.  Batches hold one job's sources each, padded with -1; a
+// launch takes batches while their records fit.
+struct UnionCall {
+    const gc_graph *gu;
+    const Ws *w;
+    const std::vector<BatchJob> *jobs;
+    int64_t *d_bbase;
+    int32_t *d_src;      // max_batches * 64 sources
+    int64_t *d_gain;     // max_batches * 64 gains, then as many adjacency counts
+    int64_t max_batches;
+    const void *d_dist;
+    int dist_bytes;
+    int32_t nlev;
+    const Split *split;
+    hipStream_t s;
+    PinnedBuf *pin_src, *pin_base;
+    std::vector<int64_t> hout;
+    int64_t launches = 0;
+};
+
+int union_call(UnionCall &c, const std::vector<std::pair<int32_t, std::vector<int32_t>>> &lists, bool write,
+               std::vector<int64_t> &gain, std::vector<int64_t> &edges) {
+    const Ws &w = *c.w;
+    const gc_graph *gu = c.gu;
+    const int64_t R_all = w.L.kmax * (int64_t)w.L.vis_stride;  // records of the union workspace
+    // flat layout: per list, its batches of 64 slots
+    struct Bt {
+        int32_t list, job;
+        int64_t first;  // index of the batch's first source in the list
+    };
+    std::vector<Bt> bts;
+    std::vector<int64_t> out_off(lists.size() + 1, 0);
+    for (size_t l = 0; l < lists.size(); ++l) {
+        const int64_t cnt = (int64_t)lists[l].second.size();
+        for (int64_t f = 0; f < cnt; f += 64) bts.push_back({(int32_t)l, lists[l].first, f});
+        out_off[l + 1] = out_off[l] + cnt;
+    }
+    gain.assign((size_t)out_off.back(), 0);
+    edges.assign((size_t)out_off.back(), 0);
+    if (bts.empty()) return GC_OK;
+    const int64_t slots_cap = std::min<int64_t>(c.max_batches * 64, (int64_t)(c.pin_src->bytes / 4));
+    int64_t R = R_all;
+    const int grid = wide_grid(gu);
+    size_t b0 = 0;
+    while (b0 < bts.size()) {
+        // the batches of this launch
+        size_t b1 = b0;
+        int64_t recs = 0;
+        while (b1 < bts.size()) {
+            const int64_t nj = (*c.jobs)[(size_t)bts[b1].job].g->n;
+            if (b1 > b0 && (recs + nj > R || (int64_t)(b1 - b0 + 1) * 64 > slots_cap ||
+                            (int64_t)(b1 - b0 + 1) > c.max_batches))
+                break;
+            recs += nj;
+            ++b1;
+        }
+        if (recs > R_all) return fail(GC_EWORKSPACE, "union workspace too small for one batch");
+        const int64_t nb = (int64_t)(b1 - b0);
+        int32_t *hs = reinterpret_cast<int32_t *>(c.pin_src->p);
+        int64_t *hb = reinterpret_cast<int64_t *>(c.pin_base->p);
+        int64_t rec_at = 0;
+        for (int64_t q = 0; q < nb; ++q) {
+            const Bt &bt = bts[b0 + (size_t)q];
+            const BatchJob &J = (*c.jobs)[(size_t)bt.job];
+            hb[q] = rec_at - J.nb;
+            rec_at += J.g->n;
+            const auto &L = lists[(size_t)bt.list].second;
+            for (int64_t j = 0; j < 64; ++j) {
+                const int64_t x = bt.first + j;
+                hs[q * 64 + j] = x < (int64_t)L.size() ? L[(size_t)x] : -1;
+            }
+        }
+        const int64_t nsrc = nb * 64;
+        HIP_OK(hipMemcpyAsync(c.d_src, hs, sizeof(int32_t) * (size_t)nsrc, hipMemcpyHostToDevice, c.s));
+        HIP_OK(hipMemcpyAsync(c.d_bbase, hb, sizeof(int64_t) * (size_t)nb, hipMemcpyHostToDevice, c.s));
+        WideArgs a = w.wide();
+        a.unroll = nsrc <= 1024 ? gu->unroll_small : gu->unroll;
+        a.min_edges = nsrc <= 1024 ? gu->min_edges_small : gu->min_edges;
+        a.rp = gu->d_rp;
+        a.ci = gu->d_ci;
+        a.n = gu->n;
+        a.dist = c.d_dist;
+        a.src = c.d_src;
+        a.nsrc = nsrc;
+        a.spb = 64;
+        a.gain = c.d_gain;
+        a.edges = c.d_gain + nsrc;
+        a.visited = nullptr;
+        a.tag = 1;
+        a.dist_bytes = c.dist_bytes;
+        a.words = w.words();
+        a.write = write;
+        a.far = nullptr;
+        a.bbase = c.d_bbase;
+        apply_split(a, c.split);
+        a.pack = gu->nnz < (1ll << kPackShift) &&
+                 (int64_t)gu->n * (int64_t)(c.nlev + 1) < (1ll << (62 - kPackShift));
+        HIP_OK(launch_wide_begin(a, c.dist_bytes, c.nlev, c.s));
+        HIP_OK(launch_wide_levels(a, c.dist_bytes, 0, c.nlev, grid, c.s));
+        HIP_OK(launch_wide_end(a, c.nlev, grid, c.s));
+        c.launches += 1;
+        int32_t flag = 0;
+        // results into ordinary (cached) host memory: the scatter below reads
+        // every value, and reads of pinned memory bypass the CPU caches
+        c.hout.resize(2 * (size_t)nsrc);
+        int64_t *ho = c.hout.data();
+        HIP_OK(hipMemcpyAsync(&flag, w.flags(), sizeof(flag), hipMemcpyDeviceToHost, c.s));
+        HIP_OK(hipMemcpyAsync(ho, c.d_gain, sizeof(int64_t) * 2 * (size_t)nsrc, hipMemcpyDeviceToHost, c.s));
+        HIP_OK(hipStreamSynchronize(c.s));
+        if (flag) {
+            // the frontier log overflowed: clear, and redo with fewer records per launch
+            if (write) return fail(GC_EWORKSPACE, "frontier log too small for the batched update");
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.wvis),
+                                   (size_t)w.L.kmax * w.L.vis_stride * 8, 0u, c.s));
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.lvl),
+                                   (size_t)(c.nlev + 2) * sizeof(WideLevel) / 4, 0u, c.s));
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.zcnt()), 2, 0u, c.s));
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, c.s));
+            if (nb == 1) return fail(GC_EWORKSPACE, "frontier log too small for one batch");
+            R = std::max<int64_t>(1, recs / 2);
+            continue;
+        }
+        for (int64_t q = 0; q < nb; ++q) {
+            const Bt &bt = bts[b0 + (size_t)q];
+            const int64_t cnt = (int64_t)lists[(size_t)bt.list].second.size();
+            for (int64_t j = 0; j < 64 && bt.first + j < cnt; ++j) {
+                const size_t o = (size_t)(out_off[(size_t)bt.list] + bt.first + j);
+                gain[o] = ho[q * 64 + j];
+                edges[o] = ho[nsrc + q * 64 + j];
+            }
+        }
+        b0 = b1;
+    }
+    return GC_OK;
+}
+
+}  // namespace
+
+extern "C" int gc_batch_union_size(int32_t count, const gc_graph *const *graphs, int32_t block, size_t *bytes) {
+    if (count < 1 || !graphs || !bytes) return fail(GC_EINVAL, "bad argument");
+    int64_t N = 0, NNZ = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!graphs[i]) return fail(GC_EINVAL, "graph %d is NULL", i);
+        if (graphs[i]->weighted) return fail(GC_EINVAL, "graph %d is weighted: batches take unweighted graphs", i);
+        N += graphs[i]->n;
+        NNZ += graphs[i]->nnz;
+    }
+    if (N >= INT32_MAX || NNZ >= INT32_MAX) return fail(GC_ERANGE, "the union of the graphs exceeds 2^31 nodes or entries");
+    gc_graph gu;
+    batch_union_graph(graphs, count, block > 0 ? block : kSrc, &gu);
+    *bytes = batch_union_layout(&gu, count).total;
+    return GC_OK;
+}
+
+extern "C" int gc_greedy_batch(int32_t count, const gc_graph *const *graphs, const int32_t *k,
+                               const gc_opts *opts, int32_t nworkers, void *const *d_ws,
+                               const size_t *ws_bytes, const hipStream_t *streams, void *d_union,
+                               size_t union_bytes, int32_t *h_group, int64_t *h_farness, gc_stats *h_stats) {
+    const double t_start = now_ms();
+    if (count < 0) return fail(GC_EINVAL, "count < 0");
+    if (count == 0) return GC_OK;
+    if (!graphs || !k || !d_ws || !ws_bytes || !streams || !h_group || !h_farness || !d_union)
+        return fail(GC_EINVAL, "NULL argument");
+    if (nworkers < 1 || nworkers > 64) return fail(GC_EINVAL, "nworkers = %d outside [1, 64]", nworkers);
+    gc_opts o{};
+    if (opts) o = *opts;
+    if (o.nprefix != 0 || o.log_capacity > 0 || o.d_bits || o.early_exit || o.d_mlp)
+        return fail(GC_EINVAL, "gc_greedy_batch: plain or CELF order, no prefix, log, bit vectors or early exit");
+    if (o.order != GC_ORDER_PLAIN && o.order != GC_ORDER_CELF)
+        return fail(GC_EINVAL, "gc_greedy_batch: plain or CELF order");
+    if (o.bitset_width != 0 && o.bitset_width != 64) return fail(GC_EINVAL, "bitset_width must be 64");
+    if (o.block < 0) return fail(GC_EINVAL, "block < 0");
+    if (o.block_growth < 0 || o.block_growth > 8) return fail(GC_EINVAL, "block_growth outside [0, 8]");
+    const int32_t block = o.block > 0 ? o.block : kSrc;
+    const int32_t growth = o.block_growth > 0 ? o.block_growth : 2;
+    for (int32_t w = 0; w < nworkers; ++w) {
+        if (!d_ws[w]) return fail(GC_EINVAL, "workspace %d is NULL", w);
+        if (nworkers > 1 && !streams[w]) return fail(GC_EINVAL, "worker %d on the null stream", w);
+    }
+    size_t need = 0;
+    int rc = gc_batch_union_size(count, graphs, block, &need);
+    if (rc) return rc;
+    if (((uintptr_t)d_union & 255) != 0) return fail(GC_EWORKSPACE, "union workspace must be 256-byte aligned");
+    if (union_bytes < need)
+        return fail(GC_EWORKSPACE, "union workspace has %zu bytes, needs %zu", union_bytes, need);
+    std::vector<BatchJob> jobs((size_t)count);
+    std::vector<int64_t> off((size_t)count + 1, 0);
+    int64_t nb = 0, eb = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        if (k[i] < 1 || k[i] > graphs[i]->n) return fail(GC_EINVAL, "job %d: k = %d outside [1, n]", i, k[i]);
+        jobs[(size_t)i].g = graphs[i];
+        jobs[(size_t)i].k = k[i];
+        jobs[(size_t)i].nb = (int32_t)nb;
+        jobs[(size_t)i].eb = eb;
+        nb += graphs[i]->n;
+        eb += graphs[i]->nnz;
+        off[(size_t)i + 1] = off[(size_t)i] + k[i];
+    }
+    // the union graph over the caller's buffer
+    gc_graph gu;
+    batch_union_graph(graphs, count, block, &gu);
+    const BatchUnionLayout U = batch_union_layout(&gu, count);
+    char *ub = reinterpret_cast<char *>(d_union);
+    int32_t *urp = reinterpret_cast<int32_t *>(ub + U.rp);
+    int32_t *uci = reinterpret_cast<int32_t *>(ub + U.ci);
+    gu.d_rp = urp;
+    gu.d_ci = uci;
+    Ws wu;
+    wu.L = U.L;
+    wu.base = ub;
+    wu.bytes = U.L.total;
+    const hipStream_t s0 = streams[0];
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(ub), U.L.total / 4, 0u, s0));
+    for (const BatchJob &J : jobs) {
+        HIP_OK(launch_copy_add_i32(J.g->d_rp, urp + J.nb, J.g->n, (int32_t)J.eb, s0));
+        if (J.g->nnz > 0) HIP_OK(launch_copy_add_i32(J.g->d_ci, uci + J.eb, J.g->nnz, J.nb, s0));
+    }
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(urp + gu.n), 1, (uint32_t)gu.nnz, s0));
+    HIP_OK(hipStreamSynchronize(s0));
+    uint16_t *u16 = wu.dist16();
+
+    // ---- phase 1 on the workers, largest graph first
+    const double t1 = now_ms();
+    std::vector<int32_t> order((size_t)count);
+    for (int32_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return graphs[a]->nnz + graphs[a]->n > graphs[b]->nnz + graphs[b]->n;
+    });
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::atomic<int32_t> next{0};
+    for (BatchJob &J : jobs) {
+        J.rc = GC_EDEVICE;
+        J.msg = "not run: no worker could select the device";
+    }
+    auto work = [&](int32_t wk) {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        for (;;) {
+            const int32_t t = next.fetch_add(1);
+            if (t >= count) break;
+            BatchJob &J = jobs[(size_t)order[(size_t)t]];
+            const int r = batch_phase1(J, d_ws[wk], ws_bytes[wk], streams[wk], u16);
+            J.rc = r;
+            if (r != GC_OK) J.msg = g_last_error;
+        }
+    };
+    if (nworkers == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        th.reserve((size_t)nworkers);
+        for (int32_t w = 0; w < nworkers; ++w) th.emplace_back(work, w);
+        for (auto &t : th) t.join();
+    }
+    for (int32_t i = 0; i < count; ++i)
+        if (jobs[(size_t)i].rc != GC_OK) return fail(jobs[(size_t)i].rc, "job %d: %s", i, jobs[(size_t)i].msg.c_str());
+    const double ms_phase1 = now_ms() - t1;
+
+    // ---- phase 2: every job's later rounds in lockstep, on streams[0]
+    const double t2 = now_ms();
+    int32_t maxecc = 0;
+    for (const BatchJob &J : jobs) maxecc = std::max(maxecc, J.ecc);
+    const void *udist = u16;
+    int dist_bytes = 2;
+    if (maxecc <= 254) {
+        HIP_OK(launch_u16_to_u8(u16, wu.dist8(), gu.n, s0));
+        udist = wu.dist8();
+        dist_bytes = 1;
+    }
+    const int32_t nlev = std::max(maxecc - 1, 0);
+    Split usplit;
+    rc = build_split(&gu, wu, udist, dist_bytes, s0, &usplit);
+    if (rc) return rc;
+    int alloc_count = 0;
+    PinnedBuf pin_src, pin_base;
+    pin_src.counter = pin_base.counter = &alloc_count;
+    const int64_t max_slots = U.max_batches * 64;
+    if (pin_src.ensure(sizeof(int32_t) * (size_t)max_slots) != hipSuccess ||
+        pin_base.ensure(sizeof(int64_t) * (size_t)U.max_batches) != hipSuccess)
+        return fail(GC_ENOMEM, "pinned host buffers");
+    UnionCall c;
+    c.gu = &gu;
+    c.w = &wu;
+    c.jobs = &jobs;
+    c.d_bbase = reinterpret_cast<int64_t *>(ub + U.bbase);
+    c.d_src = reinterpret_cast<int32_t *>(ub + U.src);
+    c.d_gain = reinterpret_cast<int64_t *>(ub + U.gout);
+    c.max_batches = U.max_batches;
+    c.d_dist = udist;
+    c.dist_bytes = dist_bytes;
+    c.nlev = nlev;
+    c.split = &usplit;
+    c.s = s0;
+    c.pin_src = &pin_src;
+    c.pin_base = &pin_base;
+    const bool celf = o.order == GC_ORDER_CELF;
+    for (BatchJob &J : jobs) {
+        if ((int32_t)J.group.size() >= J.k) continue;
+        if (celf) J.keys.build(J.ub, J.inS, -1);
+        else J.tree.build(J.ub, J.inS);
+    }
+    // The jobs' selection work (the lazy rule, the stale-gain trees) runs on
+    // `nt` host threads, each owning the jobs i = tid (mod nt); thread 0 also
+    // issues the shared gain and update calls.  Four barriers per step.
+    const int32_t nt = std::max<int32_t>(1, std::min<int32_t>(nworkers, count));
+    struct Barrier {
+        std::atomic<int32_t> arrived{0}, gen{0};
+        int32_t n = 1;
+        void wait() {
+            const int32_t g = gen.load(std::memory_order_acquire);
+            if (arrived.fetch_add(1, std::memory_order_acq_rel) == n - 1) {
+                arrived.store(0, std::memory_order_relaxed);
+                gen.fetch_add(1, std::memory_order_acq_rel);
+            } else {
+                while (gen.load(std::memory_order_acquire) == g) std::this_thread::yield();
+            }
+        }
+    } bar;
+    bar.n = nt;
+    std::vector<std::pair<int32_t, std::vector<int32_t>>> lists, picks;
+    std::vector<int64_t> gain, edges, pgain, pedges;
+    std::vector<int64_t> list_off((size_t)count, -1), pick_off((size_t)count, -1);
+    std::vector<int32_t> job_rc((size_t)count, GC_OK);
+    std::vector<std::string> job_msg((size_t)count);
+    std::atomic<bool> stop{false};
+    int call_rc = GC_OK;
+    std::string call_msg;
+    const bool verbose = getenv("GC_VERBOSE") != nullptr;
+    const double t_loop = now_ms();
+    double ms_gain_calls = 0, ms_update_calls = 0;
+    int64_t steps = 0, gain_calls = 0, update_calls = 0, sources = 0;
+    auto gather = [&](int32_t i) {
+        BatchJob &J = jobs[(size_t)i];
+        J.batch.clear();
+        if ((int32_t)J.group.size() >= J.k || job_rc[(size_t)i] != GC_OK) return;
+        const int32_t n = J.g->n;
+        if (!J.in_round) {
+            J.in_round = true;
+            J.pos = 0;
+            J.bid = -1;
+            J.bgain = -1;
+            J.nev = 0;
+            J.cur = std::min<int64_t>(block, std::min<int64_t>(16LL * block, n));
+        }
+        if (celf) {
+            while ((int64_t)J.batch.size() < J.cur) {
+                const int32_t v = J.keys.top();
+                if (v < 0) break;
+                const int64_t u = J.ub[(size_t)v];
+                // stop unless (u, -v) beats (bgain, -bid)
+                if (J.bid >= 0 && (u < J.bgain || (u == J.bgain && v >= J.bid))) break;
+                J.batch.push_back(v);
+                J.keys.set(v, -1);
+            }
+        } else {
+            J.tree.collect(J.pos, J.bid < 0 ? 0 : J.bgain + 1, J.cur, J.batch);
+            if (!J.batch.empty()) J.pos = J.batch.back() + 1;
+        }
+        if (J.batch.empty() && J.bid < 0) {
+            job_rc[(size_t)i] = GC_EDEVICE;
+            job_msg[(size_t)i] = "no candidate left";
+        }
+    };
+    auto distribute = [&](int32_t i) {
+        BatchJob &J = jobs[(size_t)i];
+        const int64_t o0 = list_off[(size_t)i];
+        if (o0 < 0) return;
+        for (size_t q = 0; q < J.batch.size(); ++q) {
+            const int32_t v = J.batch[q];
+            const int64_t gv = gain[(size_t)o0 + q];
+            if (gv > J.ub[(size_t)v] && job_rc[(size_t)i] == GC_OK) {
+                job_rc[(size_t)i] = GC_EDEVICE;
+                job_msg[(size_t)i] = "a gain grew between rounds (supermodularity)";
+            }
+            J.ub[(size_t)v] = gv;
+            if (celf) J.keys.set(v, gv);
+            else J.tree.set(v, gv);
+            J.st.edges_alg += edges[(size_t)o0 + q];
+            if (gv > J.bgain || (gv == J.bgain && v < J.bid)) {
+                J.bgain = gv;
+                J.bid = v;
+            }
+        }
+        J.nev += (int64_t)J.batch.size();
+        J.st.gain_launches += 1;
+        J.cur = std::min<int64_t>(J.cur * growth, std::min<int64_t>(16LL * block, J.g->n));
+    };
+    auto apply_pick = [&](int32_t i) {
+        BatchJob &J = jobs[(size_t)i];
+        const int64_t o0 = pick_off[(size_t)i];
+        if (o0 < 0) return;
+        if (pgain[(size_t)o0] != J.bgain && job_rc[(size_t)i] == GC_OK) {
+            job_rc[(size_t)i] = GC_EDEVICE;
+            job_msg[(size_t)i] = "the update's gain differs from the evaluated gain";
+        }
+        const int32_t r = (int32_t)J.group.size();
+        J.group.push_back(J.bid);
+        J.F.push_back(J.F.back() - J.bgain);
+        J.inS[(size_t)J.bid] = 1;
+        J.ub[(size_t)J.bid] = -1;
+        if (celf) J.keys.set(J.bid, -1);
+        else J.tree.set(J.bid, -1);
+        J.evals[(size_t)r] = J.nev;
+        J.st.evals_later += J.nev;
+        J.in_round = false;
+    };
+    auto phase2 = [&](int32_t tid) {
+        // (only thread 0 touches the device; the others work on host data)
+        for (;;) {
+            for (int32_t i = tid; i < count; i += nt) gather(i);
+            bar.wait();
+            if (tid == 0) {
+                ++steps;
+                lists.clear();
+                picks.clear();
+                std::fill(list_off.begin(), list_off.end(), -1);
+                std::fill(pick_off.begin(), pick_off.end(), -1);
+                int64_t lo = 0, po = 0;
+                for (int32_t i = 0; i < count; ++i) {
+                    BatchJob &J = jobs[(size_t)i];
+                    if ((int32_t)J.group.size() >= J.k || job_rc[(size_t)i] != GC_OK) continue;
+                    if (J.batch.empty()) {
+                        pick_off[(size_t)i] = po++;
+                        picks.push_back({i, std::vector<int32_t>{J.nb + J.bid}});
+                    } else {
+                        list_off[(size_t)i] = lo;
+                        lo += (int64_t)J.batch.size();
+                        std::vector<int32_t> ids(J.batch.size());
+                        for (size_t q = 0; q < ids.size(); ++q) ids[q] = J.nb + J.batch[q];
+                        lists.push_back({i, std::move(ids)});
+                    }
+                }
+                if (lists.empty() && picks.empty()) {
+                    stop = true;
+                } else if (!lists.empty()) {
+                    const double tc = now_ms();
+                    const int r = union_call(c, lists, false, gain, edges);
+                    ms_gain_calls += now_ms() - tc;
+                    ++gain_calls;
+                    sources += (int64_t)gain.size();
+                    if (r) {
+                        call_rc = r;
+                        call_msg = g_last_error;
+                        stop = true;
+                    }
+                }
+            }
+            bar.wait();
+            if (stop) break;
+            for (int32_t i = tid; i < count; i += nt) distribute(i);
+            bar.wait();
+            if (tid == 0 && !picks.empty()) {
+                const double tc = now_ms();
+                const int r = union_call(c, picks, true, pgain, pedges);
+                ms_update_calls += now_ms() - tc;
+                ++update_calls;
+                if (r) {
+                    call_rc = r;
+                    call_msg = g_last_error;
+                    stop = true;
+                }
+            }
+            bar.wait();
+            if (stop) break;
+            for (int32_t i = tid; i < count; i += nt) apply_pick(i);
+        }
+    };
+    {
+        std::vector<std::thread> th;
+        th.reserve((size_t)nt);
+        for (int32_t tid = 1; tid < nt; ++tid) th.emplace_back(phase2, tid);
+        phase2(0);
+        for (auto &t : th) t.join();
+    }
+    if (call_rc) return fail(call_rc, "%s", call_msg.c_str());
+    for (int32_t i = 0; i < count; ++i)
+        if (job_rc[(size_t)i] != GC_OK) return fail(job_rc[(size_t)i], "job %d: %s", i, job_msg[(size_t)i].c_str());
+    const double ms_phase2 = now_ms() - t2;
+    if (verbose) {
+        fprintf(stderr,
+                "[gc] batch: phase 1 %.1f ms; phase 2 %.1f ms (setup %.1f, %lld steps: %lld gain calls %.1f ms "
+                "over %lld sources, %lld update calls %.1f ms, %lld launches)\n",
+                ms_phase1, ms_phase2, t_loop - t2, (long long)steps, (long long)gain_calls, ms_gain_calls,
+                (long long)sources, (long long)update_calls, ms_update_calls, (long long)c.launches);
+        fflush(stderr);
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        BatchJob &J = jobs[(size_t)i];
+        for (int32_t q = 0; q < J.k; ++q) {
+            h_group[off[(size_t)i] + q] = J.group[(size_t)q];
+            h_farness[off[(size_t)i] + q] = J.F[(size_t)q];
+        }
+        if (h_stats) {
+            gc_stats st = J.st;
+            st.evals_total = st.evals_round1 + st.evals_later;
+            st.dist_bytes = dist_bytes;
+            st.ms_later = ms_phase2;           // shared by every job
+            st.ms_total = now_ms() - t_start;  // the whole batch
+            st.h_evals_per_round = nullptr;
+            (void)ms_phase1;
+            h_stats[i] = st;
+        }
+    }
     return GC_OK;
 }
 

@@ -71,6 +71,10 @@ struct WideArgs {
     int32_t *visited;              // out [nsrc] or null
     uint64_t *vis;                 // batch b, node y: 4 words at (b*vis_stride + y)*4, zero between launches
     size_t vis_stride;
+    // or, when set, at (bbase[b] + y)*4: a batch whose sources all lie in one
+    // component of a disjoint union gets records for that component's nodes
+    // only (bbase[b] = its first record minus the component's first node id)
+    const int64_t *bbase;
     int32_t *ly;                   // frontier log: node
     int32_t *lr;                   //               row start of the node
     int32_t *lb;                   //               batch
@@ -171,6 +175,10 @@ hipError_t launch_max_dist(const void *dist, int dist_bytes, int64_t n, int32_t 
 
 hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s);
 hipError_t launch_u16_to_u8(const uint16_t *in, uint8_t *out, int64_t n, hipStream_t s);
+// uint8 distances to uint16 (INF 255 -> 65535)
+hipError_t launch_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n, hipStream_t s);
+// out[i] = in[i] + add (building the disjoint union of several CSRs)
+hipError_t launch_copy_add_i32(const int32_t *in, int32_t *out, int64_t n, int32_t add, hipStream_t s);
 hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);
 
 }  // namespace gck

@@ -154,6 +154,20 @@ __global__ void k_set_i64(int64_t *p, int64_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+__global__ void k_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = in[i];
+        out[i] = (uint16_t)(v == 0xFFu ? 0xFFFFu : v);
+    }
+}
+
+__global__ void k_copy_add_i32(const int32_t *in, int32_t *out, int64_t n, int32_t add) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i] + add;
+}
+
 }  // namespace
 
 hipError_t launch_bfs_init(const BfsArgs &a, int dist_bytes, int32_t root, hipStream_t s) {
@@ -190,6 +204,21 @@ hipError_t launch_u16_to_u8(const uint16_t *in, uint8_t *out, int64_t n, hipStre
     int64_t g = (n + 255) / 256;
     int grid = (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
     hipLaunchKernelGGL(k_u16_to_u8, dim3(grid), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n, hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    int grid = (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+    hipLaunchKernelGGL(k_u8_to_u16, dim3(grid), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_add_i32(const int32_t *in, int32_t *out, int64_t n, int32_t add, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    int grid = (int)(g > 4096 ? 4096 : g);
+    hipLaunchKernelGGL(k_copy_add_i32, dim3(grid), dim3(256), 0, s, in, out, n, add);
     return hipGetLastError();
 }
 

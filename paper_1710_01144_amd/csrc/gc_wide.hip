@@ -59,8 +59,13 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
 __device__ __forceinline__ void set_flag(int32_t *flag, int32_t v) { atomicCAS(flag, 0, v); }
 
 // word k (0 = visited, 1..3 = frontier of level k-1 mod 3) of (batch b, node y)
+// first record of batch b, counted from node 0
+__device__ __forceinline__ int64_t batch_base(const WideArgs &a, int64_t b) {
+    return a.bbase ? a.bbase[b] : b * (int64_t)a.vis_stride;
+}
+
 __device__ __forceinline__ unsigned long long *rec(const WideArgs &a, int64_t b, int64_t y, int k) {
-    return reinterpret_cast<unsigned long long *>(a.vis) + ((size_t)b * a.vis_stride + (size_t)y) * 4 + k;
+    return reinterpret_cast<unsigned long long *>(a.vis) + (batch_base(a, b) + y) * 4 + k;
 }
 
 // The log is a ring of a.cap (a power of two) entries addressed by position
@@ -301,7 +306,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     __shared__ int32_t s_rs[kWin];
     __shared__ int32_t s_b[kWin];
     __shared__ uint64_t s_m[kWin];
-    __shared__ size_t s_rb[kWin];   // first record of the entry's batch
+    __shared__ int64_t s_rb[kWin];  // first record of the entry's batch (from node 0)
     __shared__ int16_t s_idx[kStep];  // window entry of each adjacency entry of a step
     __shared__ int32_t s_wmax[kWG / 64];
     __shared__ int64_t s_first;
@@ -402,7 +407,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
             s_off[tid] = off;
             s_rs[tid] = a.lr[q];
             s_b[tid] = b;
-            s_rb[tid] = (size_t)b * a.vis_stride;
+            s_rb[tid] = batch_base(a, b);
             // an entry starting at or past this workgroup's last adjacency
             // entry is never expanded here: skip its frontier word (a random
             // line per entry)
@@ -488,7 +493,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
                 if (own[r] >= 0 && nl < d[r]) {
                     bb[r] = s_b[own[r]];
                     unsigned long long *vw =
-                        reinterpret_cast<unsigned long long *>(a.vis) + (s_rb[own[r]] + (size_t)y[r]) * 4;
+                        reinterpret_cast<unsigned long long *>(a.vis) + (s_rb[own[r]] + (int64_t)y[r]) * 4;
                     // row data is needed only for a claim: load it with the visited word
                     int4 ri;
                     uint32_t d1 = 0;

@@ -40,7 +40,8 @@ EXPORTED = ["gc_load_csr", "gc_free_graph", "gc_graph_n", "gc_graph_nnz", "gc_wo
             "gc_mlp_forward", "gc_mlp_scratch_floats", "gc_mlp_backward", "gc_mlp_adam",
             "gc_node_features", "gc_timing_enable", "gc_timing_last_ms", "gc_greedy_many",
             "gc_topk_closeness", "gc_get_tuning", "gc_set_tuning", "gc_bits_size", "gc_bits_prepare",
-            "gc_bits_gains", "gc_marginal_gains_noalloc", "gc_load_csr_weighted"]
+            "gc_bits_gains", "gc_marginal_gains_noalloc", "gc_load_csr_weighted", "gc_batch_union_size",
+            "gc_greedy_batch"]
 TUNING_FIELDS = ("unroll", "unroll_small", "min_edges", "min_edges_small", "level_wgs_per_cu")
 MLP_PARAMS = 4801
 MLP_IN = 8
@@ -142,6 +143,13 @@ def load_library():
                                    i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t),
                                    ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(i64),
                                    ctypes.POINTER(GcStats)]
+    lib.gc_batch_union_size.restype = ctypes.c_int
+    lib.gc_batch_union_size.argtypes = [i32, ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.gc_greedy_batch.restype = ctypes.c_int
+    lib.gc_greedy_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(GcOpts),
+                                    i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(vp), vp, ctypes.c_size_t, ctypes.POINTER(i32),
+                                    ctypes.POINTER(i64), ctypes.POINTER(GcStats)]
     lib.gc_mlp_block_bytes.restype = ctypes.c_size_t
     lib.gc_mlp_block_bytes.argtypes = []
     lib.gc_mlp_pack.restype = ctypes.c_int
@@ -471,8 +479,11 @@ class Many:
         self.streams = [torch.cuda.Stream(device=dev) for _ in range(self.workers)]
 
     def run(self, ks, order: str = "plain", block: int = 0, block_growth: int = 0,
-            mlp_params=None):
-        """(groups, farness, stats): per job, in the order of `graphs`."""
+            mlp_params=None, lockstep: bool = False):
+        """(groups, farness, stats): per job, in the order of `graphs`.
+        lockstep=True: gc_greedy_batch (first rounds on the workers, every
+        later round of every job in shared calls over the union of the
+        graphs; plain or CELF order)."""
         lib = load_library()
         cnt = len(self.graphs)
         ks = [int(k) for k in ks]
@@ -495,9 +506,20 @@ class Many:
         stats = (GcStats * cnt)()
         # the jobs must see every earlier write of the caller's stream
         torch.cuda.current_stream().synchronize()
-        _check(lib.gc_greedy_many(cnt, handles, karr, ctypes.byref(opts), self.workers, ws, wsb, st,
-                                  group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                  far.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), stats))
+        if lockstep:
+            need = ctypes.c_size_t()
+            _check(lib.gc_batch_union_size(cnt, handles, int(block), ctypes.byref(need)))
+            if getattr(self, "union", None) is None or self.union.numel() < need.value:
+                self.union = None
+                self.union = torch.empty(need.value, dtype=torch.uint8, device=self.ws[0].device)
+            _check(lib.gc_greedy_batch(cnt, handles, karr, ctypes.byref(opts), self.workers, ws, wsb, st,
+                                       ctypes.c_void_p(self.union.data_ptr()), need.value,
+                                       group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       far.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), stats))
+        else:
+            _check(lib.gc_greedy_many(cnt, handles, karr, ctypes.byref(opts), self.workers, ws, wsb, st,
+                                      group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      far.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), stats))
         out_g, out_f, off = [], [], 0
         for k in ks:
             out_g.append(group[off:off + k])

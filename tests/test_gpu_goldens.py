@@ -56,6 +56,24 @@ def test_batched_ba_all_graphs(gclib):
         assert grps[i].tolist() == r["group"] and fars[i].tolist() == r["F"], i
 
 
+def test_batched_ba_lockstep(gclib):
+    """All 256 batched graphs through gc_greedy_batch (later rounds in
+    lockstep over the union of the graphs): every group, F and (plain) the
+    evaluations of each job equal the stored tier-B run."""
+    gold_b = _gold("batchba_tierB.json")
+    items = graphgen.batch_ba(3, 256)
+    Gs = [gclib.Graph.from_graphgen(g, workspace=False) for g, _ in items]
+    many = gclib.Many(Gs, workers=8)
+    ks = [k for _, k in items]
+    for order in ("plain", "celf"):
+        _note("batched BA: 256 jobs in lockstep, %s order" % order)
+        grps, fars, sts = many.run(ks, order=order, block=64, lockstep=True)
+        for i, r in enumerate(gold_b["graphs"]):
+            assert grps[i].tolist() == r["group"] and fars[i].tolist() == r["F"], (order, i)
+            if order == "plain":
+                assert int(sts[i]["evals_total"]) == int(np.sum(r["evals"])), i
+
+
 def test_rmat20_k100_against_stored_tier_b(gclib):
     """R-MAT scale 20, k = 100: plain and CELF groups, F and (plain) the
     evaluations of every round equal the stored tier-B run."""
