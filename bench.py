@@ -97,6 +97,8 @@ def parse():
                     help="skip the weighted-graph leg (R-MAT scale 16 with edge lengths 1..255, k=50)")
     ap.add_argument("--no-early-exit", action="store_true",
                     help="skip the early-exit comparison (first-round searches stopped by their bound)")
+    ap.add_argument("--no-lockstep", action="store_true",
+                    help="batched workload: gc_greedy_many only (no lockstep later rounds)")
     ap.add_argument("--workers", type=int, default=8,
                     help="batched workload: host threads (each with its own stream and workspace)")
     ap.add_argument("--reduce-profile", metavar="PREFIX",
@@ -156,9 +158,12 @@ def log(msg):
 
 def run_batched(args):
     """The batched BA workload: every graph with its own k through
-    gc_greedy_many -- `--workers` host threads, each with its own stream and
-    a workspace sized for the largest graph (initialised per graph inside the
-    timed region), largest graphs first."""
+    gc_greedy_batch -- each job's first pick and first gain round on
+    `--workers` host threads (own stream and workspace each, initialised per
+    graph inside the timed region, largest graphs first), then every job's
+    later rounds in lockstep, one gain call per step over the union of the
+    graphs.  gc_greedy_many (every job on the worker threads alone) is timed
+    beside it; --no-lockstep times only that."""
     import torch
     import graphgen
     from paper_1710_01144_amd import gc
@@ -174,20 +179,31 @@ def run_batched(args):
     log("%d workers, workspace %.1f MiB each" % (many.workers, many.ws_bytes / 2**20))
     ks = [k for _, k in items]
 
-    def one_pass():
-        grps, fars, sts = many.run(ks, order=args.order, block=args.block)
+    def one_pass(lockstep):
+        grps, fars, sts = many.run(ks, order=args.order, block=args.block, lockstep=lockstep)
         edges = sum(int(st["edges_alg"]) for st in sts)
         evals = sum(int(st["evals_total"]) for st in sts)
         return edges, evals, list(zip(grps, fars))
 
-    for _ in range(args.warmup):
-        one_pass()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        edges, evals, groups = one_pass()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
+    def timed(lockstep):
+        for _ in range(args.warmup):
+            one_pass(lockstep)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            edges, evals, groups = one_pass(lockstep)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t_start, edges, evals, groups
+
+    lockstep = not args.no_lockstep
+    threads_ms = None
+    if lockstep:
+        wall_t, _, _, groups_t = timed(False)
+        threads_ms = round(1000 * wall_t / args.steps, 3)
+        log("gc_greedy_many (worker threads only): %.2f ms per pass" % threads_ms)
+    wall, edges, evals, groups = timed(lockstep)
+    if lockstep:
+        assert [g.tolist() for g, _ in groups] == [g.tolist() for g, _ in groups_t], "engines disagree"
     ms = 1000 * wall / args.steps
     log("batch pass %.2f ms, %d evaluations, edges_alg %d" % (ms, evals, edges))
     cpu = None
@@ -215,7 +231,9 @@ def run_batched(args):
         "config": {"workload": "%s, %s lazy order" % (desc, args.order), "graphs": len(items),
                    "n_total": sum(g.n for g, _ in items), "nnz_total": sum(g.nnz for g, _ in items),
                    "k_total": sum(k for _, k in items), "order": args.order, "block": args.block,
-                   "workers": many.workers},
+                   "workers": many.workers,
+                   "engine": "gc_greedy_batch (later rounds in lockstep)" if lockstep else "gc_greedy_many"},
+        "threads_only_ms": threads_ms,
         "evals": evals, "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
