@@ -1008,6 +1008,53 @@ extern "C" int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes,
 
 namespace {
 
+// Byte range [lo, hi) of a worker's workspace known to hold zeros between the
+// jobs of gc_greedy_many / gc_greedy_batch: the wide engine's records of the
+// last job (every call of the engine returns the records it touched to zero;
+// an overflow clears them all).
+struct ZeroRange {
+    size_t lo = 0, hi = 0;
+};
+
+hipError_t fill_zero(char *base, size_t lo, size_t hi, hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    return launch_fill_u32(reinterpret_cast<uint32_t *>(base + lo), (hi - lo) / 4, 0u, s);
+}
+
+// gc_workspace_init for the next job on a worker's workspace: zero everything
+// but the frontier log and clean-up list (written before they are read) and
+// the part of the record range already known to be zero.  `z` is cleared here
+// and set to this job's record range by the caller once the job has ended
+// without error.
+int ws_init_reuse(const gc_graph *g, void *d_ws, size_t ws_bytes, hipStream_t s, ZeroRange &z) {
+    const ZeroRange known = z;
+    z = ZeroRange{};
+    if (g->weighted) return gc_workspace_init(g, d_ws, ws_bytes, s);
+    Ws w;
+    int rc = get_ws(g, d_ws, ws_bytes, &w);
+    if (rc) return rc;
+    const size_t rlo = w.L.wvis, rhi = w.L.ly;  // records (all of [wvis, ly))
+    HIP_OK(fill_zero(w.base, 0, rlo, s));
+    if (known.hi <= rlo || known.lo >= rhi) {
+        HIP_OK(fill_zero(w.base, rlo, rhi, s));
+    } else {
+        HIP_OK(fill_zero(w.base, rlo, known.lo, s));
+        HIP_OK(fill_zero(w.base, known.hi, rhi, s));
+    }
+    HIP_OK(fill_zero(w.base, w.L.lvl, w.L.total, s));
+    return write_graph_tables(g, w, s);
+}
+
+// the record range ws_init_reuse may take as zero after a job on g ended
+ZeroRange ws_record_range(const gc_graph *g) {
+    ZeroRange r;
+    if (g->weighted) return r;
+    const WsLayout L = ws_layout(g);
+    r.lo = L.wvis;
+    r.hi = L.ly;
+    return r;
+}
+
 int bfs_grid(const gc_graph *g) {
     return std::max(1, std::min(4 * g->num_cu, (g->n + 3) / 4 + 1));
 }
@@ -3138,16 +3185,18 @@ extern "C" int gc_greedy_many(int32_t count, const gc_graph *const *graphs, cons
     std::vector<std::string> msg((size_t)count, std::string("not run: no worker could select the device"));
     auto work = [&](int32_t w) {
         if (hipSetDevice(dev) != hipSuccess) return;
+        ZeroRange zero;  // nothing is known of the workspace before its first job
         for (;;) {
             const int32_t t = next.fetch_add(1);
             if (t >= count) break;
             const int32_t i = order[(size_t)t];
             if (h_stats) h_stats[i].h_evals_per_round = nullptr;
-            int r = gc_workspace_init(graphs[i], d_ws[w], ws_bytes[w], streams[w]);
+            int r = ws_init_reuse(graphs[i], d_ws[w], ws_bytes[w], streams[w], zero);
             if (r == GC_OK)
                 r = gc_greedy_group(graphs[i], k[i], opts, d_ws[w], ws_bytes[w], streams[w],
                                     h_group + off[(size_t)i], h_farness + off[(size_t)i],
                                     h_stats ? &h_stats[i] : nullptr);
+            if (r == GC_OK) zero = ws_record_range(graphs[i]);
             rc[(size_t)i] = r;
             if (r != GC_OK) msg[(size_t)i] = g_last_error;
         }
@@ -3262,10 +3311,10 @@ BatchUnionLayout batch_union_layout(const gc_graph *gu, int32_t count) {
 
 // Phase 1 of one job on a worker: s1, d(s1,.), every first-round gain, s2 and
 // the update; d(S,.) goes to the union's uint16 array at the job's offset.
-int batch_phase1(BatchJob &J, void *d_ws, size_t ws_bytes, hipStream_t s, uint16_t *u_dist16) {
+int batch_phase1(BatchJob &J, void *d_ws, size_t ws_bytes, hipStream_t s, uint16_t *u_dist16, ZeroRange &zero) {
     const gc_graph *g = J.g;
     const int32_t n = g->n;
-    int rc = gc_workspace_init(g, d_ws, ws_bytes, s);
+    int rc = ws_init_reuse(g, d_ws, ws_bytes, s, zero);
     if (rc) return rc;
     Ws w;
     rc = get_ws(g, d_ws, ws_bytes, &w);
@@ -3606,11 +3655,13 @@ extern "C" int gc_greedy_batch(int32_t count, const gc_graph *const *graphs, con
     }
     auto work = [&](int32_t wk) {
         if (hipSetDevice(dev) != hipSuccess) return;
+        ZeroRange zero;
         for (;;) {
             const int32_t t = next.fetch_add(1);
             if (t >= count) break;
             BatchJob &J = jobs[(size_t)order[(size_t)t]];
-            const int r = batch_phase1(J, d_ws[wk], ws_bytes[wk], streams[wk], u16);
+            const int r = batch_phase1(J, d_ws[wk], ws_bytes[wk], streams[wk], u16, zero);
+            if (r == GC_OK) zero = ws_record_range(J.g);
             J.rc = r;
             if (r != GC_OK) J.msg = g_last_error;
         }

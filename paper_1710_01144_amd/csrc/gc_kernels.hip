@@ -136,10 +136,19 @@ __global__ void k_bfs_finish(BfsArgs a, int64_t *far) {
     }
 }
 
+// 16-byte stores over the 16-byte aligned body, single words before and after
 __global__ void k_fill_u32(uint32_t *p, size_t count, uint32_t v) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
-         i += (size_t)gridDim.x * blockDim.x)
-        p[i] = v;
+    const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t nt = (size_t)gridDim.x * blockDim.x;
+    size_t head = ((16 - ((uintptr_t)p & 15)) & 15) / 4;
+    if (head > count) head = count;
+    const size_t nv = (count - head) / 4;
+    uint4 *q = reinterpret_cast<uint4 *>(p + head);
+    const uint4 vv = make_uint4(v, v, v, v);
+    for (size_t i = t0; i < nv; i += nt) q[i] = vv;
+    const size_t tail = head + nv * 4;
+    if (t0 < head) p[t0] = v;
+    if (t0 < count - tail) p[tail + t0] = v;
 }
 
 __global__ void k_u16_to_u8(const uint16_t *in, uint8_t *out, int64_t n) {
@@ -159,6 +168,42 @@ __global__ void k_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n) {
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t v = in[i];
         out[i] = (uint16_t)(v == 0xFFu ? 0xFFFFu : v);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_seg_sum_max_u16(const uint16_t *d, const int32_t *nb, const int32_t *n,
+                                                          int64_t *sum, int32_t *mx) {
+    __shared__ int64_t s_s[4];
+    __shared__ int32_t s_m[4];
+    const int32_t j = blockIdx.x;
+    const int64_t b0 = nb[j], cnt = n[j];
+    int64_t acc = 0;
+    int32_t m = 0;
+    for (int64_t i = threadIdx.x; i < cnt; i += 256) {
+        const int32_t v = d[b0 + i];
+        acc += v;
+        m = v > m ? v : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        acc += __shfl_down(acc, o, 64);
+        const int32_t t = __shfl_down(m, o, 64);
+        m = t > m ? t : m;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_s[threadIdx.x >> 6] = acc;
+        s_m[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        int32_t tm = 0;
+        for (int w = 0; w < 4; ++w) {
+            t += s_s[w];
+            tm = s_m[w] > tm ? s_m[w] : tm;
+        }
+        sum[j] = t;
+        mx[j] = tm;
     }
 }
 
@@ -194,8 +239,8 @@ hipError_t launch_bfs_finish(const BfsArgs &a, int64_t *d_far, hipStream_t s) {
 
 hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    size_t g = (count + 255) / 256;
-    int grid = (int)(g > 4096 ? 4096 : g);
+    size_t g = (count / 4 + 255) / 256;
+    int grid = (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
     hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, count, v);
     return hipGetLastError();
 }
@@ -211,6 +256,13 @@ hipError_t launch_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n, hipStre
     int64_t g = (n + 255) / 256;
     int grid = (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
     hipLaunchKernelGGL(k_u8_to_u16, dim3(grid), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_sum_max_u16(const uint16_t *d, const int32_t *nb, const int32_t *n, int32_t count,
+                                  int64_t *sum, int32_t *mx, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_sum_max_u16, dim3(count), dim3(256), 0, s, d, nb, n, sum, mx);
     return hipGetLastError();
 }
 
