@@ -3311,7 +3311,8 @@ BatchUnionLayout batch_union_layout(const gc_graph *gu, int32_t count) {
 
 // Phase 1 of one job on a worker: s1, d(s1,.), every first-round gain, s2 and
 // the update; d(S,.) goes to the union's uint16 array at the job's offset.
-int batch_phase1(BatchJob &J, void *d_ws, size_t ws_bytes, hipStream_t s, uint16_t *u_dist16, ZeroRange &zero) {
+int batch_phase1(BatchJob &J, void *d_ws, size_t ws_bytes, hipStream_t s, uint16_t *u_dist16, ZeroRange &zero,
+                 bool celf) {
     const gc_graph *g = J.g;
     const int32_t n = g->n;
     int rc = ws_init_reuse(g, d_ws, ws_bytes, s, zero);
@@ -3410,6 +3411,11 @@ int batch_phase1(BatchJob &J, void *d_ws, size_t ws_bytes, hipStream_t s, uint16
     } else {
         HIP_OK(hipMemcpyAsync(u_dist16 + J.nb, w.dist16(), sizeof(uint16_t) * (size_t)n, hipMemcpyDeviceToDevice,
                               s));
+    }
+    // the stale-gain tree of the later rounds, built while the copy runs
+    if ((int32_t)J.group.size() < J.k) {
+        if (celf) J.keys.build(J.ub, J.inS, -1);
+        else J.tree.build(J.ub, J.inS);
     }
     // the worker's workspace is prepared again for its next job: wait for the copy
     HIP_OK(hipStreamSynchronize(s));
@@ -3660,7 +3666,8 @@ extern "C" int gc_greedy_batch(int32_t count, const gc_graph *const *graphs, con
             const int32_t t = next.fetch_add(1);
             if (t >= count) break;
             BatchJob &J = jobs[(size_t)order[(size_t)t]];
-            const int r = batch_phase1(J, d_ws[wk], ws_bytes[wk], streams[wk], u16, zero);
+            const int r = batch_phase1(J, d_ws[wk], ws_bytes[wk], streams[wk], u16, zero,
+                                       o.order == GC_ORDER_CELF);
             if (r == GC_OK) zero = ws_record_range(J.g);
             J.rc = r;
             if (r != GC_OK) J.msg = g_last_error;
@@ -3716,11 +3723,6 @@ extern "C" int gc_greedy_batch(int32_t count, const gc_graph *const *graphs, con
     c.pin_src = &pin_src;
     c.pin_base = &pin_base;
     const bool celf = o.order == GC_ORDER_CELF;
-    for (BatchJob &J : jobs) {
-        if ((int32_t)J.group.size() >= J.k) continue;
-        if (celf) J.keys.build(J.ub, J.inS, -1);
-        else J.tree.build(J.ub, J.inS);
-    }
     // The jobs' selection work (the lazy rule, the stale-gain trees) runs on
     // `nt` host threads, each owning the jobs i = tid (mod nt); thread 0 also
     // issues the shared gain and update calls.  Four barriers per step.

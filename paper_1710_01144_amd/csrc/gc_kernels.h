@@ -75,12 +75,6 @@ struct WideArgs {
     // component of a disjoint union gets records for that component's nodes
     // only (bbase[b] = its first record minus the component's first node id)
     const int64_t *bbase;
-    // and, for the closeness search over such a union, per batch: the node
-    // count of its component, the index of its best farness in `best` of
-    // k_wide_cut, and whether its graph is directed (null: a.n, best[0], a.directed)
-    const int32_t *bn;
-    const int32_t *bjob;
-    const int32_t *bdir;
     int32_t *ly;                   // frontier log: node
     int32_t *lr;                   //               row start of the node
     int32_t *lb;                   //               batch
@@ -183,10 +177,6 @@ hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t s)
 hipError_t launch_u16_to_u8(const uint16_t *in, uint8_t *out, int64_t n, hipStream_t s);
 // uint8 distances to uint16 (INF 255 -> 65535)
 hipError_t launch_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n, hipStream_t s);
-// per job j of a disjoint union: sum[j] and max[j] of the uint16 distances of
-// its nodes [nb[j], nb[j] + n[j]) (one workgroup per job)
-hipError_t launch_seg_sum_max_u16(const uint16_t *d, const int32_t *nb, const int32_t *n, int32_t count,
-                                  int64_t *sum, int32_t *mx, hipStream_t s);
 // out[i] = in[i] + add (building the disjoint union of several CSRs)
 hipError_t launch_copy_add_i32(const int32_t *in, int32_t *out, int64_t n, int32_t add, hipStream_t s);
 hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);

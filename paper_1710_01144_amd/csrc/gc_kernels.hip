@@ -171,42 +171,6 @@ __global__ void k_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_seg_sum_max_u16(const uint16_t *d, const int32_t *nb, const int32_t *n,
-                                                          int64_t *sum, int32_t *mx) {
-    __shared__ int64_t s_s[4];
-    __shared__ int32_t s_m[4];
-    const int32_t j = blockIdx.x;
-    const int64_t b0 = nb[j], cnt = n[j];
-    int64_t acc = 0;
-    int32_t m = 0;
-    for (int64_t i = threadIdx.x; i < cnt; i += 256) {
-        const int32_t v = d[b0 + i];
-        acc += v;
-        m = v > m ? v : m;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        acc += __shfl_down(acc, o, 64);
-        const int32_t t = __shfl_down(m, o, 64);
-        m = t > m ? t : m;
-    }
-    if ((threadIdx.x & 63) == 0) {
-        s_s[threadIdx.x >> 6] = acc;
-        s_m[threadIdx.x >> 6] = m;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        int32_t tm = 0;
-        for (int w = 0; w < 4; ++w) {
-            t += s_s[w];
-            tm = s_m[w] > tm ? s_m[w] : tm;
-        }
-        sum[j] = t;
-        mx[j] = tm;
-    }
-}
-
 __global__ void k_copy_add_i32(const int32_t *in, int32_t *out, int64_t n, int32_t add) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -256,13 +220,6 @@ hipError_t launch_u8_to_u16(const uint8_t *in, uint16_t *out, int64_t n, hipStre
     int64_t g = (n + 255) / 256;
     int grid = (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
     hipLaunchKernelGGL(k_u8_to_u16, dim3(grid), dim3(256), 0, s, in, out, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_seg_sum_max_u16(const uint16_t *d, const int32_t *nb, const int32_t *n, int32_t count,
-                                  int64_t *sum, int32_t *mx, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_sum_max_u16, dim3(count), dim3(256), 0, s, d, nb, n, sum, mx);
     return hipGetLastError();
 }
 

@@ -681,11 +681,7 @@ __global__ void k_wide_cut(WideArgs a, int32_t L, int64_t *best, int32_t fixed) 
     a.prev[2 * t] = r;
     a.prev[2 * t + 1] = e;
     const int64_t sum = r * 65535 - a.gain[t];
-    // the batch's component (a disjoint union of graphs) or the whole graph
-    const int64_t nn = a.bn ? (int64_t)a.bn[b] : (int64_t)a.n;
-    if (a.bjob) best += a.bjob[b];
-    const int32_t directed = a.bdir ? a.bdir[b] : a.directed;
-    if (r == nn) {
+    if (r == a.n) {
         a.far_out[t] = sum;
         if (!fixed) atomicMin(reinterpret_cast<unsigned long long *>(best), (unsigned long long)sum);
         atomicAnd(&a.active[b], ~bit);
@@ -695,9 +691,9 @@ __global__ void k_wide_cut(WideArgs a, int32_t L, int64_t *best, int32_t fixed) 
         atomicAnd(&a.active[b], ~bit);
         return;
     }
-    const int64_t rem = nn - r;
+    const int64_t rem = (int64_t)a.n - r;
     // (undirected: one of each new node's adjacency entries leads back)
-    const int64_t ef = directed ? de : de - dr;
+    const int64_t ef = a.directed ? de : de - dr;
     const int64_t near = ef < rem ? ef : rem;
     const int64_t lb = sum + (int64_t)(L + 2) * near + (int64_t)(L + 3) * (rem - near);
     const int64_t bv = (int64_t)__hip_atomic_load(reinterpret_cast<unsigned long long *>(best),
