@@ -500,7 +500,7 @@ static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const in
         g->wslots = (int32_t)slots;
         if (const char *e = getenv("GC_WCLOSE_THREADS")) g->wclose_threads = strtol(e, nullptr, 10) == 256 ? 256 : 1024;
         // the closeness searches are full SSSPs: fewer, wider workgroups keep
-        // their records (16 bytes per node each) closer to the caches
+        // per-node state (20 bytes per node each) closer to the caches
         g->wclose_slots = 256;
         if (const char *e = getenv("GC_WCLOSE_SLOTS")) {
             const long long v = strtoll(e, nullptr, 10);
@@ -717,7 +717,7 @@ int get_ws(const gc_graph *g, void *d_ws, size_t ws_bytes, Ws *w) {
 // result, sum, one node id, F(S); then d(S,.) (int32), per-candidate outputs,
 // the candidate list, and the slots (records, then work lists)
 struct WLayout {
-    size_t ctr, dist, out, edges, vis, cand, d0, t0, hist, rec, lists, total;
+    size_t ctr, dist, out, edges, vis, cand, d0, t0, hist, enc, rec, lists, total;
     int64_t t0_cap;  // entries of the closeness bound's tail table
 };
 
@@ -737,6 +737,7 @@ WLayout wlayout(const gc_graph *g) {
     L.d0 = o; o += al256(n * 4);
     L.t0 = o; o += al256((size_t)L.t0_cap * 8);
     L.hist = o; o += al256((size_t)L.t0_cap * 4);
+    L.enc = o; o += al256(slots * n * 4);
     L.rec = o; o += al256(slots * n * sizeof(WRec));
     L.lists = o; o += al256(slots * n * kWLists * 4);
     L.total = o;
@@ -762,6 +763,7 @@ struct WWs {
     int64_t *t0() const { return reinterpret_cast<int64_t *>(base + L.t0); }
     uint32_t *hist() const { return reinterpret_cast<uint32_t *>(base + L.hist); }
     int32_t *maxd0() const { return reinterpret_cast<int32_t *>(base + L.ctr + 56); }
+    uint32_t *enc() const { return reinterpret_cast<uint32_t *>(base + L.enc); }
     WRec *rec() const { return reinterpret_cast<WRec *>(base + L.rec); }
     int32_t *lists() const { return reinterpret_cast<int32_t *>(base + L.lists); }
 };
@@ -807,6 +809,7 @@ int wlaunch(const gc_graph *g, const WWs &w, int32_t mode, int32_t *dS, const in
     a.out = out;
     a.edges = edges;
     a.visited = vis;
+    a.enc = w.enc();
     a.rec = w.rec();
     a.lists = w.lists();
     a.delta = mode == W_CLOSE ? g->wdelta_close : g->wdelta_gain;

@@ -14,22 +14,24 @@
 
 namespace gck {
 
-// Per-node state of one slot (16 bytes, zero = untouched).
-//   enc    0x7FFFFFFF - tentative distance (atomicMax lowers the distance)
+// Per-node state of one slot (zero = untouched), in two arrays: the word
+// every relaxation reads, 4 bytes per node,
+//   enc    0x7FFFFFFF - tentative distance (atomicMax lowers the distance),
+// and the bookkeeping of the nodes whose distance dropped, 16 bytes:
 //   mark   stamp of the last near-list iteration the node was queued for
 //   far    1 once the node has been put on the far list
 //   phase  stamp of the phase in which the node was settled (closeness mode)
 struct WRec {
-    uint32_t enc;
     uint32_t mark;
     uint32_t far;
     uint32_t phase;
+    uint32_t pad;
 };
 // Work lists of one slot: near (current, next), far (current, next), the
 // touched list (every node whose record the search changed, once) and the
 // nodes settled in the current phase; each n entries.
 constexpr int kWLists = 6;
-constexpr size_t kWSlotBytesPerNode = sizeof(WRec) + kWLists * sizeof(int32_t);  // 40
+constexpr size_t kWSlotBytesPerNode = 4 + sizeof(WRec) + kWLists * sizeof(int32_t);  // 44
 
 enum WMode : int32_t {
     W_GAIN = 0,   // g(u,S) = sum over settled y of d(S,y) - d(u,y), search pruned by d(S,.)
@@ -50,6 +52,7 @@ struct WArgs {
     int64_t *out;           // W_GAIN / W_WRITE: gain; W_CLOSE: F({u}) or -1 when cut
     int64_t *edges;         // optional: sum of degrees over the settled nodes
     int32_t *visited;       // optional: settled nodes
+    uint32_t *enc;          // slots x n distance words
     WRec *rec;              // slots x n records
     int32_t *lists;         // slots x kWLists x n entries
     int32_t delta;          // bucket width

@@ -101,6 +101,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
     const int32_t n = a.n;
     const bool close = a.mode == W_CLOSE;
     WRec *rec = a.rec + (size_t)blockIdx.x * (size_t)n;
+    uint32_t *enc = a.enc + (size_t)blockIdx.x * (size_t)n;
     int32_t *lists = a.lists + (size_t)blockIdx.x * kWLists * (size_t)n;
     int32_t *const touch = lists + 4 * (size_t)n;
     int32_t *const setl = lists + 5 * (size_t)n;
@@ -123,7 +124,8 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
         }
         int32_t *cur = lists, *nxt = lists + n, *far = lists + 2 * (size_t)n, *far2 = lists + 3 * (size_t)n;
         if (tid == 0) {
-            rec[u] = WRec{kEncZero, 1u, 0u, 0u};
+            enc[u] = kEncZero;
+            rec[u] = WRec{1u, 0u, 0u, 0u};
             cur[0] = u;
             touch[0] = u;
             s_ncur = 1;
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
                     int32_t x = 0, deg = 0, dx = 0, row = 0;
                     if (i < ncur) {
                         x = cur[i];
-                        dx = dist_of(ld_acq(&rec[x].enc));
+                        dx = dist_of(ld_acq(&enc[x]));
                         row = a.rp[x];
                         deg = a.rp[x + 1] - row;
                         if (close && atomicExch(&rec[x].phase, ph) != ph) {
@@ -193,10 +195,10 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
                         const int32_t y = a.ci[idx];
                         const int32_t nd = s_d[lo] + (int32_t)a.w[idx];
                         if (!close && nd >= a.dS[y]) continue;  // S is at least as close
-                        const uint32_t enc = kEncZero - (uint32_t)nd;
-                        if (ld_acq(&rec[y].enc) >= enc) continue;
-                        const uint32_t old = atomicMax(&rec[y].enc, enc);
-                        if (old >= enc) continue;
+                        const uint32_t e_new = kEncZero - (uint32_t)nd;
+                        if (ld_acq(&enc[y]) >= e_new) continue;
+                        const uint32_t old = atomicMax(&enc[y], e_new);
+                        if (old >= e_new) continue;
                         if (old == 0u) {
                             const int32_t t = atomicAdd(&s_ntouch, 1);
                             touch[t] = y;
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
             if (close) {
                 const int32_t ns = s_nset;
                 int64_t part = 0;
-                for (int32_t i = tid; i < ns; i += BS) part += dist_of(ld_acq(&rec[setl[i]].enc));
+                for (int32_t i = tid; i < ns; i += BS) part += dist_of(ld_acq(&enc[setl[i]]));
                 set_sum += block_sum64<BS>(part, s_red);
                 set_cnt += ns;
                 if (tid == 0) {
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
             __syncthreads();
             for (int32_t i = tid; i < nf; i += BS) {
                 const int32_t y = far[i];
-                const int32_t d = dist_of(ld_acq(&rec[y].enc));
+                const int32_t d = dist_of(ld_acq(&enc[y]));
                 if (d < th_old) continue;  // settled in an earlier phase
                 if (d < theta) {
                     const int32_t q = atomicAdd(&s_ncur, 1);
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
                 __syncthreads();
                 for (int32_t i = tid; i < nf2; i += BS) {
                     const int32_t y = far2[i];
-                    const int32_t d = dist_of(ld_acq(&rec[y].enc));
+                    const int32_t d = dist_of(ld_acq(&enc[y]));
                     if (d < theta) {
                         const int32_t q = atomicAdd(&s_ncur, 1);
                         cur[q] = y;
@@ -304,12 +306,13 @@ __global__ __launch_bounds__(BS) void k_wsearch(WArgs a) {
         int64_t gsum = 0, esum = 0;
         for (int32_t i = tid; i < nt; i += BS) {
             const int32_t y = touch[i];
-            const int32_t d = dist_of(ld_acq(&rec[y].enc));
+            const int32_t d = dist_of(ld_acq(&enc[y]));
             if (!close) {
                 gsum += (int64_t)a.dS[y] - d;
                 if (a.mode == W_WRITE) a.dS[y] = d;
             }
             esum += a.rp[y + 1] - a.rp[y];
+            enc[y] = 0u;
             rec[y] = WRec{0u, 0u, 0u, 0u};
         }
         gsum = block_sum64<BS>(gsum, s_red);
