@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-order comparison (training + four timed orders)")
     ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--learned-warmup", type=int, default=1,
+                    help="untimed runs of each order before its timed ones (learned comparison)")
+    ap.add_argument("--no-wide-pool", action="store_true",
+                    help="skip the learned order with a pool of 16 blocks (long workloads)")
     ap.add_argument("--only-weighted", action="store_true",
                     help="run only the weighted-graph leg (one JSON object)")
     ap.add_argument("--no-weighted", action="store_true",
@@ -343,7 +347,8 @@ def learned_comparison(G, g, k, args, grp, F):
     for name, kw in [("plain", {"order": "plain"}), ("celf", {"order": "celf"}),
                      ("learned", {"order": "learned", "mlp_params": net.block}),
                      ("untrained", {"order": "learned", "mlp_params": untrained.block})]:
-        G.greedy_group(k, block=args.block, **kw)
+        for _ in range(args.learned_warmup):
+            G.greedy_group(k, block=args.block, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.learned_reps):
@@ -351,11 +356,14 @@ def learned_comparison(G, g, k, args, grp, F):
         torch.cuda.synchronize()
         ms = 1000 * (time.perf_counter() - t1) / args.learned_reps
         assert gv.tolist() == grp.tolist() and Fv.tolist() == F.tolist(), name
+        log("learned comparison: %s %.1f ms, %d later evaluations" % (name, ms, int(sv["evals_later"])))
         out[name] = {"ms": round(ms, 3), "evals_round1": int(sv["evals_round1"]),
                      "evals_later": int(sv["evals_later"]), "ms_mlp": round(float(sv["ms_mlp"]), 3),
                      "ms_later": round(float(sv["ms_later"]), 3), "ms_first": round(
                          float(sv["ms_closest"]) + float(sv["ms_round1"]), 3),
                      "gain_launches": int(sv["gain_launches"]), "mlp_launches": int(sv["mlp_launches"])}
+    if args.no_wide_pool:
+        return out
     # the network ranking a wide pool (16 blocks of the largest bounds): its
     # ranking then decides which candidates go first
     os.environ["GC_LEARNED_POOL_PCT"] = "1600"
