@@ -99,6 +99,9 @@ struct gc_graph {
     // of 64 nearby nodes (GC_BALLS=0: the degree order and ascending ids)
     std::vector<int32_t> by_ball;
     std::vector<int32_t> ball_rank;  // position of every node in by_ball
+    // the row split's chunks of the rows of more than kSplitLongRow entries:
+    // pairs {row, index of the row's first pair}, one per kSplitChunk entries
+    std::vector<int32_t> split_chunks;
     int32_t max_deg;
     int32_t num_cu;
     // tuning read once at load time so the workspace layout never changes
@@ -413,6 +416,15 @@ static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const in
     std::stable_sort(g->by_degree.begin(), g->by_degree.end(), [&](int32_t x, int32_t y) {
         return (rp[x + 1] - rp[x]) > (rp[y + 1] - rp[y]);
     });
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t d = rp[v + 1] - rp[v];
+        if (d <= kSplitLongRow) continue;
+        const int32_t first = (int32_t)(g->split_chunks.size() / 2);
+        for (int32_t c = 0; c < (d + kSplitChunk - 1) / kSplitChunk; ++c) {
+            g->split_chunks.push_back(v);
+            g->split_chunks.push_back(first);
+        }
+    }
     if (g->balls) {
         try {
             ball_order(n, rp, ci, g->by_degree, g->by_ball, g->ball_rank);
@@ -570,6 +582,8 @@ struct WsLayout {
     size_t vis_stride;  // words per batch
     int64_t cap;        // frontier log entries (a ring: a power of two)
     int64_t zcap;       // clean-up list entries
+    size_t lchunk = 0, lcnt = 0;  // long rows' chunk list and part sizes of the row split
+    int64_t nchunk = 0;           // chunks the layout has room for (0: none)
 };
 
 constexpr int32_t kMaxLevels = 65536;  // 16-bit distances: at most 65534 levels
@@ -634,6 +648,10 @@ WsLayout ws_layout(const gc_graph *g) {
     L.two = o; o += al256(n * 8);
     // early exit: a histogram of d(S,.) and the bound's tail table T
     L.tails = o; o += al256((size_t)2 * (kMaxLevels + 2) * 8);
+    // the row split's chunks of long rows (see launch_row_split)
+    L.nchunk = (int64_t)g->split_chunks.size() / 2;
+    L.lchunk = o; o += al256((size_t)L.nchunk * 8);
+    L.lcnt = o; o += al256((size_t)L.nchunk * 8);
     L.total = o;
     return L;
 }
@@ -1121,7 +1139,18 @@ int build_split(const gc_graph *g, const Ws &w, const void *d_dist, int dist_byt
     int32_t *ci = reinterpret_cast<int32_t *>(w.base + w.L.cisplit);
     int4 *ri = reinterpret_cast<int4 *>(w.base + w.L.rinfo);
     void *d1 = w.base + w.L.dist1;
-    HIP_OK(launch_row_split(g->d_rp, g->d_ci, g->n, d_dist, dist_bytes, ci, ri, d1, s));
+    // long rows by chunks when the layout holds their list (uploaded here, so
+    // that any workspace of the graph works)
+    int32_t *chunks = nullptr, *cnt = nullptr;
+    int32_t nch = 0;
+    if (w.L.nchunk > 0 && (int64_t)g->split_chunks.size() == 2 * w.L.nchunk) {
+        chunks = reinterpret_cast<int32_t *>(w.base + w.L.lchunk);
+        cnt = reinterpret_cast<int32_t *>(w.base + w.L.lcnt);
+        nch = (int32_t)w.L.nchunk;
+        HIP_OK(hipMemcpyAsync(chunks, g->split_chunks.data(), sizeof(int32_t) * g->split_chunks.size(),
+                              hipMemcpyHostToDevice, s));
+    }
+    HIP_OK(launch_row_split(g->d_rp, g->d_ci, g->n, d_dist, dist_bytes, ci, ri, d1, chunks, nch, cnt, s));
     out->ci = ci;
     out->rinfo = ri;
     out->dist1 = d1;

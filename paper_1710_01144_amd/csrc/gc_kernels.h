@@ -142,10 +142,17 @@ struct WideArgs {
 };
 constexpr int kPackShift = 30;
 // Split every row of (rp, ci) by the distances dist (see WideArgs::rinfo);
-// dist1 receives a copy of dist.
+// dist1 receives a copy of dist.  Rows of more than kSplitLongRow entries
+// may be listed in `chunks` (nchunks pairs {row, index of the row's first
+// pair}, one pair per kSplitChunk entries of the row, rows ascending): a
+// workgroup then splits each chunk, with `cnt` (2 * nchunks ints) holding the
+// chunks' part sizes between its two passes; without a list (chunks null)
+// one wave splits each row, however long.
+constexpr int32_t kSplitLongRow = 1024;
+constexpr int32_t kSplitChunk = 2048;
 hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, const void *dist,
                             int dist_bytes, int32_t *ci_out, int4 *rinfo, void *dist1,
-                            hipStream_t s);
+                            const int32_t *chunks, int32_t nchunks, int32_t *cnt, hipStream_t s);
 // After level L: BFScut test for every live source of a closeness launch
 // (distances from an all-INF 16-bit array, so F = reached*65535 - gain).
 hipError_t launch_wide_cut(const WideArgs &a, int32_t L, int64_t *best, bool fixed, hipStream_t s);

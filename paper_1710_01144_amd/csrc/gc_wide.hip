@@ -788,11 +788,12 @@ __global__ __launch_bounds__(256) void k_twohop_i64(const int32_t *rp, const int
 template <typename DistT>
 __global__ __launch_bounds__(256) void k_row_split(const int32_t *rp, const int32_t *ci, int32_t n,
                                                     const DistT *dist, int32_t *ci_out, int4 *rinfo,
-                                                    DistT *dist1) {
+                                                    DistT *dist1, int32_t skip_long) {
     const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int lane = lane_id();
     if (row >= n) return;
     const int32_t rs = rp[row], re = rp[row + 1];
+    if (skip_long && re - rs > kSplitLongRow) return;  // split chunk by chunk (below)
     const uint32_t dy = dist[row];
     if (re - rs <= 64) {
         // one chunk: classify and place in one pass
@@ -847,6 +848,110 @@ __global__ __launch_bounds__(256) void k_row_split(const int32_t *rp, const int3
     if (lane == 0) {
         rinfo[row] = make_int4(rs, re - rs, nd, nd + ns);
         dist1[row] = (DistT)dy;
+    }
+}
+
+// The rows of more than kSplitLongRow entries, a workgroup per chunk of
+// kSplitChunk entries (a hub's row is split by many workgroups, not by one
+// wave).  Pass 1 counts each chunk's entries of the first two parts.
+template <typename DistT>
+__global__ __launch_bounds__(256) void k_row_split_count(const int32_t *rp, const int32_t *ci, const DistT *dist,
+                                                         const int32_t *chunks, int32_t *cnt) {
+    __shared__ int32_t s_d[4], s_s[4];
+    const int32_t i = blockIdx.x;
+    const int32_t row = chunks[2 * i], first = chunks[2 * i + 1];
+    const int32_t end = rp[row + 1];
+    const int32_t rs = rp[row] + (i - first) * kSplitChunk;
+    const int32_t re = end - rs < kSplitChunk ? end : rs + kSplitChunk;
+    const uint32_t dy = dist[row];
+    int32_t nd = 0, ns = 0;
+    for (int32_t e = rs + (int32_t)threadIdx.x; e < re; e += 256) {
+        const uint32_t dz = dist[ci[e]];
+        nd += dz > dy ? 1 : 0;
+        ns += dz == dy ? 1 : 0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        nd += __shfl_down(nd, o, 64);
+        ns += __shfl_down(ns, o, 64);
+    }
+    if (lane_id() == 0) {
+        s_d[threadIdx.x >> 6] = nd;
+        s_s[threadIdx.x >> 6] = ns;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cnt[2 * i] = s_d[0] + s_d[1] + s_d[2] + s_d[3];
+        cnt[2 * i + 1] = s_s[0] + s_s[1] + s_s[2] + s_s[3];
+    }
+}
+
+// Pass 2: each chunk places its entries after the earlier chunks' entries of
+// each part, in order; the row's first chunk writes the row's record.
+template <typename DistT>
+__global__ __launch_bounds__(256) void k_row_split_place(const int32_t *rp, const int32_t *ci, const DistT *dist,
+                                                         const int32_t *chunks, const int32_t *cnt,
+                                                         int32_t *ci_out, int4 *rinfo, DistT *dist1) {
+    __shared__ int32_t s_pos[3];
+    __shared__ int32_t s_w[3][4];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int32_t i = blockIdx.x;
+    const int32_t row = chunks[2 * i], first = chunks[2 * i + 1];
+    const int32_t k = i - first;
+    const int32_t RS = rp[row], RE = rp[row + 1];
+    const uint32_t dy = dist[row];
+    if (tid == 0) {
+        const int32_t nch = (RE - RS + kSplitChunk - 1) / kSplitChunk;
+        int32_t ND = 0, NS = 0, pd = 0, ps = 0;
+        for (int32_t j = 0; j < nch; ++j) {
+            const int32_t d = cnt[2 * (first + j)], sm = cnt[2 * (first + j) + 1];
+            if (j < k) {
+                pd += d;
+                ps += sm;
+            }
+            ND += d;
+            NS += sm;
+        }
+        s_pos[0] = RS + pd;
+        s_pos[1] = RS + ND + ps;
+        s_pos[2] = RS + ND + NS + (k * kSplitChunk - pd - ps);
+        if (k == 0) {
+            rinfo[row] = make_int4(RS, RE - RS, ND, ND + NS);
+            dist1[row] = (DistT)dy;
+        }
+    }
+    __syncthreads();
+    const int32_t rs = RS + k * kSplitChunk;
+    const int32_t re = RE - rs < kSplitChunk ? RE : rs + kSplitChunk;
+    for (int32_t base = rs; base < re; base += 256) {
+        const int32_t e = base + tid;
+        const bool ok = e < re;
+        int32_t z = 0;
+        uint32_t dz = dy;
+        if (ok) {
+            z = ci[e];
+            dz = dist[z];
+        }
+        const bool down = ok && dz > dy, same = ok && dz == dy, up = ok && dz < dy;
+        const uint64_t bd = __ballot(down), bs = __ballot(same), bu = __ballot(up);
+        if (lane == 0) {
+            s_w[0][wave] = __popcll(bd);
+            s_w[1][wave] = __popcll(bs);
+            s_w[2][wave] = __popcll(bu);
+        }
+        __syncthreads();
+        int32_t od = s_pos[0], os = s_pos[1], ou = s_pos[2];
+        for (int w = 0; w < wave; ++w) {
+            od += s_w[0][w];
+            os += s_w[1][w];
+            ou += s_w[2][w];
+        }
+        if (down) ci_out[od + bits_below(bd)] = z;
+        if (same) ci_out[os + bits_below(bs)] = z;
+        if (up) ci_out[ou + bits_below(bu)] = z;
+        __syncthreads();  // every thread has read s_pos and s_w
+        if (tid < 3) s_pos[tid] += s_w[tid][0] + s_w[tid][1] + s_w[tid][2] + s_w[tid][3];
+        __syncthreads();
     }
 }
 
@@ -997,19 +1102,30 @@ hipError_t launch_twohop_i64(const int32_t *rp, const int32_t *ci, int32_t n, in
     return hipGetLastError();
 }
 
+template <typename DistT>
+static void launch_split_t(const int32_t *rp, const int32_t *ci, int32_t n, const void *dist, int32_t *ci_out,
+                           int4 *rinfo, void *dist1, const int32_t *chunks, int32_t nchunks, int32_t *cnt,
+                           hipStream_t s) {
+    const DistT *d = reinterpret_cast<const DistT *>(dist);
+    DistT *d1 = reinterpret_cast<DistT *>(dist1);
+    const bool chunked = chunks != nullptr && nchunks > 0;
+    const int64_t g = ((int64_t)n * 64 + 255) / 256;
+    hipLaunchKernelGGL((k_row_split<DistT>), dim3((unsigned)(g < 1 ? 1 : g)), dim3(256), 0, s, rp, ci, n, d,
+                       ci_out, rinfo, d1, (int32_t)chunked);
+    if (!chunked) return;
+    hipLaunchKernelGGL((k_row_split_count<DistT>), dim3((unsigned)nchunks), dim3(256), 0, s, rp, ci, d, chunks,
+                       cnt);
+    hipLaunchKernelGGL((k_row_split_place<DistT>), dim3((unsigned)nchunks), dim3(256), 0, s, rp, ci, d, chunks,
+                       cnt, ci_out, rinfo, d1);
+}
+
 hipError_t launch_row_split(const int32_t *rp, const int32_t *ci, int32_t n, const void *dist,
                             int dist_bytes, int32_t *ci_out, int4 *rinfo, void *dist1,
-                            hipStream_t s) {
-    const int64_t g = ((int64_t)n * 64 + 255) / 256;
-    const dim3 grid((unsigned)(g < 1 ? 1 : g));
+                            const int32_t *chunks, int32_t nchunks, int32_t *cnt, hipStream_t s) {
     if (dist_bytes == 1)
-        hipLaunchKernelGGL((k_row_split<uint8_t>), grid, dim3(256), 0, s, rp, ci, n,
-                           reinterpret_cast<const uint8_t *>(dist), ci_out, rinfo,
-                           reinterpret_cast<uint8_t *>(dist1));
+        launch_split_t<uint8_t>(rp, ci, n, dist, ci_out, rinfo, dist1, chunks, nchunks, cnt, s);
     else
-        hipLaunchKernelGGL((k_row_split<uint16_t>), grid, dim3(256), 0, s, rp, ci, n,
-                           reinterpret_cast<const uint16_t *>(dist), ci_out, rinfo,
-                           reinterpret_cast<uint16_t *>(dist1));
+        launch_split_t<uint16_t>(rp, ci, n, dist, ci_out, rinfo, dist1, chunks, nchunks, cnt, s);
     return hipGetLastError();
 }
 
