@@ -463,3 +463,53 @@ def test_schedule_autotuner_keeps_the_picks(gclib):
     grp_b, F_b, ev_b, _ = oracle.greedypp(g, 15, block=out["block"], growth=out["growth"])
     assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
     assert st["evals_per_round"].tolist() == ev_b.tolist()
+
+
+def _broom(path_len, hub_at, satellites, seed):
+    """A path with a hub on it: `satellites` extra nodes joined to the hub, to
+    their next satellite (a ring) and, every tenth, to a random one of the
+    path's first 100 nodes, so the hub's row (more than 2048 entries) has
+    neighbours nearer, as near and farther than the hub from a group, and the
+    rest of the path stays a long tail."""
+    rng = np.random.default_rng(seed)
+    src = list(range(path_len - 1))
+    dst = list(range(1, path_len))
+    sat = np.arange(path_len, path_len + satellites)
+    src += [hub_at] * satellites
+    dst += sat.tolist()
+    src += sat.tolist()
+    dst += np.roll(sat, 1).tolist()
+    tenth = sat[::10]
+    src += tenth.tolist()
+    dst += rng.integers(0, min(100, path_len), tenth.shape[0]).tolist()
+    return graphgen.from_edges("broom%d_%d" % (path_len, satellites), path_len + satellites,
+                               np.array(src), np.array(dst))
+
+
+@pytest.mark.parametrize("path_len,dist_bytes", [(120, 1), (700, 2)])
+def test_long_rows_split_by_chunks(gclib, device, path_len, dist_bytes):
+    """Rows of more than 1024 entries are split by 2048-entry chunks: every
+    gain, |V(v)| and adjacency count of a round matches the oracle with 8- and
+    16-bit distances, and the greedy matches CPU Greedy++ round by round."""
+    g = _broom(path_len, 40, 5000, 11)
+    deg = np.diff(g.row_ptr)
+    assert deg.max() > 2 * 2048
+    G = _graph(gclib, g)
+    dist = G.new_dist(dist_bytes)
+    far = torch.zeros(1, dtype=torch.int64, device=device)
+    S = [60, path_len - 1]
+    for s in S:
+        G.update_dist(s, dist, dist_bytes, far)
+    torch.cuda.synchronize()
+    dS = oracle.group_dist(g, S)
+    assert int(dS.max()) > 254 if dist_bytes == 2 else int(dS.max()) <= 254
+    cand = np.arange(g.n, dtype=np.int32)
+    _note("gains broom%d (%d-byte distances)" % (path_len, dist_bytes))
+    gain = G.marginal_gains(dist, dist_bytes, torch.from_numpy(cand)).cpu().numpy()
+    assert np.array_equal(gain, oracle.gains(g, dS, cand))
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 8, block=64, growth=2)
+    _note("greedy broom%d k=8" % path_len)
+    grp, F, st = G.greedy_group(8, debug=True)
+    assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+    assert st["evals_per_round"].tolist() == ev_b.tolist()
+    assert st["edges_alg"] == int(ed_b.sum())
