@@ -431,9 +431,12 @@ int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts, void *d_w
  * gc_greedy_many -- gc_greedy_group for `count` independent jobs (graph
  * graphs[i], k[i]) run by `nworkers` host threads.  Worker w works on its own
  * stream streams[w] with its own workspace d_ws[w] of ws_bytes[w] bytes (at
- * least gc_workspace_size of every graph), which it re-initialises
- * (gc_workspace_init) for each job; jobs go to the next free worker, largest
- * graph first, so independent jobs overlap their launch latencies on the GPU.
+ * least gc_workspace_size of every graph), which it prepares for each job as
+ * gc_workspace_init would (the first job on it: gc_workspace_init itself;
+ * later jobs: only what the previous job may have left non-zero, since the
+ * engine returns every record it touches to zero); jobs go to the next free
+ * worker, largest graph first, so independent jobs overlap their launch
+ * latencies on the GPU.
  * Every job gets the same picks as gc_greedy_group would give it alone.
  *   count       >= 0 jobs; graphs[i] and k[i] as for gc_greedy_group
  *   opts        NULL or one gc_opts for every job (nprefix must be 0, no log)
