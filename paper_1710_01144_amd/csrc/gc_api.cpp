@@ -1029,6 +1029,17 @@ extern "C" int gc_workspace_init(const gc_graph *g, void *d_ws, size_t ws_bytes,
 
 namespace {
 
+// Set on the worker threads of the multi-job engines: their gain launches
+// sum per-source results in LDS slots (WideArgs::pack == 2), which pays when
+// several jobs' launches share the GPU's atomic units and costs a little when
+// one launch has the chip to itself.
+thread_local bool t_slot_sums = false;
+struct SlotSums {  // on for the lifetime of a worker's loop (also when it runs on the caller's thread)
+    bool prev;
+    SlotSums() : prev(t_slot_sums) { t_slot_sums = true; }
+    ~SlotSums() { t_slot_sums = prev; }
+};
+
 // Byte range [lo, hi) of a worker's workspace known to hold zeros between the
 // jobs of gc_greedy_many / gc_greedy_batch: the wide engine's records of the
 // last job (every call of the engine returns the records it touched to zero;
@@ -1285,6 +1296,7 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
             // overflow its field: edges <= nnz, gain <= n * max d(S,.)
             a.pack = d_edges && g->nnz < (1ll << kPackShift) &&
                      (int64_t)g->n * (int64_t)(nlev + 1) < (1ll << (62 - kPackShift));
+            if (a.pack && t_slot_sums) a.pack = 2;
             if (cut) {
                 // the cut test reads each source's gain, reach and adjacency
                 // between levels: separate counters, per-launch scratch
@@ -3217,6 +3229,7 @@ extern "C" int gc_greedy_many(int32_t count, const gc_graph *const *graphs, cons
     std::vector<std::string> msg((size_t)count, std::string("not run: no worker could select the device"));
     auto work = [&](int32_t w) {
         if (hipSetDevice(dev) != hipSuccess) return;
+        const SlotSums slot_sums;
         ZeroRange zero;  // nothing is known of the workspace before its first job
         for (;;) {
             const int32_t t = next.fetch_add(1);
@@ -3551,8 +3564,11 @@ int union_call(UnionCall &c, const std::vector<std::pair<int32_t, std::vector<in
         a.far = nullptr;
         a.bbase = c.d_bbase;
         apply_split(a, c.split);
+        // (many jobs in one launch: window sums in LDS slots)
         a.pack = gu->nnz < (1ll << kPackShift) &&
-                 (int64_t)gu->n * (int64_t)(c.nlev + 1) < (1ll << (62 - kPackShift));
+                         (int64_t)gu->n * (int64_t)(c.nlev + 1) < (1ll << (62 - kPackShift))
+                     ? 2
+                     : 0;
         HIP_OK(launch_wide_begin(a, c.dist_bytes, c.nlev, c.s));
         HIP_OK(launch_wide_levels(a, c.dist_bytes, 0, c.nlev, grid, c.s));
         HIP_OK(launch_wide_end(a, c.nlev, grid, c.s));
@@ -3693,6 +3709,7 @@ extern "C" int gc_greedy_batch(int32_t count, const gc_graph *const *graphs, con
     }
     auto work = [&](int32_t wk) {
         if (hipSetDevice(dev) != hipSuccess) return;
+        const SlotSums slot_sums;
         ZeroRange zero;
         for (;;) {
             const int32_t t = next.fetch_add(1);

@@ -127,7 +127,9 @@ struct WideArgs {
     // gain and edge count of a source summed in one 64-bit word during the
     // launch, (gain << kPackShift) + edges, unpacked by the final kernel; the
     // host sets it only when edges < 2^kPackShift and the gain cannot reach
-    // 2^(63 - kPackShift)
+    // 2^(63 - kPackShift).  2: the same, and a launch of more than kLdsSrc
+    // sources first sums each window's batches in LDS slots, which cuts the
+    // global atomics when many launches share the chip (the multi-job engines)
     int32_t pack;
     // early exit inside the candidates' BFS (gain launches with `active`):
     // cut_gain selects it; the bound's tail table T (cut_maxd + 2 entries),

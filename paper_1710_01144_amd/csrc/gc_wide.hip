@@ -41,6 +41,7 @@ namespace {
 
 constexpr int kWin = 256;      // entries staged per window
 constexpr int kLdsSrc = 1024;  // launches with at most this many sources sum gains in LDS
+constexpr int kBatchSlots = 16; // larger launches: batches of a window summed in LDS
 constexpr uint64_t kMEdges = (1ull << kCntShift) - 1;
 
 __device__ __forceinline__ int lane_id() {
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
 // One BFS level.  LDS: per-source sums in LDS (launches of <= kLdsSrc
 // sources); large launches add straight to global memory and keep LDS small
 // for occupancy.  U: edges per thread per step.
-template <typename DistT, bool WRITE, bool LDS, int U>
+template <typename DistT, bool WRITE, bool LDS, int U, bool SLOTS>
 __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     constexpr int kStep = kWG * U;  // adjacency entries per workgroup step
     __shared__ int64_t s_off[kWin + 1];
@@ -316,6 +317,13 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     __shared__ unsigned long long s_e[LDS ? kLdsSrc : 1];
     __shared__ unsigned int s_v[LDS ? kLdsSrc : 1];
     __shared__ int32_t s_flag;
+    // large launches with packed sums in slots (pack == 2): the window's
+    // batches get LDS slots of 64 per-source sums, added to global memory once
+    // per window instead of once per claimed bit
+    constexpr bool kSlotAcc = !LDS && SLOTS;
+    __shared__ int32_t s_sb[kSlotAcc ? kBatchSlots : 1];                 // batch of each slot (-1: free)
+    __shared__ unsigned long long s_sg[kSlotAcc ? kBatchSlots * 64 : 1];  // packed sums per slot and bit
+    __shared__ int8_t s_es[kSlotAcc ? kWin : 1];                         // slot of each window entry (-1: none)
 
     // another workgroup may raise the overflow flag while this one starts:
     // read it once, so that every wave of the workgroup takes the same exit
@@ -327,6 +335,11 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     if (threadIdx.x == 0) s_flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (s_flag) return;
+    const bool slot_acc = kSlotAcc && a.pack == 2;  // (uniform)
+    if (slot_acc) {
+        for (int q = threadIdx.x; q < kBatchSlots * 64; q += kWG) s_sg[q] = 0ull;
+        if (threadIdx.x < kBatchSlots) s_sb[threadIdx.x] = -1;
+    }
     const int64_t N = (int64_t)(me.packed >> kCntShift);
     const int64_t E = (int64_t)(me.packed & kMEdges);
     const int64_t start = me.start;
@@ -408,6 +421,19 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
             s_rs[tid] = a.lr[q];
             s_b[tid] = b;
             s_rb[tid] = batch_base(a, b);
+            if (slot_acc) {
+                // the entry's batch: its slot, a free one, or none (table full)
+                int slot = -1;
+                for (int k = 0; k < kBatchSlots; ++k) {
+                    int cur = s_sb[k];
+                    if (cur == -1) cur = atomicCAS(&s_sb[k], -1, b);
+                    if (cur == -1 || cur == b) {
+                        slot = k;
+                        break;
+                    }
+                }
+                s_es[tid] = (int8_t)slot;
+            }
             // an entry starting at or past this workgroup's last adjacency
             // entry is never expanded here: skip its frontier word (a random
             // line per entry)
@@ -521,10 +547,13 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
                             const int64_t gb = (int64_t)bb[r] * a.spb;
                             const unsigned long long cp =
                                 a.pack ? (c << kPackShift) + (unsigned long long)full : c;
+                            const int sl = slot_acc ? (int)s_es[own[r]] : -1;
                             for (uint64_t mm = nw; mm; mm &= mm - 1) {
-                                const int64_t j = gb + (__ffsll((unsigned long long)mm) - 1);
+                                const int bit = __ffsll((unsigned long long)mm) - 1;
+                                const int64_t j = gb + bit;
                                 if (a.pack) {
                                     if (lds_acc) atomicAdd(&s_g[j], cp);
+                                    else if (sl >= 0) atomicAdd(&s_sg[sl * 64 + bit], cp);
                                     else atomicAdd(reinterpret_cast<unsigned long long *>(a.gain + j), cp);
                                     if (a.visited) {
                                         if (lds_acc) atomicAdd(&s_v[j], 1u);
@@ -553,6 +582,20 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
             push_block<U>(a, next, nbase, live, p, y, rs, bb, deg, s_wc, s_wd, &s_old);
         }
         __syncthreads();
+        if (slot_acc) {
+            // the window's sums to global memory; the slots free again
+            for (int q = tid; q < kBatchSlots * 64; q += kWG) {
+                const unsigned long long v = s_sg[q];
+                if (v) {
+                    const int32_t sb = s_sb[q >> 6];
+                    atomicAdd(reinterpret_cast<unsigned long long *>(a.gain + (int64_t)sb * a.spb + (q & 63)), v);
+                    s_sg[q] = 0ull;
+                }
+            }
+            __syncthreads();
+            if (tid < kBatchSlots) s_sb[tid] = -1;
+            __syncthreads();
+        }
         if (whi >= ee || i + cnt >= N) break;
         i += cnt;
     }
@@ -567,9 +610,9 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     if (L >= 1 && G == (int64_t)gridDim.x) clear_prev(blockIdx.x, gridDim.x);
 }
 
-template <typename DistT, bool WRITE, bool LDS, int U>
+template <typename DistT, bool WRITE, bool LDS, int U, bool SLOTS = false>
 __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
-    level_body<DistT, WRITE, LDS, U>(a, L);
+    level_body<DistT, WRITE, LDS, U, SLOTS>(a, L);
 }
 
 // End of a launch: return every touched record to zero, copy the results
@@ -1034,6 +1077,14 @@ static void launch_level(const WideArgs &a, int32_t L, int grid, hipStream_t s) 
             hipLaunchKernelGGL((k_wide_level<DistT, WRITE, true, 8>), dim3(grid), dim3(kWG), 0, s, a, L);
         else
             hipLaunchKernelGGL((k_wide_level<DistT, WRITE, true, 4>), dim3(grid), dim3(kWG), 0, s, a, L);
+    } else if (a.pack == 2) {
+        // (a separate instantiation: the slots' LDS and code stay out of the others)
+        if (a.unroll == 16)
+            hipLaunchKernelGGL((k_wide_level<DistT, WRITE, false, 16, true>), dim3(grid), dim3(kWG), 0, s, a, L);
+        else if (a.unroll == 8)
+            hipLaunchKernelGGL((k_wide_level<DistT, WRITE, false, 8, true>), dim3(grid), dim3(kWG), 0, s, a, L);
+        else
+            hipLaunchKernelGGL((k_wide_level<DistT, WRITE, false, 4, true>), dim3(grid), dim3(kWG), 0, s, a, L);
     } else if (a.unroll == 16) {
         hipLaunchKernelGGL((k_wide_level<DistT, WRITE, false, 16>), dim3(grid), dim3(kWG), 0, s, a, L);
     } else if (a.unroll == 8) {
