@@ -42,6 +42,7 @@ namespace {
 constexpr int kWin = 256;      // entries staged per window
 constexpr int kLdsSrc = 1024;  // launches with at most this many sources sum gains in LDS
 constexpr int kBatchSlots = 16; // larger launches: batches of a window summed in LDS
+constexpr int64_t kReadFirstEdges = 1 << 20;  // levels beyond this read a visited word before its atomic
 constexpr uint64_t kMEdges = (1ull << kCntShift) - 1;
 
 __device__ __forceinline__ int lane_id() {
@@ -336,6 +337,7 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     __syncthreads();
     if (s_flag) return;
     const bool slot_acc = kSlotAcc && a.pack == 2;  // (uniform)
+    const bool read_first = !LDS || (int64_t)(me.packed & kMEdges) > kReadFirstEdges;
     if (slot_acc) {
         for (int q = threadIdx.x; q < kBatchSlots * 64; q += kWG) s_sg[q] = 0ull;
         if (threadIdx.x < kBatchSlots) s_sb[threadIdx.x] = -1;
@@ -530,10 +532,11 @@ __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
                         const int32_t r0 = rp[y[r]];
                         ri = make_int4(r0, rp[y[r] + 1] - r0, 0, 0);
                     }
-                    // small launches (latency-bound): claim with the atomic
-                    // alone; large ones first read the word, so that targets
-                    // every source has reached cost no atomic
-                    const uint64_t m = LDS ? s_m[own[r]] : s_m[own[r]] & ~(uint64_t)(*vw);
+                    // small levels (latency-bound): claim with the atomic
+                    // alone; large ones (many sources, or a level of a full
+                    // BFS with many adjacency entries) first read the word, so
+                    // that targets every source has reached cost no atomic
+                    const uint64_t m = read_first ? s_m[own[r]] & ~(uint64_t)(*vw) : s_m[own[r]];
                     if (m) {
                         const uint64_t ov = atomicOr(vw, (unsigned long long)m);
                         tz[r] = ov == 0ull;
