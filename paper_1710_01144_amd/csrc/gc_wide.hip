@@ -299,8 +299,8 @@ __global__ __launch_bounds__(256) void k_wide_roots(WideArgs a) {
 }
 
 // One BFS level.  LDS: per-source sums in LDS (launches of <= kLdsSrc
-// sources); large launches add straight to global memory and keep LDS small
-// for occupancy.  U: edges per thread per step.
+// sources); large launches add to global memory, straight or (SLOTS) through
+// per-window LDS slots of the window's batches.  U: edges per thread per step.
 template <typename DistT, bool WRITE, bool LDS, int U, bool SLOTS>
 __device__ __forceinline__ void level_body(const WideArgs &a, int32_t L) {
     constexpr int kStep = kWG * U;  // adjacency entries per workgroup step
