@@ -584,6 +584,7 @@ struct WsLayout {
     int64_t zcap;       // clean-up list entries
     size_t lchunk = 0, lcnt = 0;  // long rows' chunk list and part sizes of the row split
     int64_t nchunk = 0;           // chunks the layout has room for (0: none)
+    size_t acc = 0;               // level-0 sums of launch_wide_first (0: no room)
 };
 
 constexpr int32_t kMaxLevels = 65536;  // 16-bit distances: at most 65534 levels
@@ -635,6 +636,8 @@ WsLayout ws_layout(const gc_graph *g) {
     L.lo = o; o += al256((size_t)L.cap * 8);
     L.lz = o; o += al256((size_t)L.zcap * 8);
     L.lvl = o; o += al256((size_t)(kMaxLevels + 2) * sizeof(WideLevel));
+    // level-0 sums of launches that fold the roots into level 0 (zero between launches)
+    L.acc = o; o += al256((size_t)kFirstMaxSrc * 8);
     L.act = o; o += al256((size_t)kmax * 8);
     L.cutprev = o; o += al256(n * 16);
     L.farout = o; o += al256(n * 8);
@@ -1207,6 +1210,17 @@ struct HostIO {
     // done), added to *gpu_ms
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double *gpu_ms = nullptr;
+    // launches of at most kFirstMaxSrc sources run their roots and level 0 as
+    // one kernel (launch_wide_first) where its conditions hold
+    bool first_level = false;
+    // optional: candidate lists in pinned memory, seen by the device at
+    // cand_dev and by the host at cand_host (cand_len ids); a launch whose
+    // candidates lie there gets them as a kernel argument and a grid cut to
+    // its level-0 adjacency entries.  Only for lists the host wrote: ids that
+    // a kernel writes there are not in the host's view at enqueue time.
+    const int32_t *cand_dev = nullptr;
+    const int32_t *cand_host = nullptr;
+    size_t cand_len = 0;
 };
 
 struct LaunchShape {
@@ -1339,6 +1353,34 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                     if (L + 1 < nlev) HIP_OK(launch_gain_cut(a, L + 1, s));
                 }
                 HIP_OK(launch_wide_end(a, nlev, grid, s));
+            } else if (io && io->first_level && w.L.acc && a.pack && !a.visited && a.nsrc <= kFirstMaxSrc &&
+                       nlev >= 1) {
+                // roots and level 0 in one kernel (its sums in acc until the end)
+                a.acc = reinterpret_cast<unsigned long long *>(w.base + w.L.acc);
+                FirstIds ids;
+                int32_t nids = 0;
+                int gfirst = grid;
+                const int32_t *src = a.src;
+                if (io->cand_host && src >= io->cand_dev && src + a.nsrc <= io->cand_dev + io->cand_len) {
+                    // the host's view of the same ids: their full rows bound
+                    // level 0's adjacency entries, hence the workgroups it uses
+                    const int32_t *hs = io->cand_host + (src - io->cand_dev);
+                    const int32_t *hrp = g->h_rp.data();
+                    int64_t ef = 0;
+                    for (int64_t j = 0; j < a.nsrc; ++j) {
+                        const int32_t v = hs[j];
+                        if ((uint32_t)v < (uint32_t)g->n) ef += hrp[v + 1] - hrp[v];
+                    }
+                    const int64_t gw = (ef + a.min_edges - 1) / a.min_edges;
+                    gfirst = (int)std::max<int64_t>(1, std::min<int64_t>(grid, gw));
+                    if (a.nsrc <= kFirstArgIds) {
+                        nids = (int32_t)a.nsrc;
+                        std::memcpy(ids.id, hs, sizeof(int32_t) * (size_t)nids);
+                    }
+                }
+                HIP_OK(launch_wide_first(a, dist_bytes, gfirst, ids, nids, s));
+                HIP_OK(launch_wide_levels(a, dist_bytes, 1, nlev, grid, s));
+                HIP_OK(launch_wide_end(a, nlev, grid, s));
             } else {
                 HIP_OK(launch_wide_begin(a, dist_bytes, nlev, s));
                 HIP_OK(launch_wide_levels(a, dist_bytes, 0, nlev, grid, s));
@@ -1412,6 +1454,8 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                                (size_t)(nlev + 2) * sizeof(WideLevel) / 4, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.zcnt()), 2, 0u, s));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.flags()), 1, 0u, s));
+        if (w.L.acc)
+            HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(w.base + w.L.acc), (size_t)kFirstMaxSrc * 2, 0u, s));
         if (kb > 1) kb = std::max<int64_t>(1, kb / 2);
         else if (spb > 1) spb = std::max(1, spb / 2);
         else
@@ -2511,6 +2555,10 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
     io.hm_done = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(dflag) + 64);
     io.h_done = reinterpret_cast<volatile int64_t *>(reinterpret_cast<char *>(hflag) + 64);
     *io.h_done = 0;
+    io.first_level = true;
+    io.cand_dev = dc;
+    io.cand_host = hc;
+    io.cand_len = (size_t)n * 2;
     const bool want_edges = true;
     const bool learned = o.order == GC_ORDER_LEARNED;
     const bool logging = o.log_capacity > 0 && o.h_log_round && o.h_log_node && o.h_log_gain &&
@@ -3115,8 +3163,12 @@ extern "C" int gc_greedy_group(const gc_graph *g, int32_t k, const gc_opts *opts
                 io.round = r + 1;
                 first_nlev = nlev_now();
                 bool q = false;
+                // (ids chosen on the device are not in the host's view until the stream gets there)
+                const int32_t *const cand_host = io.cand_host;
+                if (pending_scored) io.cand_host = nullptr;
                 rc = run_gains(g, w, d_dist, dist_bytes, dc, first_cnt, w.gain(), w.aux(), nullptr, s,
                                first_nlev, hg, he, &io, &shape_later, &split, false, kGainsLaunch, &q);
+                io.cand_host = cand_host;
                 if (rc) return rc;
                 st.gain_launches += 1;
                 first_state = q ? 1 : 2;

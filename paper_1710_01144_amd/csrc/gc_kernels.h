@@ -141,8 +141,19 @@ struct WideArgs {
     int32_t cut_id;
     unsigned long long *cut_count; // sources stopped, added to
     int32_t directed;              // rows are out-neighbour lists of a directed graph
+    // launches started by launch_wide_first: level 0's packed sums per source
+    // (zero between launches; the final kernel adds them to gain and clears them)
+    unsigned long long *acc;
 };
 constexpr int kPackShift = 30;
+// most sources of a launch started by launch_wide_first
+constexpr int64_t kFirstMaxSrc = 1024;
+// the first kFirstArgIds candidates of such a launch may come as a kernel
+// argument (read from the argument segment instead of WideArgs::src)
+constexpr int kFirstArgIds = 256;
+struct FirstIds {
+    int32_t id[kFirstArgIds];
+};
 // Split every row of (rp, ci) by the distances dist (see WideArgs::rinfo);
 // dist1 receives a copy of dist.  Rows of more than kSplitLongRow entries
 // may be listed in `chunks` (nchunks pairs {row, index of the row's first
@@ -176,6 +187,14 @@ hipError_t launch_lb1_filter(const int32_t *order, const int32_t *rp, const int6
 hipError_t launch_gather_i64(const int64_t *src, const int32_t *idx, int32_t cnt, int64_t *out,
                              hipStream_t s);
 hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hipStream_t s);
+// Roots and level 0 of a gain launch in one kernel, in place of
+// launch_wide_begin and level 0 (the level kernels then start at level 1):
+// at most kFirstMaxSrc sources, packed sums (pack != 0) with acc set, no
+// per-source visited counts, active masks, early exit or write-back.  ids
+// holds a.src[0 .. nids) (nids <= kFirstArgIds; 0: none); grid may be cut to
+// the workgroups the level-0 adjacency entries can need.
+hipError_t launch_wide_first(const WideArgs &a, int dist_bytes, int grid, const FirstIds &ids, int32_t nids,
+                             hipStream_t s);
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,
                               hipStream_t s);
 hipError_t launch_wide_end(const WideArgs &a, int32_t nlev, int grid, hipStream_t s);

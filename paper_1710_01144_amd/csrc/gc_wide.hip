@@ -618,20 +618,237 @@ __global__ __launch_bounds__(256) void k_wide_level(WideArgs a, int32_t L) {
     level_body<DistT, WRITE, LDS, U, SLOTS>(a, L);
 }
 
+// Adds a wave's entries (lanes with p, deg adjacency entries each) to a level
+// record without log entries (every lane of a fully active wave calls it).
+__device__ __forceinline__ void count_wave(const WideArgs &a, WideLevel *l, bool p, int32_t deg) {
+    const uint64_t bal = __ballot(p);
+    if (bal == 0) return;
+    unsigned long long e = p ? (unsigned long long)deg : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+    if (lane_id() == 0) {
+        const unsigned long long old =
+            atomicAdd(&l->packed, ((unsigned long long)__popcll(bal) << kCntShift) + e);
+        if ((old & kMEdges) + e >= (1ull << (kCntShift - 1)) ||
+            (old >> kCntShift) + 64 >= (1ull << (63 - kCntShift)))
+            set_flag(a.flags, a.tag);
+    }
+}
+
+// Roots and level 0 of a gain launch in one kernel: the first two steps of
+// every candidate's pruned BFS (Section 4.1), for launches of at most
+// kFirstMaxSrc candidates with packed sums.  The candidates take the place of
+// level 0's log: every workgroup reads all of them, forms the prefix sums of
+// their expandable row prefixes in LDS and expands its share of those
+// adjacency entries (edge-balanced, as a level kernel does), each candidate
+// with its own bit.  A candidate's bit is set only by its own search, and no
+// row holds its own node (a self-loop is skipped), so a root claimed by
+// another workgroup later than its neighbours changes no result.  The
+// workgroups also claim the roots (candidate t by thread t mod 256 of
+// workgroup t / 256, grid-strided): they store the root terms in gain[] and
+// count the roots into level 0's record as the roots kernel does, but write
+// no log entries and no level-0 frontier words.  Level-0 sums therefore go to
+// acc[] (zero between launches), which the final kernel adds to gain[].
+// Level 0 and level 1 both start at log position nsrc: level 1 has nothing of
+// level 0 to clear.  The first nids candidate ids come from the argument
+// segment (every workgroup reads them all; src may be host memory).
+template <typename DistT, int U>
+__global__ __launch_bounds__(256) void k_wide_first(WideArgs a, FirstIds ids, int32_t nids) {
+    constexpr int kStep = kWG * U;
+    constexpr int kPer = (int)(kFirstMaxSrc / kWG);  // candidates per thread in the scan
+    __shared__ int64_t c_off[kFirstMaxSrc + 1];       // first adjacency entry of each candidate
+    __shared__ int32_t c_rs[kFirstMaxSrc];            // its row start
+    __shared__ int32_t c_y[kFirstMaxSrc];             // its node
+    __shared__ unsigned long long s_g[kFirstMaxSrc];  // packed level-0 sums
+    __shared__ int64_t s_wc[kWG / 64], s_wd[kWG / 64];
+    __shared__ uint64_t s_old;
+    __shared__ int32_t s_flag;
+    if (threadIdx.x == 0) s_flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_flag) return;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int64_t ns = a.nsrc;
+    DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
+    if (blockIdx.x == 0 && tid == 0) {
+        a.lvl[0].start = ns;
+        a.lvl[1].start = ns;
+    }
+    // the roots (uniform trip count per workgroup: the appends are wave ops)
+    for (int64_t t0 = (int64_t)blockIdx.x * kWG; t0 < ns; t0 += (int64_t)gridDim.x * kWG) {
+        const int64_t t = t0 + tid;
+        bool touched = false, p = false;
+        int32_t v = 0, b = 0, deg = 0;
+        if (t < ns) {
+            v = t < nids ? ids.id[t] : a.src[t];
+            b = (int32_t)(t / a.spb);
+            const uint64_t bit = 1ull << (t - (int64_t)b * a.spb);
+            const uint32_t d = (uint32_t)v < (uint32_t)a.n ? (uint32_t)dist[v] : 0u;
+            int64_t gv = 0;
+            if (d > 0u) {
+                const uint64_t old = atomicOr(rec(a, b, v, 0), (unsigned long long)bit);
+                touched = old == 0ull;
+                if (bit & ~old) {
+                    int32_t full;
+                    if (a.rinfo) {
+                        const int4 ri = a.rinfo[v];
+                        full = ri.y;
+                        deg = expand_len(ri, load_d1<DistT>(a, v), 0u);
+                    } else {
+                        full = a.rp[v + 1] - a.rp[v];
+                        deg = full;
+                    }
+                    gv = ((int64_t)d << kPackShift) + full;
+                    p = deg > 0;
+                }
+            }
+            a.gain[t] = gv;
+        }
+        touch_wave<1>(a, &touched, &b, &v);
+        count_wave(a, &a.lvl[0], p, deg);
+    }
+    // every candidate's expandable prefix (none for a node of S or an id
+    // outside [0, n)); thread tid takes candidates kPer*tid .. kPer*tid+kPer-1
+    int32_t dg[kPer];
+    int64_t loc = 0;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int64_t q = (int64_t)kPer * tid + r;
+        int32_t deg = 0;
+        if (q < ns) {
+            const int32_t v = q < nids ? ids.id[q] : a.src[q];
+            int32_t rs = 0;
+            const uint32_t d = (uint32_t)v < (uint32_t)a.n ? (uint32_t)dist[v] : 0u;
+            if (d > 0u) {
+                if (a.rinfo) {
+                    const int4 ri = a.rinfo[v];
+                    rs = ri.x;
+                    deg = expand_len(ri, load_d1<DistT>(a, v), 0u);
+                } else {
+                    rs = a.rp[v];
+                    deg = a.rp[v + 1] - rs;
+                }
+            }
+            c_rs[q] = rs;
+            c_y[q] = v;
+            s_g[q] = 0ull;
+        }
+        dg[r] = deg;
+        loc += deg;
+    }
+    int64_t inc = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) s_wc[tid >> 6] = inc;
+    __syncthreads();
+    int64_t pre = inc - loc, E = 0;
+#pragma unroll
+    for (int k = 0; k < kWG / 64; ++k) {
+        if (k < (tid >> 6)) pre += s_wc[k];
+        E += s_wc[k];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int64_t q = (int64_t)kPer * tid + r;
+        if (q < ns) c_off[q] = pre;
+        pre += dg[r];
+    }
+    if (tid == 0) c_off[ns] = E;
+    __syncthreads();
+    // this workgroup's adjacency entries [eb, ee), as a level kernel takes them
+    int64_t G = E == 0 ? 0 : (E + a.min_edges - 1) / a.min_edges;
+    if (G > (int64_t)gridDim.x) G = gridDim.x;
+    if ((int64_t)blockIdx.x >= G) return;
+    const int64_t eb = E * (int64_t)blockIdx.x / G;
+    const int64_t ee = E * ((int64_t)blockIdx.x + 1) / G;
+    if (eb >= ee) return;
+    const uint32_t nl = 1u;
+    const int32_t *__restrict__ ci = a.ci;
+    for (int64_t e0 = eb; e0 < ee; e0 += kStep) {
+        int32_t y[U], own[U], bb[U], deg[U], rs[U];
+        uint32_t d[U];
+        bool p[U], tz[U];
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            const int64_t e = e0 + tid + (int64_t)r * kWG;
+            own[r] = -1;
+            y[r] = 0;
+            if (e < ee) {
+                // the last candidate whose first entry is at or before e (its prefix holds e)
+                int lo = 0, hi = (int)ns - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (c_off[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                own[r] = lo;
+                y[r] = ci[c_rs[lo] + (int32_t)(e - c_off[lo])];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < U; ++r) d[r] = own[r] >= 0 ? (uint32_t)dist[y[r]] : 0u;
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            p[r] = false;
+            tz[r] = false;
+            bb[r] = 0;
+            deg[r] = 0;
+            rs[r] = 0;
+            if (own[r] >= 0 && nl < d[r] && y[r] != c_y[own[r]]) {
+                const int q = own[r];
+                const int32_t b = (int32_t)(q / a.spb);
+                bb[r] = b;
+                const uint64_t bit = 1ull << (q - b * a.spb);
+                unsigned long long *vw = rec(a, b, y[r], 0);
+                int4 ri;
+                uint32_t d1 = 0;
+                if (a.rinfo) {
+                    ri = a.rinfo[y[r]];
+                    d1 = load_d1<DistT>(a, y[r]);
+                } else {
+                    const int32_t r0 = a.rp[y[r]];
+                    ri = make_int4(r0, a.rp[y[r] + 1] - r0, 0, 0);
+                }
+                const uint64_t ov = atomicOr(vw, (unsigned long long)bit);
+                tz[r] = ov == 0ull;
+                if (!(ov & bit)) {
+                    const int32_t full = ri.y;
+                    rs[r] = ri.x;
+                    deg[r] = a.rinfo ? expand_len(ri, d1, nl) : full;
+                    atomicAdd(&s_g[q], ((unsigned long long)(d[r] - nl) << kPackShift) + (unsigned long long)full);
+                    // level 1's frontier word is word 1 + (1 mod 3)
+                    p[r] = deg[r] > 0 && atomicOr(vw + 2, (unsigned long long)bit) == 0ull;
+                }
+            }
+        }
+        touch_wave<U>(a, tz, bb, y);
+        push_block<U>(a, &a.lvl[1], ns, ns, p, y, rs, bb, deg, s_wc, s_wd, &s_old);
+    }
+    __syncthreads();
+    for (int q = tid; q < ns; q += kWG)
+        if (s_g[q]) atomicAdd(a.acc + q, s_g[q]);
+}
+
 // End of a launch: return every touched record to zero, copy the results
 // to the host-mapped buffers if given and scatter them into the lazy-loop
 // state if asked.  After an overflow nothing is cleared here; the host clears
 // and retries.
 __device__ __forceinline__ void end_body(const WideArgs &a) {
     const int32_t flag = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     if (flag) {
         if (a.h_flag && blockIdx.x == 0 && threadIdx.x == 0) *a.h_flag = flag;
+        // (the launch is redone: its level-0 sums go)
+        if (a.acc)
+            for (int64_t i = t0; i < a.nsrc; i += nt) a.acc[i] = 0ull;
         return;
     }
     int64_t tot = (int64_t)*a.zcnt;
     if (tot > a.zcap) tot = a.zcap;
-    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = t0; i < tot; i += nt) {
         const int64_t z = a.lz[i];
         unsigned long long *r0 = rec(a, z >> 32, (int32_t)(uint32_t)z, 0);
@@ -642,7 +859,11 @@ __device__ __forceinline__ void end_body(const WideArgs &a) {
     }
     if (a.pack)
         for (int64_t i = t0; i < a.nsrc; i += nt) {
-            const int64_t v = a.gain[i];
+            int64_t v = a.gain[i];
+            if (a.acc) {
+                v += (int64_t)a.acc[i];
+                a.acc[i] = 0ull;
+            }
             a.gain[i] = v >> kPackShift;
             if (a.edges) a.edges[i] = v & ((1ll << kPackShift) - 1);
         }
@@ -1068,6 +1289,20 @@ hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hi
     } else {
         if (a.write) hipLaunchKernelGGL((k_wide_roots<uint16_t, true>), dim3(groots), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_wide_roots<uint16_t, false>), dim3(groots), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_first(const WideArgs &a, int dist_bytes, int grid, const FirstIds &ids, int32_t nids,
+                             hipStream_t s) {
+    const int g = grid < 1 ? 1 : grid;
+    const int32_t k = nids < 0 ? 0 : (nids > kFirstArgIds ? kFirstArgIds : nids);
+    if (dist_bytes == 1) {
+        if (a.unroll >= 8) hipLaunchKernelGGL((k_wide_first<uint8_t, 8>), dim3(g), dim3(kWG), 0, s, a, ids, k);
+        else hipLaunchKernelGGL((k_wide_first<uint8_t, 4>), dim3(g), dim3(kWG), 0, s, a, ids, k);
+    } else {
+        if (a.unroll >= 8) hipLaunchKernelGGL((k_wide_first<uint16_t, 8>), dim3(g), dim3(kWG), 0, s, a, ids, k);
+        else hipLaunchKernelGGL((k_wide_first<uint16_t, 4>), dim3(g), dim3(kWG), 0, s, a, ids, k);
     }
     return hipGetLastError();
 }

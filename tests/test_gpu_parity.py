@@ -198,6 +198,23 @@ def test_greedy_rmat16(gclib, block):
     assert grp_c.tolist() == grp_b.tolist() and F_c.tolist() == F_b.tolist()
 
 
+@pytest.mark.parametrize("block", [255, 256, 257, 1024, 1025])
+def test_greedy_launch_sizes(gclib, block):
+    """Later-round launches of 255..1025 candidates: the roots and level 0
+    of launches of at most 1024 candidates run as one kernel (ids as a kernel
+    argument up to 256 of them, read from the candidate list beyond), larger
+    ones as roots plus level kernels.  Picks, F(S_i), evaluations and the
+    scanned adjacency entries equal the CPU Greedy++'s."""
+    g = graphgen.ba(1100, 3, 17)
+    G = _graph(gclib, g)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 8, block=block, growth=1)
+    _note("greedy ba1100 k=8 plain block %d" % block)
+    grp, F, st = G.greedy_group(8, order="plain", block=block, block_growth=1, debug=True)
+    assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+    assert st["evals_per_round"].tolist() == ev_b.tolist()
+    assert st["edges_alg"] == int(ed_b.sum())
+
+
 def test_greedy_block_growth(gclib):
     """Every batch schedule gives the same group; the CELF order with a
     growing block matches the CPU Greedy++ picks; out-of-range factors are
