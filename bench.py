@@ -412,8 +412,8 @@ def reduce_profile(prefix, workload, k, order, out_dir, jobs):
     --warmup 0): the top kernels by time, and the HBM bytes of the greedy job's
     gain launches.  The job is every dispatch before the first k_bfs_level (the
     bench's own d(S,.) update that follows it); its gain launches run from a
-    k_wide_roots<., false> dispatch through the next k_wide_reset, except the
-    closeness search's (they contain k_wide_cut).  Each counter is scaled by
+    k_wide_roots<., false> or k_wide_first dispatch through the next
+    k_wide_reset, except the closeness search's (they contain k_wide_cut).  Each counter is scaled by
     what it reads for the bench's 1 GiB device copy.
     `jobs` greedy jobs run before that update (the counter runs' warm-up and
     timed steps plus the event-timed job), all the same job."""
@@ -439,6 +439,9 @@ def reduce_profile(prefix, workload, k, order, out_dir, jobs):
         for name, val in disp[:end]:
             if "k_wide_roots" in name:
                 gain = "false>" in name
+                seq = []
+            elif "k_wide_first" in name:
+                gain = True
                 seq = []
             if gain and "k_wide_" in name:
                 seq.append((_short_kernel(name), val))
@@ -787,8 +790,8 @@ def main():
                          ("ms_closest", "ms_round1", "ms_later", "ms_update", "ms_mlp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "kernel": "gain launches of the job (k_wide_roots, k_wide_level, k_wide_end, "
-                               "k_wide_reset; rows split by k_row_split)",
+                     "kernel": "gain launches of the job (k_wide_roots or k_wide_first, k_wide_level, "
+                               "k_wide_end, k_wide_reset; rows split by k_row_split)",
                      "launches": launches, "launch_ms": round(gain_gpu_ms / launches, 5),
                      "alg_bytes_per_launch": round(job_alg / launches, 1),
                      "copy_gbs_measured": round(copy_gbs, 1) if copy_gbs else None},
