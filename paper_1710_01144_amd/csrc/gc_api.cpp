@@ -1372,7 +1372,8 @@ int run_gains(const gc_graph *g, const Ws &w, const void *d_dist, int dist_bytes
                         if ((uint32_t)v < (uint32_t)g->n) ef += hrp[v + 1] - hrp[v];
                     }
                     const int64_t gw = (ef + a.min_edges - 1) / a.min_edges;
-                    gfirst = (int)std::max<int64_t>(1, std::min<int64_t>(grid, gw));
+                    // (and one workgroup per 256 roots after them)
+                    gfirst = (int)(std::max<int64_t>(1, std::min<int64_t>(grid, gw)) + (a.nsrc + kWG - 1) / kWG);
                     if (a.nsrc <= kFirstArgIds) {
                         nids = (int32_t)a.nsrc;
                         std::memcpy(ids.id, hs, sizeof(int32_t) * (size_t)nids);

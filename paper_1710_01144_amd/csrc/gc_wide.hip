@@ -644,10 +644,10 @@ __device__ __forceinline__ void count_wave(const WideArgs &a, WideLevel *l, bool
 // with its own bit.  A candidate's bit is set only by its own search, and no
 // row holds its own node (a self-loop is skipped), so a root claimed by
 // another workgroup later than its neighbours changes no result.  The
-// workgroups also claim the roots (candidate t by thread t mod 256 of
-// workgroup t / 256, grid-strided): they store the root terms in gain[] and
-// count the roots into level 0's record as the roots kernel does, but write
-// no log entries and no level-0 frontier words.  Level-0 sums therefore go to
+// workgroups also claim the roots (candidate t by thread t mod 256 of the
+// (t / 256)-th workgroup from the last, grid-strided): they store the root
+// terms in gain[] and count the roots into level 0's record as the roots
+// kernel does, but write no log entries and no level-0 frontier words.  Level-0 sums therefore go to
 // acc[] (zero between launches), which the final kernel adds to gain[].
 // Level 0 and level 1 both start at log position nsrc: level 1 has nothing of
 // level 0 to clear.  The first nids candidate ids come from the argument
@@ -674,8 +674,11 @@ __global__ __launch_bounds__(256) void k_wide_first(WideArgs a, FirstIds ids, in
         a.lvl[0].start = ns;
         a.lvl[1].start = ns;
     }
-    // the roots (uniform trip count per workgroup: the appends are wave ops)
-    for (int64_t t0 = (int64_t)blockIdx.x * kWG; t0 < ns; t0 += (int64_t)gridDim.x * kWG) {
+    // the roots, from the last workgroup down (the host adds workgroups for
+    // them beyond those level 0 can use, which keeps them off the
+    // expansion's path; uniform trip count per workgroup: the appends are
+    // wave ops)
+    for (int64_t t0 = ((int64_t)gridDim.x - 1 - blockIdx.x) * kWG; t0 < ns; t0 += (int64_t)gridDim.x * kWG) {
         const int64_t t = t0 + tid;
         bool touched = false, p = false;
         int32_t v = 0, b = 0, deg = 0;
