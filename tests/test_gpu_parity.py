@@ -215,6 +215,25 @@ def test_greedy_launch_sizes(gclib, block):
     assert st["edges_alg"] == int(ed_b.sum())
 
 
+def test_greedy_fused_launch_overflow(gclib, monkeypatch):
+    """Later-round launches of 1024 candidates on a 48x48 grid, whose
+    frontier levels (about 11,000 entries over the 16 batches at the widest)
+    overflow a ring of 4,096 entries: each launch is redone with fewer
+    batches until it fits, the level-0 sums of the overflowed ones are
+    dropped, and every result still equals the CPU Greedy++'s."""
+    monkeypatch.setenv("GC_LOG_ENTRIES", "3000")
+    g = graphgen.grid(48, 48, 5)
+    G = _graph(gclib, g)
+    grp_b, F_b, ev_b, ed_b = oracle.greedypp(g, 5, block=1024, growth=1)
+    for order in ("plain", "celf"):
+        _note("greedy grid48x48 k=5 %s block 1024, small ring" % order)
+        grp, F, st = G.greedy_group(5, order=order, block=1024, block_growth=1, debug=True)
+        assert grp.tolist() == grp_b.tolist() and F.tolist() == F_b.tolist()
+        if order == "plain":
+            assert st["evals_per_round"].tolist() == ev_b.tolist()
+            assert st["edges_alg"] == int(ed_b.sum())
+
+
 def test_greedy_block_growth(gclib):
     """Every batch schedule gives the same group; the CELF order with a
     growing block matches the CPU Greedy++ picks; out-of-range factors are
