@@ -349,7 +349,7 @@ def test_greedy_rmat20_k100_full_size(gclib):
     assert st["edges_alg"] == int(ed_b.sum())
     # F(S_k) from the definition, one BFS per member
     assert int(F[-1]) == oracle.farness(g, grp)
-    # sampled round-2 gains one by one by full BFS
+    # sampled gains of the second pick, one by one by full BFS
     dS = oracle.group_dist(g, grp[:1])
     rng = np.random.default_rng(5)
     cand = rng.choice(g.n, 40, replace=False).astype(np.int32)
