@@ -192,7 +192,9 @@ hipError_t launch_wide_begin(const WideArgs &a, int dist_bytes, int32_t nlev, hi
 // at most kFirstMaxSrc sources, packed sums (pack != 0) with acc set, no
 // per-source visited counts, active masks, early exit or write-back.  ids
 // holds a.src[0 .. nids) (nids <= kFirstArgIds; 0: none); grid may be cut to
-// the workgroups the level-0 adjacency entries can need.
+// the workgroups the level-0 adjacency entries can need plus one per 256
+// sources (the roots are claimed from the last workgroup down).  A launch of
+// more than kFirstMaxSrc sources raises the overflow flag and does nothing.
 hipError_t launch_wide_first(const WideArgs &a, int dist_bytes, int grid, const FirstIds &ids, int32_t nids,
                              hipStream_t s);
 hipError_t launch_wide_levels(const WideArgs &a, int dist_bytes, int32_t l0, int32_t l1, int grid,

@@ -669,6 +669,12 @@ __global__ __launch_bounds__(256) void k_wide_first(WideArgs a, FirstIds ids, in
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int64_t ns = a.nsrc;
+    if (ns > kFirstMaxSrc) {
+        // (the LDS tables hold kFirstMaxSrc candidates: flag the launch, which
+        // the host then redoes with fewer batches)
+        if (blockIdx.x == 0 && tid == 0) set_flag(a.flags, a.tag);
+        return;
+    }
     DistT *dist = reinterpret_cast<DistT *>(const_cast<void *>(a.dist));
     if (blockIdx.x == 0 && tid == 0) {
         a.lvl[0].start = ns;
