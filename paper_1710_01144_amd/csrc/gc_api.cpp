@@ -460,7 +460,11 @@ static int load_graph(int32_t n, int64_t nnz, const int32_t *d_row_ptr, const in
     }
     g->unroll_small = 4;
     if (const char *e = getenv("GC_UNROLL_SMALL")) g->unroll_small = strtol(e, nullptr, 10) >= 8 ? 8 : 4;
-    g->min_edges_small = 512;
+    // adjacency entries per workgroup of small launches: graphs below 2^24 CSR
+    // entries (small territories, levels of a few thousand entries) gain from
+    // spreading a level over twice the workgroups; large ones (hub rows, more
+    // work per workgroup) do not
+    g->min_edges_small = nnz < (1LL << 24) ? 256 : 512;
     if (const char *e = getenv("GC_MIN_EDGES_SMALL")) {
         long v = strtol(e, nullptr, 10);
         if (v >= 16) g->min_edges_small = (int32_t)v;
